@@ -1,0 +1,32 @@
+"""FP64 CPU oracle for the Fresnel + matrix-Fourier-transform hot path of
+Douglas & Perrin, "Accelerated Modeling of Near and Far-Field Diffraction for
+Coronagraphic Optical Systems" (SPIE 2018, arXiv:1806.06467).
+
+TEST INFRASTRUCTURE. Only the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product path (the HIP library
+and its Python binding) never does, and this package imports nothing from it.
+
+Every routine here is the plain definition of what the paper's method computes,
+written out in float64 with explicit DFT / MFT matrices and no FFT: slow on
+purpose, so that it can be checked against the paper and the mathematics by eye.
+
+Pins (see tests/test_oracle_*.py): brute-force DFT on tiny grids, Parseval,
+the complex Gaussian-beam closed form, the Talbot self-imaging closed form,
+the thin-lens q-parameter law, the Airy pattern, the exact DFT special case of
+the MFT, dot-product (adjoint) identities, the AS/MFT lattice invariance,
+finite differences and a Taylor test of the gradient.
+
+parity unpinned: the composed Lyot-train intensity (O5) beyond its component
+pins, its no-occulter reduction and its adjoint identity — there is no printed
+value in the paper for that system to compare against.
+"""
+
+from .core import (  # noqa: F401
+    centred, signed_index, dft_matrix, dft2, idft2, transfer_function,
+    as_propagate, optic_phasor, fresnel_step, mft_matrix, mft, mft_adjoint,
+)
+from .train import (  # noqa: F401
+    embed, extract, dm_influence, dm_surface, TrainGeometry, train_forward,
+    dm_to_detector, dm_to_detector_adjoint,
+    train_psf, train_backward, train_loss, train_grad, fd_grad,
+)

@@ -1,0 +1,158 @@
+"""Core FP64 definitions: DFT, optic phasor, angular-spectrum step, MFT.
+
+TEST INFRASTRUCTURE (see the package docstring): never imported by the product path.
+
+Conventions (fixed readings of points the paper leaves open):
+  * arrays are indexed [y, x]; the optical axis sits on pixel n//2 of every
+    plane, so the centred coordinate of index i is c(i) = i - n//2 (the
+    fftshift discussion of Sec. 2.4 is about exactly this re-centring);
+  * the signed frequency index of DFT bin k is k if k < n/2, else k - n;
+  * no e^{ikz} piston and no 1/(i lambda z) factor are applied (intensity-
+    invariant; Sec. 1.1 does not state them).
+"""
+
+from functools import lru_cache
+
+import numpy as np
+
+
+def centred(n):
+    """c(i) = i - n//2 as int64 (axis on pixel n//2)."""
+    return np.arange(n, dtype=np.int64) - n // 2
+
+
+def signed_index(n):
+    """Signed DFT frequency index: k for k < n/2, k - n otherwise."""
+    k = np.arange(n, dtype=np.int64)
+    return np.where(2 * k < n, k, k - n)
+
+
+# --------------------------------------------------------------------------------------------
+# O1. Discrete Fourier transform (Sec. 1.2: the transform the FFT evaluates in O(n log n)).
+# --------------------------------------------------------------------------------------------
+
+@lru_cache(maxsize=4)
+def _dft_matrix_cached(n):
+    k = np.arange(n, dtype=np.int64)
+    p = np.outer(k, k) % n                      # exact integer index reduction
+    w = np.exp((-2j * np.pi / n) * p)
+    w.setflags(write=False)
+    return w
+
+
+def dft_matrix(n):
+    """W[k, m] = exp(-2 pi i ((k m) mod n) / n), the n-point DFT matrix (symmetric)."""
+    return _dft_matrix_cached(int(n))
+
+
+def dft2(u):
+    """Unnormalised 2-D DFT, W U W^T (first along y, then along x)."""
+    n = u.shape[0]
+    if u.shape != (n, n):
+        raise ValueError("square arrays only")
+    w = dft_matrix(n)
+    return w @ u @ w.T
+
+
+def idft2(u):
+    """Inverse 2-D DFT, conj(W) U conj(W)^T / n^2."""
+    n = u.shape[0]
+    if u.shape != (n, n):
+        raise ValueError("square arrays only")
+    wc = dft_matrix(n).conj()
+    return (wc @ u @ wc.T) / (n * n)
+
+
+# --------------------------------------------------------------------------------------------
+# O3. Angular-spectrum plane-to-plane step, paraxial transfer function
+#     (Sec. 1.1: angular spectrum propagation after Lawrence Eqs. 82-89).
+# --------------------------------------------------------------------------------------------
+
+def transfer_function(n, dx, wavelength, z):
+    """H[ky, kx] = exp(-i pi lambda z (fx^2 + fy^2)), f = signed index / (n dx).
+
+    Formed per pixel (not factored): the integer kx^2 + ky^2 is exact, the phase
+    is taken in turns in float64 and reduced to [-1/2, 1/2] before the exponential.
+    """
+    k = signed_index(n)
+    q = k[:, None] ** 2 + k[None, :] ** 2
+    turns = q * (-float(wavelength) * float(z) / (2.0 * (n * float(dx)) ** 2))
+    turns = turns - np.round(turns)
+    return np.exp(2j * np.pi * turns)
+
+
+def as_propagate(u, dx, wavelength, z):
+    """U(z) = IDFT2( H . DFT2(U) ): one angular-spectrum step over signed distance z."""
+    n = u.shape[0]
+    return idft2(transfer_function(n, dx, wavelength, z) * dft2(np.asarray(u, dtype=np.complex128)))
+
+
+# --------------------------------------------------------------------------------------------
+# O2. Optic multiply: the complex phasor of Eq. (3), A exp(2 pi i phi / lambda), plus a
+#     reflective surface (OPD = 2 x surface) and a thin lens exp(-i pi r^2 / (lambda f))
+#     (Sec. 1.1: powered optics as thin lenses, Goodman Eq. 5-10; Eq. (2) is the
+#     quadratic-phase exponential).
+# --------------------------------------------------------------------------------------------
+
+def optic_phasor(n, dx, wavelength, amp=None, opd=None, surface=None, lens_focal=0.0):
+    """A exp(2 pi i (opd + 2 surface) / lambda) exp(-i pi r^2 / (lambda f)) on an n x n grid.
+
+    amp, opd, surface: n x n real arrays or None. lens_focal: focal length in m (0: no lens).
+    """
+    lam = float(wavelength)
+    turns = np.zeros((n, n))
+    if opd is not None:
+        turns = turns + np.asarray(opd, dtype=np.float64) / lam
+    if surface is not None:
+        turns = turns + 2.0 * np.asarray(surface, dtype=np.float64) / lam
+    if lens_focal:
+        c = centred(n)
+        r2 = (c[:, None] ** 2 + c[None, :] ** 2) * (float(dx) ** 2)
+        turns = turns - r2 / (2.0 * lam * float(lens_focal))
+    turns = turns - np.round(turns)
+    ph = np.exp(2j * np.pi * turns)
+    if amp is not None:
+        ph = ph * np.asarray(amp, dtype=np.float64)
+    return ph
+
+
+def fresnel_step(u, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, adjoint=False):
+    """One Fresnel plane: optic multiply (Eq. 3 + thin lens) then AS step over z.
+
+    adjoint=True applies the exact adjoint of that linear map: AS over -z, then
+    multiply by the conjugate optic phasor.
+    """
+    u = np.asarray(u, dtype=np.complex128)
+    n = u.shape[0]
+    ph = optic_phasor(n, dx, wavelength, amp, opd, None, lens_focal)
+    if adjoint:
+        return as_propagate(u, dx, wavelength, -z) * np.conj(ph)
+    return as_propagate(u * ph, dx, wavelength, z)
+
+
+# --------------------------------------------------------------------------------------------
+# O4. Matrix Fourier transform (Sec. 1.1: the semi-analytic coronagraph of Soummer et al. uses
+#     matrix DFTs of modest arrays; Sec. 2.3: the sin/cos arrays of the matrix DFT).
+# --------------------------------------------------------------------------------------------
+
+def mft_matrix(m_out, n_in, n_d, du):
+    """W[k, m] = exp(-2 pi i u_k x_m), u_k = (k - m_out//2) du  [lambda/D],
+    x_m = (m - n_in//2) / n_d  [D].  The index product is an exact integer."""
+    p = np.outer(centred(m_out), centred(n_in))
+    turns = p * (float(du) / float(n_d))
+    turns = turns - np.round(turns)
+    return np.exp(-2j * np.pi * turns)
+
+
+def mft(e, n_d, m_out, du):
+    """E_B = (du / n_d) W E W^T: n_in x n_in pupil field -> m_out x m_out focal field."""
+    e = np.asarray(e, dtype=np.complex128)
+    w = mft_matrix(m_out, e.shape[0], n_d, du)
+    return (float(du) / float(n_d)) * (w @ e @ w.T)
+
+
+def mft_adjoint(eb, n_d, n_out, du):
+    """Exact adjoint of mft: E_A = (du / n_d) W^H E_B conj(W), focal m x m -> pupil n_out x n_out."""
+    eb = np.asarray(eb, dtype=np.complex128)
+    w = mft_matrix(eb.shape[0], n_out, n_d, du)
+    return (float(du) / float(n_d)) * (w.conj().T @ eb @ w.conj())
