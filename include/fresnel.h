@@ -1,0 +1,173 @@
+/* fresnel.h - C ABI of libfresnel.so, the gfx950 (MI355X) Fresnel + matrix-Fourier-transform
+ * propagation library.
+ *
+ * The operations are those of Douglas & Perrin, "Accelerated Modeling of Near and Far-Field
+ * Diffraction for Coronagraphic Optical Systems" (SPIE 2018, arXiv:1806.06467):
+ *   - fresnel_step: one plane-to-plane step, i.e. the optic multiply of Eq. (3) (and a thin
+ *     lens, Sec. 1.1 after Goodman Eq. 5-10) followed by angular-spectrum propagation
+ *     (Sec. 1.1, after Lawrence Eqs. 82-89): 2-D FFT, transfer function, inverse 2-D FFT;
+ *   - mft_forward / mft_adjoint: the matrix Fourier transform between pupil and focal planes
+ *     used by the semi-analytic Lyot coronagraph (Sec. 1.1, Soummer et al.; Sec. 2.3, the
+ *     sin/cos arrays of the matrix DFT);
+ *   - propagate_train: a complete coronagraph train repeated over wavelengths (Sec. 1.2),
+ *     with an optional adjoint pass giving deformable-mirror gradients.
+ *
+ * Conventions (all entry points):
+ *   - complex data are interleaved float pairs (fr_c64), row-major [y][x], in DEVICE memory;
+ *     real maps (amplitude, OPD, masks) are float, row-major, device memory;
+ *   - the optical axis of an n x n plane sits on pixel (n/2, n/2) (integer division);
+ *   - forward transforms use exp(-2 pi i ...); the angular-spectrum transfer function is the
+ *     paraxial H(fx, fy) = exp(-i pi lambda z (fx^2 + fy^2)) with no e^{ikz} piston;
+ *   - lengths are SI metres, angles on focal planes are in lambda/D;
+ *   - every call is asynchronous on `stream` (a hipStream_t; NULL = the null stream); device
+ *     buffers are owned by the caller and must stay valid until the stream reaches the call;
+ *   - return value: FR_OK (0), a negative FR_E* error (nothing was launched and no output
+ *     was touched), or a positive FR_W_* bitmask (results were written; a sampling warning).
+ *   - an fr_ctx caches per-geometry tables (FFT roots, transfer functions, lens chirps, MFT
+ *     matrices, DM influence matrices). The first call with new parameters builds them
+ *     (allocating device memory and waiting on `stream` for the upload); later calls with the
+ *     same parameters allocate nothing. One fr_ctx may be used by one host thread at a time.
+ */
+#ifndef FRESNEL_H
+#define FRESNEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status ------------------------------------------------------------------------ */
+#define FR_OK 0
+#define FR_EINVAL (-1)        /* bad argument: null pointer, non-positive size, bad flag   */
+#define FR_EUNSUPPORTED (-2)  /* size or combination the kernels do not implement          */
+#define FR_EWORKSPACE (-3)    /* workspace missing or smaller than the *_workspace_bytes   */
+#define FR_EHIP (-4)          /* a HIP runtime call or a kernel launch failed              */
+#define FR_ENOMEM (-5)        /* device allocation for a cached table failed               */
+
+#define FR_W_AS_UNDERSAMPLED 1 /* |z| > n dx^2 / lambda: the transfer function aliases     */
+#define FR_W_MFT_ALIASED 2     /* du > n_d / n_in: focal sampling beyond the input lattice */
+
+/* flags of fresnel_step */
+#define FR_ADJOINT 1 /* apply the adjoint: AS over -z first, then the conjugate optic      */
+
+typedef struct fr_ctx fr_ctx;
+typedef struct {
+  float re, im;
+} fr_c64;
+
+/* Create a context bound to HIP device `device`. *ctx receives the handle. */
+int fr_create(fr_ctx **ctx, int device);
+/* Free every cached table and the context (synchronises the device). NULL is accepted. */
+int fr_destroy(fr_ctx *ctx);
+/* Static text for a status code (never NULL). For FR_EHIP the last HIP error is appended. */
+const char *fr_status_string(int status);
+/* 1 if n is a plane edge fresnel_step implements, else 0. */
+int fr_fft_size_supported(int32_t n);
+
+/* ---- one Fresnel plane (Sec. 1.1; Eq. 3) ----------------------------------------------
+ * field  : n x n c64, in place. On return field <- AS_z( field * optic ), where
+ *          optic = amp * exp(2 pi i opd / lambda) * exp(-i pi r^2 / (lambda f)),
+ *          r^2 = ((x - n/2)^2 + (y - n/2)^2) dx^2 and the two-dimensional AS step is
+ *          U <- IDFT2( H . DFT2(U) ), H[ky][kx] = exp(-i pi lambda z (kx^2 + ky^2)/(n dx)^2),
+ *          kx, ky the signed frequency indices.
+ *          With FR_ADJOINT: field <- conj(optic) * AS_{-z}(field), the exact adjoint.
+ * amp    : n x n float or NULL (= 1).   opd_m : n x n float OPD in metres or NULL (= 0).
+ * lens_focal_m : thin-lens focal length, 0 = no lens.
+ * Implemented edges: fr_fft_size_supported(n). Errors: FR_EINVAL (null field, n <= 0,
+ * dx/lambda <= 0, unknown flag), FR_EUNSUPPORTED (edge). Warning: FR_W_AS_UNDERSAMPLED.
+ * Uses no workspace: each sweep owns whole rows/columns, so the update is in place. */
+int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wavelength_m,
+                 double z_m, const float *amp, const float *opd_m, double lens_focal_m,
+                 int32_t flags, void *stream);
+
+/* Many independent planes in one launch per sweep (e.g. the wavelengths of a broadband
+ * model, Sec. 1.2). Each entry has the meaning of the fresnel_step arguments. `planes` is a
+ * HOST array read during the call. All planes must share one edge n. Returns the OR of
+ * the per-plane warnings, or the first error (then nothing was launched). */
+typedef struct {
+  fr_c64 *field;
+  const float *amp;
+  const float *opd_m;
+  double dx_m, wavelength_m, z_m, lens_focal_m;
+  int32_t n, flags;
+} fr_plane;
+int fresnel_step_batched(fr_ctx *ctx, const fr_plane *planes, int32_t count, void *stream);
+
+/* ---- matrix Fourier transform (Sec. 1.1, Soummer et al.; Sec. 2.3) ---------------------
+ * Pupil sample m of an n_in-wide window sits at x_m = (m - n_in/2)/n_d  [D];
+ * focal sample k of an m_out grid sits at u_k = (k - m_out/2) du      [lambda/D].
+ *   mft_forward: out[ky][kx] = (du/n_d) sum_{y,x} W[ky][y] in[y][x] W[kx][x] (* out_mask),
+ *                W[k][m] = exp(-2 pi i u_k x_m); phases are formed from the exact integer
+ *                (k - m_out/2)(m - n_in/2) times du/n_d in float64 turns.
+ *   mft_adjoint: out = alpha (du/n_d) W^H in conj(W) + beta out, then out *= out_mask;
+ *                the exact adjoint of mft_forward for alpha = 1, beta = 0; alpha = -1,
+ *                beta = 1 is the Babinet subtraction of an occulting spot.
+ * ld_in / ld_out: row strides in elements (>= width), so a window of a larger plane can be
+ * read or updated in place. out_mask: float, same shape as out, or NULL.
+ * ws: device workspace of at least mft_workspace_bytes(n_in, m_out) bytes (forward) or
+ * mft_workspace_bytes(n_out, m_in) bytes (adjoint); contents on entry are ignored.
+ * Errors: FR_EINVAL, FR_EWORKSPACE. Warning: FR_W_MFT_ALIASED. */
+size_t mft_workspace_bytes(int32_t n_pupil, int32_t m_focal);
+int mft_forward(fr_ctx *ctx, const fr_c64 *in, int32_t n_in, int32_t ld_in, fr_c64 *out,
+                int32_t m_out, int32_t ld_out, double n_d, double du, const float *out_mask,
+                void *ws, size_t ws_bytes, void *stream);
+int mft_adjoint(fr_ctx *ctx, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_c64 *out,
+                int32_t n_out, int32_t ld_out, double n_d, double du, float alpha, float beta,
+                const float *out_mask, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- Lyot coronagraph train over wavelengths (Sec. 1.1 and 1.2) ------------------------
+ * Per wavelength lambda_j on an n_pad[j]-wide grid (dx = d_m / n_d):
+ *   E   = embed( pupil_amp * exp(2 pi i pupil_opd / lambda) )  [* DM1 phasor if n_dm == 2]
+ *   E   = AS_z(E) * exp(4 pi i s / lambda)      (last DM; s = G A G^T, Gaussian influence
+ *         G[i][a] = exp(-(i - n/2 - xi_a)^2 / (2 p^2)), xi_a = (a - (n_act-1)/2) p, p = n_d/n_act)
+ *   Eo  = MFT(E: whole padded plane -> occ_m^2, du = occ_du_c lambda_c / lambda)
+ *   EL  = lyot * ( window_{n_d}(E) - MFT^H(occ_mask * Eo -> n_d^2) )
+ *   Ed  = MFT(EL -> det_m^2, du = det_du_c lambda_c / lambda)
+ *   psf = sum_j weight_j |Ed_j|^2                           (det_m^2 float, overwritten)
+ * FR_TRAIN_NO_OCCULTER skips the occulter term (the reference PSF).
+ * FR_TRAIN_GRAD additionally takes grad_psf = dL/dpsf (det_m^2 float) and writes
+ * grad_heights = dL/dA (n_dm * n_act^2 float, DM1 first), the chain rule through every
+ * adjoint above. Arrays lambda_m, n_pad, weight are HOST arrays of n_lambda entries.
+ * ws: device workspace of propagate_train_workspace_bytes(...) bytes. */
+#define FR_TRAIN_NO_OCCULTER 1
+#define FR_TRAIN_GRAD 2
+typedef struct {
+  int32_t n_d;               /* pupil pixels across D                                   */
+  double d_m;                /* pupil diameter [m]                                      */
+  const float *pupil_amp;    /* n_d x n_d                                               */
+  const float *pupil_opd_m;  /* n_d x n_d or NULL                                       */
+  int32_t n_dm;              /* 0, 1 (after the step) or 2 (pupil and after the step)   */
+  int32_t n_act;             /* actuators per DM edge                                   */
+  const float *dm_heights_m; /* n_dm x n_act x n_act surface heights [m]                */
+  double z_m;                /* pupil -> last-DM distance [m]                           */
+  int32_t occ_m;             /* occulter grid edge                                      */
+  double occ_du_c;           /* occulter pitch [lambda_c/D]                             */
+  const float *occ_mask;     /* occ_m x occ_m, 1 where the spot blocks                  */
+  const float *lyot;         /* n_d x n_d                                               */
+  int32_t det_m;             /* detector grid edge                                      */
+  double det_du_c;           /* detector pitch [lambda_c/D]                             */
+  double lambda_c_m;         /* reference wavelength of the focal grids [m]             */
+} fr_train_desc;
+size_t propagate_train_workspace_bytes(const fr_train_desc *desc, int32_t n_lambda,
+                                       const int32_t *n_pad, int32_t mode);
+int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda,
+                    const double *lambda_m, const int32_t *n_pad, const float *weight,
+                    int32_t mode, float *psf, const float *grad_psf, float *grad_heights,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* ---- kernel timing (profiling aid; Sec. 2.1: profiling decides what to optimise) -------
+ * While enabled, every kernel the context launches is bracketed by two HIP events recorded
+ * on the launch stream. fr_profile_read waits for the recorded events, returns per-kernel
+ * totals (names "kernel/tag", NUL-terminated, name_len bytes each; total milliseconds;
+ * launch counts; at most max_entries rows, *n_entries written) and forgets them.
+ * Errors: FR_EINVAL (null ctx or outputs), FR_EHIP (an event failed). */
+int fr_profile_enable(fr_ctx *ctx, int enable);
+int fr_profile_read(fr_ctx *ctx, int32_t max_entries, char *names, int32_t name_len,
+                    double *total_ms, int64_t *launches, int32_t *n_entries);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRESNEL_H */

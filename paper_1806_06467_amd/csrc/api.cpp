@@ -1,0 +1,512 @@
+// Host runtime behind the C ABI of include/fresnel.h: argument checks, the per-context cache
+// of float64-built tables, and the launches.
+//
+// Tables (Sec. 2.3: sin/cos arrays; Sec. 1.1: transfer function and lens chirp): every phase
+// is formed from an exact integer (k^2, c^2 or an index product) times a float64 constant,
+// reduced to a fraction of a turn in float64, evaluated in float64 and only then rounded to
+// float. Separability keeps them O(n) per plane instead of O(n^2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fresnel.h"
+#include "fr_internal.h"
+#include "fr_runtime.h"
+
+using fr::PlaneArgs;
+
+namespace {
+
+thread_local std::string g_status_text;
+thread_local hipError_t g_last_hip = hipSuccess;
+
+}  // namespace
+
+namespace fr {
+
+double frac_turn(double t) { return t - std::nearbyint(t); }
+
+float2 turn_to_c64(double turns, double scale) {
+  const double f = frac_turn(turns);
+  return make_float2(float(std::cos(2.0 * M_PI * f) * scale), float(std::sin(2.0 * M_PI * f) * scale));
+}
+
+int signed_index(int k, int n) { return (2 * k < n) ? k : k - n; }
+
+int record_hip(hipError_t e) {
+  if (e == hipSuccess) return FR_OK;
+  g_last_hip = e;
+  return FR_EHIP;
+}
+
+Ctx::~Ctx() {
+  (void)hipSetDevice(device);
+  (void)hipDeviceSynchronize();
+  for (auto &kv : tables) (void)hipFree(kv.second);
+  tables.clear();
+  for (auto &t : timed) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (auto e : event_pool) (void)hipEventDestroy(e);
+}
+
+hipEvent_t Ctx::take_event() {
+  if (!event_pool.empty()) {
+    hipEvent_t e = event_pool.back();
+    event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static void timing_hook(void *user, hipStream_t s, const char *name, int tag, int phase) {
+  Ctx *c = static_cast<Ctx *>(user);
+  hipEvent_t e = c->take_event();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  if (phase == 0) {
+    c->pending_start = e;
+  } else if (c->pending_start) {
+    c->timed.push_back({std::string(name) + "/" + std::to_string(tag), c->pending_start, e});
+    c->pending_start = nullptr;
+  } else {
+    c->event_pool.push_back(e);
+  }
+}
+
+LaunchHook Ctx::hook() {
+  LaunchHook h;
+  if (profiling) {
+    h.fn = timing_hook;
+    h.user = this;
+  }
+  return h;
+}
+
+int Ctx::upload(const TableKey &key, const void *host, size_t bytes, hipStream_t s, void **out) {
+  auto it = tables.find(key);
+  if (it != tables.end()) {
+    *out = it->second;
+    return FR_OK;
+  }
+  if (tables.size() >= kMaxTables) {
+    // bounded cache: drop everything once it is full (tables are cheap to rebuild)
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return record_hip(e);
+    for (auto &kv : tables) (void)hipFree(kv.second);
+    tables.clear();
+  }
+  void *d = nullptr;
+  if (hipMalloc(&d, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return FR_ENOMEM;
+  }
+  hipError_t e = hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return record_hip(e);
+  }
+  tables.emplace(key, d);
+  *out = d;
+  return FR_OK;
+}
+
+static uint64_t bits(double v) {
+  uint64_t b;
+  std::memcpy(&b, &v, sizeof b);
+  return b;
+}
+
+int Ctx::roots(int n, hipStream_t s, const float2 **out) {
+  TableKey key{kRoots, n, 0, 0, 0, 0};
+  if (auto it = tables.find(key); it != tables.end()) {
+    *out = static_cast<const float2 *>(it->second);
+    return FR_OK;
+  }
+  std::vector<float2> h(n);
+  for (int m = 0; m < n; ++m) h[m] = turn_to_c64(-double(m) / double(n), 1.0);
+  void *d;
+  int st = upload(key, h.data(), h.size() * sizeof(float2), s, &d);
+  *out = static_cast<const float2 *>(d);
+  return st;
+}
+
+// h[k] = exp(-i pi lambda z k~^2 / (n dx)^2) / n  (signed index k~; 1/n folds the IFFT scale)
+int Ctx::transfer(int n, double dx, double lam, double z, hipStream_t s, const float2 **out) {
+  TableKey key{kTransfer, n, bits(dx), bits(lam), bits(z), 0};
+  if (auto it = tables.find(key); it != tables.end()) {
+    *out = static_cast<const float2 *>(it->second);
+    return FR_OK;
+  }
+  std::vector<float2> h(n);
+  const double coef = -lam * z / (2.0 * (double(n) * dx) * (double(n) * dx));
+  for (int k = 0; k < n; ++k) {
+    const long long kt = signed_index(k, n);
+    h[k] = turn_to_c64(double(kt * kt) * coef, 1.0 / double(n));
+  }
+  void *d;
+  int st = upload(key, h.data(), h.size() * sizeof(float2), s, &d);
+  *out = static_cast<const float2 *>(d);
+  return st;
+}
+
+// l[i] = exp(-i pi c(i)^2 dx^2 / (lambda f)), c(i) = i - n/2
+int Ctx::lens(int n, double dx, double lam, double f, hipStream_t s, const float2 **out) {
+  TableKey key{kLens, n, bits(dx), bits(lam), bits(f), 0};
+  if (auto it = tables.find(key); it != tables.end()) {
+    *out = static_cast<const float2 *>(it->second);
+    return FR_OK;
+  }
+  std::vector<float2> h(n);
+  const double coef = -dx * dx / (2.0 * lam * f);
+  for (int i = 0; i < n; ++i) {
+    const long long c = i - n / 2;
+    h[i] = turn_to_c64(double(c * c) * coef, 1.0);
+  }
+  void *d;
+  int st = upload(key, h.data(), h.size() * sizeof(float2), s, &d);
+  *out = static_cast<const float2 *>(d);
+  return st;
+}
+
+// W[k][m] = exp(-2 pi i (k - M/2)(m - N/2) du / n_d), M x N row-major
+int Ctx::mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out) {
+  TableKey key{kMft, m_out, uint64_t(n_in), bits(n_d), bits(du), 0};
+  if (auto it = tables.find(key); it != tables.end()) {
+    *out = static_cast<const float2 *>(it->second);
+    return FR_OK;
+  }
+  std::vector<float2> h(size_t(m_out) * n_in);
+  const double coef = -du / n_d;
+  for (int k = 0; k < m_out; ++k) {
+    const long long a = k - m_out / 2;
+    for (int m = 0; m < n_in; ++m) {
+      const long long b = m - n_in / 2;
+      h[size_t(k) * n_in + m] = turn_to_c64(double(a * b) * coef, 1.0);
+    }
+  }
+  void *d;
+  int st = upload(key, h.data(), h.size() * sizeof(float2), s, &d);
+  *out = static_cast<const float2 *>(d);
+  return st;
+}
+
+// G[i][a] = exp(-(c(i) - xi_a)^2 / (2 p^2)), xi_a = (a - (n_act-1)/2) p, p = n_d / n_act
+int Ctx::dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **out) {
+  TableKey key{kDm, n, uint64_t(n_d), uint64_t(n_act), 0, 0};
+  if (auto it = tables.find(key); it != tables.end()) {
+    *out = static_cast<const float *>(it->second);
+    return FR_OK;
+  }
+  std::vector<float> h(size_t(n) * n_act);
+  const double p = double(n_d) / double(n_act);
+  for (int i = 0; i < n; ++i) {
+    const double c = double(i - n / 2);
+    for (int a = 0; a < n_act; ++a) {
+      const double xi = (double(a) - (n_act - 1) / 2.0) * p;
+      const double d = c - xi;
+      h[size_t(i) * n_act + a] = float(std::exp(-d * d / (2.0 * p * p)));
+    }
+  }
+  void *d;
+  int st = upload(key, h.data(), h.size() * sizeof(float), s, &d);
+  *out = static_cast<const float *>(d);
+  return st;
+}
+
+}  // namespace fr
+
+// ============================================================================================
+// C ABI
+// ============================================================================================
+using fr::Ctx;
+
+extern "C" {
+
+int fr_create(fr_ctx **ctx, int device) {
+  if (!ctx) return FR_EINVAL;
+  *ctx = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return fr::record_hip(e);
+  if (device < 0 || device >= ndev) return FR_EINVAL;
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fr::record_hip(e);
+  Ctx *c = new Ctx();
+  c->device = device;
+  *ctx = reinterpret_cast<fr_ctx *>(c);
+  return FR_OK;
+}
+
+int fr_destroy(fr_ctx *ctx) {
+  delete reinterpret_cast<Ctx *>(ctx);
+  return FR_OK;
+}
+
+const char *fr_status_string(int status) {
+  switch (status) {
+    case FR_OK: return "ok";
+    case FR_EINVAL: return "invalid argument";
+    case FR_EUNSUPPORTED: return "unsupported size or combination";
+    case FR_EWORKSPACE: return "workspace missing or too small";
+    case FR_ENOMEM: return "device allocation for a cached table failed";
+    case FR_EHIP:
+      g_status_text = std::string("HIP error: ") + hipGetErrorString(g_last_hip);
+      return g_status_text.c_str();
+    default:
+      if (status > 0) return "ok with sampling warning";
+      return "unknown status";
+  }
+}
+
+int fr_fft_size_supported(int32_t n) { return fr::fresnel_size_supported(n) ? 1 : 0; }
+
+static int check_plane(const fr_plane &p) {
+  if (!p.field || p.n <= 0) return FR_EINVAL;
+  if (!(p.dx_m > 0) || !(p.wavelength_m > 0) || !std::isfinite(p.z_m)) return FR_EINVAL;
+  if (!std::isfinite(p.lens_focal_m)) return FR_EINVAL;
+  if (p.flags & ~FR_ADJOINT) return FR_EINVAL;
+  if (!fr::fresnel_size_supported(p.n)) return FR_EUNSUPPORTED;
+  return FR_OK;
+}
+
+static int plane_warnings(const fr_plane &p) {
+  return (std::fabs(p.z_m) > double(p.n) * p.dx_m * p.dx_m / p.wavelength_m) ? FR_W_AS_UNDERSAMPLED
+                                                                             : 0;
+}
+
+int fresnel_step_batched(fr_ctx *ctx_, const fr_plane *planes, int32_t count, void *stream) {
+  // arguments are validated before the context is touched
+  if (!planes || count <= 0) return FR_EINVAL;
+  const int n = planes[0].n;
+  int warn = 0;
+  for (int i = 0; i < count; ++i) {
+    int st = check_plane(planes[i]);
+    if (st != FR_OK) return st;
+    if (planes[i].n != n) return FR_EINVAL;
+    warn |= plane_warnings(planes[i]);
+  }
+  Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
+  if (!ctx) return FR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fr::record_hip(e);
+  const float2 *root;
+  int st = ctx->roots(n, s, &root);
+  if (st != FR_OK) return st;
+  std::vector<PlaneArgs> args(count);
+  for (int i = 0; i < count; ++i) {
+    const fr_plane &p = planes[i];
+    PlaneArgs &a = args[i];
+    a.field = reinterpret_cast<float2 *>(p.field);
+    a.amp = p.amp;
+    a.opd = p.opd_m;
+    a.inv_lambda = float(1.0 / p.wavelength_m);
+    a.flags = p.flags;
+    st = ctx->transfer(n, p.dx_m, p.wavelength_m, p.z_m, s, &a.h);
+    if (st != FR_OK) return st;
+    a.lens = nullptr;
+    if (p.lens_focal_m != 0.0) {
+      st = ctx->lens(n, p.dx_m, p.wavelength_m, p.lens_focal_m, s, &a.lens);
+      if (st != FR_OK) return st;
+    }
+  }
+  for (int i = 0; i < count; i += fr::kMaxBatch) {
+    const int c = std::min(count - i, fr::kMaxBatch);
+    e = fr::launch_fresnel_batch(args.data() + i, c, n, root, s, ctx->hook());
+    if (e != hipSuccess) return fr::record_hip(e);
+  }
+  return warn;
+}
+
+int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wavelength_m,
+                 double z_m, const float *amp, const float *opd_m, double lens_focal_m,
+                 int32_t flags, void *stream) {
+  fr_plane p;
+  p.field = field;
+  p.amp = amp;
+  p.opd_m = opd_m;
+  p.dx_m = dx_m;
+  p.wavelength_m = wavelength_m;
+  p.z_m = z_m;
+  p.lens_focal_m = lens_focal_m;
+  p.n = n;
+  p.flags = flags;
+  return fresnel_step_batched(ctx, &p, 1, stream);
+}
+
+}  // extern "C"
+
+// ============================================================================================
+// MFT entry points
+// ============================================================================================
+namespace {
+
+int mft_common_checks(const void *in, const void *out, int n, int ld_n, int m, int ld_m,
+                      double n_d, double du) {
+  if (!in || !out) return FR_EINVAL;
+  if (n <= 0 || m <= 0 || ld_n < n || ld_m < m) return FR_EINVAL;
+  if (!(n_d > 0) || !std::isfinite(n_d) || !(du > 0) || !std::isfinite(du)) return FR_EINVAL;
+  return FR_OK;
+}
+
+size_t mft_ws(int32_t n, int32_t m) { return size_t(1 + fr::kMaxSplit) * size_t(n) * size_t(m) * sizeof(float2); }
+
+hipError_t run_gemm(Ctx *ctx, fr::CGemmArgs &g, float2 *partial, size_t partial_elems, hipStream_t s) {
+  int split = fr::cgemm_split_for(g.M, g.N, g.K);
+  while (split > 1 && size_t(split) * size_t(g.M) * size_t(g.N) > partial_elems) split /= 2;
+  return fr::launch_cgemm_split(g, split, partial, s, ctx->hook());
+}
+
+fr::CGemmArgs gemm_args() {
+  fr::CGemmArgs g;
+  std::memset(&g, 0, sizeof g);
+  g.alpha_re = 1.0f;
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mft_workspace_bytes(int32_t n_pupil, int32_t m_focal) {
+  if (n_pupil <= 0 || m_focal <= 0) return 0;
+  return mft_ws(n_pupil, m_focal);
+}
+
+int mft_forward(fr_ctx *ctx_, const fr_c64 *in, int32_t n_in, int32_t ld_in, fr_c64 *out,
+                int32_t m_out, int32_t ld_out, double n_d, double du, const float *out_mask,
+                void *ws, size_t ws_bytes, void *stream) {
+  int st = mft_common_checks(in, out, n_in, ld_in, m_out, ld_out, n_d, du);
+  if (st != FR_OK) return st;
+  if (!ws || ws_bytes < mft_ws(n_in, m_out)) return FR_EWORKSPACE;
+  Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
+  if (!ctx) return FR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fr::record_hip(e);
+  const float2 *w;
+  st = ctx->mft_matrix(m_out, n_in, n_d, du, s, &w);
+  if (st != FR_OK) return st;
+  float2 *t = static_cast<float2 *>(ws);
+  float2 *partial = t + size_t(n_in) * m_out;
+  const size_t pcap = size_t(fr::kMaxSplit) * n_in * m_out;
+  // T = E W^T  (n_in x m_out)
+  fr::CGemmArgs g1 = gemm_args();
+  g1.M = n_in; g1.N = m_out; g1.K = n_in;
+  g1.A = reinterpret_cast<const float2 *>(in); g1.lda = ld_in;
+  g1.B = w; g1.ldb = n_in; g1.transB = 1;
+  g1.C = t; g1.ldc = m_out;
+  e = run_gemm(ctx, g1, partial, pcap, s);
+  if (e != hipSuccess) return fr::record_hip(e);
+  // out = (du / n_d) W T (* mask)
+  fr::CGemmArgs g2 = gemm_args();
+  g2.M = m_out; g2.N = m_out; g2.K = n_in;
+  g2.A = w; g2.lda = n_in;
+  g2.B = t; g2.ldb = m_out;
+  g2.C = reinterpret_cast<float2 *>(out); g2.ldc = ld_out;
+  g2.alpha_re = float(du / n_d);
+  g2.mask = out_mask; g2.ldm = m_out;
+  e = run_gemm(ctx, g2, partial, pcap, s);
+  if (e != hipSuccess) return fr::record_hip(e);
+  return (du > n_d / double(n_in)) ? FR_W_MFT_ALIASED : FR_OK;
+}
+
+int mft_adjoint(fr_ctx *ctx_, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_c64 *out,
+                int32_t n_out, int32_t ld_out, double n_d, double du, float alpha, float beta,
+                const float *out_mask, void *ws, size_t ws_bytes, void *stream) {
+  int st = mft_common_checks(in, out, n_out, ld_out, m_in, ld_in, n_d, du);
+  if (st != FR_OK) return st;
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return FR_EINVAL;
+  if (!ws || ws_bytes < mft_ws(n_out, m_in)) return FR_EWORKSPACE;
+  Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
+  if (!ctx) return FR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fr::record_hip(e);
+  const float2 *w;
+  st = ctx->mft_matrix(m_in, n_out, n_d, du, s, &w);
+  if (st != FR_OK) return st;
+  float2 *t = static_cast<float2 *>(ws);
+  float2 *partial = t + size_t(n_out) * m_in;
+  const size_t pcap = size_t(fr::kMaxSplit) * n_out * m_in;
+  // T = E_B conj(W)  (m_in x n_out)
+  fr::CGemmArgs g1 = gemm_args();
+  g1.M = m_in; g1.N = n_out; g1.K = m_in;
+  g1.A = reinterpret_cast<const float2 *>(in); g1.lda = ld_in;
+  g1.B = w; g1.ldb = n_out; g1.conjB = 1;
+  g1.C = t; g1.ldc = n_out;
+  e = run_gemm(ctx, g1, partial, pcap, s);
+  if (e != hipSuccess) return fr::record_hip(e);
+  // out = alpha (du / n_d) W^H T + beta out (* mask)
+  fr::CGemmArgs g2 = gemm_args();
+  g2.M = n_out; g2.N = n_out; g2.K = m_in;
+  g2.A = w; g2.lda = n_out; g2.transA = 1; g2.conjA = 1;
+  g2.B = t; g2.ldb = n_out;
+  g2.C = reinterpret_cast<float2 *>(out); g2.ldc = ld_out;
+  g2.alpha_re = float(alpha * (du / n_d));
+  g2.beta = beta;
+  g2.mask = out_mask; g2.ldm = n_out;
+  e = run_gemm(ctx, g2, partial, pcap, s);
+  if (e != hipSuccess) return fr::record_hip(e);
+  return (du > n_d / double(n_out)) ? FR_W_MFT_ALIASED : FR_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================================
+// Kernel timing
+// ============================================================================================
+extern "C" {
+
+int fr_profile_enable(fr_ctx *ctx_, int enable) {
+  Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
+  if (!ctx) return FR_EINVAL;
+  ctx->profiling = enable != 0;
+  return FR_OK;
+}
+
+int fr_profile_read(fr_ctx *ctx_, int32_t max_entries, char *names, int32_t name_len,
+                    double *total_ms, int64_t *launches, int32_t *n_entries) {
+  Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
+  if (!ctx || max_entries < 0 || (max_entries > 0 && (!names || name_len <= 1 || !total_ms || !launches)) ||
+      !n_entries)
+    return FR_EINVAL;
+  std::map<std::string, std::pair<double, int64_t>> acc;
+  int status = FR_OK;
+  for (auto &t : ctx->timed) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(t.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.start, t.stop);
+    if (e != hipSuccess) status = fr::record_hip(e);
+    auto &a = acc[t.name];
+    a.first += ms;
+    a.second += 1;
+    ctx->event_pool.push_back(t.start);
+    ctx->event_pool.push_back(t.stop);
+  }
+  ctx->timed.clear();
+  int i = 0;
+  for (auto &kv : acc) {
+    if (i >= max_entries) break;
+    std::snprintf(names + size_t(i) * name_len, size_t(name_len), "%s", kv.first.c_str());
+    total_ms[i] = kv.second.first;
+    launches[i] = kv.second.second;
+    ++i;
+  }
+  *n_entries = i;
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+// Register-resident small DFTs (radix 2, 3, 4, 5, 7, 8, 16) and compile-time twiddles.
+//
+// These are the butterflies of the Cooley-Tukey FFT that the paper relies on for its
+// O(n log n) plane transforms (Sec. 1.2). Sign convention: forward kernel exp(-2 pi i nk/R).
+// Constants are computed here at compile time from their definition (a Taylor series of
+// cos/sin about 0 after reduction to |x| <= pi/4); no library constants are used.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fr {
+
+struct c32 {
+  float x, y;
+};
+
+__device__ __forceinline__ c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ c32 cmul(c32 a, c32 b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ c32 cmulc(c32 a, c32 b) {  // a * conj(b)
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+__device__ __forceinline__ c32 cconj(c32 a) { return {a.x, -a.y}; }
+__device__ __forceinline__ c32 cscale(c32 a, float s) { return {a.x * s, a.y * s}; }
+__device__ __forceinline__ c32 mul_mi(c32 a) { return {a.y, -a.x}; }  // a * (-i)
+__device__ __forceinline__ c32 mul_pi(c32 a) { return {-a.y, a.x}; }  // a * (+i)
+
+// ---- compile-time trig ------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double ct_sin_small(double x) {  // |x| <= pi/4
+  double term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ct_cos_small(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+// cos / sin of 2 pi k / m for integers (exact octant reduction)
+constexpr double ct_cos_turn(long k, long m) {
+  k %= m;
+  if (k < 0) k += m;
+  // reduce to the first octant using symmetries of the circle
+  const double t = double(k) / double(m);  // in [0, 1)
+  const double q = t * 8.0;
+  const int oct = int(q);
+  const double f = (t - oct / 8.0) * 2.0 * kPi;  // angle inside the octant, [0, pi/4)
+  switch (oct) {
+    case 0: return ct_cos_small(f);
+    case 1: return ct_sin_small(kPi / 4 - f);
+    case 2: return -ct_sin_small(f);
+    case 3: return -ct_cos_small(kPi / 4 - f);
+    case 4: return -ct_cos_small(f);
+    case 5: return -ct_sin_small(kPi / 4 - f);
+    case 6: return ct_sin_small(f);
+    default: return ct_cos_small(kPi / 4 - f);
+  }
+}
+constexpr double ct_sin_turn(long k, long m) {
+  k %= m;
+  if (k < 0) k += m;
+  const double t = double(k) / double(m);
+  const double q = t * 8.0;
+  const int oct = int(q);
+  const double f = (t - oct / 8.0) * 2.0 * kPi;
+  switch (oct) {
+    case 0: return ct_sin_small(f);
+    case 1: return ct_cos_small(kPi / 4 - f);
+    case 2: return ct_cos_small(f);
+    case 3: return ct_sin_small(kPi / 4 - f);
+    case 4: return -ct_sin_small(f);
+    case 5: return -ct_cos_small(kPi / 4 - f);
+    case 6: return -ct_cos_small(f);
+    default: return -ct_sin_small(kPi / 4 - f);
+  }
+}
+
+// v * exp(-2 pi i K / M), with the multiples of pi/4 done without multiplications
+template <int K, int M>
+__device__ __forceinline__ c32 twmul(c32 v) {
+  constexpr int k = ((K % M) + M) % M;
+  constexpr float h = 0.70710678118654752440f;
+  if constexpr (k == 0) {
+    return v;
+  } else if constexpr (2 * k == M) {
+    return {-v.x, -v.y};
+  } else if constexpr (4 * k == M) {
+    return mul_mi(v);
+  } else if constexpr (4 * k == 3 * M) {
+    return mul_pi(v);
+  } else if constexpr (8 * k == M) {  // (1 - i)/sqrt2
+    return {(v.x + v.y) * h, (v.y - v.x) * h};
+  } else if constexpr (8 * k == 3 * M) {  // (-1 - i)/sqrt2
+    return {(v.y - v.x) * h, -(v.x + v.y) * h};
+  } else if constexpr (8 * k == 5 * M) {  // (-1 + i)/sqrt2
+    return {-(v.x + v.y) * h, (v.x - v.y) * h};
+  } else if constexpr (8 * k == 7 * M) {  // (1 + i)/sqrt2
+    return {(v.x - v.y) * h, (v.x + v.y) * h};
+  } else {
+    constexpr float c = float(ct_cos_turn(k, M));
+    constexpr float s = float(-ct_sin_turn(k, M));
+    return {v.x * c - v.y * s, v.x * s + v.y * c};
+  }
+}
+
+// ---- small DFTs in place on u[0..R) (natural order in, natural order out) --------------
+template <int R>
+struct Dft;
+
+template <>
+struct Dft<1> {
+  __device__ __forceinline__ static void run(c32*) {}
+};
+
+template <>
+struct Dft<2> {
+  __device__ __forceinline__ static void run(c32* u) {
+    c32 a = u[0], b = u[1];
+    u[0] = cadd(a, b);
+    u[1] = csub(a, b);
+  }
+};
+
+template <>
+struct Dft<4> {
+  __device__ __forceinline__ static void run(c32* u) {
+    c32 t0 = cadd(u[0], u[2]), t1 = csub(u[0], u[2]);
+    c32 t2 = cadd(u[1], u[3]), t3 = csub(u[1], u[3]);
+    u[0] = cadd(t0, t2);
+    u[2] = csub(t0, t2);
+    u[1] = cadd(t1, mul_mi(t3));
+    u[3] = csub(t1, mul_mi(t3));
+  }
+};
+
+template <>
+struct Dft<3> {
+  __device__ __forceinline__ static void run(c32* u) {
+    constexpr float s3 = 0.86602540378443864676f;  // sqrt(3)/2
+    c32 t = cadd(u[1], u[2]), d = csub(u[1], u[2]);
+    c32 a = u[0];
+    c32 m = {a.x - 0.5f * t.x, a.y - 0.5f * t.y};
+    c32 r = {d.x * s3, d.y * s3};
+    u[0] = cadd(a, t);
+    u[1] = cadd(m, mul_mi(r));
+    u[2] = csub(m, mul_mi(r));
+  }
+};
+
+// odd prime R: pair n with R - n; X_k = x0 + sum s_n cos - i sum d_n sin, X_{R-k} with +i
+template <int R>
+struct DftOdd {
+  __device__ __forceinline__ static void run(c32* u) {
+    constexpr int H = (R - 1) / 2;
+    c32 s[H], d[H];
+#pragma unroll
+    for (int n = 1; n <= H; ++n) {
+      s[n - 1] = cadd(u[n], u[R - n]);
+      d[n - 1] = csub(u[n], u[R - n]);
+    }
+    c32 x0 = u[0];
+    c32 sum = x0;
+#pragma unroll
+    for (int n = 0; n < H; ++n) sum = cadd(sum, s[n]);
+    c32 out[R];
+    out[0] = sum;
+    run_k<1>(x0, s, d, out);
+#pragma unroll
+    for (int k = 0; k < R; ++k) u[k] = out[k];
+  }
+  template <int K>
+  __device__ __forceinline__ static void run_k(c32 x0, const c32* s, const c32* d, c32* out) {
+    constexpr int H = (R - 1) / 2;
+    if constexpr (K <= H) {
+      c32 a = x0, b = {0.f, 0.f};
+      acc<K, 1>(a, b, s, d);
+      out[K] = cadd(a, mul_mi(b));
+      out[R - K] = csub(a, mul_mi(b));
+      run_k<K + 1>(x0, s, d, out);
+    }
+  }
+  template <int K, int N1>
+  __device__ __forceinline__ static void acc(c32& a, c32& b, const c32* s, const c32* d) {
+    constexpr int H = (R - 1) / 2;
+    if constexpr (N1 <= H) {
+      constexpr float c = float(ct_cos_turn(long(K) * N1, R));
+      constexpr float sn = float(ct_sin_turn(long(K) * N1, R));
+      a.x += s[N1 - 1].x * c;
+      a.y += s[N1 - 1].y * c;
+      b.x += d[N1 - 1].x * sn;
+      b.y += d[N1 - 1].y * sn;
+      acc<K, N1 + 1>(a, b, s, d);
+    }
+  }
+};
+
+template <>
+struct Dft<5> : DftOdd<5> {};
+template <>
+struct Dft<7> : DftOdd<7> {};
+
+// composite R = A * B: n = B*n1 + n2, k = k1 + A*k2
+//   step 1: for each n2, DFT_A over n1; twiddle by w_R^(n2 k1); step 2: for each k1, DFT_B over n2
+template <int A, int B>
+struct DftComposite {
+  __device__ __forceinline__ static void run(c32* u) {
+    constexpr int R = A * B;
+    c32 t[R];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+      c32 a[A];
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) a[n1] = u[B * n1 + n2];
+      Dft<A>::run(a);
+      tw_row<0>(a, n2);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) t[k1 * B + n2] = a[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      c32 b[B];
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) b[n2] = t[k1 * B + n2];
+      Dft<B>::run(b);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) u[k1 + A * k2] = b[k2];
+    }
+  }
+  // a[k1] *= w_R^(n2 k1); n2 is a loop index that unrolls to a constant
+  template <int K1>
+  __device__ __forceinline__ static void tw_row(c32* a, int n2) {
+    if constexpr (K1 < A) {
+      a[K1] = tw_dispatch<K1, 0>(a[K1], n2);
+      tw_row<K1 + 1>(a, n2);
+    }
+  }
+  template <int K1, int N2>
+  __device__ __forceinline__ static c32 tw_dispatch(c32 v, int n2) {
+    if constexpr (N2 < B) {
+      if (n2 == N2) return twmul<K1 * N2, A * B>(v);
+      return tw_dispatch<K1, N2 + 1>(v, n2);
+    } else {
+      return v;
+    }
+  }
+};
+
+template <>
+struct Dft<8> : DftComposite<2, 4> {};
+template <>
+struct Dft<16> : DftComposite<4, 4> {};
+template <>
+struct Dft<32> : DftComposite<4, 8> {};
+
+}  // namespace fr

@@ -1,0 +1,68 @@
+// Internal interfaces between the host runtime (api.cpp) and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fr {
+
+struct c32;
+
+// Optional per-launch callback (kernel timing): phase 0 just before a kernel launch on `s`,
+// phase 1 just after it. `tag` distinguishes launches of one kernel (e.g. the plane edge).
+struct LaunchHook {
+  void (*fn)(void *user, hipStream_t s, const char *name, int tag, int phase) = nullptr;
+  void *user = nullptr;
+  void operator()(hipStream_t s, const char *name, int tag, int phase) const {
+    if (fn) fn(user, s, name, tag, phase);
+  }
+};
+
+// One plane of a Fresnel batch, as the sweep kernels see it (device pointers).
+struct PlaneArgs {
+  float2 *field;       // n x n, in place
+  const float *amp;    // n x n or null
+  const float *opd;    // n x n OPD [m] or null
+  const float2 *h;     // n: exp(-i pi lambda z k^2/(n dx)^2) / n over signed index k
+  const float2 *lens;  // n: exp(-i pi c^2 dx^2 / (lambda f)) or null
+  float inv_lambda;    // 1 / lambda [1/m]
+  int flags;           // FR_ADJOINT
+};
+
+constexpr int kMaxBatch = 64;
+struct BatchArgs {
+  PlaneArgs p[kMaxBatch];
+};
+
+// Row sweep then column sweep over `count` planes of edge n (count <= kMaxBatch).
+// root: n complex roots exp(-2 pi i m / n). Returns a hipError_t.
+hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const float2 *root,
+                                hipStream_t stream, const LaunchHook &hook);
+bool fresnel_size_supported(int n);
+
+// ---- MFT: out = alpha * c * A in B^T (+ beta * out) (* mask), complex, FP32 MFMA ------
+// Generic complex GEMM pieces used by the MFT entry points.
+struct CGemmArgs {
+  int M, N, K;
+  const float2 *A;  // M x K, row stride lda
+  int lda;
+  const float2 *B;  // K x N (or its transpose), row stride ldb
+  int ldb;
+  float2 *C;        // M x N, row stride ldc
+  int ldc;
+  int transA;       // 1: A is given as K x M (use A^T)
+  int transB;       // 1: B is given as N x K (use B^T)
+  int conjA, conjB; // conjugate the operand on load
+  float alpha_re, alpha_im;
+  float beta;       // real
+  const float *mask;  // M x N (row stride ldm) or null: multiplies the result
+  int ldm;
+};
+// C = alpha op(A) op(B) (+ beta C) (* mask). split > 1 slices K; the slices' partial sums go
+// to `partial` (split x M x N c64) and are added in a fixed order by a second kernel.
+constexpr int kMaxSplit = 16;
+int cgemm_split_for(int M, int N, int K);
+hipError_t launch_cgemm_split(const CGemmArgs &a, int split, float2 *partial, hipStream_t stream,
+                              const LaunchHook &hook);
+
+}  // namespace fr

@@ -1,0 +1,315 @@
+"""ctypes binding of libfresnel.so (C ABI: include/fresnel.h).
+
+Argument marshalling only: torch tensors supply device memory and the current HIP stream,
+every step of the computation runs in the library's kernels. There is no CPU fallback: if
+the library is not built, or a tensor is not on the GPU, the call raises.
+"""
+
+import ctypes
+import os
+import re
+import threading
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfresnel.so")
+HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "fresnel.h")
+
+FR_OK = 0
+FR_EINVAL = -1
+FR_EUNSUPPORTED = -2
+FR_EWORKSPACE = -3
+FR_EHIP = -4
+FR_ENOMEM = -5
+FR_W_AS_UNDERSAMPLED = 1
+FR_W_MFT_ALIASED = 2
+FR_ADJOINT = 1
+FR_TRAIN_NO_OCCULTER = 1
+FR_TRAIN_GRAD = 2
+
+_c = ctypes
+_vp = _c.c_void_p
+
+
+class FrError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} (status {status})")
+
+
+class FrPlane(_c.Structure):
+    _fields_ = [("field", _vp), ("amp", _vp), ("opd_m", _vp), ("dx_m", _c.c_double),
+                ("wavelength_m", _c.c_double), ("z_m", _c.c_double), ("lens_focal_m", _c.c_double),
+                ("n", _c.c_int32), ("flags", _c.c_int32)]
+
+
+class FrTrainDesc(_c.Structure):
+    _fields_ = [("n_d", _c.c_int32), ("d_m", _c.c_double), ("pupil_amp", _vp),
+                ("pupil_opd_m", _vp), ("n_dm", _c.c_int32), ("n_act", _c.c_int32),
+                ("dm_heights_m", _vp), ("z_m", _c.c_double), ("occ_m", _c.c_int32),
+                ("occ_du_c", _c.c_double), ("occ_mask", _vp), ("lyot", _vp),
+                ("det_m", _c.c_int32), ("det_du_c", _c.c_double), ("lambda_c_m", _c.c_double)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load libfresnel.so once (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = _c.CDLL(LIB_PATH)
+        i32, f64, f32, sz = _c.c_int32, _c.c_double, _c.c_float, _c.c_size_t
+        sig = {
+            "fr_create": (_c.c_int, [_c.POINTER(_vp), _c.c_int]),
+            "fr_destroy": (_c.c_int, [_vp]),
+            "fr_status_string": (_c.c_char_p, [_c.c_int]),
+            "fr_fft_size_supported": (_c.c_int, [i32]),
+            "fresnel_step": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
+            "fresnel_step_batched": (_c.c_int, [_vp, _c.POINTER(FrPlane), i32, _vp]),
+            "mft_workspace_bytes": (sz, [i32, i32]),
+            "mft_forward": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, _vp, _vp, sz, _vp]),
+            "mft_adjoint": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, f32, f32, _vp,
+                                       _vp, sz, _vp]),
+            "fr_profile_enable": (_c.c_int, [_vp, _c.c_int]),
+            "fr_profile_read": (_c.c_int, [_vp, i32, _c.c_char_p, i32, _c.POINTER(f64),
+                                           _c.POINTER(_c.c_int64), _c.POINTER(i32)]),
+            "propagate_train_workspace_bytes": (sz, [_c.POINTER(FrTrainDesc), i32, _c.POINTER(i32), i32]),
+            "propagate_train": (_c.c_int, [_vp, _c.POINTER(FrTrainDesc), i32, _c.POINTER(f64),
+                                           _c.POINTER(i32), _c.POINTER(f32), i32, _vp, _vp, _vp, _vp,
+                                           sz, _vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+        return L
+
+
+def declared_symbols():
+    """Function names declared in include/fresnel.h."""
+    with open(HEADER_PATH) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\([^;{]*\)\s*;", text)) - {"if", "return"})
+
+
+def status_string(status):
+    return lib().fr_status_string(int(status)).decode()
+
+
+def _check(status, where):
+    if status < 0:
+        raise FrError(status, where)
+    return status
+
+
+# ---- contexts and streams -------------------------------------------------------------------
+
+class Context:
+    """An fr_ctx bound to one HIP device (owns the cached float64-built tables)."""
+
+    def __init__(self, device=0):
+        self.device = int(device)
+        h = _vp()
+        _check(lib().fr_create(_c.byref(h), self.device), "fr_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().fr_destroy(self.handle)
+            self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts = {}
+
+
+def context(device=None):
+    dev = torch.cuda.current_device() if device is None else int(device)
+    ctx = _contexts.get(dev)
+    if ctx is None:
+        ctx = _contexts[dev] = Context(dev)
+    return ctx
+
+
+def _stream_handle(device, stream):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return _vp(stream.cuda_stream)
+
+
+_workspaces = {}
+
+
+def workspace(nbytes, device):
+    """A cached device byte buffer of at least nbytes (one per device; grows on demand)."""
+    buf = _workspaces.get(device)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{device}")
+        _workspaces[device] = buf
+    return buf
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else _vp()
+
+
+def _need(t, dtype, shape, name, contiguous=True):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if contiguous and not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _row_stride(t, name):
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D view with unit column stride")
+    return t.stride(0)
+
+
+# ---- Fresnel plane ----------------------------------------------------------------------------
+
+def fresnel_step(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, adjoint=False,
+                 stream=None):
+    """In place: field <- AS_z(field * optic) (or its adjoint). Returns the warning bits."""
+    _need(field, torch.complex64, None, "field")
+    n = field.shape[0]
+    _need(field, torch.complex64, (n, n), "field")
+    for t, nm in ((amp, "amp"), (opd, "opd")):
+        if t is not None:
+            _need(t, torch.float32, (n, n), nm)
+    dev = field.device.index
+    st = lib().fresnel_step(context(dev).handle, _ptr(field), n, float(dx), float(wavelength),
+                            float(z), _ptr(amp), _ptr(opd), float(lens_focal),
+                            FR_ADJOINT if adjoint else 0, _stream_handle(dev, stream))
+    return _check(st, "fresnel_step")
+
+
+def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens_focals=None,
+                         adjoints=None, stream=None):
+    """Many planes of one edge in one launch per sweep; per-plane sequences (or scalars)."""
+    count = len(fields)
+    if count == 0:
+        raise ValueError("empty batch")
+    n = fields[0].shape[0]
+
+    def seq(v, default):
+        if v is None:
+            return [default] * count
+        if isinstance(v, (list, tuple)):
+            if len(v) != count:
+                raise ValueError("per-plane sequence length mismatch")
+            return list(v)
+        return [v] * count
+
+    dxs, lams, zz = seq(dx, None), seq(wavelengths, None), seq(zs, None)
+    amps, opds = seq(amps, None), seq(opds, None)
+    lf, adj = seq(lens_focals, 0.0), seq(adjoints, False)
+    arr = (FrPlane * count)()
+    for i, f in enumerate(fields):
+        _need(f, torch.complex64, (n, n), f"fields[{i}]")
+        for t, nm in ((amps[i], "amp"), (opds[i], "opd")):
+            if t is not None:
+                _need(t, torch.float32, (n, n), nm)
+        arr[i] = FrPlane(f.data_ptr(), amps[i].data_ptr() if amps[i] is not None else None,
+                         opds[i].data_ptr() if opds[i] is not None else None, float(dxs[i]),
+                         float(lams[i]), float(zz[i]), float(lf[i]), n,
+                         FR_ADJOINT if adj[i] else 0)
+    dev = fields[0].device.index
+    st = lib().fresnel_step_batched(context(dev).handle, arr, count, _stream_handle(dev, stream))
+    return _check(st, "fresnel_step_batched")
+
+
+# ---- MFT ----------------------------------------------------------------------------------
+
+def mft_forward(inp, n_d, m_out, du, mask=None, out=None, stream=None):
+    """(du/n_d) W inp W^T (* mask): n_in x n_in (view allowed) -> m_out x m_out."""
+    if inp.dtype != torch.complex64 or not inp.is_cuda:
+        raise TypeError("inp must be a complex64 GPU tensor")
+    n_in = inp.shape[0]
+    if inp.shape != (n_in, n_in):
+        raise ValueError("inp must be square")
+    ld_in = _row_stride(inp, "inp")
+    dev = inp.device.index
+    if out is None:
+        out = torch.empty((m_out, m_out), dtype=torch.complex64, device=inp.device)
+    ld_out = _row_stride(out, "out")
+    if mask is not None:
+        _need(mask, torch.float32, (m_out, m_out), "mask")
+    L = lib()
+    nbytes = L.mft_workspace_bytes(n_in, m_out)
+    ws = workspace(nbytes, dev)
+    st = L.mft_forward(context(dev).handle, _ptr(inp), n_in, ld_in, _ptr(out), m_out, ld_out,
+                       float(n_d), float(du), _ptr(mask), _ptr(ws), ws.numel(),
+                       _stream_handle(dev, stream))
+    _check(st, "mft_forward")
+    return out
+
+
+def mft_adjoint(inp, n_d, n_out, du, alpha=1.0, beta=0.0, mask=None, out=None, stream=None):
+    """alpha (du/n_d) W^H inp conj(W) + beta out (* mask): m x m -> n_out x n_out (view allowed)."""
+    if inp.dtype != torch.complex64 or not inp.is_cuda:
+        raise TypeError("inp must be a complex64 GPU tensor")
+    m_in = inp.shape[0]
+    ld_in = _row_stride(inp, "inp")
+    dev = inp.device.index
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs an out tensor")
+        out = torch.empty((n_out, n_out), dtype=torch.complex64, device=inp.device)
+    if tuple(out.shape) != (n_out, n_out):
+        raise ValueError("out shape mismatch")
+    ld_out = _row_stride(out, "out")
+    if mask is not None:
+        _need(mask, torch.float32, (n_out, n_out), "mask")
+    L = lib()
+    nbytes = L.mft_workspace_bytes(n_out, m_in)
+    ws = workspace(nbytes, dev)
+    st = L.mft_adjoint(context(dev).handle, _ptr(inp), m_in, ld_in, _ptr(out), n_out, ld_out,
+                       float(n_d), float(du), float(alpha), float(beta), _ptr(mask), _ptr(ws),
+                       ws.numel(), _stream_handle(dev, stream))
+    _check(st, "mft_adjoint")
+    return out
+
+
+# ---- kernel timing ---------------------------------------------------------------------------
+
+def profile_enable(enable=True, device=None):
+    """Bracket every kernel launch of the device's context with HIP events on its stream."""
+    _check(lib().fr_profile_enable(context(device).handle, 1 if enable else 0), "fr_profile_enable")
+
+
+def profile_read(device=None, max_entries=64):
+    """{kernel/tag: (total_ms, launches)} since the last read (waits for the events)."""
+    name_len = 96
+    names = _c.create_string_buffer(max_entries * name_len)
+    tot = (_c.c_double * max_entries)()
+    cnt = (_c.c_int64 * max_entries)()
+    n = _c.c_int32()
+    _check(lib().fr_profile_read(context(device).handle, max_entries, names, name_len, tot, cnt,
+                                 _c.byref(n)), "fr_profile_read")
+    out = {}
+    raw = names.raw
+    for i in range(n.value):
+        nm = raw[i * name_len:(i + 1) * name_len].split(b"\0", 1)[0].decode()
+        out[nm] = (tot[i], cnt[i])
+    return out

@@ -1,0 +1,110 @@
+"""The C-ABI library loads and exports every function include/fresnel.h declares, and its
+host-side argument checks answer without launching anything (no GPU needed)."""
+
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+from paper_1806_06467_amd import fresnel as fb
+
+EXPECTED = {
+    "fr_create", "fr_destroy", "fr_status_string", "fr_fft_size_supported", "fresnel_step",
+    "fresnel_step_batched", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
+    "propagate_train_workspace_bytes", "propagate_train", "fr_profile_enable", "fr_profile_read",
+}
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(fb.LIB_PATH):
+        pytest.fail("libfresnel.so is not built (run __graft_entry__.build())")
+    return fb.lib()
+
+
+def test_header_declares_the_boundary():
+    assert set(fb.declared_symbols()) == EXPECTED
+
+
+def test_library_exports_every_declared_symbol(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", fb.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = set(fb.declared_symbols()) - exported
+    assert not missing, missing
+    for name in fb.declared_symbols():
+        assert getattr(L, name) is not None
+
+
+def test_status_strings(L):
+    assert fb.status_string(0) == "ok"
+    for st in (-1, -2, -3, -5):
+        assert len(fb.status_string(st)) > 5
+    assert fb.status_string(-99) == "unknown status"
+    assert "warning" in fb.status_string(1)
+
+
+def test_supported_sizes(L):
+    for n in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        assert L.fr_fft_size_supported(n) == 1
+    for n in (0, -4, 3000, 100, 4095):
+        assert L.fr_fft_size_supported(n) == 0
+
+
+def test_workspace_query(L):
+    assert L.mft_workspace_bytes(4096, 256) == 17 * 4096 * 256 * 8
+    assert L.mft_workspace_bytes(0, 256) == 0
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+
+
+def test_fresnel_step_argument_errors(L):
+    null = ctypes.c_void_p()
+    st = L.fresnel_step(null, null, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null)
+    assert st == fb.FR_EINVAL
+    st = L.fresnel_step(null, FAKE, 3000, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null)
+    assert st == fb.FR_EUNSUPPORTED
+    st = L.fresnel_step(null, FAKE, 256, -1e-4, 5e-7, 1.0, null, null, 0.0, 0, null)
+    assert st == fb.FR_EINVAL
+    st = L.fresnel_step(null, FAKE, 256, 1e-4, 0.0, 1.0, null, null, 0.0, 0, null)
+    assert st == fb.FR_EINVAL
+    st = L.fresnel_step(null, FAKE, 256, 1e-4, 5e-7, float("nan"), null, null, 0.0, 0, null)
+    assert st == fb.FR_EINVAL
+    st = L.fresnel_step(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 4, null)
+    assert st == fb.FR_EINVAL
+    # valid arguments but no context
+    st = L.fresnel_step(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null)
+    assert st == fb.FR_EINVAL
+
+
+def test_batched_argument_errors(L):
+    null = ctypes.c_void_p()
+    arr = (fb.FrPlane * 2)()
+    arr[0] = fb.FrPlane(0x1000, None, None, 1e-4, 5e-7, 1.0, 0.0, 256, 0)
+    arr[1] = fb.FrPlane(0x2000, None, None, 1e-4, 5e-7, 1.0, 0.0, 512, 0)
+    assert L.fresnel_step_batched(null, arr, 2, null) == fb.FR_EINVAL   # mixed edges
+    assert L.fresnel_step_batched(null, arr, 0, null) == fb.FR_EINVAL
+
+
+def test_mft_argument_errors(L):
+    null = ctypes.c_void_p()
+    st = L.mft_forward(null, FAKE, 256, 256, FAKE, 128, 128, 256.0, 0.25, null, null, 0, null)
+    assert st == fb.FR_EWORKSPACE
+    st = L.mft_forward(null, FAKE, 256, 200, FAKE, 128, 128, 256.0, 0.25, null, FAKE, 1 << 30, null)
+    assert st == fb.FR_EINVAL          # row stride shorter than a row
+    st = L.mft_forward(null, FAKE, 256, 256, FAKE, 128, 128, 256.0, -0.25, null, FAKE, 1 << 30, null)
+    assert st == fb.FR_EINVAL
+    st = L.mft_adjoint(null, FAKE, 128, 128, FAKE, 256, 256, 256.0, 0.25, 1.0, float("inf"), null,
+                       FAKE, 1 << 30, null)
+    assert st == fb.FR_EINVAL
+    st = L.mft_adjoint(null, FAKE, 128, 128, FAKE, 256, 256, 256.0, 0.25, 1.0, 0.0, null, FAKE, 16, null)
+    assert st == fb.FR_EWORKSPACE
+
+
+def test_profile_argument_errors(L):
+    null = ctypes.c_void_p()
+    assert L.fr_profile_enable(null, 1) == fb.FR_EINVAL
+    n = ctypes.c_int32()
+    assert L.fr_profile_read(null, 0, None, 0, None, None, ctypes.byref(n)) == fb.FR_EINVAL
