@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of one 4096^2 c64 plane (134217728 B read, "
+                         "134217728 B written) so HBM byte counters can be scaled")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every wavelength of this workload fits one "
@@ -117,6 +120,12 @@ def main():
             fb.fresnel_step(fields[i], DX, lam_pl[i], Z, amp=amp, opd=opd, adjoint=adjs[i])
 
     stream = torch.cuda.current_stream(dev)
+    if args.copy_calibration:
+        dst = torch.empty_like(fields[0])
+        for _ in range(3):
+            dst.copy_(fields[0])
+        torch.cuda.synchronize()
+        del dst
 
     def timed(fn, steps, profile=False):
         for _ in range(args.warmup):

@@ -91,11 +91,15 @@ def _dm_phasor(surface, wavelength):
     return np.exp(2j * np.pi * (turns - np.round(turns)))
 
 
-def train_forward(geom: TrainGeometry, wavelength, n, heights: Sequence[np.ndarray], occulter=True):
+def train_forward(geom: TrainGeometry, wavelength, n, heights: Sequence[np.ndarray], occulter=True,
+                  step_cache=None):
     """One wavelength through the train on an n x n padded grid.
 
     heights: one array (the DM after the Fresnel step) or two (DM1 at the pupil, DM2 after
     the step), each n_act x n_act surface heights in m.
+    step_cache: optional dict; with zero or one DM the Fresnel step does not depend on the
+    heights, so its result is remembered there per (wavelength, n) and reused (memoisation
+    only: the arithmetic is unchanged).
     """
     lam = float(wavelength)
     nd = geom.n_d
@@ -111,7 +115,13 @@ def train_forward(geom: TrainGeometry, wavelength, n, heights: Sequence[np.ndarr
         e = e * ph1
         out.e_dm.append(e)
         out.dm_phasors.append(ph1)
-    e = as_propagate(e, geom.dx, lam, geom.z_m)
+    key = (lam, n)
+    if step_cache is not None and len(hs) < 2 and key in step_cache:
+        e = step_cache[key]
+    else:
+        e = as_propagate(e, geom.dx, lam, geom.z_m)
+        if step_cache is not None and len(hs) < 2:
+            step_cache[key] = e
     if hs:
         ph = _dm_phasor(dm_surface(hs[-1], n, nd), lam)
         e = e * ph
@@ -151,18 +161,18 @@ def dm_to_detector_adjoint(geom: TrainGeometry, wavelength, n, y, occulter=True)
     return b
 
 
-def train_psf(geom, wavelengths, ns, weights, heights, occulter=True):
+def train_psf(geom, wavelengths, ns, weights, heights, occulter=True, step_cache=None):
     """Broadband PSF sum_lambda w_lambda |E_det,lambda|^2 (det_m x det_m, float64)."""
     psf = np.zeros((geom.det_m, geom.det_m))
     for lam, n, w in zip(wavelengths, ns, weights):
-        e = train_forward(geom, lam, n, heights, occulter).e_det
+        e = train_forward(geom, lam, n, heights, occulter, step_cache).e_det
         psf += float(w) * (e.real ** 2 + e.imag ** 2)
     return psf
 
 
-def train_loss(geom, wavelengths, ns, weights, heights, dh_mask, max_ref):
+def train_loss(geom, wavelengths, ns, weights, heights, dh_mask, max_ref, step_cache=None):
     """Mean normalised contrast over the dark hole: sum_DH PSF / (|DH| max I_ref)."""
-    psf = train_psf(geom, wavelengths, ns, weights, heights, True)
+    psf = train_psf(geom, wavelengths, ns, weights, heights, True, step_cache)
     return float(np.sum(psf * dh_mask) / (np.sum(dh_mask) * max_ref))
 
 
@@ -204,7 +214,8 @@ def train_grad(geom, wavelengths, ns, weights, heights, dh_mask, max_ref):
     return total
 
 
-def fd_grad(geom, wavelengths, ns, weights, heights, dh_mask, max_ref, actuators, h=1e-12):
+def fd_grad(geom, wavelengths, ns, weights, heights, dh_mask, max_ref, actuators, h=1e-12,
+            step_cache=None):
     """Central differences of train_loss on single actuators: actuators = [(dm, row, col), ...]."""
     out = []
     for dm, r, c in actuators:
@@ -212,7 +223,7 @@ def fd_grad(geom, wavelengths, ns, weights, heights, dh_mask, max_ref, actuators
         minus = [np.array(a, dtype=np.float64, copy=True) for a in heights]
         plus[dm][r, c] += h
         minus[dm][r, c] -= h
-        lp = train_loss(geom, wavelengths, ns, weights, plus, dh_mask, max_ref)
-        lm = train_loss(geom, wavelengths, ns, weights, minus, dh_mask, max_ref)
+        lp = train_loss(geom, wavelengths, ns, weights, plus, dh_mask, max_ref, step_cache)
+        lm = train_loss(geom, wavelengths, ns, weights, minus, dh_mask, max_ref, step_cache)
         out.append((lp - lm) / (2.0 * h))
     return np.array(out)

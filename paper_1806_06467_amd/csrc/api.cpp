@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -84,6 +85,14 @@ static void timing_hook(void *user, hipStream_t s, const char *name, int tag, in
   }
 }
 
+int Ctx::sweep_variant(int n) const {
+  // FR_SWEEP_VARIANT overrides the tile configuration of the plane sweeps (for tuning runs)
+  const char *v = std::getenv("FR_SWEEP_VARIANT");
+  int k = v ? std::atoi(v) : 0;
+  if (k < 0 || k >= fr::fresnel_variants(n)) k = 0;
+  return k;
+}
+
 LaunchHook Ctx::hook() {
   LaunchHook h;
   if (profiling) {
@@ -128,17 +137,21 @@ static uint64_t bits(double v) {
   return b;
 }
 
-int Ctx::roots(int n, hipStream_t s, const float2 **out) {
+// float64 roots exp(-2 pi i m / n), from the exact fraction m / n of a turn
+int Ctx::roots(int n, hipStream_t s, const double2 **out) {
   TableKey key{kRoots, n, 0, 0, 0, 0};
   if (auto it = tables.find(key); it != tables.end()) {
-    *out = static_cast<const float2 *>(it->second);
+    *out = static_cast<const double2 *>(it->second);
     return FR_OK;
   }
-  std::vector<float2> h(n);
-  for (int m = 0; m < n; ++m) h[m] = turn_to_c64(-double(m) / double(n), 1.0);
+  std::vector<double2> h(n);
+  for (int m = 0; m < n; ++m) {
+    const double f = frac_turn(-double(m) / double(n));
+    h[m] = make_double2(std::cos(2.0 * M_PI * f), std::sin(2.0 * M_PI * f));
+  }
   void *d;
-  int st = upload(key, h.data(), h.size() * sizeof(float2), s, &d);
-  *out = static_cast<const float2 *>(d);
+  int st = upload(key, h.data(), h.size() * sizeof(double2), s, &d);
+  *out = static_cast<const double2 *>(d);
   return st;
 }
 
@@ -225,6 +238,93 @@ int Ctx::dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **ou
   return st;
 }
 
+
+size_t mft_ws_bytes(int n, int m) { return size_t(1 + kMaxSplit) * size_t(n) * size_t(m) * sizeof(float2); }
+
+static CGemmArgs gemm_args() {
+  CGemmArgs g;
+  std::memset(&g, 0, sizeof g);
+  g.alpha_re = 1.0f;
+  return g;
+}
+
+static hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, float2 *partial, size_t partial_elems, hipStream_t s) {
+  int split = cgemm_split_for(g.M, g.N, g.K);
+  while (split > 1 && size_t(split) * size_t(g.M) * size_t(g.N) > partial_elems) split /= 2;
+  return launch_cgemm_split(g, split, partial, s, ctx->hook());
+}
+
+int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out, double n_d,
+                     double du, const MftOut &o, void *ws, hipStream_t s) {
+  const float2 *w;
+  int st = ctx->mft_matrix(m_out, n_in, n_d, du, s, &w);
+  if (st != FR_OK) return st;
+  float2 *t = static_cast<float2 *>(ws);
+  float2 *partial = t + size_t(n_in) * m_out;
+  const size_t pcap = size_t(kMaxSplit) * n_in * m_out;
+  // T = E W^T  (n_in x m_out)
+  CGemmArgs g1 = gemm_args();
+  g1.M = n_in; g1.N = m_out; g1.K = n_in;
+  g1.A = in; g1.lda = ld_in;
+  g1.B = w; g1.ldb = n_in; g1.transB = 1;
+  g1.C = t; g1.ldc = m_out;
+  hipError_t e = run_gemm(ctx, g1, partial, pcap, s);
+  if (e != hipSuccess) return record_hip(e);
+  // out = (du / n_d) W T (* mask), optionally + weight |out|^2 into the intensity
+  CGemmArgs g2 = gemm_args();
+  g2.M = m_out; g2.N = m_out; g2.K = n_in;
+  g2.A = w; g2.lda = n_in;
+  g2.B = t; g2.ldb = m_out;
+  g2.C = o.out; g2.ldc = o.ld_out; g2.skip_c = o.skip_out ? 1 : 0;
+  g2.alpha_re = float(du / n_d);
+  g2.mask = o.mask; g2.ldm = m_out;
+  g2.intensity = o.intensity; g2.ldi = m_out; g2.weight = o.weight;
+  e = run_gemm(ctx, g2, partial, pcap, s);
+  return e == hipSuccess ? FR_OK : record_hip(e);
+}
+
+int mft_adjoint_impl(Ctx *ctx, const float2 *in, int m_in, int ld_in, float2 *out, int n_out,
+                     int ld_out, double n_d, double du, float alpha, float beta,
+                     const float2 *cin, int ld_cin, const float *mask, void *ws, hipStream_t s) {
+  const float2 *w;
+  int st = ctx->mft_matrix(m_in, n_out, n_d, du, s, &w);
+  if (st != FR_OK) return st;
+  float2 *t = static_cast<float2 *>(ws);
+  float2 *partial = t + size_t(n_out) * m_in;
+  const size_t pcap = size_t(kMaxSplit) * n_out * m_in;
+  // T = E_B conj(W)  (m_in x n_out)
+  CGemmArgs g1 = gemm_args();
+  g1.M = m_in; g1.N = n_out; g1.K = m_in;
+  g1.A = in; g1.lda = ld_in;
+  g1.B = w; g1.ldb = n_out; g1.conjB = 1;
+  g1.C = t; g1.ldc = n_out;
+  hipError_t e = run_gemm(ctx, g1, partial, pcap, s);
+  if (e != hipSuccess) return record_hip(e);
+  // out = alpha (du / n_d) W^H T + beta cin (* mask)
+  CGemmArgs g2 = gemm_args();
+  g2.M = n_out; g2.N = n_out; g2.K = m_in;
+  g2.A = w; g2.lda = n_out; g2.transA = 1; g2.conjA = 1;
+  g2.B = t; g2.ldb = n_out;
+  g2.C = out; g2.ldc = ld_out;
+  g2.alpha_re = float(alpha * (du / n_d));
+  g2.beta = beta; g2.Cin = cin; g2.ldcin = ld_cin;
+  g2.mask = mask; g2.ldm = n_out;
+  e = run_gemm(ctx, g2, partial, pcap, s);
+  return e == hipSuccess ? FR_OK : record_hip(e);
+}
+
+int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s) {
+  const double2 *root;
+  int st = ctx->roots(n, s, &root);
+  if (st != FR_OK) return st;
+  for (int i = 0; i < count; i += kMaxBatch) {
+    const int c = std::min(count - i, kMaxBatch);
+    hipError_t e = launch_fresnel_batch(args + i, c, n, root, s, ctx->hook(), ctx->sweep_variant(n));
+    if (e != hipSuccess) return record_hip(e);
+  }
+  return FR_OK;
+}
+
 }  // namespace fr
 
 // ============================================================================================
@@ -302,32 +402,26 @@ int fresnel_step_batched(fr_ctx *ctx_, const fr_plane *planes, int32_t count, vo
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
-  const float2 *root;
-  int st = ctx->roots(n, s, &root);
-  if (st != FR_OK) return st;
   std::vector<PlaneArgs> args(count);
   for (int i = 0; i < count; ++i) {
     const fr_plane &p = planes[i];
     PlaneArgs &a = args[i];
+    std::memset(&a, 0, sizeof a);
     a.field = reinterpret_cast<float2 *>(p.field);
     a.amp = p.amp;
     a.opd = p.opd_m;
+    a.win = n;
     a.inv_lambda = float(1.0 / p.wavelength_m);
     a.flags = p.flags;
-    st = ctx->transfer(n, p.dx_m, p.wavelength_m, p.z_m, s, &a.h);
+    int st = ctx->transfer(n, p.dx_m, p.wavelength_m, p.z_m, s, &a.h);
     if (st != FR_OK) return st;
-    a.lens = nullptr;
     if (p.lens_focal_m != 0.0) {
       st = ctx->lens(n, p.dx_m, p.wavelength_m, p.lens_focal_m, s, &a.lens);
       if (st != FR_OK) return st;
     }
   }
-  for (int i = 0; i < count; i += fr::kMaxBatch) {
-    const int c = std::min(count - i, fr::kMaxBatch);
-    e = fr::launch_fresnel_batch(args.data() + i, c, n, root, s, ctx->hook());
-    if (e != hipSuccess) return fr::record_hip(e);
-  }
-  return warn;
+  int st = fr::run_planes(ctx, args.data(), count, n, s);
+  return st != FR_OK ? st : warn;
 }
 
 int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wavelength_m,
@@ -361,20 +455,7 @@ int mft_common_checks(const void *in, const void *out, int n, int ld_n, int m, i
   return FR_OK;
 }
 
-size_t mft_ws(int32_t n, int32_t m) { return size_t(1 + fr::kMaxSplit) * size_t(n) * size_t(m) * sizeof(float2); }
-
-hipError_t run_gemm(Ctx *ctx, fr::CGemmArgs &g, float2 *partial, size_t partial_elems, hipStream_t s) {
-  int split = fr::cgemm_split_for(g.M, g.N, g.K);
-  while (split > 1 && size_t(split) * size_t(g.M) * size_t(g.N) > partial_elems) split /= 2;
-  return fr::launch_cgemm_split(g, split, partial, s, ctx->hook());
-}
-
-fr::CGemmArgs gemm_args() {
-  fr::CGemmArgs g;
-  std::memset(&g, 0, sizeof g);
-  g.alpha_re = 1.0f;
-  return g;
-}
+size_t mft_ws(int32_t n, int32_t m) { return fr::mft_ws_bytes(n, m); }
 
 }  // namespace
 
@@ -393,33 +474,15 @@ int mft_forward(fr_ctx *ctx_, const fr_c64 *in, int32_t n_in, int32_t ld_in, fr_
   if (!ws || ws_bytes < mft_ws(n_in, m_out)) return FR_EWORKSPACE;
   Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
   if (!ctx) return FR_EINVAL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
-  const float2 *w;
-  st = ctx->mft_matrix(m_out, n_in, n_d, du, s, &w);
+  fr::MftOut o;
+  o.out = reinterpret_cast<float2 *>(out);
+  o.ld_out = ld_out;
+  o.mask = out_mask;
+  st = fr::mft_forward_impl(ctx, reinterpret_cast<const float2 *>(in), n_in, ld_in, m_out, n_d, du,
+                            o, ws, static_cast<hipStream_t>(stream));
   if (st != FR_OK) return st;
-  float2 *t = static_cast<float2 *>(ws);
-  float2 *partial = t + size_t(n_in) * m_out;
-  const size_t pcap = size_t(fr::kMaxSplit) * n_in * m_out;
-  // T = E W^T  (n_in x m_out)
-  fr::CGemmArgs g1 = gemm_args();
-  g1.M = n_in; g1.N = m_out; g1.K = n_in;
-  g1.A = reinterpret_cast<const float2 *>(in); g1.lda = ld_in;
-  g1.B = w; g1.ldb = n_in; g1.transB = 1;
-  g1.C = t; g1.ldc = m_out;
-  e = run_gemm(ctx, g1, partial, pcap, s);
-  if (e != hipSuccess) return fr::record_hip(e);
-  // out = (du / n_d) W T (* mask)
-  fr::CGemmArgs g2 = gemm_args();
-  g2.M = m_out; g2.N = m_out; g2.K = n_in;
-  g2.A = w; g2.lda = n_in;
-  g2.B = t; g2.ldb = m_out;
-  g2.C = reinterpret_cast<float2 *>(out); g2.ldc = ld_out;
-  g2.alpha_re = float(du / n_d);
-  g2.mask = out_mask; g2.ldm = m_out;
-  e = run_gemm(ctx, g2, partial, pcap, s);
-  if (e != hipSuccess) return fr::record_hip(e);
   return (du > n_d / double(n_in)) ? FR_W_MFT_ALIASED : FR_OK;
 }
 
@@ -432,34 +495,12 @@ int mft_adjoint(fr_ctx *ctx_, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_
   if (!ws || ws_bytes < mft_ws(n_out, m_in)) return FR_EWORKSPACE;
   Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
   if (!ctx) return FR_EINVAL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
-  const float2 *w;
-  st = ctx->mft_matrix(m_in, n_out, n_d, du, s, &w);
+  st = fr::mft_adjoint_impl(ctx, reinterpret_cast<const float2 *>(in), m_in, ld_in,
+                            reinterpret_cast<float2 *>(out), n_out, ld_out, n_d, du, alpha, beta,
+                            nullptr, 0, out_mask, ws, static_cast<hipStream_t>(stream));
   if (st != FR_OK) return st;
-  float2 *t = static_cast<float2 *>(ws);
-  float2 *partial = t + size_t(n_out) * m_in;
-  const size_t pcap = size_t(fr::kMaxSplit) * n_out * m_in;
-  // T = E_B conj(W)  (m_in x n_out)
-  fr::CGemmArgs g1 = gemm_args();
-  g1.M = m_in; g1.N = n_out; g1.K = m_in;
-  g1.A = reinterpret_cast<const float2 *>(in); g1.lda = ld_in;
-  g1.B = w; g1.ldb = n_out; g1.conjB = 1;
-  g1.C = t; g1.ldc = n_out;
-  e = run_gemm(ctx, g1, partial, pcap, s);
-  if (e != hipSuccess) return fr::record_hip(e);
-  // out = alpha (du / n_d) W^H T + beta out (* mask)
-  fr::CGemmArgs g2 = gemm_args();
-  g2.M = n_out; g2.N = n_out; g2.K = m_in;
-  g2.A = w; g2.lda = n_out; g2.transA = 1; g2.conjA = 1;
-  g2.B = t; g2.ldb = n_out;
-  g2.C = reinterpret_cast<float2 *>(out); g2.ldc = ld_out;
-  g2.alpha_re = float(alpha * (du / n_d));
-  g2.beta = beta;
-  g2.mask = out_mask; g2.ldm = n_out;
-  e = run_gemm(ctx, g2, partial, pcap, s);
-  if (e != hipSuccess) return fr::record_hip(e);
   return (du > n_d / double(n_out)) ? FR_W_MFT_ALIASED : FR_OK;
 }
 

@@ -22,6 +22,7 @@ __device__ __forceinline__ c32 cmulc(c32 a, c32 b) {  // a * conj(b)
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 __device__ __forceinline__ c32 cconj(c32 a) { return {a.x, -a.y}; }
+__device__ __forceinline__ c32 csq(c32 a) { return {a.x * a.x - a.y * a.y, 2.0f * a.x * a.y}; }
 __device__ __forceinline__ c32 cscale(c32 a, float s) { return {a.x * s, a.y * s}; }
 __device__ __forceinline__ c32 mul_mi(c32 a) { return {a.y, -a.x}; }  // a * (-i)
 __device__ __forceinline__ c32 mul_pi(c32 a) { return {-a.y, a.x}; }  // a * (+i)
@@ -260,5 +261,101 @@ template <>
 struct Dft<16> : DftComposite<4, 4> {};
 template <>
 struct Dft<32> : DftComposite<4, 8> {};
+
+// Inverse-direction DFT (kernel exp(+2 pi i nk/R)): X_inv[k] = X_fwd[(R - k) mod R], so the
+// forward butterfly is reused and its outputs are renamed (no arithmetic).
+template <int R, bool INV>
+struct DftDir {
+  __device__ __forceinline__ static void run(c32 *u) {
+    Dft<R>::run(u);
+    if constexpr (INV) {
+#pragma unroll
+      for (int k = 1; k < (R + 1) / 2; ++k) {
+        const c32 t = u[k];
+        u[k] = u[R - k];
+        u[R - k] = t;
+      }
+    }
+  }
+};
+
+// u[r] *= w1^r (or conj(w1)^r for the inverse), r = 1..R-1. The powers are built in float64
+// (full rate on CDNA, like non-packed float32) by squarings and products of depth <= 4 from the
+// one float64 table value w1, then rounded once to float: every twiddle is within half an ulp,
+// at the cost of a single table load per butterfly.
+struct c64d {
+  double x, y;
+};
+__device__ __forceinline__ c64d dmul(c64d a, c64d b) {
+  return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
+}
+__device__ __forceinline__ c64d dsq(c64d a) { return {fma(a.x, a.x, -a.y * a.y), 2.0 * a.x * a.y}; }
+
+template <bool INV>
+__device__ __forceinline__ void twiddle_leg(c32 &u, c64d p) {
+  const c32 w = {float(p.x), float(p.y)};
+  u = INV ? cmulc(u, w) : cmul(u, w);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void apply_twiddle_powers(c32 *u, c64d w1) {
+  if constexpr (R > 1) twiddle_leg<INV>(u[1], w1);
+  if constexpr (R > 2) {
+    const c64d p2 = dsq(w1);
+    twiddle_leg<INV>(u[2], p2);
+    if constexpr (R > 3) {
+      const c64d p3 = dmul(p2, w1);
+      twiddle_leg<INV>(u[3], p3);
+      if constexpr (R > 4) {
+        const c64d p4 = dsq(p2);
+        twiddle_leg<INV>(u[4], p4);
+        if constexpr (R > 5) twiddle_leg<INV>(u[5], dmul(p4, w1));
+        if constexpr (R > 6) twiddle_leg<INV>(u[6], dmul(p4, p2));
+        if constexpr (R > 7) twiddle_leg<INV>(u[7], dmul(p4, p3));
+        if constexpr (R > 8) {
+          const c64d p8 = dsq(p4);
+          twiddle_leg<INV>(u[8], p8);
+          if constexpr (R > 9) twiddle_leg<INV>(u[9], dmul(p8, w1));
+          if constexpr (R > 10) twiddle_leg<INV>(u[10], dmul(p8, p2));
+          if constexpr (R > 11) twiddle_leg<INV>(u[11], dmul(p8, p3));
+          if constexpr (R > 12) {
+            const c64d p12 = dmul(p8, p4);
+            twiddle_leg<INV>(u[12], p12);
+            if constexpr (R > 13) twiddle_leg<INV>(u[13], dmul(p12, w1));
+            if constexpr (R > 14) twiddle_leg<INV>(u[14], dmul(p12, p2));
+            if constexpr (R > 15) twiddle_leg<INV>(u[15], dmul(p12, p3));
+          }
+          static_assert(R <= 16, "twiddle powers are written out up to radix 16");
+        }
+      }
+    }
+  }
+}
+
+// sin and cos of 2 pi t for t in turns: exact reduction t - rint(t), then to the octant
+// |2 pi f| <= pi/4 by quarter turns, then the Taylor series of sin (to x^9) and cos (to x^8)
+// on that interval (truncation below 3e-8), rotated back by the quarter-turn count.
+__device__ __forceinline__ void sincos_turns(float t, float *s, float *c) {
+  t -= rintf(t);
+  const float q = rintf(4.0f * t);
+  const float f = fmaf(-0.25f, q, t);
+  const float x = f * 6.28318530717958647692f;
+  const float x2 = x * x;
+  const float sp = x * fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 2.75573192239858906526e-6f,
+                                                       -1.98412698412698412698e-4f),
+                                              8.33333333333333333333e-3f),
+                                     -1.66666666666666666667e-1f),
+                            1.0f);
+  const float cp = fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 2.48015873015873015873e-5f,
+                                                   -1.38888888888888888889e-3f),
+                                          4.16666666666666666667e-2f),
+                                 -0.5f),
+                        1.0f);
+  const int qi = int(q) & 3;
+  const float ss = (qi & 1) ? cp : sp;
+  const float cc = (qi & 1) ? sp : cp;
+  *s = (qi & 2) ? -ss : ss;
+  *c = ((qi + 1) & 2) ? -cc : cc;
+}
 
 }  // namespace fr

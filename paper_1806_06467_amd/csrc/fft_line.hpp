@@ -9,7 +9,7 @@
 //
 // Pass with radix R after span P (P = product of earlier radices): butterfly b twiddles leg r
 // by w_{P R}^{r (b mod P)}, runs DFT_R and writes output r to (b / P) P R + (b mod P) + r P.
-// Twiddles come from a table of the N roots exp(-2 pi i m / N) built in float64 on the host.
+// Twiddles come from a float64 table of the N roots exp(-2 pi i m / N) built on the host.
 #pragma once
 #include "dft_small.hpp"
 
@@ -23,9 +23,9 @@ struct LdsLine {
   static constexpr int size = N + N / 16;
 };
 
-template <int N, int E, int P, int R, int... Rest>
+template <bool INV, int N, int E, int P, int R, int... Rest>
 __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, int t,
-                                           const c32* __restrict__ root) {
+                                           const c64d* __restrict__ root) {
   constexpr int T = N / E;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide the elements per thread");
@@ -38,12 +38,11 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
     for (int r = 0; r < R; ++r) u[r] = v[j + r * NB];
     const int b = t + j * T;
     if constexpr (P > 1) {
+      // leg r of butterfly b is twiddled by w_{PR}^{r k}, k = b mod P; w_{PR}^k is root[k N/(PR)]
       constexpr int S = N / (P * R);
-      const int k = b % P;
-#pragma unroll
-      for (int r = 1; r < R; ++r) u[r] = cmul(u[r], root[r * k * S]);
+      apply_twiddle_powers<R, INV>(u, root[(b % P) * S]);
     }
-    Dft<R>::run(u);
+    DftDir<R, INV>::run(u);
     if constexpr (last) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[j + r * NB] = u[r];
@@ -58,7 +57,7 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = lds[lds_pad(t + T * m)];
     __syncthreads();
-    fft_passes<N, E, P * R, Rest...>(v, lds, t, root);
+    fft_passes<INV, N, E, P * R, Rest...>(v, lds, t, root);
   }
 }
 
@@ -68,8 +67,13 @@ struct Plan {
   static constexpr int N = N_;
   static constexpr int E = E_;
   static constexpr int T = N_ / E_;
-  __device__ __forceinline__ static void forward(c32 (&v)[E_], c32* lds, int t, const c32* root) {
-    fft_passes<N_, E_, 1, Rs...>(v, lds, t, root);
+  // unnormalised DFT of the line, kernel exp(-2 pi i nk/N)
+  __device__ __forceinline__ static void forward(c32 (&v)[E_], c32* lds, int t, const c64d* root) {
+    fft_passes<false, N_, E_, 1, Rs...>(v, lds, t, root);
+  }
+  // unnormalised inverse DFT, kernel exp(+2 pi i nk/N)
+  __device__ __forceinline__ static void inverse(c32 (&v)[E_], c32* lds, int t, const c64d* root) {
+    fft_passes<true, N_, E_, 1, Rs...>(v, lds, t, root);
   }
 };
 

@@ -19,14 +19,24 @@ struct LaunchHook {
 };
 
 // One plane of a Fresnel batch, as the sweep kernels see it (device pointers).
+// Forward:  field <- post(x,y) * AS_z( src * pre(x,y) ),   src = field or 1 (kSourceOptic)
+// Adjoint:  field <- conj(pre) * AS_{-z}( conj(post) * field )
+//   pre  = amp * exp(2 pi i (opd + 2 pre_surf) / lambda) * lens[x] lens[y]
+//   post = exp(2 pi i 2 post_surf / lambda)               (reflective DM after the step)
+// amp and opd are win x win maps centred in the plane (offset (n - win)/2); outside the
+// window amp is 0 when given. pre_surf / post_surf are n x n surface maps [m].
+constexpr int kSourceOptic = 2;  // forward only: the input field is 1 (it is not read)
 struct PlaneArgs {
-  float2 *field;       // n x n, in place
-  const float *amp;    // n x n or null
-  const float *opd;    // n x n OPD [m] or null
-  const float2 *h;     // n: exp(-i pi lambda z k^2/(n dx)^2) / n over signed index k
-  const float2 *lens;  // n: exp(-i pi c^2 dx^2 / (lambda f)) or null
-  float inv_lambda;    // 1 / lambda [1/m]
-  int flags;           // FR_ADJOINT
+  float2 *field;             // n x n, in place
+  const float *amp;          // win x win or null
+  const float *opd;          // win x win OPD [m] or null
+  const float *pre_surf;     // n x n or null
+  const float *post_surf;    // n x n or null
+  const float2 *h;           // n: exp(-i pi lambda z k^2/(n dx)^2) / n over signed index k
+  const float2 *lens;        // n: exp(-i pi c^2 dx^2 / (lambda f)) or null
+  float inv_lambda;          // 1 / lambda [1/m]
+  int win;                   // window edge of amp / opd (n for full maps)
+  int flags;                 // FR_ADJOINT | kSourceOptic
 };
 
 constexpr int kMaxBatch = 64;
@@ -35,9 +45,12 @@ struct BatchArgs {
 };
 
 // Row sweep then column sweep over `count` planes of edge n (count <= kMaxBatch).
-// root: n complex roots exp(-2 pi i m / n). Returns a hipError_t.
-hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const float2 *root,
-                                hipStream_t stream, const LaunchHook &hook);
+// root: n float64 complex roots exp(-2 pi i m / n). Returns a hipError_t.
+// `variant` selects a tile configuration (row lines per block, column tile width); every
+// variant computes the same result. fresnel_variants(n) = number of variants for edge n.
+hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const double2 *root,
+                                hipStream_t stream, const LaunchHook &hook, int variant);
+int fresnel_variants(int n);
 bool fresnel_size_supported(int n);
 
 // ---- MFT: out = alpha * c * A in B^T (+ beta * out) (* mask), complex, FP32 MFMA ------
@@ -54,9 +67,15 @@ struct CGemmArgs {
   int transB;       // 1: B is given as N x K (use B^T)
   int conjA, conjB; // conjugate the operand on load
   float alpha_re, alpha_im;
-  float beta;       // real
+  float beta;       // real; the beta term reads Cin (row stride ldcin), or C when Cin is null
+  const float2 *Cin;
+  int ldcin;
   const float *mask;  // M x N (row stride ldm) or null: multiplies the result
   int ldm;
+  float *intensity;   // M x N (row stride ldi) or null: intensity += weight |result|^2
+  int ldi;
+  float weight;
+  int skip_c;         // 1: do not write C (only the intensity)
 };
 // C = alpha op(A) op(B) (+ beta C) (* mask). split > 1 slices K; the slices' partial sums go
 // to `partial` (split x M x N c64) and are added in a fixed order by a second kernel.

@@ -32,11 +32,12 @@ struct Ctx {
   std::vector<hipEvent_t> event_pool;
   hipEvent_t take_event();
   LaunchHook hook();
+  int sweep_variant(int n) const;
 
   ~Ctx();
   // copy `bytes` of host data to a new cached device buffer (waits on `s` for the copy)
   int upload(const TableKey &key, const void *host, size_t bytes, hipStream_t s, void **out);
-  int roots(int n, hipStream_t s, const float2 **out);
+  int roots(int n, hipStream_t s, const double2 **out);
   int transfer(int n, double dx, double lam, double z, hipStream_t s, const float2 **out);
   int lens(int n, double dx, double lam, double f, hipStream_t s, const float2 **out);
   int mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out);
@@ -44,5 +45,24 @@ struct Ctx {
 };
 
 int record_hip(hipError_t e);
+
+// Internal entry points shared by the C ABI and the train orchestration (arguments already
+// validated; tables are fetched from / added to the context cache).
+int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s);
+struct MftOut {
+  float2 *out = nullptr;
+  int ld_out = 0;
+  const float *mask = nullptr;
+  float *intensity = nullptr;  // + weight |out|^2 (det grid, row stride = width)
+  float weight = 0.f;
+  bool skip_out = false;
+};
+int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out, double n_d,
+                     double du, const MftOut &o, void *ws, hipStream_t s);
+// out = alpha (du/n_d) W^H in conj(W) + beta cin, * mask  (cin may alias out)
+int mft_adjoint_impl(Ctx *ctx, const float2 *in, int m_in, int ld_in, float2 *out, int n_out,
+                     int ld_out, double n_d, double du, float alpha, float beta,
+                     const float2 *cin, int ld_cin, const float *mask, void *ws, hipStream_t s);
+size_t mft_ws_bytes(int n_pupil, int m_focal);
 
 }  // namespace fr

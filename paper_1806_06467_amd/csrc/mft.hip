@@ -6,7 +6,9 @@
 // Complex product with real MFMA: per complex k-step, Cr += Ar Br - Ai Bi and
 // Ci += Ar Bi + Ai Br (four v_mfma_f32_32x32x2f32, A/B fragments from LDS).
 // Block tile 64 x 64, four waves in 2 x 2, each wave one 32 x 32 real and imaginary
-// accumulator. Operands may be transposed and/or conjugated on load. Small outputs with
+// accumulator per 16-deep k tile, added into float64 totals (the long Fourier sums of the
+// coronagraph cancel to tiny values in the dark hole, so their rounding must not grow with K).
+// Operands may be transposed and/or conjugated on load. Small outputs with
 // long K are split over K; the partial sums go to the workspace and one epilogue kernel adds
 // them in a fixed order (deterministic), applies alpha, beta and the mask.
 #include <hip/hip_runtime.h>
@@ -29,6 +31,27 @@ struct GemmParams {
   float2 *partial;  // split x M x N when split > 1
 };
 
+// result (i, j) = alpha acc + beta Cin, times mask; written to C and/or accumulated as
+// weight |result|^2 into the intensity map
+__device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, float cr, float ci) {
+  float2 outv = make_float2(a.alpha_re * cr - a.alpha_im * ci, a.alpha_re * ci + a.alpha_im * cr);
+  if (a.beta != 0.f) {
+    const float2 old = a.Cin ? a.Cin[size_t(i) * a.ldcin + j] : a.C[size_t(i) * a.ldc + j];
+    outv.x += a.beta * old.x;
+    outv.y += a.beta * old.y;
+  }
+  if (a.mask) {
+    const float mk = a.mask[size_t(i) * a.ldm + j];
+    outv.x *= mk;
+    outv.y *= mk;
+  }
+  if (!a.skip_c) a.C[size_t(i) * a.ldc + j] = outv;
+  if (a.intensity) {
+    float *ip = a.intensity + size_t(i) * a.ldi + j;
+    *ip += a.weight * (outv.x * outv.x + outv.y * outv.y);
+  }
+}
+
 __device__ __forceinline__ float2 load_op(const float2 *p, int ld, int r, int c, int rows, int cols,
                                           bool trans, bool conj) {
   // element (r, c) of op(X) where X is stored row-major rows x cols (or transposed)
@@ -48,8 +71,12 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmParams gp) {
   const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
   const int kbeg = blockIdx.z * gp.k_per_split;
   const int kend = min(a.K, kbeg + gp.k_per_split);
-  floatx16 accr = {0.f}, acci = {0.f};
+  // each BK-deep tile is summed by the MFMAs in float32, then added into float64 totals
+  double totr[16], toti[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) totr[r] = toti[r] = 0.0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    floatx16 accr = {0.f}, acci = {0.f};
     // A tile: op(A)[i0 + i][k0 + k]; op(A) = A (M x K) or A^T with A stored K x M.
     // The thread mapping walks memory contiguously in either case.
 #pragma unroll
@@ -88,6 +115,11 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmParams gp) {
       acci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.y, acci, 0, 0, 0);
       acci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv.x, acci, 0, 0, 0);
     }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      totr[r] += double(accr[r]);
+      toti[r] += double(acci[r]);
+    }
     __syncthreads();
   }
   // accumulator r of lane l sits at row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the wave tile
@@ -96,23 +128,11 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmParams gp) {
   for (int r = 0; r < 16; ++r) {
     const int i = i0 + wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
     if (i >= a.M || j >= a.N) continue;
-    const float cr = accr[r], ci = acci[r];
+    const float cr = float(totr[r]), ci = float(toti[r]);
     if (gp.split > 1) {
       gp.partial[(size_t(blockIdx.z) * a.M + i) * a.N + j] = make_float2(cr, ci);
     } else {
-      float2 outv = make_float2(a.alpha_re * cr - a.alpha_im * ci, a.alpha_re * ci + a.alpha_im * cr);
-      float2 *cp = a.C + size_t(i) * a.ldc + j;
-      if (a.beta != 0.f) {
-        const float2 old = *cp;
-        outv.x += a.beta * old.x;
-        outv.y += a.beta * old.y;
-      }
-      if (a.mask) {
-        const float mk = a.mask[size_t(i) * a.ldm + j];
-        outv.x *= mk;
-        outv.y *= mk;
-      }
-      *cp = outv;
+      epilogue(a, i, j, cr, ci);
     }
   }
 }
@@ -121,26 +141,14 @@ __global__ void __launch_bounds__(256) split_reduce(GemmParams gp) {
   const CGemmArgs &a = gp.a;
   const size_t total = size_t(a.M) * a.N;
   for (size_t e = size_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += size_t(gridDim.x) * 256) {
-    float sr = 0.f, si = 0.f;
+    double sr = 0.0, si = 0.0;
     for (int s = 0; s < gp.split; ++s) {
       const float2 v = gp.partial[size_t(s) * total + e];
       sr += v.x;
       si += v.y;
     }
     const int i = int(e / a.N), j = int(e % a.N);
-    float2 outv = make_float2(a.alpha_re * sr - a.alpha_im * si, a.alpha_re * si + a.alpha_im * sr);
-    float2 *cp = a.C + size_t(i) * a.ldc + j;
-    if (a.beta != 0.f) {
-      const float2 old = *cp;
-      outv.x += a.beta * old.x;
-      outv.y += a.beta * old.y;
-    }
-    if (a.mask) {
-      const float mk = a.mask[size_t(i) * a.ldm + j];
-      outv.x *= mk;
-      outv.y *= mk;
-    }
-    *cp = outv;
+    epilogue(a, i, j, float(sr), float(si));
   }
 }
 

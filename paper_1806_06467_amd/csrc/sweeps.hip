@@ -6,10 +6,11 @@
 // and each pass reads and writes the plane once. No fftshift is ever materialised: the
 // angular-spectrum step is shift-invariant and h is indexed by the signed frequency.
 //
-//   row_sweep : load a row, optic prologue (amplitude, OPD phasor of Eq. 3, thin-lens chirp),
-//               FFT, * h (scaled 1/n), IFFT (as conj . FFT . conj), store.
-//   col_sweep : load a tile of adjacent columns, FFT, * h, IFFT, conjugate-optic epilogue
-//               for the adjoint, store.
+//   row_sweep : load a row (or synthesise it from the pupil optic), optic prologue (amplitude,
+//               OPD and mirror phasors of Eq. 3, thin-lens chirp), FFT, * h (scaled 1/n),
+//               inverse FFT, store.
+//   col_sweep : load a tile of adjacent columns, FFT, * h, inverse FFT, epilogue (the mirror
+//               after the step, or the conjugate optic for the adjoint), store.
 // The column tile is LINES columns wide so that a wavefront reads LINES*8-byte contiguous
 // segments; blocks are renumbered so that the blocks resident on one XCD (one L2) work on
 // neighbouring columns at the same time.
@@ -27,69 +28,94 @@ __device__ __forceinline__ c32 ld2(const float2 *p) {
 }
 __device__ __forceinline__ void st2(float2 *p, c32 v) { *p = make_float2(v.x, v.y); }
 
-// amp * exp(2 pi i opd / lambda) * lens[x] * lens[y]
-__device__ __forceinline__ c32 optic_at(const PlaneArgs &pa, int n, int y, int x) {
-  const size_t o = size_t(y) * n + x;
-  const float a = pa.amp ? pa.amp[o] : 1.0f;
+// pre optic at (y, x): amp * exp(2 pi i (opd + 2 pre_surf) / lambda) * lens[x] lens[y]
+__device__ __forceinline__ c32 pre_optic(const PlaneArgs &pa, int n, int y, int x) {
+  float a = 1.0f, turns = 0.0f;
+  if (pa.amp || pa.opd) {
+    const int off = (n - pa.win) >> 1;
+    const int wy = y - off, wx = x - off;
+    const bool in = unsigned(wy) < unsigned(pa.win) && unsigned(wx) < unsigned(pa.win);
+    const size_t o = size_t(wy) * pa.win + wx;
+    if (pa.amp) a = in ? pa.amp[o] : 0.0f;
+    if (pa.opd && in) turns = pa.opd[o] * pa.inv_lambda;
+  }
+  if (pa.pre_surf) turns += 2.0f * pa.pre_surf[size_t(y) * n + x] * pa.inv_lambda;
   c32 ph = {a, 0.0f};
-  if (pa.opd) {
-    float t = pa.opd[o] * pa.inv_lambda;
-    t -= rintf(t);
+  if (pa.opd || pa.pre_surf) {
     float s, c;
-    sincospif(2.0f * t, &s, &c);
+    sincos_turns(turns, &s, &c);
     ph = {a * c, a * s};
   }
   if (pa.lens) ph = cmul(ph, cmul(ld2(pa.lens + x), ld2(pa.lens + y)));
   return ph;
 }
 
-__device__ __forceinline__ bool has_optic(const PlaneArgs &pa) {
-  return pa.amp || pa.opd || pa.lens;
+// post optic at (y, x): exp(2 pi i 2 post_surf / lambda)
+__device__ __forceinline__ c32 post_optic(const PlaneArgs &pa, int n, int y, int x) {
+  float s, c;
+  sincos_turns(2.0f * pa.post_surf[size_t(y) * n + x] * pa.inv_lambda, &s, &c);
+  return {c, s};
 }
 
-// frequency product of the pass: Z = conj(Y h) (forward) or conj(Y conj(h)) (adjoint)
+__device__ __forceinline__ bool has_pre(const PlaneArgs &pa) {
+  return pa.amp || pa.opd || pa.pre_surf || pa.lens;
+}
+
+// frequency product of the pass: Y h (forward) or Y conj(h) (adjoint, AS over -z); slot m
+// holds frequency t + T m. h carries the 1/n of the inverse transform.
 template <int E, int T>
 __device__ __forceinline__ void freq_product(c32 (&v)[E], const float2 *h, int t, bool adj) {
+  if (adj) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const c32 hk = ld2(h + t + T * m);
-    v[m] = adj ? cconj(cmulc(v[m], hk)) : cconj(cmul(v[m], hk));
+    for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], ld2(h + t + T * m));
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], ld2(h + t + T * m));
   }
 }
 
 template <class PL, int LINES>
-__global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const float2 *root_) {
+__global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const double2 *root_) {
   constexpr int N = PL::N, E = PL::E, T = PL::T;
   __shared__ c32 lds[LINES * LdsLine<N>::size];
   const PlaneArgs &pa = args.p[blockIdx.y];
-  const c32 *root = reinterpret_cast<const c32 *>(root_);
+  const c64d *root = reinterpret_cast<const c64d *>(root_);
   const int line = threadIdx.x / T;
   const int t = threadIdx.x - line * T;
   const int y = blockIdx.x * LINES + line;
   float2 *row = pa.field + size_t(y) * N;
   const bool adj = pa.flags & FR_ADJOINT;
   c32 v[E];
+  if (pa.flags & kSourceOptic) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = ld2(row + t + T * m);
-  if (!adj && has_optic(pa)) {
+    for (int m = 0; m < E; ++m) v[m] = pre_optic(pa, N, y, t + T * m);
+  } else {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], optic_at(pa, N, y, t + T * m));
+    for (int m = 0; m < E; ++m) v[m] = ld2(row + t + T * m);
+    if (!adj && has_pre(pa)) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cmul(v[m], pre_optic(pa, N, y, t + T * m));
+    }
+    if (adj && pa.post_surf) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], post_optic(pa, N, y, t + T * m));
+    }
   }
   c32 *my = lds + line * LdsLine<N>::size;
   PL::forward(v, my, t, root);
   freq_product<E, T>(v, pa.h, t, adj);
-  PL::forward(v, my, t, root);
+  PL::inverse(v, my, t, root);
 #pragma unroll
-  for (int m = 0; m < E; ++m) st2(row + t + T * m, cconj(v[m]));
+  for (int m = 0; m < E; ++m) st2(row + t + T * m, v[m]);
 }
 
 template <class PL, int LINES>
-__global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const float2 *root_) {
+__global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const double2 *root_) {
   constexpr int N = PL::N, E = PL::E, T = PL::T;
   constexpr int G = N / LINES;  // column groups per plane
   __shared__ c32 lds[LINES * (LdsLine<N>::size + 4)];
   const PlaneArgs &pa = args.p[blockIdx.y];
-  const c32 *root = reinterpret_cast<const c32 *>(root_);
+  const c64d *root = reinterpret_cast<const c64d *>(root_);
   const int c = threadIdx.x % LINES;
   const int t = threadIdx.x / LINES;
   // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of groups
@@ -104,20 +130,21 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   c32 *my = lds + c * (LdsLine<N>::size + 4);
   PL::forward(v, my, t, root);
   freq_product<E, T>(v, pa.h, t, adj);
-  PL::forward(v, my, t, root);
-  if (adj && has_optic(pa)) {
+  PL::inverse(v, my, t, root);
+  if (adj && has_pre(pa)) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = cmul(cconj(v[m]), cconj(optic_at(pa, N, t + T * m, x)));
-  } else {
+    for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], pre_optic(pa, N, t + T * m, x));
+  }
+  if (!adj && pa.post_surf) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = cconj(v[m]);
+    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], post_optic(pa, N, t + T * m, x));
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) st2(col + size_t(t + T * m) * N, v[m]);
 }
 
 template <class PL, int ROW_LINES, int COL_LINES>
-hipError_t launch_sweeps(const BatchArgs &args, int count, const float2 *root, hipStream_t s,
+hipError_t launch_sweeps(const BatchArgs &args, int count, const double2 *root, hipStream_t s,
                          const LaunchHook &hook) {
   constexpr int N = PL::N;
   static_assert(N % ROW_LINES == 0 && N % COL_LINES == 0, "tile must divide n");
@@ -146,8 +173,10 @@ bool fresnel_size_supported(int n) {
   }
 }
 
-hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const float2 *root,
-                                hipStream_t s, const LaunchHook &hook) {
+int fresnel_variants(int n) { return n == 4096 || n == 2048 || n == 8192 ? 3 : 1; }
+
+hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const double2 *root,
+                                hipStream_t s, const LaunchHook &hook, int variant) {
   BatchArgs args;
   for (int i = 0; i < count; ++i) args.p[i] = planes[i];
   switch (n) {
@@ -156,9 +185,21 @@ hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const
     case 256: return launch_sweeps<Plan<256, 16, 16, 16>, 16, 32>(args, count, root, s, hook);
     case 512: return launch_sweeps<Plan<512, 8, 8, 8, 8>, 4, 16>(args, count, root, s, hook);
     case 1024: return launch_sweeps<Plan<1024, 16, 16, 8, 8>, 4, 8>(args, count, root, s, hook);
-    case 2048: return launch_sweeps<Plan<2048, 16, 16, 16, 8>, 2, 8>(args, count, root, s, hook);
-    case 4096: return launch_sweeps<Plan<4096, 16, 16, 16, 16>, 1, 4>(args, count, root, s, hook);
-    case 8192: return launch_sweeps<Plan<8192, 16, 16, 16, 16, 2>, 1, 2>(args, count, root, s, hook);
+    case 2048:
+      using P2 = Plan<2048, 16, 16, 16, 8>;
+      if (variant == 1) return launch_sweeps<P2, 2, 4>(args, count, root, s, hook);
+      if (variant == 2) return launch_sweeps<P2, 4, 4>(args, count, root, s, hook);
+      return launch_sweeps<P2, 2, 8>(args, count, root, s, hook);
+    case 4096:
+      using P4 = Plan<4096, 16, 16, 16, 16>;
+      if (variant == 1) return launch_sweeps<P4, 1, 2>(args, count, root, s, hook);
+      if (variant == 2) return launch_sweeps<P4, 2, 2>(args, count, root, s, hook);
+      return launch_sweeps<P4, 1, 4>(args, count, root, s, hook);
+    case 8192:
+      using P8 = Plan<8192, 16, 16, 16, 16, 2>;
+      if (variant == 1) return launch_sweeps<P8, 1, 1>(args, count, root, s, hook);
+      if (variant == 2) return launch_sweeps<P8, 2, 1>(args, count, root, s, hook);
+      return launch_sweeps<P8, 1, 2>(args, count, root, s, hook);
     default: return hipErrorInvalidValue;
   }
 }

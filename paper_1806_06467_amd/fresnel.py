@@ -313,3 +313,96 @@ def profile_read(device=None, max_entries=64):
         nm = raw[i * name_len:(i + 1) * name_len].split(b"\0", 1)[0].decode()
         out[nm] = (tot[i], cnt[i])
     return out
+
+
+# ---- Lyot coronagraph train ----------------------------------------------------------------
+
+class Train:
+    """Geometry and optics of a Lyot coronagraph train (device tensors) for propagate_train.
+
+    pupil_amp, pupil_opd, lyot: n_d x n_d float32; occ_mask: occ_m x occ_m float32 (1 = blocked).
+    """
+
+    def __init__(self, n_d, d_m, z_m, pupil_amp, lyot, occ_mask, occ_du_c, det_m, det_du_c,
+                 lambda_c_m=550e-9, pupil_opd=None, n_act=0, n_dm=0):
+        self.n_d, self.d_m, self.z_m = int(n_d), float(d_m), float(z_m)
+        self.pupil_amp, self.pupil_opd, self.lyot, self.occ_mask = pupil_amp, pupil_opd, lyot, occ_mask
+        self.occ_m = int(occ_mask.shape[0]) if occ_mask is not None else 1
+        self.occ_du_c, self.det_m, self.det_du_c = float(occ_du_c), int(det_m), float(det_du_c)
+        self.lambda_c_m, self.n_act, self.n_dm = float(lambda_c_m), int(n_act), int(n_dm)
+        nd = self.n_d
+        _need(pupil_amp, torch.float32, (nd, nd), "pupil_amp")
+        _need(lyot, torch.float32, (nd, nd), "lyot")
+        if pupil_opd is not None:
+            _need(pupil_opd, torch.float32, (nd, nd), "pupil_opd")
+        if occ_mask is not None:
+            _need(occ_mask, torch.float32, (self.occ_m, self.occ_m), "occ_mask")
+
+    def desc(self, heights):
+        d = FrTrainDesc()
+        d.n_d, d.d_m = self.n_d, self.d_m
+        d.pupil_amp = self.pupil_amp.data_ptr()
+        d.pupil_opd_m = self.pupil_opd.data_ptr() if self.pupil_opd is not None else None
+        d.n_dm, d.n_act = self.n_dm, self.n_act
+        d.dm_heights_m = heights.data_ptr() if heights is not None else None
+        d.z_m = self.z_m
+        d.occ_m, d.occ_du_c = self.occ_m, self.occ_du_c
+        d.occ_mask = self.occ_mask.data_ptr() if self.occ_mask is not None else None
+        d.lyot = self.lyot.data_ptr()
+        d.det_m, d.det_du_c, d.lambda_c_m = self.det_m, self.det_du_c, self.lambda_c_m
+        return d
+
+
+def propagate_train(train, wavelengths, n_pad, weights, heights=None, occulter=True,
+                    grad_psf=None, stream=None):
+    """Broadband PSF (det_m x det_m float32) of the train; with grad_psf = dL/dPSF also returns
+    dL/dheights (n_dm x n_act x n_act float32)."""
+    dev = train.pupil_amp.device.index
+    nl = len(wavelengths)
+    if len(n_pad) != nl or len(weights) != nl:
+        raise ValueError("wavelengths, n_pad and weights must have one entry per wavelength")
+    if train.n_dm:
+        _need(heights, torch.float32, (train.n_dm, train.n_act, train.n_act), "heights")
+    mode = 0 if occulter else FR_TRAIN_NO_OCCULTER
+    gh = None
+    if grad_psf is not None:
+        _need(grad_psf, torch.float32, (train.det_m, train.det_m), "grad_psf")
+        mode |= FR_TRAIN_GRAD
+        gh = torch.empty((train.n_dm, train.n_act, train.n_act), dtype=torch.float32,
+                         device=train.pupil_amp.device)
+    lam = (_c.c_double * nl)(*[float(x) for x in wavelengths])
+    npd = (_c.c_int32 * nl)(*[int(x) for x in n_pad])
+    w = (_c.c_float * nl)(*[float(x) for x in weights])
+    d = train.desc(heights)
+    L = lib()
+    nbytes = L.propagate_train_workspace_bytes(_c.byref(d), nl, npd, mode)
+    if nbytes == 0:
+        raise ValueError("invalid train geometry")
+    ws = workspace(nbytes, dev)
+    psf = torch.empty((train.det_m, train.det_m), dtype=torch.float32, device=train.pupil_amp.device)
+    st = L.propagate_train(context(dev).handle, _c.byref(d), nl, lam, npd, w, mode, _ptr(psf),
+                           _ptr(grad_psf), _ptr(gh), _ptr(ws), ws.numel(), _stream_handle(dev, stream))
+    _check(st, "propagate_train")
+    return (psf, gh) if grad_psf is not None else psf
+
+
+class DMHeightsToPSF(torch.autograd.Function):
+    """heights (n_dm x n_act x n_act) -> broadband PSF, with the library's adjoint as backward.
+
+    apply(heights, train, wavelengths, n_pad, weights). The backward pass reruns the forward of
+    each wavelength inside the library (keeping that wavelength's planes in the workspace) and
+    then its adjoint."""
+
+    @staticmethod
+    def forward(ctx, heights, train, wavelengths, n_pad, weights):
+        h = heights.detach().contiguous()
+        ctx.train, ctx.args = train, (list(wavelengths), list(n_pad), list(weights))
+        ctx.save_for_backward(h)
+        return propagate_train(train, wavelengths, n_pad, weights, h)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (h,) = ctx.saved_tensors
+        wl, npd, w = ctx.args
+        _, gh = propagate_train(ctx.train, wl, npd, w, h, grad_psf=grad_out.contiguous().float())
+        return gh, None, None, None, None

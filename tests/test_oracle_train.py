@@ -127,3 +127,12 @@ def test_focal_grid_fixed_in_reference_units(lam):
     assert int(np.argmax(row)) == k0 + shift
     for d in (1, 2, 3):
         assert abs(row[k0 + shift + d] - row[k0 + shift - d]) <= 1e-11 * row.max()
+
+
+def test_step_cache_is_pure_memoisation():
+    g, heights, lams, ns, w, dh, mref = _setup(1, 2)
+    cache = {}
+    a = oracle.train_loss(g, lams, ns, w, heights, dh, mref)
+    b = oracle.train_loss(g, lams, ns, w, heights, dh, mref, step_cache=cache)
+    c = oracle.train_loss(g, lams, ns, w, heights, dh, mref, step_cache=cache)
+    assert a == b == c and len(cache) == 2
