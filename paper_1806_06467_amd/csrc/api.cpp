@@ -137,21 +137,18 @@ static uint64_t bits(double v) {
   return b;
 }
 
-// float64 roots exp(-2 pi i m / n), from the exact fraction m / n of a turn
-int Ctx::roots(int n, hipStream_t s, const double2 **out) {
+// per-pass twiddle table of the FFT plan for edge n (built in float64)
+int Ctx::twiddles(int n, hipStream_t s, const float2 **out) {
   TableKey key{kRoots, n, 0, 0, 0, 0};
   if (auto it = tables.find(key); it != tables.end()) {
-    *out = static_cast<const double2 *>(it->second);
+    *out = static_cast<const float2 *>(it->second);
     return FR_OK;
   }
-  std::vector<double2> h(n);
-  for (int m = 0; m < n; ++m) {
-    const double f = frac_turn(-double(m) / double(n));
-    h[m] = make_double2(std::cos(2.0 * M_PI * f), std::sin(2.0 * M_PI * f));
-  }
+  std::vector<float2> h(std::max(fresnel_twiddle_count(n), 1));
+  fresnel_twiddle_build(n, h.data());
   void *d;
-  int st = upload(key, h.data(), h.size() * sizeof(double2), s, &d);
-  *out = static_cast<const double2 *>(d);
+  int st = upload(key, h.data(), h.size() * sizeof(float2), s, &d);
+  *out = static_cast<const float2 *>(d);
   return st;
 }
 
@@ -314,8 +311,8 @@ int mft_adjoint_impl(Ctx *ctx, const float2 *in, int m_in, int ld_in, float2 *ou
 }
 
 int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s) {
-  const double2 *root;
-  int st = ctx->roots(n, s, &root);
+  const float2 *root;
+  int st = ctx->twiddles(n, s, &root);
   if (st != FR_OK) return st;
   for (int i = 0; i < count; i += kMaxBatch) {
     const int c = std::min(count - i, kMaxBatch);

@@ -279,17 +279,16 @@ struct DftDir {
   }
 };
 
-// u[r] *= w1^r (or conj(w1)^r for the inverse), r = 1..R-1. The powers are built in float64
-// (full rate on CDNA, like non-packed float32) by squarings and products of depth <= 4 from the
-// one float64 table value w1, then rounded once to float: every twiddle is within half an ulp,
-// at the cost of a single table load per butterfly.
+// u[r] *= w1^r (or conj(w1)^r for the inverse), r = 1..R-1. The powers are accumulated in
+// float64 (full rate on CDNA, like non-packed float32), p_r = p_{r-1} w1, whose rounding
+// (~r 1e-16) stays far below float resolution, then rounded once to float: every twiddle is
+// within half an ulp from one table value per butterfly, with two float64 values live.
 struct c64d {
   double x, y;
 };
 __device__ __forceinline__ c64d dmul(c64d a, c64d b) {
   return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
 }
-__device__ __forceinline__ c64d dsq(c64d a) { return {fma(a.x, a.x, -a.y * a.y), 2.0 * a.x * a.y}; }
 
 template <bool INV>
 __device__ __forceinline__ void twiddle_leg(c32 &u, c64d p) {
@@ -299,36 +298,11 @@ __device__ __forceinline__ void twiddle_leg(c32 &u, c64d p) {
 
 template <int R, bool INV>
 __device__ __forceinline__ void apply_twiddle_powers(c32 *u, c64d w1) {
-  if constexpr (R > 1) twiddle_leg<INV>(u[1], w1);
-  if constexpr (R > 2) {
-    const c64d p2 = dsq(w1);
-    twiddle_leg<INV>(u[2], p2);
-    if constexpr (R > 3) {
-      const c64d p3 = dmul(p2, w1);
-      twiddle_leg<INV>(u[3], p3);
-      if constexpr (R > 4) {
-        const c64d p4 = dsq(p2);
-        twiddle_leg<INV>(u[4], p4);
-        if constexpr (R > 5) twiddle_leg<INV>(u[5], dmul(p4, w1));
-        if constexpr (R > 6) twiddle_leg<INV>(u[6], dmul(p4, p2));
-        if constexpr (R > 7) twiddle_leg<INV>(u[7], dmul(p4, p3));
-        if constexpr (R > 8) {
-          const c64d p8 = dsq(p4);
-          twiddle_leg<INV>(u[8], p8);
-          if constexpr (R > 9) twiddle_leg<INV>(u[9], dmul(p8, w1));
-          if constexpr (R > 10) twiddle_leg<INV>(u[10], dmul(p8, p2));
-          if constexpr (R > 11) twiddle_leg<INV>(u[11], dmul(p8, p3));
-          if constexpr (R > 12) {
-            const c64d p12 = dmul(p8, p4);
-            twiddle_leg<INV>(u[12], p12);
-            if constexpr (R > 13) twiddle_leg<INV>(u[13], dmul(p12, w1));
-            if constexpr (R > 14) twiddle_leg<INV>(u[14], dmul(p12, p2));
-            if constexpr (R > 15) twiddle_leg<INV>(u[15], dmul(p12, p3));
-          }
-          static_assert(R <= 16, "twiddle powers are written out up to radix 16");
-        }
-      }
-    }
+  c64d p = w1;
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    if (r > 1) p = dmul(p, w1);
+    twiddle_leg<INV>(u[r], p);
   }
 }
 

@@ -9,7 +9,7 @@
 //
 // Pass with radix R after span P (P = product of earlier radices): butterfly b twiddles leg r
 // by w_{P R}^{r (b mod P)}, runs DFT_R and writes output r to (b / P) P R + (b mod P) + r P.
-// Twiddles come from a float64 table of the N roots exp(-2 pi i m / N) built on the host.
+// Twiddles come from per-pass tables built in float64 on the host (exact to half an ulp).
 #pragma once
 #include "dft_small.hpp"
 
@@ -23,9 +23,57 @@ struct LdsLine {
   static constexpr int size = N + N / 16;
 };
 
+// Padded LDS index of output r of butterfly b in a pass of span P and radix R, written as a
+// per-thread base plus a compile-time offset per r (so the stores use immediate offsets).
+template <int P, int R>
+struct PassOut {
+  int base;  // padded index of r = 0
+  __device__ __forceinline__ explicit PassOut(int b) {
+    const int i0 = (b / P) * (P * R) + (b % P);
+    base = lds_pad(i0);
+  }
+  // valid when P % 16 == 0 (the pad of i0 + rP is pad(i0) + 17 rP/16), or P == 1 and
+  // 16 % R == 0 with i0 = b R (then (b R + r) / 16 = b R / 16 for r < R)
+  __device__ __forceinline__ static constexpr int off(int r) {
+    if constexpr (P % 16 == 0) return r * (P + P / 16);
+    return r;  // P == 1
+  }
+  static constexpr bool exact = (P % 16 == 0) || (P == 1 && 16 % R == 0);
+};
+
+// Twiddles of one pass for the NB butterflies a thread owns: leg r of butterfly b is
+// multiplied by w_{PR}^{r (b mod P)}, read from the pass's float32 table laid out
+// [r - 1][k], k = b mod P, so that for each leg the lanes of a wavefront read consecutive
+// entries (the table is built in float64 on the host; each entry is within half an ulp).
+template <int P, int R, int NB, int T>
+struct PassTw {
+  c32 w[NB][R > 1 ? R - 1 : 1];
+  __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) {
+    if constexpr (P > 1) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int k = (t + j * T) % P;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float2 q = tw[(r - 1) * P + k];
+          w[j][r - 1] = {q.x, q.y};
+        }
+      }
+    }
+  }
+};
+
+template <int R0, int... Rs>
+struct FirstOf {
+  static constexpr int value = R0;
+};
+
+// Pass with radix R after span P. The twiddles of the next pass are loaded before this
+// pass's LDS exchange, so their latency overlaps the exchange.
 template <bool INV, int N, int E, int P, int R, int... Rest>
 __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, int t,
-                                           const c64d* __restrict__ root) {
+                                           const float2* __restrict__ tw,
+                                           const PassTw<P, R, E / R, N / E>& cur) {
   constexpr int T = N / E;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide the elements per thread");
@@ -38,28 +86,67 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
     for (int r = 0; r < R; ++r) u[r] = v[j + r * NB];
     const int b = t + j * T;
     if constexpr (P > 1) {
-      // leg r of butterfly b is twiddled by w_{PR}^{r k}, k = b mod P; w_{PR}^k is root[k N/(PR)]
-      constexpr int S = N / (P * R);
-      apply_twiddle_powers<R, INV>(u, root[(b % P) * S]);
+#pragma unroll
+      for (int r = 1; r < R; ++r) u[r] = INV ? cmulc(u[r], cur.w[j][r - 1]) : cmul(u[r], cur.w[j][r - 1]);
     }
     DftDir<R, INV>::run(u);
     if constexpr (last) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[j + r * NB] = u[r];
     } else {
-      const int base = (b / P) * (P * R) + (b % P);
+      if constexpr (PassOut<P, R>::exact) {
+        const PassOut<P, R> o(b);
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[lds_pad(base + r * P)] = u[r];
+        for (int r = 0; r < R; ++r) lds[o.base + PassOut<P, R>::off(r)] = u[r];
+      } else {
+        const int base = (b / P) * (P * R) + (b % P);
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lds_pad(base + r * P)] = u[r];
+      }
     }
   }
   if constexpr (!last) {
+    constexpr int R2 = FirstOf<Rest...>::value;
+    const float2* tw_next = tw + (P > 1 ? (R - 1) * P : 0);
+    PassTw<P * R, R2, E / R2, T> nxt;
+    nxt.load(tw_next, t);
     __syncthreads();
+    if constexpr (T % 16 == 0) {
+      // pad(t + T m) = pad(t) + 17 T m / 16
+      const int base = lds_pad(t);
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = lds[lds_pad(t + T * m)];
+      for (int m = 0; m < E; ++m) v[m] = lds[base + m * (T + T / 16)];
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = lds[lds_pad(t + T * m)];
+    }
     __syncthreads();
-    fft_passes<INV, N, E, P * R, Rest...>(v, lds, t, root);
+    fft_passes<INV, N, E, P * R, Rest...>(v, lds, t, tw_next, nxt);
   }
 }
+
+// float64-built twiddle table of a plan: for each pass with span P > 1 and radix R, the block
+// [r - 1][k] = exp(-2 pi i r k / (P R)), r = 1..R-1, k = 0..P-1 (rounded once to float)
+template <int N, int P, int R, int... Rest>
+struct TwiddleTable {
+  static void build(float2* out) {
+    if (P > 1) {
+      for (int r = 1; r < R; ++r)
+        for (int k = 0; k < P; ++k) {
+          const long long num = (long long)r * k % (P * R);
+          const double turn = -double(num) / double(P * R);
+          out[(r - 1) * P + k] = make_float2(float(__builtin_cos(2.0 * kPi * turn)),
+                                             float(__builtin_sin(2.0 * kPi * turn)));
+        }
+    }
+    if constexpr (sizeof...(Rest) > 0) TwiddleTable<N, P * R, Rest...>::build(out + (P > 1 ? (R - 1) * P : 0));
+  }
+  static constexpr int size() {
+    int s = P > 1 ? (R - 1) * P : 0;
+    if constexpr (sizeof...(Rest) > 0) s += TwiddleTable<N, P * R, Rest...>::size();
+    return s;
+  }
+};
 
 // compile-time FFT plan: N = product of Rs, E elements per thread
 template <int N_, int E_, int... Rs>
@@ -67,13 +154,18 @@ struct Plan {
   static constexpr int N = N_;
   static constexpr int E = E_;
   static constexpr int T = N_ / E_;
-  // unnormalised DFT of the line, kernel exp(-2 pi i nk/N)
-  __device__ __forceinline__ static void forward(c32 (&v)[E_], c32* lds, int t, const c64d* root) {
-    fft_passes<false, N_, E_, 1, Rs...>(v, lds, t, root);
+  static constexpr int twiddles = TwiddleTable<N_, 1, Rs...>::size();
+  static constexpr int R0 = FirstOf<Rs...>::value;
+  static void build_twiddles(float2* out) { TwiddleTable<N_, 1, Rs...>::build(out); }
+  // unnormalised DFT of the line, kernel exp(-2 pi i nk/N); tw = the plan's twiddle table
+  __device__ __forceinline__ static void forward(c32 (&v)[E_], c32* lds, int t, const float2* tw) {
+    PassTw<1, R0, E_ / R0, N_ / E_> none;
+    fft_passes<false, N_, E_, 1, Rs...>(v, lds, t, tw, none);
   }
   // unnormalised inverse DFT, kernel exp(+2 pi i nk/N)
-  __device__ __forceinline__ static void inverse(c32 (&v)[E_], c32* lds, int t, const c64d* root) {
-    fft_passes<true, N_, E_, 1, Rs...>(v, lds, t, root);
+  __device__ __forceinline__ static void inverse(c32 (&v)[E_], c32* lds, int t, const float2* tw) {
+    PassTw<1, R0, E_ / R0, N_ / E_> none;
+    fft_passes<true, N_, E_, 1, Rs...>(v, lds, t, tw, none);
   }
 };
 

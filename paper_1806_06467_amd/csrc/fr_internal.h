@@ -45,12 +45,14 @@ struct BatchArgs {
 };
 
 // Row sweep then column sweep over `count` planes of edge n (count <= kMaxBatch).
-// root: n float64 complex roots exp(-2 pi i m / n). Returns a hipError_t.
+// tw: the plan's twiddle table (fresnel_twiddle_build). Returns a hipError_t.
 // `variant` selects a tile configuration (row lines per block, column tile width); every
 // variant computes the same result. fresnel_variants(n) = number of variants for edge n.
-hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const double2 *root,
+hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const float2 *tw,
                                 hipStream_t stream, const LaunchHook &hook, int variant);
 int fresnel_variants(int n);
+int fresnel_twiddle_count(int n);
+void fresnel_twiddle_build(int n, float2 *out);  // host
 bool fresnel_size_supported(int n);
 
 // ---- MFT: out = alpha * c * A in B^T (+ beta * out) (* mask), complex, FP32 MFMA ------

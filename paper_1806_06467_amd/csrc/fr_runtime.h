@@ -37,7 +37,7 @@ struct Ctx {
   ~Ctx();
   // copy `bytes` of host data to a new cached device buffer (waits on `s` for the copy)
   int upload(const TableKey &key, const void *host, size_t bytes, hipStream_t s, void **out);
-  int roots(int n, hipStream_t s, const double2 **out);
+  int twiddles(int n, hipStream_t s, const float2 **out);
   int transfer(int n, double dx, double lam, double z, hipStream_t s, const float2 **out);
   int lens(int n, double dx, double lam, double f, hipStream_t s, const float2 **out);
   int mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out);

@@ -26,7 +26,25 @@ __device__ __forceinline__ c32 ld2(const float2 *p) {
   float2 v = *p;
   return {v.x, v.y};
 }
-__device__ __forceinline__ void st2(float2 *p, c32 v) { *p = make_float2(v.x, v.y); }
+
+// Raw buffer access to one plane: a 32-bit per-lane offset plus a wave-uniform offset held in a
+// scalar register, so that the sixteen strided accesses of a thread cost one address VGPR;
+// accesses beyond the plane's bytes read 0 and are not written (hardware bounds check).
+// (The 64-bit results are moved whole with bit casts: extracting single elements of the
+// builtin's vector type was observed to address the wrong half.)
+struct PlaneBuf {
+  __amdgpu_buffer_rsrc_t r;
+  typedef unsigned int raw64 __attribute__((__vector_size__(8)));  // the builtin's value type
+  __device__ __forceinline__ PlaneBuf(const void *p, unsigned bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, int(bytes), 0x00020000)) {}
+  __device__ __forceinline__ c32 load(unsigned vo, unsigned so) const {
+    const float2 q = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    return {q.x, q.y};
+  }
+  __device__ __forceinline__ void store(unsigned vo, unsigned so, c32 v) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(raw64, make_float2(v.x, v.y)), r, vo, so, 0);
+  }
+};
 
 // pre optic at (y, x): amp * exp(2 pi i (opd + 2 pre_surf) / lambda) * lens[x] lens[y]
 __device__ __forceinline__ c32 pre_optic(const PlaneArgs &pa, int n, int y, int x) {
@@ -75,23 +93,23 @@ __device__ __forceinline__ void freq_product(c32 (&v)[E], const float2 *h, int t
 }
 
 template <class PL, int LINES>
-__global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const double2 *root_) {
+__global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const float2 *tw) {
   constexpr int N = PL::N, E = PL::E, T = PL::T;
   __shared__ c32 lds[LINES * LdsLine<N>::size];
   const PlaneArgs &pa = args.p[blockIdx.y];
-  const c64d *root = reinterpret_cast<const c64d *>(root_);
   const int line = threadIdx.x / T;
   const int t = threadIdx.x - line * T;
   const int y = blockIdx.x * LINES + line;
-  float2 *row = pa.field + size_t(y) * N;
   const bool adj = pa.flags & FR_ADJOINT;
+  const PlaneBuf buf(pa.field, unsigned(N) * N * 8u);
+  const unsigned vo = unsigned(y * N + t) * 8u;
   c32 v[E];
   if (pa.flags & kSourceOptic) {
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = pre_optic(pa, N, y, t + T * m);
   } else {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = ld2(row + t + T * m);
+    for (int m = 0; m < E; ++m) v[m] = buf.load(vo, unsigned(T * m) * 8u);
     if (!adj && has_pre(pa)) {
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = cmul(v[m], pre_optic(pa, N, y, t + T * m));
@@ -102,20 +120,19 @@ __global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const 
     }
   }
   c32 *my = lds + line * LdsLine<N>::size;
-  PL::forward(v, my, t, root);
+  PL::forward(v, my, t, tw);
   freq_product<E, T>(v, pa.h, t, adj);
-  PL::inverse(v, my, t, root);
+  PL::inverse(v, my, t, tw);
 #pragma unroll
-  for (int m = 0; m < E; ++m) st2(row + t + T * m, v[m]);
+  for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * 8u, v[m]);
 }
 
 template <class PL, int LINES>
-__global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const double2 *root_) {
+__global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const float2 *tw) {
   constexpr int N = PL::N, E = PL::E, T = PL::T;
   constexpr int G = N / LINES;  // column groups per plane
   __shared__ c32 lds[LINES * (LdsLine<N>::size + 4)];
   const PlaneArgs &pa = args.p[blockIdx.y];
-  const c64d *root = reinterpret_cast<const c64d *>(root_);
   const int c = threadIdx.x % LINES;
   const int t = threadIdx.x / LINES;
   // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of groups
@@ -123,14 +140,15 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   if constexpr (G % 8 == 0) g = (blockIdx.x & 7) * (G / 8) + (blockIdx.x >> 3);
   const int x = g * LINES + c;
   const bool adj = pa.flags & FR_ADJOINT;
-  float2 *col = pa.field + x;
+  const PlaneBuf buf(pa.field, unsigned(N) * N * 8u);
+  const unsigned vo = unsigned(t * N + x) * 8u;
   c32 v[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = ld2(col + size_t(t + T * m) * N);
+  for (int m = 0; m < E; ++m) v[m] = buf.load(vo, unsigned(T * m) * unsigned(N) * 8u);
   c32 *my = lds + c * (LdsLine<N>::size + 4);
-  PL::forward(v, my, t, root);
+  PL::forward(v, my, t, tw);
   freq_product<E, T>(v, pa.h, t, adj);
-  PL::inverse(v, my, t, root);
+  PL::inverse(v, my, t, tw);
   if (adj && has_pre(pa)) {
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], pre_optic(pa, N, t + T * m, x));
@@ -140,11 +158,11 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
     for (int m = 0; m < E; ++m) v[m] = cmul(v[m], post_optic(pa, N, t + T * m, x));
   }
 #pragma unroll
-  for (int m = 0; m < E; ++m) st2(col + size_t(t + T * m) * N, v[m]);
+  for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
 }
 
 template <class PL, int ROW_LINES, int COL_LINES>
-hipError_t launch_sweeps(const BatchArgs &args, int count, const double2 *root, hipStream_t s,
+hipError_t launch_sweeps(const BatchArgs &args, int count, const float2 *root, hipStream_t s,
                          const LaunchHook &hook) {
   constexpr int N = PL::N;
   static_assert(N % ROW_LINES == 0 && N % COL_LINES == 0, "tile must divide n");
@@ -173,9 +191,37 @@ bool fresnel_size_supported(int n) {
   }
 }
 
+// the twiddle table of the plan the sweeps use for edge n (same Plan types as the launches)
+int fresnel_twiddle_count(int n) {
+  switch (n) {
+    case 64: return Plan<64, 8, 8, 8>::twiddles;
+    case 128: return Plan<128, 16, 16, 8>::twiddles;
+    case 256: return Plan<256, 16, 16, 16>::twiddles;
+    case 512: return Plan<512, 8, 8, 8, 8>::twiddles;
+    case 1024: return Plan<1024, 16, 16, 8, 8>::twiddles;
+    case 2048: return Plan<2048, 16, 16, 16, 8>::twiddles;
+    case 4096: return Plan<4096, 16, 16, 16, 16>::twiddles;
+    case 8192: return Plan<8192, 16, 16, 16, 16, 2>::twiddles;
+    default: return 0;
+  }
+}
+void fresnel_twiddle_build(int n, float2 *out) {
+  switch (n) {
+    case 64: Plan<64, 8, 8, 8>::build_twiddles(out); break;
+    case 128: Plan<128, 16, 16, 8>::build_twiddles(out); break;
+    case 256: Plan<256, 16, 16, 16>::build_twiddles(out); break;
+    case 512: Plan<512, 8, 8, 8, 8>::build_twiddles(out); break;
+    case 1024: Plan<1024, 16, 16, 8, 8>::build_twiddles(out); break;
+    case 2048: Plan<2048, 16, 16, 16, 8>::build_twiddles(out); break;
+    case 4096: Plan<4096, 16, 16, 16, 16>::build_twiddles(out); break;
+    case 8192: Plan<8192, 16, 16, 16, 16, 2>::build_twiddles(out); break;
+    default: break;
+  }
+}
+
 int fresnel_variants(int n) { return n == 4096 || n == 2048 || n == 8192 ? 3 : 1; }
 
-hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const double2 *root,
+hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const float2 *root,
                                 hipStream_t s, const LaunchHook &hook, int variant) {
   BatchArgs args;
   for (int i = 0; i < count; ++i) args.p[i] = planes[i];
