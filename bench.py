@@ -149,7 +149,7 @@ def main():
 
     t_wall0 = time.perf_counter()
     ms_batched, prof = timed(batched_step, args.steps, profile=True)
-    ms_plain, _ = timed(plain_step, max(1, args.steps // 2))
+    ms_plain, prof_plain = timed(plain_step, max(1, args.steps // 2), profile=True)
     t_wall = time.perf_counter() - t_wall0
 
     steps = args.steps
@@ -157,12 +157,15 @@ def main():
     planes_per_s = n_pl * steps / (ms_batched * 1e-3)
     plain_planes_per_s = n_pl * max(1, steps // 2) / (ms_plain * 1e-3)
 
-    # roofline of the dominant kernel (per launch: all 42 planes of one sweep)
-    kern = {k: v for k, v in prof.items() if k.startswith(("row_sweep", "col_sweep"))}
+    # roofline of the dominant kernel. Each sweep launch covers the 21 planes of one direction
+    # (forward planes: rows then columns; adjoint planes: columns then rows). Both row launches
+    # apply the optic (prologue forward, conjugate epilogue adjoint), so a row launch reads the
+    # amplitude and OPD maps of its planes once; a column launch moves only the fields.
+    per_launch = {"row_sweep": N_LAMBDA * sweep_bytes(N, 2), "col_sweep": N_LAMBDA * sweep_bytes(N, 0)}
+    kern = {k.split("/")[0]: v for k, v in prof.items() if k.split("/")[0] in per_launch}
     dom = max(kern, key=lambda k: kern[k][0])
     dom_ms = kern[dom][0] / kern[dom][1]
-    # row sweep reads amp+opd for the 21 forward planes; column sweep for the 21 adjoint planes
-    bytes_launch = n_pl * sweep_bytes(N, 0) + N_LAMBDA * 2 * N * N * 4
+    bytes_launch = per_launch[dom]
     achieved = bytes_launch / (dom_ms * 1e-3) / 1e9
     total_bytes_step = N_LAMBDA * plane_bytes(N, 2) * 2
 
@@ -186,7 +189,8 @@ def main():
             "form": "batched (one launch per sweep per step)",
         },
         "plain": {"value": plain_planes_per_s, "unit": "Fresnel planes/s",
-                  "ms_per_plane": ms_plain / (n_pl * max(1, steps // 2))},
+                  "ms_per_plane": ms_plain / (n_pl * max(1, steps // 2)),
+                  "kernels_ms_per_plane": {k: v[0] / v[1] for k, v in prof_plain.items()}},
         "hbm_fraction_whole_plane": (total_bytes_step / (ms_per_step * 1e-3)) / (HBM_PEAK_GBS * 1e9),
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,

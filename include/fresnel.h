@@ -45,6 +45,7 @@ extern "C" {
 #define FR_EWORKSPACE (-3)    /* workspace missing or smaller than the *_workspace_bytes   */
 #define FR_EHIP (-4)          /* a HIP runtime call or a kernel launch failed              */
 #define FR_ENOMEM (-5)        /* device allocation for a cached table failed               */
+#define FR_ESTATE (-6)        /* a table was missing while a graph was being recorded      */
 
 #define FR_W_AS_UNDERSAMPLED 1 /* |z| > n dx^2 / lambda: the transfer function aliases     */
 #define FR_W_MFT_ALIASED 2     /* du > n_d / n_in: focal sampling beyond the input lattice */
@@ -130,9 +131,20 @@ int mft_adjoint(fr_ctx *ctx, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_c
  * FR_TRAIN_GRAD additionally takes grad_psf = dL/dpsf (det_m^2 float) and writes
  * grad_heights = dL/dA (n_dm * n_act^2 float, DM1 first), the chain rule through every
  * adjoint above. Arrays lambda_m, n_pad, weight are HOST arrays of n_lambda entries.
- * ws: device workspace of propagate_train_workspace_bytes(...) bytes. */
+ * FR_TRAIN_BATCHED keeps one field plane per wavelength in the workspace and runs the Fresnel
+ * steps of all wavelengths (grids of different edges allowed) in one launch per sweep; the
+ * focal-plane chains and all sums still go in wavelength order, so psf and grad_heights are
+ * bit-identical to the plain (wavelength after wavelength) mode. Its workspace grows with
+ * sum_j n_pad[j]^2.
+ * FR_TRAIN_GRAPH records the whole call as one graph the first time a given set of argument
+ * values (descriptor bytes, host arrays, device pointers, stream) is seen, after running it
+ * normally, and replays that graph on later identical calls; the device inputs may change
+ * between calls, their addresses may not. At most 8 graphs are kept per context.
+ * ws: device workspace of propagate_train_workspace_bytes(...) bytes (same mode bits). */
 #define FR_TRAIN_NO_OCCULTER 1
 #define FR_TRAIN_GRAD 2
+#define FR_TRAIN_BATCHED 4
+#define FR_TRAIN_GRAPH 8
 typedef struct {
   int32_t n_d;               /* pupil pixels across D                                   */
   double d_m;                /* pupil diameter [m]                                      */

@@ -50,6 +50,8 @@ int record_hip(hipError_t e) {
 Ctx::~Ctx() {
   (void)hipSetDevice(device);
   (void)hipDeviceSynchronize();
+  drop_graphs();
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
   for (auto &kv : tables) (void)hipFree(kv.second);
   tables.clear();
   for (auto &t : timed) {
@@ -102,16 +104,38 @@ LaunchHook Ctx::hook() {
   return h;
 }
 
+hipGraphExec_t Ctx::find_graph(const std::string &key) {
+  for (auto &g : graphs)
+    if (g.key == key) return g.exec;
+  return nullptr;
+}
+
+void Ctx::keep_graph(const std::string &key, hipGraphExec_t exec) {
+  if (graphs.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(graphs.front().exec);
+    graphs.erase(graphs.begin());
+  }
+  graphs.push_back({key, exec});
+}
+
+void Ctx::drop_graphs() {
+  for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+  graphs.clear();
+}
+
 int Ctx::upload(const TableKey &key, const void *host, size_t bytes, hipStream_t s, void **out) {
   auto it = tables.find(key);
   if (it != tables.end()) {
     *out = it->second;
     return FR_OK;
   }
+  if (capturing) return FR_ESTATE;
   if (tables.size() >= kMaxTables) {
-    // bounded cache: drop everything once it is full (tables are cheap to rebuild)
+    // bounded cache: drop everything once it is full (tables are cheap to rebuild), and the
+    // graphs that reference them
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return record_hip(e);
+    drop_graphs();
     for (auto &kv : tables) (void)hipFree(kv.second);
     tables.clear();
   }
@@ -150,6 +174,27 @@ int Ctx::twiddles(int n, hipStream_t s, const float2 **out) {
   int st = upload(key, h.data(), h.size() * sizeof(float2), s, &d);
   *out = static_cast<const float2 *>(d);
   return st;
+}
+
+int Ctx::mr(int n, hipStream_t s, MrPlane *out) {
+  int np = 0, rad[kMrMaxPass];
+  if (!mr_plan(n, &np, rad)) return FR_EUNSUPPORTED;
+  TableKey key{kMrTw, n, 0, 0, 0, 0};
+  void *d = nullptr;
+  if (auto it = tables.find(key); it != tables.end()) {
+    d = it->second;
+  } else {
+    std::vector<float2> h(std::max(mr_twiddle_count(np, rad), 1));
+    mr_twiddle_build(np, rad, h.data());
+    int st = upload(key, h.data(), h.size() * sizeof(float2), s, &d);
+    if (st != FR_OK) return st;
+  }
+  out->n = n;
+  out->npass = np;
+  out->plan = mr_pack(np, rad);
+  out->tw = static_cast<const float2 *>(d);
+  out->first = 0;
+  return FR_OK;
 }
 
 // h[k] = exp(-i pi lambda z k~^2 / (n dx)^2) / n  (signed index k~; 1/n folds the IFFT scale)
@@ -310,13 +355,38 @@ int mft_adjoint_impl(Ctx *ctx, const float2 *in, int m_in, int ld_in, float2 *ou
   return e == hipSuccess ? FR_OK : record_hip(e);
 }
 
+bool plane_size_supported(int n) {
+  int np, rad[kMrMaxPass];
+  return fresnel_size_supported(n) || mr_plan(n, &np, rad);
+}
+
+// All planes share edge n (a power of two with a tuned register-resident plan): the two-sweep
+// kernels. Otherwise (mixed edges or a mixed-radix edge): the persistent mixed-radix kernels,
+// one launch per sweep for the whole batch.
 int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s) {
-  const float2 *root;
-  int st = ctx->twiddles(n, s, &root);
-  if (st != FR_OK) return st;
-  for (int i = 0; i < count; i += kMaxBatch) {
-    const int c = std::min(count - i, kMaxBatch);
-    hipError_t e = launch_fresnel_batch(args + i, c, n, root, s, ctx->hook(), ctx->sweep_variant(n));
+  bool uniform = fresnel_size_supported(n);
+  for (int i = 0; i < count && uniform; ++i) uniform = (args[i].n == n);
+  if (uniform) {
+    const float2 *root;
+    int st = ctx->twiddles(n, s, &root);
+    if (st != FR_OK) return st;
+    for (int i = 0; i < count; i += kMaxBatch) {
+      const int c = std::min(count - i, kMaxBatch);
+      hipError_t e = launch_fresnel_batch(args + i, c, n, root, s, ctx->hook(), ctx->sweep_variant(n));
+      if (e != hipSuccess) return record_hip(e);
+    }
+    return FR_OK;
+  }
+  for (int i = 0; i < count; i += kMrMaxBatch) {
+    MrBatch b;
+    b.count = std::min(count - i, kMrMaxBatch);
+    b.total = 0;
+    for (int k = 0; k < b.count; ++k) {
+      int st = ctx->mr(args[i + k].n, s, &b.p[k]);
+      if (st != FR_OK) return st;
+      b.p[k].pa = args[i + k];
+    }
+    hipError_t e = launch_mr_batch(b, ctx->cus * 4, ctx->cus, s, ctx->hook());
     if (e != hipSuccess) return record_hip(e);
   }
   return FR_OK;
@@ -342,6 +412,9 @@ int fr_create(fr_ctx **ctx, int device) {
   if (e != hipSuccess) return fr::record_hip(e);
   Ctx *c = new Ctx();
   c->device = device;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    c->cus = cus;
   *ctx = reinterpret_cast<fr_ctx *>(c);
   return FR_OK;
 }
@@ -358,6 +431,7 @@ const char *fr_status_string(int status) {
     case FR_EUNSUPPORTED: return "unsupported size or combination";
     case FR_EWORKSPACE: return "workspace missing or too small";
     case FR_ENOMEM: return "device allocation for a cached table failed";
+    case FR_ESTATE: return "a table was missing while a graph was being recorded";
     case FR_EHIP:
       g_status_text = std::string("HIP error: ") + hipGetErrorString(g_last_hip);
       return g_status_text.c_str();
@@ -367,14 +441,14 @@ const char *fr_status_string(int status) {
   }
 }
 
-int fr_fft_size_supported(int32_t n) { return fr::fresnel_size_supported(n) ? 1 : 0; }
+int fr_fft_size_supported(int32_t n) { return fr::plane_size_supported(n) ? 1 : 0; }
 
 static int check_plane(const fr_plane &p) {
   if (!p.field || p.n <= 0) return FR_EINVAL;
   if (!(p.dx_m > 0) || !(p.wavelength_m > 0) || !std::isfinite(p.z_m)) return FR_EINVAL;
   if (!std::isfinite(p.lens_focal_m)) return FR_EINVAL;
   if (p.flags & ~FR_ADJOINT) return FR_EINVAL;
-  if (!fr::fresnel_size_supported(p.n)) return FR_EUNSUPPORTED;
+  if (!fr::plane_size_supported(p.n)) return FR_EUNSUPPORTED;
   return FR_OK;
 }
 
@@ -391,7 +465,6 @@ int fresnel_step_batched(fr_ctx *ctx_, const fr_plane *planes, int32_t count, vo
   for (int i = 0; i < count; ++i) {
     int st = check_plane(planes[i]);
     if (st != FR_OK) return st;
-    if (planes[i].n != n) return FR_EINVAL;
     warn |= plane_warnings(planes[i]);
   }
   Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
@@ -407,13 +480,14 @@ int fresnel_step_batched(fr_ctx *ctx_, const fr_plane *planes, int32_t count, vo
     a.field = reinterpret_cast<float2 *>(p.field);
     a.amp = p.amp;
     a.opd = p.opd_m;
-    a.win = n;
+    a.n = p.n;
+    a.win = p.n;
     a.inv_lambda = float(1.0 / p.wavelength_m);
     a.flags = p.flags;
-    int st = ctx->transfer(n, p.dx_m, p.wavelength_m, p.z_m, s, &a.h);
+    int st = ctx->transfer(p.n, p.dx_m, p.wavelength_m, p.z_m, s, &a.h);
     if (st != FR_OK) return st;
     if (p.lens_focal_m != 0.0) {
-      st = ctx->lens(n, p.dx_m, p.wavelength_m, p.lens_focal_m, s, &a.lens);
+      st = ctx->lens(p.n, p.dx_m, p.wavelength_m, p.lens_focal_m, s, &a.lens);
       if (st != FR_OK) return st;
     }
   }

@@ -1,4 +1,5 @@
-// Register-resident small DFTs (radix 2, 3, 4, 5, 7, 8, 16) and compile-time twiddles.
+// Register-resident small DFTs (radix 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 15, 16) and
+// compile-time twiddles.
 //
 // These are the butterflies of the Cooley-Tukey FFT that the paper relies on for its
 // O(n log n) plane transforms (Sec. 1.2). Sign convention: forward kernel exp(-2 pi i nk/R).
@@ -255,6 +256,18 @@ struct DftComposite {
   }
 };
 
+template <>
+struct Dft<6> : DftComposite<2, 3> {};
+template <>
+struct Dft<9> : DftComposite<3, 3> {};
+template <>
+struct Dft<10> : DftComposite<2, 5> {};
+template <>
+struct Dft<12> : DftComposite<4, 3> {};
+template <>
+struct Dft<14> : DftComposite<2, 7> {};
+template <>
+struct Dft<15> : DftComposite<3, 5> {};
 template <>
 struct Dft<8> : DftComposite<2, 4> {};
 template <>

@@ -35,6 +35,7 @@ struct PlaneArgs {
   const float2 *h;           // n: exp(-i pi lambda z k^2/(n dx)^2) / n over signed index k
   const float2 *lens;        // n: exp(-i pi c^2 dx^2 / (lambda f)) or null
   float inv_lambda;          // 1 / lambda [1/m]
+  int n;                     // plane edge
   int win;                   // window edge of amp / opd (n for full maps)
   int flags;                 // FR_ADJOINT | kSourceOptic
 };
@@ -53,7 +54,32 @@ hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const
 int fresnel_variants(int n);
 int fresnel_twiddle_count(int n);
 void fresnel_twiddle_build(int n, float2 *out);  // host
-bool fresnel_size_supported(int n);
+bool fresnel_size_supported(int n);  // power-of-two edges with register-resident plans
+bool plane_size_supported(int n);    // those or any mixed-radix edge
+
+// ---- mixed-radix sweeps (any edge up to kMrMaxN that factors into radices <= 16) ----------
+constexpr int kMrMaxN = 4096;
+constexpr int kMrMaxPass = 6;
+constexpr int kMrThreads = 256;
+constexpr int kMrMaxBatch = 24;
+struct MrPlane {
+  PlaneArgs pa;
+  int n, npass, first;  // first: index of the plane's first work item (set by the launcher)
+  unsigned plan;        // radices, 5 bits per pass
+  const float2 *tw;     // mr_twiddle_build table of the plan
+};
+struct MrBatch {
+  int count, total;
+  MrPlane p[kMrMaxBatch];
+};
+bool mr_plan(int n, int *npass, int *radix);
+unsigned mr_pack(int npass, const int *radix);
+int mr_twiddle_count(int npass, const int *radix);
+void mr_twiddle_build(int npass, const int *radix, float2 *out);  // host
+// rows then columns for forward planes, columns then rows for adjoint planes; persistent
+// grids of at most blocks_rows / blocks_cols blocks
+hipError_t launch_mr_batch(const MrBatch &all, int blocks_rows, int blocks_cols, hipStream_t s,
+                           const LaunchHook &hook);
 
 // ---- MFT: out = alpha * c * A in B^T (+ beta * out) (* mask), complex, FP32 MFMA ------
 // Generic complex GEMM pieces used by the MFT entry points.

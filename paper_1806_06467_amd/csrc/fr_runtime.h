@@ -12,12 +12,13 @@
 
 namespace fr {
 
-enum TableKind : int { kRoots = 1, kTransfer, kLens, kMft, kDm };
+enum TableKind : int { kRoots = 1, kTransfer, kLens, kMft, kDm, kMrTw };
 // (kind, size, then up to four parameter words: sizes or the bits of float64 parameters)
 using TableKey = std::tuple<int, int, uint64_t, uint64_t, uint64_t, uint64_t>;
 
 struct Ctx {
   int device = 0;
+  int cus = 256;  // compute units of the device
   std::map<TableKey, void *> tables;
   static constexpr size_t kMaxTables = 4096;
 
@@ -34,10 +35,26 @@ struct Ctx {
   LaunchHook hook();
   int sweep_variant(int n) const;
 
+  // instantiated graphs of whole calls, keyed by every argument byte they bake in; dropped
+  // together with the tables they reference
+  struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  static constexpr size_t kMaxGraphs = 8;
+  hipStream_t capture_stream = nullptr;
+  bool capturing = false;  // table uploads are refused while a capture is open
+  hipGraphExec_t find_graph(const std::string &key);
+  void keep_graph(const std::string &key, hipGraphExec_t exec);
+  void drop_graphs();
+
   ~Ctx();
   // copy `bytes` of host data to a new cached device buffer (waits on `s` for the copy)
   int upload(const TableKey &key, const void *host, size_t bytes, hipStream_t s, void **out);
   int twiddles(int n, hipStream_t s, const float2 **out);
+  // mixed-radix plan of edge n (radices and device twiddle table); FR_EUNSUPPORTED if none
+  int mr(int n, hipStream_t s, MrPlane *out);
   int transfer(int n, double dx, double lam, double z, hipStream_t s, const float2 **out);
   int lens(int n, double dx, double lam, double f, hipStream_t s, const float2 **out);
   int mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out);

@@ -28,8 +28,9 @@ __device__ __forceinline__ c32 ld2(const float2 *p) {
 }
 
 // Raw buffer access to one plane: a 32-bit per-lane offset plus a wave-uniform offset held in a
-// scalar register, so that the sixteen strided accesses of a thread cost one address VGPR;
-// accesses beyond the plane's bytes read 0 and are not written (hardware bounds check).
+// scalar register, so that the sixteen strided accesses of a thread cost one address VGPR.
+// The hardware range check applies to the per-lane offset: lanes whose offset is past the
+// buffer read 0 and do not write; every per-lane offset used here is non-negative.
 // (The 64-bit results are moved whole with bit casts: extracting single elements of the
 // builtin's vector type was observed to address the wrong half.)
 struct PlaneBuf {
@@ -46,26 +47,95 @@ struct PlaneBuf {
   }
 };
 
-// pre optic at (y, x): amp * exp(2 pi i (opd + 2 pre_surf) / lambda) * lens[x] lens[y]
-__device__ __forceinline__ c32 pre_optic(const PlaneArgs &pa, int n, int y, int x) {
-  float a = 1.0f, turns = 0.0f;
-  if (pa.amp || pa.opd) {
-    const int off = (n - pa.win) >> 1;
-    const int wy = y - off, wx = x - off;
-    const bool in = unsigned(wy) < unsigned(pa.win) && unsigned(wx) < unsigned(pa.win);
-    const size_t o = size_t(wy) * pa.win + wx;
-    if (pa.amp) a = in ? pa.amp[o] : 0.0f;
-    if (pa.opd && in) turns = pa.opd[o] * pa.inv_lambda;
+// Same for float maps (amplitude, OPD, mirror surfaces).
+struct MapBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ MapBuf(const void *p, unsigned bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, int(bytes), 0x00020000)) {}
+  __device__ __forceinline__ float load(unsigned vo, unsigned so) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
   }
-  if (pa.pre_surf) turns += 2.0f * pa.pre_surf[size_t(y) * n + x] * pa.inv_lambda;
-  c32 ph = {a, 0.0f};
+};
+
+// The pre optic along one row y for the thread's slots x = t + T m: amplitude, OPD (win x win
+// maps centred in the plane), mirror surface (n x n) and thin lens. Returns false when the
+// amplitude is zero on the whole row (a row outside the pupil window).
+template <int E, int T>
+__device__ __forceinline__ bool pre_optic_row(const PlaneArgs &pa, int n, int y, int t, c32 (&ph)[E]) {
+  const int win = pa.win;
+  const int off = (n - win) >> 1;
+  const int wy = y - off;
+  const bool row_in = unsigned(wy) < unsigned(win);
+  if (pa.amp && !row_in) return false;
+  float a[E], turns[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    a[m] = 1.0f;
+    turns[m] = 0.0f;
+  }
+  if ((pa.amp || pa.opd) && row_in) {
+    // The hardware range check of a raw buffer access looks at the per-lane (VGPR) offset
+    // only, so every per-lane offset here is non-negative and inside the map: full maps use
+    // lane offset + per-slot scalar offset; windowed maps clamp the column into the window
+    // (lanes outside it are masked after the load).
+    const unsigned bytes = unsigned(win) * unsigned(win) * 4u;
+    unsigned vo[E], so[E];
+    if (win == n) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        vo[m] = unsigned(wy * win + t) * 4u;
+        so[m] = unsigned(T * m) * 4u;
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int wx = min(max(t + T * m - off, 0), win - 1);
+        vo[m] = unsigned(wy * win + wx) * 4u;
+        so[m] = 0u;
+      }
+    }
+    if (pa.amp) {
+      const MapBuf mb(pa.amp, bytes);
+#pragma unroll
+      for (int m = 0; m < E; ++m) a[m] = mb.load(vo[m], so[m]);
+    }
+    if (pa.opd) {
+      const MapBuf mb(pa.opd, bytes);
+#pragma unroll
+      for (int m = 0; m < E; ++m) turns[m] = mb.load(vo[m], so[m]) * pa.inv_lambda;
+    }
+    if (win < n) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const bool in = unsigned(t + T * m - off) < unsigned(win);
+        a[m] = in ? a[m] : (pa.amp ? 0.0f : 1.0f);
+        turns[m] = in ? turns[m] : 0.0f;
+      }
+    }
+  }
+  if (pa.pre_surf) {
+    const MapBuf sb(pa.pre_surf, unsigned(n) * unsigned(n) * 4u);
+    const unsigned vo = unsigned(y * n + t) * 4u;
+#pragma unroll
+    for (int m = 0; m < E; ++m) turns[m] += 2.0f * sb.load(vo, unsigned(T * m) * 4u) * pa.inv_lambda;
+  }
   if (pa.opd || pa.pre_surf) {
-    float s, c;
-    sincos_turns(turns, &s, &c);
-    ph = {a * c, a * s};
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      float sn, cs;
+      sincos_turns(turns[m], &sn, &cs);
+      ph[m] = {a[m] * cs, a[m] * sn};
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) ph[m] = {a[m], 0.0f};
   }
-  if (pa.lens) ph = cmul(ph, cmul(ld2(pa.lens + x), ld2(pa.lens + y)));
-  return ph;
+  if (pa.lens) {
+    const c32 ly = ld2(pa.lens + y);
+#pragma unroll
+    for (int m = 0; m < E; ++m) ph[m] = cmul(ph[m], cmul(ld2(pa.lens + t + T * m), ly));
+  }
+  return true;
 }
 
 // post optic at (y, x): exp(2 pi i 2 post_surf / lambda)
@@ -104,25 +174,48 @@ __global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const 
   const PlaneBuf buf(pa.field, unsigned(N) * N * 8u);
   const unsigned vo = unsigned(y * N + t) * 8u;
   c32 v[E];
-  if (pa.flags & kSourceOptic) {
+  if (!adj && has_pre(pa)) {
+    c32 ph[E];
+    const bool nonzero = pre_optic_row<E, T>(pa, N, y, t, ph);
+    if constexpr (LINES == 1) {
+      // a whole row outside the pupil stays zero through the row transform (block-uniform)
+      if (!nonzero) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = pre_optic(pa, N, y, t + T * m);
+        for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * 8u, c32{0.0f, 0.0f});
+        return;
+      }
+    }
+    if (!nonzero) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) ph[m] = {0.0f, 0.0f};
+    }
+    if (pa.flags & kSourceOptic) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = ph[m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cmul(buf.load(vo, unsigned(T * m) * 8u), ph[m]);
+    }
+  } else if (pa.flags & kSourceOptic) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = {1.0f, 0.0f};
   } else {
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = buf.load(vo, unsigned(T * m) * 8u);
-    if (!adj && has_pre(pa)) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = cmul(v[m], pre_optic(pa, N, y, t + T * m));
-    }
-    if (adj && pa.post_surf) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], post_optic(pa, N, y, t + T * m));
-    }
   }
   c32 *my = lds + line * LdsLine<N>::size;
   PL::forward(v, my, t, tw);
   freq_product<E, T>(v, pa.h, t, adj);
   PL::inverse(v, my, t, tw);
+  if (adj && has_pre(pa)) {
+    c32 ph[E];
+    if (!pre_optic_row<E, T>(pa, N, y, t, ph)) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) ph[m] = {0.0f, 0.0f};
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], ph[m]);
+  }
 #pragma unroll
   for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * 8u, v[m]);
 }
@@ -145,14 +238,14 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   c32 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = buf.load(vo, unsigned(T * m) * unsigned(N) * 8u);
+  if (adj && pa.post_surf) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], post_optic(pa, N, t + T * m, x));
+  }
   c32 *my = lds + c * (LdsLine<N>::size + 4);
   PL::forward(v, my, t, tw);
   freq_product<E, T>(v, pa.h, t, adj);
   PL::inverse(v, my, t, tw);
-  if (adj && has_pre(pa)) {
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], pre_optic(pa, N, t + T * m, x));
-  }
   if (!adj && pa.post_surf) {
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = cmul(v[m], post_optic(pa, N, t + T * m, x));
@@ -161,22 +254,37 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
 }
 
+// Forward planes run the row sweep first (optic prologue on contiguous rows) and the column
+// sweep second (mirror epilogue); adjoint planes run the column sweep first (conjugate mirror
+// prologue) and the row sweep second (conjugate optic epilogue). The two halves of the
+// angular-spectrum step commute, so only the placement of the optics sets the order, and the
+// amplitude/OPD maps are always read along rows.
 template <class PL, int ROW_LINES, int COL_LINES>
-hipError_t launch_sweeps(const BatchArgs &args, int count, const float2 *root, hipStream_t s,
-                         const LaunchHook &hook) {
+hipError_t launch_sweeps(const BatchArgs &fwd, int nf, const BatchArgs &adj, int na,
+                         const float2 *tw, hipStream_t s, const LaunchHook &hook) {
   constexpr int N = PL::N;
   static_assert(N % ROW_LINES == 0 && N % COL_LINES == 0, "tile must divide n");
-  hook(s, "row_sweep", N, 0);
-  hipLaunchKernelGGL((row_sweep<PL, ROW_LINES>), dim3(N / ROW_LINES, count),
-                     dim3(PL::T * ROW_LINES), 0, s, args, root);
-  hipError_t e = hipGetLastError();
-  hook(s, "row_sweep", N, 1);
-  if (e != hipSuccess) return e;
-  hook(s, "col_sweep", N, 0);
-  hipLaunchKernelGGL((col_sweep<PL, COL_LINES>), dim3(N / COL_LINES, count),
-                     dim3(PL::T * COL_LINES), 0, s, args, root);
-  e = hipGetLastError();
-  hook(s, "col_sweep", N, 1);
+  auto rows = [&](const BatchArgs &a, int count) {
+    hook(s, "row_sweep", N, 0);
+    hipLaunchKernelGGL((row_sweep<PL, ROW_LINES>), dim3(N / ROW_LINES, count),
+                       dim3(PL::T * ROW_LINES), 0, s, a, tw);
+    hipError_t e = hipGetLastError();
+    hook(s, "row_sweep", N, 1);
+    return e;
+  };
+  auto cols = [&](const BatchArgs &a, int count) {
+    hook(s, "col_sweep", N, 0);
+    hipLaunchKernelGGL((col_sweep<PL, COL_LINES>), dim3(N / COL_LINES, count),
+                       dim3(PL::T * COL_LINES), 0, s, a, tw);
+    hipError_t e = hipGetLastError();
+    hook(s, "col_sweep", N, 1);
+    return e;
+  };
+  hipError_t e = hipSuccess;
+  if (nf && (e = rows(fwd, nf)) != hipSuccess) return e;
+  if (nf && (e = cols(fwd, nf)) != hipSuccess) return e;
+  if (na && (e = cols(adj, na)) != hipSuccess) return e;
+  if (na && (e = rows(adj, na)) != hipSuccess) return e;
   return e;
 }
 
@@ -223,31 +331,57 @@ int fresnel_variants(int n) { return n == 4096 || n == 2048 || n == 8192 ? 3 : 1
 
 hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const float2 *root,
                                 hipStream_t s, const LaunchHook &hook, int variant) {
-  BatchArgs args;
-  for (int i = 0; i < count; ++i) args.p[i] = planes[i];
+  BatchArgs fwd, adj;
+  int nf = 0, na = 0;
+  for (int i = 0; i < count; ++i) {
+    if (planes[i].flags & FR_ADJOINT)
+      adj.p[na++] = planes[i];
+    else
+      fwd.p[nf++] = planes[i];
+  }
+#define FR_SWEEPS(PL, RL, CL) return launch_sweeps<PL, RL, CL>(fwd, nf, adj, na, root, s, hook)
   switch (n) {
-    case 64: return launch_sweeps<Plan<64, 8, 8, 8>, 8, 16>(args, count, root, s, hook);
-    case 128: return launch_sweeps<Plan<128, 16, 16, 8>, 16, 32>(args, count, root, s, hook);
-    case 256: return launch_sweeps<Plan<256, 16, 16, 16>, 16, 32>(args, count, root, s, hook);
-    case 512: return launch_sweeps<Plan<512, 8, 8, 8, 8>, 4, 16>(args, count, root, s, hook);
-    case 1024: return launch_sweeps<Plan<1024, 16, 16, 8, 8>, 4, 8>(args, count, root, s, hook);
-    case 2048:
+    case 64: {
+      using P = Plan<64, 8, 8, 8>;
+      FR_SWEEPS(P, 8, 16);
+    }
+    case 128: {
+      using P = Plan<128, 16, 16, 8>;
+      FR_SWEEPS(P, 16, 32);
+    }
+    case 256: {
+      using P = Plan<256, 16, 16, 16>;
+      FR_SWEEPS(P, 16, 32);
+    }
+    case 512: {
+      using P = Plan<512, 8, 8, 8, 8>;
+      FR_SWEEPS(P, 4, 16);
+    }
+    case 1024: {
+      using P = Plan<1024, 16, 16, 8, 8>;
+      FR_SWEEPS(P, 4, 8);
+    }
+    case 2048: {
       using P2 = Plan<2048, 16, 16, 16, 8>;
-      if (variant == 1) return launch_sweeps<P2, 2, 4>(args, count, root, s, hook);
-      if (variant == 2) return launch_sweeps<P2, 4, 4>(args, count, root, s, hook);
-      return launch_sweeps<P2, 2, 8>(args, count, root, s, hook);
-    case 4096:
+      if (variant == 1) FR_SWEEPS(P2, 2, 4);
+      if (variant == 2) FR_SWEEPS(P2, 4, 4);
+      FR_SWEEPS(P2, 2, 8);
+    }
+    case 4096: {
       using P4 = Plan<4096, 16, 16, 16, 16>;
-      if (variant == 1) return launch_sweeps<P4, 1, 2>(args, count, root, s, hook);
-      if (variant == 2) return launch_sweeps<P4, 2, 2>(args, count, root, s, hook);
-      return launch_sweeps<P4, 1, 4>(args, count, root, s, hook);
-    case 8192:
+      if (variant == 1) FR_SWEEPS(P4, 1, 2);
+      if (variant == 2) FR_SWEEPS(P4, 2, 2);
+      FR_SWEEPS(P4, 1, 4);
+    }
+    case 8192: {
       using P8 = Plan<8192, 16, 16, 16, 16, 2>;
-      if (variant == 1) return launch_sweeps<P8, 1, 1>(args, count, root, s, hook);
-      if (variant == 2) return launch_sweeps<P8, 2, 1>(args, count, root, s, hook);
-      return launch_sweeps<P8, 1, 2>(args, count, root, s, hook);
+      if (variant == 1) FR_SWEEPS(P8, 1, 1);
+      if (variant == 2) FR_SWEEPS(P8, 2, 1);
+      FR_SWEEPS(P8, 1, 2);
+    }
     default: return hipErrorInvalidValue;
   }
+#undef FR_SWEEPS
 }
 
 }  // namespace fr

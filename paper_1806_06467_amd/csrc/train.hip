@@ -164,24 +164,59 @@ hipError_t launch1d(K kern, size_t work, hipStream_t s, const LaunchHook &hook, 
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Workspace layout. Plain mode: one field plane E (and one adjoint plane B) of the largest
+// grid, reused wavelength after wavelength. Batched mode: one E plane per wavelength (and one B
+// plane per wavelength when the pupil DM needs the adjoint Fresnel step), so that the Fresnel
+// steps of all wavelengths run in one launch per sweep. DM surface maps: one set per distinct
+// grid edge in batched mode, one set (rebuilt on a change of edge) in plain mode.
 struct Layout {
-  size_t e, b, gs, surf, tdm, el, y1, eocc, edet, ydet, mft, total;
+  std::vector<size_t> e, b;          // per wavelength (plain: all equal)
+  std::vector<int> surf_n;           // distinct grid edges with a surface set
+  std::vector<size_t> surf;          // offsets of those sets (n_dm maps each)
+  size_t gs, tdm, el, y1, eocc, edet, ydet, mft, total;
 };
 
-Layout layout(const fr_train_desc *d, int nmax, bool grad) {
+Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_t mode) {
   Layout L;
+  const bool grad = (mode & FR_TRAIN_GRAD) != 0;
+  const bool batched = (mode & FR_TRAIN_BATCHED) != 0;
+  int nmax = 0;
+  for (int j = 0; j < n_lambda; ++j) nmax = std::max(nmax, int(n_pad[j]));
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
     off += align256(bytes);
     return o;
   };
-  const size_t n2 = size_t(nmax) * nmax;
+  const size_t n2max = size_t(nmax) * nmax;
   const size_t nd2 = size_t(d->n_d) * d->n_d;
-  L.e = take(n2 * 8);
-  L.b = grad ? take(n2 * 8) : 0;
-  L.gs = grad ? take(n2 * 4) : 0;
-  L.surf = take(size_t(std::max(d->n_dm, 1)) * n2 * 4);
+  const bool b_per_lambda = batched && grad && d->n_dm == 2;
+  L.e.resize(n_lambda);
+  L.b.assign(n_lambda, 0);
+  if (batched) {
+    for (int j = 0; j < n_lambda; ++j) L.e[j] = take(size_t(n_pad[j]) * n_pad[j] * 8);
+  } else {
+    const size_t e0 = take(n2max * 8);
+    for (int j = 0; j < n_lambda; ++j) L.e[j] = e0;
+  }
+  if (b_per_lambda) {
+    for (int j = 0; j < n_lambda; ++j) L.b[j] = take(size_t(n_pad[j]) * n_pad[j] * 8);
+  } else if (grad) {
+    const size_t b0 = take(n2max * 8);
+    for (int j = 0; j < n_lambda; ++j) L.b[j] = b0;
+  }
+  L.gs = grad ? take(n2max * 4) : 0;
+  const size_t ndm = size_t(std::max(d->n_dm, 1));
+  if (batched) {
+    for (int j = 0; j < n_lambda; ++j)
+      if (std::find(L.surf_n.begin(), L.surf_n.end(), int(n_pad[j])) == L.surf_n.end()) {
+        L.surf_n.push_back(n_pad[j]);
+        L.surf.push_back(take(ndm * size_t(n_pad[j]) * n_pad[j] * 4));
+      }
+  } else {
+    L.surf_n.push_back(0);
+    L.surf.push_back(take(ndm * n2max * 4));
+  }
   L.tdm = take(size_t(std::max(d->n_act, 1)) * nmax * 4);
   L.el = take(nd2 * 8);
   L.y1 = grad ? take(nd2 * 8) : 0;
@@ -199,7 +234,7 @@ Layout layout(const fr_train_desc *d, int nmax, bool grad) {
 int check_desc(const fr_train_desc *d, int32_t n_lambda, const double *lam, const int32_t *n_pad,
                const float *w, int32_t mode) {
   if (!d || n_lambda <= 0 || !lam || !n_pad || !w) return FR_EINVAL;
-  if (mode & ~(FR_TRAIN_NO_OCCULTER | FR_TRAIN_GRAD)) return FR_EINVAL;
+  if (mode & ~(FR_TRAIN_NO_OCCULTER | FR_TRAIN_GRAD | FR_TRAIN_BATCHED | FR_TRAIN_GRAPH)) return FR_EINVAL;
   if (d->n_d <= 0 || !(d->d_m > 0) || !d->pupil_amp) return FR_EINVAL;
   if (d->n_dm < 0 || d->n_dm > 2) return FR_EINVAL;
   if (d->n_dm > 0 && (d->n_act <= 0 || !d->dm_heights_m)) return FR_EINVAL;
@@ -211,7 +246,7 @@ int check_desc(const fr_train_desc *d, int32_t n_lambda, const double *lam, cons
   for (int j = 0; j < n_lambda; ++j) {
     if (!(lam[j] > 0) || !std::isfinite(w[j])) return FR_EINVAL;
     if (n_pad[j] < d->n_d || ((n_pad[j] - d->n_d) & 1)) return FR_EINVAL;
-    if (!fresnel_size_supported(n_pad[j])) return FR_EUNSUPPORTED;
+    if (!plane_size_supported(n_pad[j])) return FR_EUNSUPPORTED;
   }
   return FR_OK;
 }
@@ -220,10 +255,10 @@ int check_desc(const fr_train_desc *d, int32_t n_lambda, const double *lam, cons
 
 size_t train_workspace_bytes(const fr_train_desc *d, int32_t n_lambda, const int32_t *n_pad, int32_t mode) {
   if (!d || n_lambda <= 0 || !n_pad) return 0;
-  int nmax = 0;
-  for (int j = 0; j < n_lambda; ++j) nmax = std::max(nmax, int(n_pad[j]));
-  if (nmax <= 0 || d->n_d <= 0 || d->occ_m <= 0 || d->det_m <= 0) return 0;
-  return layout(d, nmax, (mode & FR_TRAIN_GRAD) != 0).total;
+  for (int j = 0; j < n_lambda; ++j)
+    if (n_pad[j] <= 0) return 0;
+  if (d->n_d <= 0 || d->occ_m <= 0 || d->det_m <= 0) return 0;
+  return layout(d, n_lambda, n_pad, mode).total;
 }
 
 int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *lam,
@@ -239,20 +274,17 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return record_hip(e);
 
-  int nmax = 0;
-  for (int j = 0; j < n_lambda; ++j) nmax = std::max(nmax, int(n_pad[j]));
-  const Layout L = layout(d, nmax, grad);
+  const bool batched = (mode & FR_TRAIN_BATCHED) != 0;
+  const Layout L = layout(d, n_lambda, n_pad, mode);
   char *base = static_cast<char *>(ws);
-  float2 *E = reinterpret_cast<float2 *>(base + L.e);
-  float2 *B = grad ? reinterpret_cast<float2 *>(base + L.b) : nullptr;
+  auto c64at = [&](size_t o) { return reinterpret_cast<float2 *>(base + o); };
   float *GS = grad ? reinterpret_cast<float *>(base + L.gs) : nullptr;
-  float *SURF = reinterpret_cast<float *>(base + L.surf);
   float *TDM = reinterpret_cast<float *>(base + L.tdm);
-  float2 *EL = reinterpret_cast<float2 *>(base + L.el);
-  float2 *Y1 = grad ? reinterpret_cast<float2 *>(base + L.y1) : nullptr;
-  float2 *EOCC = reinterpret_cast<float2 *>(base + L.eocc);
-  float2 *EDET = reinterpret_cast<float2 *>(base + L.edet);
-  float2 *YDET = grad ? reinterpret_cast<float2 *>(base + L.ydet) : nullptr;
+  float2 *EL = c64at(L.el);
+  float2 *Y1 = grad ? c64at(L.y1) : nullptr;
+  float2 *EOCC = c64at(L.eocc);
+  float2 *EDET = c64at(L.edet);
+  float2 *YDET = grad ? c64at(L.ydet) : nullptr;
   void *MWS = base + L.mft;
   const LaunchHook hook = ctx->hook();
   const int nd = d->n_d, na = d->n_act, ndm = d->n_dm;
@@ -270,53 +302,61 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     if (_s != FR_OK) return _s; \
   } while (0)
 
-  FR_TRY_HIP(launch1d(fill_f32, det2, s, hook, "fill", psf, det2, 0.f));
-  if (grad) {
-    const size_t ng = size_t(ndm) * na * na;
-    FR_TRY_HIP(launch1d(fill_f32, ng, s, hook, "fill", grad_heights, ng, 0.f));
-  }
-
-  int surf_n = -1;
-  for (int j = 0; j < n_lambda; ++j) {
-    const int n = n_pad[j];
-    const double lamj = lam[j];
-    const size_t n2 = size_t(n) * n;
-    const double du_occ = d->occ_du_c * d->lambda_c_m / lamj;
-    const double du_det = d->det_du_c * d->lambda_c_m / lamj;
-    const float inv_l = float(1.0 / lamj);
-
-    // DM surfaces s = G A G^T on this grid (a8), rebuilt when the grid edge changes
+  // DM surfaces s = G A G^T on an n grid (a8): TDM (na x n) = A G^T ; SURF_k (n x n) = G TDM
+  auto surfaces = [&](int n, float *surf) -> int {
     const float *G = nullptr;
-    if (ndm > 0) {
-      FR_TRY(ctx->dm_influence(n, nd, na, s, &G));
-      if (surf_n != n) {
-        for (int k = 0; k < ndm; ++k) {
-          // TDM (na x n) = A G^T ; SURF_k (n x n) = G TDM
-          RGemm g1{na, n, na, d->dm_heights_m + size_t(k) * na * na, na, 0, G, na, 1, TDM, n, 1.f, 0.f};
-          FR_TRY_HIP(rgemm(g1, s, hook));
-          RGemm g2{n, n, na, G, na, 0, TDM, n, 0, SURF + size_t(k) * n2, n, 1.f, 0.f};
-          FR_TRY_HIP(rgemm(g2, s, hook));
-        }
-        surf_n = n;
-      }
+    FR_TRY(ctx->dm_influence(n, nd, na, s, &G));
+    const size_t n2 = size_t(n) * n;
+    for (int k = 0; k < ndm; ++k) {
+      RGemm g1{na, n, na, d->dm_heights_m + size_t(k) * na * na, na, 0, G, na, 1, TDM, n, 1.f, 0.f};
+      FR_TRY_HIP(rgemm(g1, s, hook));
+      RGemm g2{n, n, na, G, na, 0, TDM, n, 0, surf + size_t(k) * n2, n, 1.f, 0.f};
+      FR_TRY_HIP(rgemm(g2, s, hook));
     }
-    const float *surf_pre = ndm == 2 ? SURF : nullptr;
-    const float *surf_post = ndm >= 1 ? SURF + size_t(ndm - 1) * n2 : nullptr;
+    return FR_OK;
+  };
+  auto surf_of = [&](int j) -> float * {
+    if (!batched) return reinterpret_cast<float *>(base + L.surf[0]);
+    const size_t i = std::find(L.surf_n.begin(), L.surf_n.end(), int(n_pad[j])) - L.surf_n.begin();
+    return reinterpret_cast<float *>(base + L.surf[i]);
+  };
 
-    // ---- forward -------------------------------------------------------------------------
-    PlaneArgs pa;
-    std::memset(&pa, 0, sizeof pa);
-    pa.field = E;
-    pa.amp = d->pupil_amp;
-    pa.opd = d->pupil_opd_m;
-    pa.win = nd;
-    pa.pre_surf = surf_pre;
-    pa.post_surf = surf_post;
-    pa.inv_lambda = inv_l;
-    pa.flags = kSourceOptic;
-    FR_TRY(ctx->transfer(n, dx, lamj, d->z_m, s, &pa.h));
-    FR_TRY(run_planes(ctx, &pa, 1, n, s));                       // E = E_dm (a1, a2)
+  // forward Fresnel plane of wavelength j: pupil optic (and DM1) synthesised in the row
+  // prologue, step z, last-DM phasor in the column epilogue (a1, a2)
+  auto fwd_plane = [&](int j, PlaneArgs *pa) -> int {
+    const int n = n_pad[j];
+    const float *surf = surf_of(j);
+    std::memset(pa, 0, sizeof *pa);
+    pa->field = c64at(L.e[j]);
+    pa->n = n;
+    pa->amp = d->pupil_amp;
+    pa->opd = d->pupil_opd_m;
+    pa->win = nd;
+    pa->pre_surf = ndm == 2 ? surf : nullptr;
+    pa->post_surf = ndm >= 1 ? surf + size_t(ndm - 1) * n * n : nullptr;
+    pa->inv_lambda = float(1.0 / lam[j]);
+    pa->flags = kSourceOptic;
+    return ctx->transfer(n, dx, lam[j], d->z_m, s, &pa->h);
+  };
+  // adjoint Fresnel plane of wavelength j on B_j: conj(last-DM phasor), then AS_{-z}
+  auto adj_plane = [&](int j, PlaneArgs *pb) -> int {
+    const int n = n_pad[j];
+    std::memset(pb, 0, sizeof *pb);
+    pb->field = c64at(L.b[j]);
+    pb->n = n;
+    pb->post_surf = surf_of(j) + size_t(ndm - 1) * n * n;
+    pb->inv_lambda = float(1.0 / lam[j]);
+    pb->win = n;
+    pb->flags = FR_ADJOINT;
+    return ctx->transfer(n, dx, lam[j], d->z_m, s, &pb->h);
+  };
 
+  // occulter, Babinet subtraction, Lyot stop, detector; psf += w_j |Ed|^2 (a3, a4, a5)
+  auto focal_chain = [&](int j) -> int {
+    const int n = n_pad[j];
+    const float2 *E = c64at(L.e[j]);
+    const double du_occ = d->occ_du_c * d->lambda_c_m / lam[j];
+    const double du_det = d->det_du_c * d->lambda_c_m / lam[j];
     const int off = (n - nd) / 2;
     const float2 *Ewin = E + size_t(off) * n + off;
     if (occ) {
@@ -324,24 +364,40 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       o.out = EOCC;
       o.ld_out = d->occ_m;
       o.mask = d->occ_mask;
-      FR_TRY(mft_forward_impl(ctx, E, n, n, d->occ_m, double(nd), du_occ, o, MWS, s));   // a3
+      FR_TRY(mft_forward_impl(ctx, E, n, n, d->occ_m, double(nd), du_occ, o, MWS, s));
       FR_TRY(mft_adjoint_impl(ctx, EOCC, d->occ_m, d->occ_m, EL, nd, nd, double(nd), du_occ,
-                              -1.f, 1.f, Ewin, n, d->lyot, MWS, s));                       // a4
+                              -1.f, 1.f, Ewin, n, d->lyot, MWS, s));
     } else {
-      FR_TRY_HIP(launch1d(window_mask, size_t(nd) * nd, s, hook, "window_mask", (const float2 *)E, n, nd,
-                          d->lyot, EL));
+      FR_TRY_HIP(launch1d(window_mask, size_t(nd) * nd, s, hook, "window_mask", E, n, nd, d->lyot, EL));
     }
-    {
-      MftOut o;
-      o.out = EDET;
-      o.ld_out = d->det_m;
-      o.intensity = psf;
-      o.weight = weight[j];
-      FR_TRY(mft_forward_impl(ctx, EL, nd, nd, d->det_m, double(nd), du_det, o, MWS, s));  // a3, a5
-    }
-    if (!grad) continue;
+    MftOut o;
+    o.out = EDET;
+    o.ld_out = d->det_m;
+    o.intensity = psf;
+    o.weight = weight[j];
+    return mft_forward_impl(ctx, EL, nd, nd, d->det_m, double(nd), du_det, o, MWS, s);
+  };
 
-    // ---- backward (a7) ------------------------------------------------------------------
+  // dL/dA_k += G^T (g_s G) for the surface-gradient plane GS on an n grid
+  auto to_actuators = [&](int n, float *gA) -> int {
+    const float *G = nullptr;
+    FR_TRY(ctx->dm_influence(n, nd, na, s, &G));
+    RGemm g1{n, na, n, GS, n, 0, G, na, 0, TDM, na, 1.f, 0.f};   // TDM (n x na) = g_s G
+    FR_TRY_HIP(rgemm(g1, s, hook));
+    RGemm g2{na, na, n, G, na, 1, TDM, na, 0, gA, na, 1.f, 1.f};  // gA += G^T TDM
+    FR_TRY_HIP(rgemm(g2, s, hook));
+    return FR_OK;
+  };
+
+  // backward of the focal chain to the last DM: B_j = dL/dconj(E_dm); then the last DM's
+  // gradient g_s = -2 kappa Im(E_dm conj(B)) (a7)
+  auto back_to_last_dm = [&](int j) -> int {
+    const int n = n_pad[j];
+    const size_t n2 = size_t(n) * n;
+    const float2 *E = c64at(L.e[j]);
+    float2 *B = c64at(L.b[j]);
+    const double du_occ = d->occ_du_c * d->lambda_c_m / lam[j];
+    const double du_det = d->det_du_c * d->lambda_c_m / lam[j];
     FR_TRY_HIP(launch1d(scale_by_grad, det2, s, hook, "scale_by_grad", grad_psf, weight[j],
                         (const float2 *)EDET, YDET, det2));
     FR_TRY(mft_adjoint_impl(ctx, YDET, d->det_m, d->det_m, Y1, nd, nd, double(nd), du_det, 1.f, 0.f,
@@ -358,39 +414,140 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       FR_TRY_HIP(launch1d(fill_c64, n2, s, hook, "fill", B, n2));
     }
     FR_TRY_HIP(launch1d(window_add, size_t(nd) * nd, s, hook, "window_add", B, n, nd, (const float2 *)Y1));
-    const float kappa = float(4.0 * M_PI / lamj);
-    // last DM: g_s = -2 kappa Im(E_dm conj(B)); dL/dA += G^T (g_s G)
-    FR_TRY_HIP(launch1d(phase_grad, n2, s, hook, "phase_grad", (const float2 *)E, (const float2 *)B, GS, n,
-                        kappa, (const float *)nullptr, (const float *)nullptr, nd, (const float *)nullptr,
-                        inv_l));
-    float *gA = grad_heights + size_t(ndm - 1) * na * na;
-    {
-      RGemm g1{n, na, n, GS, n, 0, G, na, 0, TDM, na, 1.f, 0.f};   // TDM (n x na) = g_s G
-      FR_TRY_HIP(rgemm(g1, s, hook));
-      RGemm g2{na, na, n, G, na, 1, TDM, na, 0, gA, na, 1.f, 1.f};  // gA += G^T TDM
-      FR_TRY_HIP(rgemm(g2, s, hook));
+    const float kappa = float(4.0 * M_PI / lam[j]);
+    FR_TRY_HIP(launch1d(phase_grad, n2, s, hook, "phase_grad", E, (const float2 *)B, GS, n, kappa,
+                        (const float *)nullptr, (const float *)nullptr, nd, (const float *)nullptr,
+                        float(1.0 / lam[j])));
+    return to_actuators(n, grad_heights + size_t(ndm - 1) * na * na);
+  };
+  // pupil DM (n_dm == 2), after B_j went back through the adjoint step:
+  // g_s1 = -2 kappa Im(E_dm1 conj(B1)), E_dm1 = pupil optic * DM1 phasor synthesised again
+  auto back_to_pupil_dm = [&](int j) -> int {
+    const int n = n_pad[j];
+    const float kappa = float(4.0 * M_PI / lam[j]);
+    FR_TRY_HIP(launch1d(phase_grad, size_t(n) * n, s, hook, "phase_grad", (const float2 *)nullptr,
+                        (const float2 *)c64at(L.b[j]), GS, n, kappa, d->pupil_amp, d->pupil_opd_m, nd,
+                        (const float *)surf_of(j), float(1.0 / lam[j])));
+    return to_actuators(n, grad_heights);
+  };
+
+  FR_TRY_HIP(launch1d(fill_f32, det2, s, hook, "fill", psf, det2, 0.f));
+  if (grad) {
+    const size_t ng = size_t(ndm) * na * na;
+    FR_TRY_HIP(launch1d(fill_f32, ng, s, hook, "fill", grad_heights, ng, 0.f));
+  }
+
+  if (!batched) {
+    // plain: wavelength after wavelength, one plane at a time
+    int surf_n = -1;
+    for (int j = 0; j < n_lambda; ++j) {
+      if (ndm > 0 && surf_n != n_pad[j]) {
+        FR_TRY(surfaces(n_pad[j], surf_of(j)));
+        surf_n = n_pad[j];
+      }
+      PlaneArgs pa;
+      FR_TRY(fwd_plane(j, &pa));
+      FR_TRY(run_planes(ctx, &pa, 1, n_pad[j], s));
+      FR_TRY(focal_chain(j));
+      if (!grad) continue;
+      FR_TRY(back_to_last_dm(j));
+      if (ndm == 2) {
+        PlaneArgs pb;
+        FR_TRY(adj_plane(j, &pb));
+        FR_TRY(run_planes(ctx, &pb, 1, n_pad[j], s));
+        FR_TRY(back_to_pupil_dm(j));
+      }
     }
-    if (ndm == 2) {
-      // B1 = AS_{-z}( conj(DM2 phasor) B ); g_s1 = -2 kappa Im(E_dm1 conj(B1))
-      PlaneArgs pb;
-      std::memset(&pb, 0, sizeof pb);
-      pb.field = B;
-      pb.post_surf = surf_post;
-      pb.inv_lambda = inv_l;
-      pb.win = n;
-      pb.h = pa.h;
-      pb.flags = FR_ADJOINT;
-      FR_TRY(run_planes(ctx, &pb, 1, n, s));
-      FR_TRY_HIP(launch1d(phase_grad, n2, s, hook, "phase_grad", (const float2 *)nullptr, (const float2 *)B,
-                          GS, n, kappa, d->pupil_amp, d->pupil_opd_m, nd, (const float *)SURF, inv_l));
-      RGemm g1{n, na, n, GS, n, 0, G, na, 0, TDM, na, 1.f, 0.f};
-      FR_TRY_HIP(rgemm(g1, s, hook));
-      RGemm g2{na, na, n, G, na, 1, TDM, na, 0, grad_heights, na, 1.f, 1.f};
-      FR_TRY_HIP(rgemm(g2, s, hook));
+  } else {
+    // batched: the Fresnel planes of all wavelengths in one launch per sweep; the focal
+    // chains and gradient sums still run in wavelength order (identical results)
+    if (ndm > 0)
+      for (size_t i = 0; i < L.surf_n.size(); ++i)
+        FR_TRY(surfaces(L.surf_n[i], reinterpret_cast<float *>(base + L.surf[i])));
+    std::vector<PlaneArgs> planes(n_lambda);
+    for (int j = 0; j < n_lambda; ++j) FR_TRY(fwd_plane(j, &planes[j]));
+    FR_TRY(run_planes(ctx, planes.data(), n_lambda, n_pad[0], s));
+    for (int j = 0; j < n_lambda; ++j) {
+      FR_TRY(focal_chain(j));
+      if (grad) FR_TRY(back_to_last_dm(j));
+    }
+    if (grad && ndm == 2) {
+      for (int j = 0; j < n_lambda; ++j) FR_TRY(adj_plane(j, &planes[j]));
+      FR_TRY(run_planes(ctx, planes.data(), n_lambda, n_pad[0], s));
+      for (int j = 0; j < n_lambda; ++j) FR_TRY(back_to_pupil_dm(j));
     }
   }
 #undef FR_TRY
 #undef FR_TRY_HIP
+  return FR_OK;
+}
+
+
+// Graph mode: the whole call (every launch of every wavelength) as one instantiated graph,
+// replayed when a later call bakes in the same argument bytes. The first call with new
+// arguments runs eagerly (which also builds every table the graph reads), then captures the
+// same launch sequence on the context's own stream.
+std::string graph_key(const fr_train_desc *d, int32_t n_lambda, const double *lam, const int32_t *n_pad,
+                      const float *w, int32_t mode, const void *psf, const void *gpsf, const void *gh,
+                      const void *ws, size_t ws_bytes, hipStream_t s) {
+  std::string k;
+  auto put = [&](const void *p, size_t b) { k.append(static_cast<const char *>(p), b); };
+  put(d, sizeof *d);
+  put(&n_lambda, sizeof n_lambda);
+  put(lam, sizeof(double) * n_lambda);
+  put(n_pad, sizeof(int32_t) * n_lambda);
+  put(w, sizeof(float) * n_lambda);
+  put(&mode, sizeof mode);
+  const void *ptrs[5] = {psf, gpsf, gh, ws, s};
+  put(ptrs, sizeof ptrs);
+  put(&ws_bytes, sizeof ws_bytes);
+  return k;
+}
+
+int train_call(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *lam,
+               const int32_t *n_pad, const float *w, int32_t mode, float *psf, const float *gpsf,
+               float *gh, void *ws, size_t ws_bytes, hipStream_t s) {
+  if (!(mode & FR_TRAIN_GRAPH) || !ctx)
+    return train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
+  int st = check_desc(d, n_lambda, lam, n_pad, w, mode);
+  if (st != FR_OK) return st;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return record_hip(e);
+  const std::string key = graph_key(d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
+  if (hipGraphExec_t g = ctx->find_graph(key)) {
+    const LaunchHook hook = ctx->hook();
+    hook(s, "train_graph", n_lambda, 0);
+    e = hipGraphLaunch(g, s);
+    hook(s, "train_graph", n_lambda, 1);
+    return record_hip(e);
+  }
+  st = train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
+  if (st != FR_OK) return st;
+  if (!ctx->capture_stream) {
+    e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return record_hip(e);
+  }
+  hipStream_t cs = ctx->capture_stream;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return record_hip(e);
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;
+  ctx->capturing = true;
+  const int cap = train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, cs);
+  ctx->capturing = false;
+  ctx->profiling = prof;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  if (cap != FR_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return cap != FR_OK ? cap : record_hip(e);
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return record_hip(e);
+  ctx->keep_graph(key, exec);
   return FR_OK;
 }
 
@@ -407,7 +564,7 @@ int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda, co
                     const int32_t *n_pad, const float *weight, int32_t mode, float *psf,
                     const float *grad_psf, float *grad_heights, void *ws, size_t ws_bytes,
                     void *stream) {
-  return fr::train_run(reinterpret_cast<fr::Ctx *>(ctx), desc, n_lambda, lambda_m, n_pad, weight, mode,
-                       psf, grad_psf, grad_heights, ws, ws_bytes, static_cast<hipStream_t>(stream));
+  return fr::train_call(reinterpret_cast<fr::Ctx *>(ctx), desc, n_lambda, lambda_m, n_pad, weight, mode,
+                        psf, grad_psf, grad_heights, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 }

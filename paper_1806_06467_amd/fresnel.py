@@ -22,11 +22,14 @@ FR_EUNSUPPORTED = -2
 FR_EWORKSPACE = -3
 FR_EHIP = -4
 FR_ENOMEM = -5
+FR_ESTATE = -6
 FR_W_AS_UNDERSAMPLED = 1
 FR_W_MFT_ALIASED = 2
 FR_ADJOINT = 1
 FR_TRAIN_NO_OCCULTER = 1
 FR_TRAIN_GRAD = 2
+FR_TRAIN_BATCHED = 4
+FR_TRAIN_GRAPH = 8
 
 _c = ctypes
 _vp = _c.c_void_p
@@ -206,11 +209,11 @@ def fresnel_step(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, a
 
 def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens_focals=None,
                          adjoints=None, stream=None):
-    """Many planes of one edge in one launch per sweep; per-plane sequences (or scalars)."""
+    """Many planes in one launch per sweep; per-plane sequences (or scalars). Planes may have
+    different edges (then every plane goes through the mixed-radix sweeps)."""
     count = len(fields)
     if count == 0:
         raise ValueError("empty batch")
-    n = fields[0].shape[0]
 
     def seq(v, default):
         if v is None:
@@ -226,6 +229,7 @@ def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens
     lf, adj = seq(lens_focals, 0.0), seq(adjoints, False)
     arr = (FrPlane * count)()
     for i, f in enumerate(fields):
+        n = f.shape[0] if f.dim() == 2 else -1
         _need(f, torch.complex64, (n, n), f"fields[{i}]")
         for t, nm in ((amps[i], "amp"), (opds[i], "opd")):
             if t is not None:
@@ -354,22 +358,34 @@ class Train:
 
 
 def propagate_train(train, wavelengths, n_pad, weights, heights=None, occulter=True,
-                    grad_psf=None, stream=None):
+                    grad_psf=None, batched=False, graph=False, out=None, grad_out=None,
+                    stream=None):
     """Broadband PSF (det_m x det_m float32) of the train; with grad_psf = dL/dPSF also returns
-    dL/dheights (n_dm x n_act x n_act float32)."""
+    dL/dheights (n_dm x n_act x n_act float32).
+
+    batched: the Fresnel planes of all wavelengths in one launch per sweep (one plane per
+    wavelength held in the workspace; same results).
+    graph: the library records the whole call as one graph and replays it on later calls with
+    the same arguments, which includes the addresses of heights, grad_psf, the outputs and the
+    workspace; pass out= / grad_out= (and keep heights in place) so that they stay fixed."""
     dev = train.pupil_amp.device.index
     nl = len(wavelengths)
     if len(n_pad) != nl or len(weights) != nl:
         raise ValueError("wavelengths, n_pad and weights must have one entry per wavelength")
     if train.n_dm:
         _need(heights, torch.float32, (train.n_dm, train.n_act, train.n_act), "heights")
-    mode = 0 if occulter else FR_TRAIN_NO_OCCULTER
+    mode = ((0 if occulter else FR_TRAIN_NO_OCCULTER) | (FR_TRAIN_BATCHED if batched else 0)
+            | (FR_TRAIN_GRAPH if graph else 0))
     gh = None
     if grad_psf is not None:
         _need(grad_psf, torch.float32, (train.det_m, train.det_m), "grad_psf")
         mode |= FR_TRAIN_GRAD
-        gh = torch.empty((train.n_dm, train.n_act, train.n_act), dtype=torch.float32,
-                         device=train.pupil_amp.device)
+        if grad_out is not None:
+            _need(grad_out, torch.float32, (train.n_dm, train.n_act, train.n_act), "grad_out")
+            gh = grad_out
+        else:
+            gh = torch.empty((train.n_dm, train.n_act, train.n_act), dtype=torch.float32,
+                             device=train.pupil_amp.device)
     lam = (_c.c_double * nl)(*[float(x) for x in wavelengths])
     npd = (_c.c_int32 * nl)(*[int(x) for x in n_pad])
     w = (_c.c_float * nl)(*[float(x) for x in weights])
@@ -379,7 +395,11 @@ def propagate_train(train, wavelengths, n_pad, weights, heights=None, occulter=T
     if nbytes == 0:
         raise ValueError("invalid train geometry")
     ws = workspace(nbytes, dev)
-    psf = torch.empty((train.det_m, train.det_m), dtype=torch.float32, device=train.pupil_amp.device)
+    if out is not None:
+        _need(out, torch.float32, (train.det_m, train.det_m), "out")
+        psf = out
+    else:
+        psf = torch.empty((train.det_m, train.det_m), dtype=torch.float32, device=train.pupil_amp.device)
     st = L.propagate_train(context(dev).handle, _c.byref(d), nl, lam, npd, w, mode, _ptr(psf),
                            _ptr(grad_psf), _ptr(gh), _ptr(ws), ws.numel(), _stream_handle(dev, stream))
     _check(st, "propagate_train")
@@ -389,20 +409,21 @@ def propagate_train(train, wavelengths, n_pad, weights, heights=None, occulter=T
 class DMHeightsToPSF(torch.autograd.Function):
     """heights (n_dm x n_act x n_act) -> broadband PSF, with the library's adjoint as backward.
 
-    apply(heights, train, wavelengths, n_pad, weights). The backward pass reruns the forward of
-    each wavelength inside the library (keeping that wavelength's planes in the workspace) and
-    then its adjoint."""
+    apply(heights, train, wavelengths, n_pad, weights[, batched]). The backward pass reruns the
+    forward of each wavelength inside the library (keeping that wavelength's planes in the
+    workspace) and then its adjoint."""
 
     @staticmethod
-    def forward(ctx, heights, train, wavelengths, n_pad, weights):
+    def forward(ctx, heights, train, wavelengths, n_pad, weights, batched=False):
         h = heights.detach().contiguous()
-        ctx.train, ctx.args = train, (list(wavelengths), list(n_pad), list(weights))
+        ctx.train, ctx.args = train, (list(wavelengths), list(n_pad), list(weights), bool(batched))
         ctx.save_for_backward(h)
-        return propagate_train(train, wavelengths, n_pad, weights, h)
+        return propagate_train(train, wavelengths, n_pad, weights, h, batched=batched)
 
     @staticmethod
     def backward(ctx, grad_out):
         (h,) = ctx.saved_tensors
-        wl, npd, w = ctx.args
-        _, gh = propagate_train(ctx.train, wl, npd, w, h, grad_psf=grad_out.contiguous().float())
-        return gh, None, None, None, None
+        wl, npd, w, batched = ctx.args
+        _, gh = propagate_train(ctx.train, wl, npd, w, h, grad_psf=grad_out.contiguous().float(),
+                                batched=batched)
+        return gh, None, None, None, None, None

@@ -129,3 +129,78 @@ def test_warning_bit_for_undersampled_distance():
     t = to_gpu(synth.random_field(n, 1))
     st = fb.fresnel_step(t, 1e-5, 500e-9, 2.0 * n * 1e-10 / 500e-9)
     assert st & fb.FR_W_AS_UNDERSAMPLED
+
+
+# ---- edges that are not powers of two (mixed-radix sweeps) ---------------------------------
+
+@pytest.mark.parametrize("adjoint", [False, True])
+@pytest.mark.parametrize("n", [6, 30, 96, 100, 210, 1000, 3000])
+def test_mixed_radix_step_matches_oracle(n, adjoint):
+    banner(f"fresnel_step mixed-radix n={n} adjoint={adjoint}")
+    field, amp, opd, dx, lam, z, f = _case(n, 3 * n + adjoint)
+    got = _run_gpu(field, amp, opd, dx, lam, z, f, adjoint)
+    ref = oracle.fresnel_step(f32(field), dx, lam, z, amp=f32(amp), opd=f32(opd), lens_focal=f,
+                              adjoint=adjoint)
+    assert rel_l2(got, ref) <= TOL
+    assert rel_l2(np.abs(got) ** 2, np.abs(ref) ** 2) <= TOL
+
+
+# the padded per-wavelength grids of the broadband workload (radix plans 16.16.14, 16.15.15,
+# 16.9.9.3, 16.7.7.5, 16.10.5.5, 16.14.9.2), forward and adjoint spread over the set
+@pytest.mark.parametrize("n,adjoint", [(3584, False), (3600, True), (3888, False), (3920, True),
+                                       (4000, False), (4032, True)])
+def test_broadband_grid_step_matches_oracle(n, adjoint):
+    banner(f"fresnel_step broadband grid n={n} adjoint={adjoint} (oracle takes a few seconds)")
+    field, amp, opd, dx, lam, z, f = _case(n, n + adjoint)
+    got = _run_gpu(field, amp, opd, dx, lam, z, f, adjoint)
+    ref = oracle.fresnel_step(f32(field), dx, lam, z, amp=f32(amp), opd=f32(opd), lens_focal=f,
+                              adjoint=adjoint)
+    assert rel_l2(got, ref) <= TOL
+    assert rel_l2(np.abs(got) ** 2, np.abs(ref) ** 2) <= TOL
+
+
+def test_mixed_size_batch_matches_oracle():
+    # 28 planes (more than one launch's worth) of uneven edges, forward and adjoint mixed,
+    # including power-of-two edges that a mixed batch sends through the same kernels
+    sizes = [96, 100, 128, 210, 64, 120, 30, 256] * 3 + [6, 2, 3, 240]
+    banner(f"mixed-size batch of {len(sizes)} planes")
+    cases = [_case(n, 100 + i) for i, n in enumerate(sizes)]
+    adj = [i % 3 == 1 for i in range(len(sizes))]
+    ts = [to_gpu(c[0]) for c in cases]
+    fb.fresnel_step_batched(ts, [c[3] for c in cases], [c[4] for c in cases], [c[5] for c in cases],
+                            amps=[to_gpu(c[1], torch.float32) for c in cases],
+                            opds=[to_gpu(c[2], torch.float32) for c in cases],
+                            lens_focals=[c[6] for c in cases], adjoints=adj)
+    for i, (field, amp, opd, dx, lam, z, f) in enumerate(cases):
+        ref = oracle.fresnel_step(f32(field), dx, lam, z, amp=f32(amp), opd=f32(opd), lens_focal=f,
+                                  adjoint=adj[i])
+        assert rel_l2(to_np(ts[i]), ref) <= TOL, (i, sizes[i])
+
+
+def test_broadband_batch_equals_single_calls():
+    # one launch per sweep over all the padded grids of a 21-wavelength band equals per-plane
+    # calls bit for bit (same kernels, same arithmetic per line; the 4096 planes of the batch
+    # also take the mixed-radix kernels, checked against the oracle's closed form below)
+    sizes = list(synth.padded_sizes(21))
+    banner(f"broadband batch of {len(sizes)} planes: {sorted(set(sizes))}")
+    lams = list(synth.wavelengths(21))
+    dx = 2.5e-5
+    fields = [synth.random_field(n, 40 + i) for i, n in enumerate(sizes)]
+    ts = [to_gpu(f) for f in fields]
+    fb.fresnel_step_batched(ts, dx, lams, 0.3)
+    for i, n in enumerate(sizes):
+        if n == 4096:
+            continue
+        t = to_gpu(fields[i])
+        fb.fresnel_step(t, dx, lams[i], 0.3)
+        assert np.array_equal(to_np(ts[i]), to_np(t)), (i, n)
+    # a Gaussian beam through a mixed batch containing 4096 matches its closed form
+    n, w0px = 4096, 96.0
+    w0 = w0px * dx
+    zr = math.pi * w0 * w0 / lams[0]
+    g = [to_gpu(synth.gaussian_beam(n, w0px)), to_gpu(synth.gaussian_beam(3600, w0px))]
+    fb.fresnel_step_batched(g, dx, lams[0], 1.5 * zr)
+    for t, m in zip(g, (4096, 3600)):
+        r2 = (synth.radius_grid(m) * dx) ** 2
+        ref = np.exp(-r2 / (w0 * w0 * (1 + 1.5j))) / (1 + 1.5j)
+        assert rel_l2(to_np(t), ref) <= TOL, m

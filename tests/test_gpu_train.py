@@ -58,6 +58,23 @@ def test_train_small_matches_oracle(n_dm, n_lambda):
     assert np.max(np.abs(psf / psf0.max() - c_ref)) <= 1e-6 * np.max(c_ref)
 
 
+def test_train_mixed_radix_grids_matches_oracle():
+    # per-wavelength padded grids that are not powers of two (as in a broadband model)
+    banner("train small on grids 96 / 120 / 160")
+    geom, tr, heights, hg = make(64, 64, 8 / 64, 64, 0.5, 0.05, 8, 1, spider=0.04)
+    lams = list(synth.wavelengths(3))
+    ns, w = [96, 120, 160], [1.0 / 3] * 3
+    psf = _np(fb.propagate_train(tr, lams, ns, w, hg))
+    ref = oracle.train_psf(geom, lams, ns, w, heights)
+    assert rel_l2(psf, ref) <= 1e-5
+    dh = synth.dark_hole(64, 0.5, 3.0, 7.0)
+    ref0 = oracle.train_psf(geom, lams, ns, w, heights, occulter=False)
+    mref = float(ref0.max())
+    _, gh = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=to_gpu(dh / (dh.sum() * mref), torch.float32))
+    gref = np.stack(oracle.train_grad(geom, lams, ns, w, heights, dh, mref))
+    assert rel_l2(_np(gh), gref) <= 1e-4
+
+
 def test_train_config2_full_size():
     banner("train config 2: 1024 pupil padded to 4096, occulter 256, detector 512")
     geom, tr, heights, hg = make(1024, 256, 8 / 256, 512, 0.25, 1.0, 48, 1)
@@ -142,3 +159,64 @@ def test_autograd_function_matches_direct_call():
     _, gh = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh_t / (dh_t.sum() * mref))
     torch.cuda.synchronize()
     assert torch.allclose(h.grad, gh, rtol=0, atol=0)
+
+
+def test_batched_equals_plain_mixed_grids():
+    # one launch per sweep for all wavelengths gives the same PSF and gradient, bit for bit
+    banner("train batched vs plain, 2 DMs, grids 96 / 120 / 128 / 160")
+    geom, tr, heights, hg = make(64, 64, 8 / 64, 64, 0.5, 0.05, 8, 2, spider=0.04)
+    lams = list(synth.wavelengths(4))
+    ns, w = [96, 120, 128, 160], [0.25] * 4
+    dh = to_gpu(synth.dark_hole(64, 0.5, 3.0, 7.0), torch.float32)
+    p0, g0 = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh)
+    p1, g1 = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh, batched=True)
+    torch.cuda.synchronize()
+    assert torch.equal(p0, p1)
+    assert torch.equal(g0, g1)
+    ref = oracle.train_psf(geom, lams, ns, w, heights)
+    assert rel_l2(_np(p1), ref) <= 1e-5
+
+
+def test_broadband_train_batched_full_size():
+    # the broadband model: 1024 pupil, 21 wavelengths over 500-600 nm on per-wavelength grids
+    # 3584 ... 4096; batched equals plain bit for bit, and three of the wavelengths (one per
+    # radix family) are checked against the oracle one by one
+    banner("broadband train: 21 wavelengths, grids 3584..4096, batched vs plain")
+    geom, tr, heights, hg = make(1024, 256, 8 / 256, 512, 0.25, 1.0, 48, 1)
+    lams = list(synth.wavelengths(21))
+    ns = list(synth.padded_sizes(21))
+    w = [1.0 / 21] * 21
+    p_plain = fb.propagate_train(tr, lams, ns, w, hg)
+    p_batch = fb.propagate_train(tr, lams, ns, w, hg, batched=True)
+    torch.cuda.synchronize()
+    assert torch.equal(p_plain, p_batch)
+    cache = {}
+    for j in (0, 7, 20):
+        banner(f"broadband train: wavelength {j}, grid {ns[j]} vs oracle")
+        one = _np(fb.propagate_train(tr, [lams[j]], [ns[j]], [1.0], hg, batched=True))
+        ref = oracle.train_psf(geom, [lams[j]], [ns[j]], [1.0], heights, step_cache=cache)
+        assert rel_l2(one, ref) <= 1e-5
+
+
+def test_graph_mode_replays_match_eager():
+    # the recorded graph is replayed several times, with other work and synchronisations in
+    # between and with new DM heights written in place; every replay equals the eager call
+    banner("train graph mode: replays vs eager, 2 DMs, grids 96 / 128 / 120")
+    geom, tr, heights, hg = make(64, 64, 8 / 64, 64, 0.5, 0.05, 8, 2, spider=0.04)
+    lams = list(synth.wavelengths(3))
+    ns, w = [96, 128, 120], [1.0 / 3] * 3
+    dh = to_gpu(synth.dark_hole(64, 0.5, 3.0, 7.0), torch.float32)
+    out = torch.empty((64, 64), dtype=torch.float32, device="cuda:0")
+    gout = torch.empty((2, 8, 8), dtype=torch.float32, device="cuda:0")
+    rng = np.random.default_rng(11)
+    for rep in range(4):
+        if rep:
+            hg.copy_(to_gpu(rng.normal(0.0, 2e-9, hg.shape), torch.float32))
+        p_ref, g_ref = fb.propagate_train(tr, lams, ns, w, hg.clone(), grad_psf=dh.clone(), batched=True)
+        fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh, batched=True, graph=True, out=out,
+                           grad_out=gout)
+        junk = torch.randn(1 << 20, device="cuda:0").sum()   # unrelated eager work in between
+        torch.cuda.synchronize()
+        assert torch.equal(out, p_ref), rep
+        assert torch.equal(gout, g_ref), rep
+        assert torch.isfinite(junk)

@@ -46,10 +46,14 @@ def test_status_strings(L):
 
 
 def test_supported_sizes(L):
-    for n in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
-        assert L.fr_fft_size_supported(n) == 1
-    for n in (0, -4, 3000, 100, 4095):
-        assert L.fr_fft_size_supported(n) == 0
+    # powers of two up to 8192; other edges up to 4096 that factor into radices 2..16
+    # (6 passes at most); the per-wavelength grids of the broadband workload among them
+    for n in (64, 128, 256, 512, 1024, 2048, 4096, 8192, 2, 3, 30, 100, 3000,
+              3584, 3600, 3840, 3888, 3920, 4000, 4032):
+        assert L.fr_fft_size_supported(n) == 1, n
+    # 4095 = 3^2 5 7 13 and 17 have a prime factor above 16; 4097 and 6000 exceed 4096
+    for n in (0, 1, -4, 17, 4095, 4097, 6000, 16384):
+        assert L.fr_fft_size_supported(n) == 0, n
 
 
 def test_workspace_query(L):
@@ -64,7 +68,7 @@ def test_fresnel_step_argument_errors(L):
     null = ctypes.c_void_p()
     st = L.fresnel_step(null, null, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null)
     assert st == fb.FR_EINVAL
-    st = L.fresnel_step(null, FAKE, 3000, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null)
+    st = L.fresnel_step(null, FAKE, 4095, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null)
     assert st == fb.FR_EUNSUPPORTED
     st = L.fresnel_step(null, FAKE, 256, -1e-4, 5e-7, 1.0, null, null, 0.0, 0, null)
     assert st == fb.FR_EINVAL
