@@ -1,13 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark: Fresnel planes/s at 4096^2 c64, forward + adjoint, batched vs plain, with the
-dominant kernel's HBM-roofline fraction and the FP64 oracle timed on the host as baseline.
+dominant kernel's roofline fraction and the FP64 oracle timed on the host as baseline.
 
-Workload (one step): 21 wavelengths uniform over 500-600 nm, each with one forward Fresnel
-plane and one adjoint plane on a dense 4096^2 complex64 field: the optic prologue (amplitude
-map and power-law OPD phasor of a 1024 px pupil geometry padded 4x, dx = 25 um) then the
-angular-spectrum step over z = 1 m. 42 planes per step, all resident in HBM.
-  batched form (timed, `value`): one fresnel_step_batched call per step (one launch per sweep);
-  plain form (reported beside it): one fresnel_step call per plane, stream-ordered.
+Step (one pass of the whole hot path): the Lyot coronagraph train of a 1024 px pupil (10 %
+central obscuration, four 1 % D spiders, power-law OPD 10 nm rms) padded 4x to 4096^2, two
+48 x 48-actuator DMs (one in the pupil, one after a 1 m Fresnel step), occulter MFT to 256^2
+(3 lambda/D spot), Babinet MFT back, Lyot stop 0.9 D, detector MFT to 512^2, over 21
+wavelengths uniform in 500-600 nm; broadband PSF plus the gradient of the mean dark-hole
+(3-10 lambda/D half annulus) contrast with respect to both DMs' actuator heights. Per step:
+21 forward and 21 adjoint Fresnel planes at 4096^2, the forward and adjoint MFTs, the DM
+synthesis and the DM-gradient projections. All inputs resident in HBM; data synthetic.
+  batched form (`value`): one propagate_train call with FR_TRAIN_BATCHED | FR_TRAIN_GRAPH
+      (all wavelengths' Fresnel planes in one launch per sweep, the whole call one graph);
+  plain form (reported beside it): the same call wavelength after wavelength.
+Also reported: the Fresnel sweeps alone (42 planes at 4096^2 in one batched call) with their
+HBM-roofline fraction.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 Prints one JSON line.
@@ -26,43 +33,39 @@ if ROOT not in sys.path:
 N = 4096
 N_D = 1024
 N_LAMBDA = 21
-DX = 25.6e-3 / N_D
+N_ACT = 48
+D_M = N_D * 25e-6
+DX = D_M / N_D
 Z = 1.0
+OCC_M, OCC_DU = 256, 8.0 / 256
+DET_M, DET_DU = 512, 0.25
+LAMBDA_C = 550e-9
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
-def plane_bytes(n, optic_reads):
-    """Algorithmic HBM bytes of one Fresnel plane: two sweeps, each reading and writing the
-    n^2 c64 field once, plus one read of each float optic map the plane uses."""
-    return 4 * n * n * 8 + optic_reads * n * n * 4
+def sweep_bytes(n, optic_maps):
+    """Algorithmic HBM bytes of one sweep of one plane: the n^2 c64 field read and written once,
+    plus one read of each float n^2 map the sweep applies."""
+    return 2 * n * n * 8 + optic_maps * n * n * 4
 
 
-def sweep_bytes(n, optic_maps_in_this_sweep):
-    return 2 * n * n * 8 + optic_maps_in_this_sweep * n * n * 4
-
-
-def build_inputs(torch, np, synth, dev):
-    lams = synth.wavelengths(N_LAMBDA)
+def train_inputs(torch, np, synth, dev):
+    def f(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
     pupil = synth.pupil_amplitude(N_D, 0.1, 0.01)
-    opd_p = synth.power_law_opd(N_D, pupil, 10e-9, -3.0, 0)
-    off = (N - N_D) // 2
-    rng = np.random.default_rng(42)
-    amp = rng.uniform(0.99, 1.0, (N, N)).astype(np.float32)       # dense optic amplitude
-    amp[off:off + N_D, off:off + N_D] *= pupil.astype(np.float32)
-    opd = np.zeros((N, N), np.float32)
-    opd[off:off + N_D, off:off + N_D] = opd_p
-    amp_t = torch.from_numpy(amp).to(dev)
-    opd_t = torch.from_numpy(opd).to(dev)
-    fields = []
-    for i in range(2 * N_LAMBDA):
-        g = torch.Generator(device=dev)
-        g.manual_seed(1000 + i)
-        fields.append(torch.randn((N, N), dtype=torch.complex64, device=dev, generator=g))
-    return lams, amp_t, opd_t, fields
+    opd = synth.power_law_opd(N_D, pupil, 10e-9, -3.0, 0)
+    occ = synth.occulter_spot(OCC_M, OCC_DU, 3.0)
+    lyot = synth.lyot_stop(N_D, 0.9)
+    heights = np.stack([synth.dm_heights(N_ACT, 1 + k) for k in range(2)])
+    dh = synth.dark_hole(DET_M, DET_DU, 3.0, 10.0)
+    return dict(pupil=f(pupil), opd=f(opd), occ=f(occ), lyot=f(lyot), heights=f(heights),
+                dh=dh, lams=[float(x) for x in synth.wavelengths(N_LAMBDA)])
 
 
 def cpu_baseline(np):
-    """The FP64 oracle on a bounded sample: one forward + one adjoint 4096^2 Fresnel plane."""
+    """The FP64 oracle on a bounded sample of the same step: one wavelength of the train
+    (forward + gradient, which contains one forward and one adjoint Fresnel plane at 4096^2)."""
     import oracle
     from paper_1806_06467_amd import synth
     try:
@@ -70,17 +73,22 @@ def cpu_baseline(np):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         threads = len(os.sched_getaffinity(0))
-    rng = np.random.default_rng(7)
-    field = synth.random_field(N, 99)
-    amp = rng.uniform(0.99, 1.0, (N, N))
-    opd = rng.normal(0.0, 10e-9, (N, N))
+    pupil = synth.pupil_amplitude(N_D, 0.1, 0.01)
+    geom = oracle.TrainGeometry(
+        n_d=N_D, d_m=D_M, z_m=Z, occ_m=OCC_M, occ_du_c=OCC_DU, det_m=DET_M, det_du_c=DET_DU,
+        lambda_c=LAMBDA_C, pupil_amp=pupil, occ_mask=synth.occulter_spot(OCC_M, OCC_DU, 3.0),
+        lyot=synth.lyot_stop(N_D, 0.9), pupil_opd=synth.power_law_opd(N_D, pupil, 10e-9, -3.0, 0))
+    heights = [synth.dm_heights(N_ACT, 1 + k) for k in range(2)]
+    dh = synth.dark_hole(DET_M, DET_DU, 3.0, 10.0)
+    lam = float(synth.wavelengths(N_LAMBDA)[N_LAMBDA // 2])
     t0 = time.perf_counter()
-    out = oracle.fresnel_step(field, DX, 550e-9, Z, amp=amp, opd=opd)
-    out = oracle.fresnel_step(out, DX, 550e-9, Z, amp=amp, opd=opd, adjoint=True)
+    fwd = oracle.train_forward(geom, lam, N, heights, True)
+    oracle.train_backward(geom, lam, N, heights, fwd, dh / dh.sum())
     dt = time.perf_counter() - t0
     return {"value": 2.0 / dt, "unit": "Fresnel planes/s", "cores": int(threads), "kind": "oracle",
-            "sample": "1 forward + 1 adjoint Fresnel plane at 4096^2 with amplitude+OPD optic, "
-                      "FP64 oracle (explicit DFT matrices, zgemm), %.1f s" % dt}
+            "sample": "one wavelength (550 nm) of the step: train forward + gradient with two DMs "
+                      "at 4096^2 (1 forward + 1 adjoint Fresnel plane and the MFTs), FP64 oracle "
+                      "(explicit DFT matrices, zgemm), %.1f s" % dt}
 
 
 def main():
@@ -107,28 +115,30 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    lams, amp, opd, fields = build_inputs(torch, np, synth, dev)
-    n_pl = len(fields)
-    adjs = [i >= N_LAMBDA for i in range(n_pl)]
-    lam_pl = [float(lams[i % N_LAMBDA]) for i in range(n_pl)]
+    stream = torch.cuda.current_stream(dev)
+    inp = train_inputs(torch, np, synth, dev)
+    lams = inp["lams"]
+    tr = fb.Train(N_D, D_M, Z, inp["pupil"], inp["lyot"], inp["occ"], OCC_DU, DET_M, DET_DU,
+                  LAMBDA_C, inp["opd"], n_act=N_ACT, n_dm=2)
+    ns, w = [N] * N_LAMBDA, [1.0 / N_LAMBDA] * N_LAMBDA
+    hg = inp["heights"]
+    # the reference peak, held fixed in the loss (not differentiated)
+    ref0 = fb.propagate_train(tr, lams, ns, w, hg, occulter=False, batched=True)
+    dh = inp["dh"]
+    g_psf = torch.from_numpy((dh / (dh.sum() * float(ref0.max()))).astype(np.float32)).to(dev)
+    psf = torch.empty((DET_M, DET_M), dtype=torch.float32, device=dev)
+    gh = torch.empty_like(hg)
+    planes_per_step = 2 * N_LAMBDA  # forward + adjoint Fresnel planes
 
     def batched_step():
-        fb.fresnel_step_batched(fields, DX, lam_pl, Z, amps=amp, opds=opd, adjoints=adjs)
+        fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g_psf, batched=True, graph=True, out=psf,
+                           grad_out=gh)
 
     def plain_step():
-        for i in range(n_pl):
-            fb.fresnel_step(fields[i], DX, lam_pl[i], Z, amp=amp, opd=opd, adjoint=adjs[i])
+        fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g_psf, out=psf, grad_out=gh)
 
-    stream = torch.cuda.current_stream(dev)
-    if args.copy_calibration:
-        dst = torch.empty_like(fields[0])
-        for _ in range(3):
-            dst.copy_(fields[0])
-        torch.cuda.synchronize()
-        del dst
-
-    def timed(fn, steps, profile=False):
-        for _ in range(args.warmup):
+    def timed(fn, steps, warmup, profile=False):
+        for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         if profile:
@@ -148,30 +158,80 @@ def main():
         return e0.elapsed_time(e1), prof
 
     t_wall0 = time.perf_counter()
-    ms_batched, prof = timed(batched_step, args.steps, profile=True)
-    ms_plain, prof_plain = timed(plain_step, max(1, args.steps // 2), profile=True)
-    t_wall = time.perf_counter() - t_wall0
-
     steps = args.steps
+    ms_batched, _ = timed(batched_step, steps, args.warmup)
+    psf_sum = float(psf.sum())
+    n_plain = max(1, steps // 4)
+    ms_plain, _ = timed(plain_step, n_plain, 1)
+    _, prof_plain = timed(plain_step, n_plain, 0, profile=True)
     ms_per_step = ms_batched / steps
-    planes_per_s = n_pl * steps / (ms_batched * 1e-3)
-    plain_planes_per_s = n_pl * max(1, steps // 2) / (ms_plain * 1e-3)
+    value = planes_per_step * steps / (ms_batched * 1e-3)
+    plain_value = planes_per_step * n_plain / (ms_plain * 1e-3)
 
-    # roofline of the dominant kernel. Each sweep launch covers the 21 planes of one direction
-    # (forward planes: rows then columns; adjoint planes: columns then rows). Both row launches
-    # apply the optic (prologue forward, conjugate epilogue adjoint), so a row launch reads the
-    # amplitude and OPD maps of its planes once; a column launch moves only the fields.
+    # per-kernel times of one step, from the plain form (the same kernels, launched one
+    # wavelength at a time; the graph form is timed as a whole)
+    agg = {}
+    for k, (tot, cnt) in prof_plain.items():
+        name = k.split("/")[0]
+        a = agg.setdefault(name, [0.0, 0])
+        a[0] += tot
+        a[1] += cnt
+    kernels_ms_per_step = {k: v[0] / n_plain for k, v in sorted(agg.items(), key=lambda kv: -kv[1][0])}
+
+    # dominant kernel of the step; a complex GEMM launch is tagged with its M x N x K
+    dom = next(iter(kernels_ms_per_step))
+    dom_ms = agg[dom][0] / agg[dom][1]
+    if dom.startswith("cgemm"):
+        m, n_, k = (int(x) for x in dom.split("_")[1].split("x"))
+        flops = 8.0 * m * n_ * k
+        achieved = flops / (dom_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                    "flops_per_launch": flops, "avg_launch_ms": dom_ms,
+                    "note": "8 real flops per complex multiply-add over the launch's M x N x K"}
+    else:
+        roofline = {"bound": "unmodelled", "kernel": dom, "avg_launch_ms": dom_ms}
+
+    # the Fresnel sweeps alone: 42 planes (21 forward, 21 adjoint) of 4096^2 with a dense
+    # amplitude + OPD optic in one batched call; per-launch HBM roofline of the sweep kernels
+    rng = np.random.default_rng(42)
+    amp = torch.from_numpy(rng.uniform(0.99, 1.0, (N, N)).astype(np.float32)).to(dev)
+    opd = torch.from_numpy(rng.normal(0.0, 10e-9, (N, N)).astype(np.float32)).to(dev)
+    fields = []
+    for i in range(2 * N_LAMBDA):
+        g = torch.Generator(device=dev)
+        g.manual_seed(1000 + i)
+        fields.append(torch.randn((N, N), dtype=torch.complex64, device=dev, generator=g))
+    adjs = [i >= N_LAMBDA for i in range(2 * N_LAMBDA)]
+    lam_pl = [lams[i % N_LAMBDA] for i in range(2 * N_LAMBDA)]
+    fr_calls = 10
+    ms_fr, prof_fr = timed(lambda: fb.fresnel_step_batched(fields, DX, lam_pl, Z, amps=amp, opds=opd,
+                                                           adjoints=adjs), fr_calls, 2, profile=True)
+    # each sweep launch covers the 21 planes of one direction; both row launches apply the
+    # amplitude and OPD maps (prologue forward, conjugate epilogue adjoint)
     per_launch = {"row_sweep": N_LAMBDA * sweep_bytes(N, 2), "col_sweep": N_LAMBDA * sweep_bytes(N, 0)}
-    kern = {k.split("/")[0]: v for k, v in prof.items() if k.split("/")[0] in per_launch}
-    dom = max(kern, key=lambda k: kern[k][0])
-    dom_ms = kern[dom][0] / kern[dom][1]
-    bytes_launch = per_launch[dom]
-    achieved = bytes_launch / (dom_ms * 1e-3) / 1e9
-    total_bytes_step = N_LAMBDA * plane_bytes(N, 2) * 2
+    fr_rl = {}
+    for key, (tot, cnt) in prof_fr.items():
+        name = key.split("/")[0]
+        if name not in per_launch:
+            continue
+        ms = tot / cnt
+        gbs = per_launch[name] / (ms * 1e-3) / 1e9
+        fr_rl[name] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": per_launch[name],
+                       "avg_launch_ms": ms}
+    del fields
+    if args.copy_calibration:
+        src = torch.randn((N, N), dtype=torch.complex64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
 
     result = {
         "metric": "Fresnel planes/sec at 4096^2 c64 (fwd+adjoint, batched vs plain), %HBM roofline",
-        "value": planes_per_s,
+        "value": value,
         "unit": "Fresnel planes/s",
         "n_gpus": 1,
         "steps": steps,
@@ -183,21 +243,21 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "fresnel_planes_4096_fwd_adj_21lambda",
-            "n": N, "planes_per_step": n_pl, "wavelengths_nm": [500, 600, N_LAMBDA],
-            "dx_m": DX, "z_m": Z, "optic": "amplitude + OPD phasor per plane",
-            "form": "batched (one launch per sweep per step)",
+            "workload": "lyot_train_4096_21lambda_2dm_psf_and_gradient",
+            "n": N, "n_d": N_D, "wavelengths_nm": [500, 600, N_LAMBDA], "n_dm": 2, "n_act": N_ACT,
+            "occulter": [OCC_M, OCC_DU], "detector": [DET_M, DET_DU], "z_m": Z,
+            "fresnel_planes_per_step": planes_per_step,
+            "form": "batched: FR_TRAIN_BATCHED | FR_TRAIN_GRAPH, one call per step",
         },
-        "plain": {"value": plain_planes_per_s, "unit": "Fresnel planes/s",
-                  "ms_per_plane": ms_plain / (n_pl * max(1, steps // 2)),
-                  "kernels_ms_per_plane": {k: v[0] / v[1] for k, v in prof_plain.items()}},
-        "hbm_fraction_whole_plane": (total_bytes_step / (ms_per_step * 1e-3)) / (HBM_PEAK_GBS * 1e9),
-        "roofline": {
-            "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "bytes_per_launch": bytes_launch, "avg_launch_ms": dom_ms,
+        "plain": {"value": plain_value, "unit": "Fresnel planes/s", "ms_per_step": ms_plain / n_plain},
+        "roofline": roofline,
+        "kernels_ms_per_step": kernels_ms_per_step,
+        "fresnel_only": {
+            "value": 2 * N_LAMBDA * fr_calls / (ms_fr * 1e-3), "unit": "Fresnel planes/s",
+            "planes_per_call": 2 * N_LAMBDA, "ms_per_call": ms_fr / fr_calls,
+            "roofline": fr_rl,
         },
-        "kernels_ms_per_launch": {k: v[0] / v[1] for k, v in prof.items()},
+        "checksum_psf_sum": psf_sum,
         "wall_s": t_wall,
     }
     if not args.no_cpu_baseline:

@@ -133,9 +133,10 @@ int mft_adjoint(fr_ctx *ctx, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_c
  * adjoint above. Arrays lambda_m, n_pad, weight are HOST arrays of n_lambda entries.
  * FR_TRAIN_BATCHED keeps one field plane per wavelength in the workspace and runs the Fresnel
  * steps of all wavelengths (grids of different edges allowed) in one launch per sweep; the
- * focal-plane chains and all sums still go in wavelength order, so psf and grad_heights are
- * bit-identical to the plain (wavelength after wavelength) mode. Its workspace grows with
- * sum_j n_pad[j]^2.
+ * focal-plane chains and all sums still go in wavelength order. With one power-of-two edge
+ * for all wavelengths, psf and grad_heights are bit-identical to the plain (wavelength after
+ * wavelength) mode; with mixed edges every plane takes the mixed-radix sweeps and the results
+ * agree with the plain mode to float32 rounding. Its workspace grows with sum_j n_pad[j]^2.
  * FR_TRAIN_GRAPH records the whole call as one graph the first time a given set of argument
  * values (descriptor bytes, host arrays, device pointers, stream) is seen, after running it
  * normally, and replays that graph on later identical calls; the device inputs may change

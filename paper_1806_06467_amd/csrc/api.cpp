@@ -281,7 +281,12 @@ int Ctx::dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **ou
 }
 
 
-size_t mft_ws_bytes(int n, int m) { return size_t(1 + kMaxSplit) * size_t(n) * size_t(m) * sizeof(float2); }
+// workspace of one MFT: the n x m c64 intermediate, then (256-byte aligned) the float64
+// split-K partials
+static size_t mft_t_bytes(int n, int m) { return (size_t(n) * size_t(m) * sizeof(float2) + 255) & ~size_t(255); }
+size_t mft_ws_bytes(int n, int m) {
+  return mft_t_bytes(n, m) + size_t(kMaxSplit) * size_t(n) * size_t(m) * 2 * sizeof(double);
+}
 
 static CGemmArgs gemm_args() {
   CGemmArgs g;
@@ -290,7 +295,7 @@ static CGemmArgs gemm_args() {
   return g;
 }
 
-static hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, float2 *partial, size_t partial_elems, hipStream_t s) {
+static hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, void *partial, size_t partial_elems, hipStream_t s) {
   int split = cgemm_split_for(g.M, g.N, g.K);
   while (split > 1 && size_t(split) * size_t(g.M) * size_t(g.N) > partial_elems) split /= 2;
   return launch_cgemm_split(g, split, partial, s, ctx->hook());
@@ -302,7 +307,7 @@ int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out,
   int st = ctx->mft_matrix(m_out, n_in, n_d, du, s, &w);
   if (st != FR_OK) return st;
   float2 *t = static_cast<float2 *>(ws);
-  float2 *partial = t + size_t(n_in) * m_out;
+  void *partial = static_cast<char *>(ws) + mft_t_bytes(n_in, m_out);
   const size_t pcap = size_t(kMaxSplit) * n_in * m_out;
   // T = E W^T  (n_in x m_out)
   CGemmArgs g1 = gemm_args();
@@ -332,7 +337,7 @@ int mft_adjoint_impl(Ctx *ctx, const float2 *in, int m_in, int ld_in, float2 *ou
   int st = ctx->mft_matrix(m_in, n_out, n_d, du, s, &w);
   if (st != FR_OK) return st;
   float2 *t = static_cast<float2 *>(ws);
-  float2 *partial = t + size_t(n_out) * m_in;
+  void *partial = static_cast<char *>(ws) + mft_t_bytes(n_out, m_in);
   const size_t pcap = size_t(kMaxSplit) * n_out * m_in;
   // T = E_B conj(W)  (m_in x n_out)
   CGemmArgs g1 = gemm_args();

@@ -106,10 +106,11 @@ struct CGemmArgs {
   int skip_c;         // 1: do not write C (only the intensity)
 };
 // C = alpha op(A) op(B) (+ beta C) (* mask). split > 1 slices K; the slices' partial sums go
-// to `partial` (split x M x N c64) and are added in a fixed order by a second kernel.
+// to `partial` (split x M x N complex float64, 16-byte aligned) and are added in a fixed order
+// by a second kernel.
 constexpr int kMaxSplit = 16;
 int cgemm_split_for(int M, int N, int K);
-hipError_t launch_cgemm_split(const CGemmArgs &a, int split, float2 *partial, hipStream_t stream,
+hipError_t launch_cgemm_split(const CGemmArgs &a, int split, void *partial, hipStream_t stream,
                               const LaunchHook &hook);
 
 }  // namespace fr

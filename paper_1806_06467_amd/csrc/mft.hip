@@ -4,14 +4,19 @@
 // the matrix cores.
 //
 // Complex product with real MFMA: per complex k-step, Cr += Ar Br - Ai Bi and
-// Ci += Ar Bi + Ai Br (four v_mfma_f32_32x32x2f32, A/B fragments from LDS).
-// Block tile 64 x 64, four waves in 2 x 2, each wave one 32 x 32 real and imaginary
-// accumulator per 16-deep k tile, added into float64 totals (the long Fourier sums of the
-// coronagraph cancel to tiny values in the dark hole, so their rounding must not grow with K).
-// Operands may be transposed and/or conjugated on load. Small outputs with
-// long K are split over K; the partial sums go to the workspace and one epilogue kernel adds
-// them in a fixed order (deterministic), applies alpha, beta and the mask.
+// Ci += Ar Bi + Ai Br (four v_mfma_f32_32x32x2f32 per 32 x 32 tile, fragments from LDS).
+// Block tile 128 x 128, eight waves in 4 x 2, each wave a 32 x 64 piece (two 32 x 32 MFMA
+// tiles). Operand tiles 16 deep are staged through double-buffered LDS, the next tile's
+// global loads in flight while the current one is multiplied (one barrier per tile). Each
+// 16-deep tile is summed by the MFMAs in float32 and then added into float64 totals (the long
+// Fourier sums of the coronagraph cancel to tiny values in the dark hole, so their rounding
+// must not grow with K); the epilogue (alpha, beta, mask, intensity) runs in float64.
+// Operands may be transposed (template) and/or conjugated (on the LDS store). Outputs with few
+// tiles and long K are split over K; the float64 partial sums go to the workspace and one
+// epilogue kernel adds them in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
+
+#include <cstdio>
 
 #include "fr_internal.h"
 
@@ -21,30 +26,32 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BK = 16;
 constexpr int PAD = 4;
 
 struct GemmParams {
   CGemmArgs a;
   int split;        // number of K slices (gridDim.z)
   int k_per_split;  // multiple of BK
-  float2 *partial;  // split x M x N when split > 1
+  double2 *partial; // split x M x N when split > 1
 };
 
-// result (i, j) = alpha acc + beta Cin, times mask; written to C and/or accumulated as
-// weight |result|^2 into the intensity map
-__device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, float cr, float ci) {
-  float2 outv = make_float2(a.alpha_re * cr - a.alpha_im * ci, a.alpha_re * ci + a.alpha_im * cr);
+// result (i, j) = alpha acc + beta Cin, times mask, in float64; written to C and/or
+// accumulated as weight |result|^2 into the intensity map
+__device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, double cr, double ci) {
+  double orr = double(a.alpha_re) * cr - double(a.alpha_im) * ci;
+  double oi = double(a.alpha_re) * ci + double(a.alpha_im) * cr;
   if (a.beta != 0.f) {
     const float2 old = a.Cin ? a.Cin[size_t(i) * a.ldcin + j] : a.C[size_t(i) * a.ldc + j];
-    outv.x += a.beta * old.x;
-    outv.y += a.beta * old.y;
+    orr += double(a.beta) * double(old.x);
+    oi += double(a.beta) * double(old.y);
   }
   if (a.mask) {
-    const float mk = a.mask[size_t(i) * a.ldm + j];
-    outv.x *= mk;
-    outv.y *= mk;
+    const double mk = a.mask[size_t(i) * a.ldm + j];
+    orr *= mk;
+    oi *= mk;
   }
+  const float2 outv = make_float2(float(orr), float(oi));
   if (!a.skip_c) a.C[size_t(i) * a.ldc + j] = outv;
   if (a.intensity) {
     float *ip = a.intensity + size_t(i) * a.ldi + j;
@@ -52,87 +59,156 @@ __device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, float
   }
 }
 
-__device__ __forceinline__ float2 load_op(const float2 *p, int ld, int r, int c, int rows, int cols,
-                                          bool trans, bool conj) {
-  // element (r, c) of op(X) where X is stored row-major rows x cols (or transposed)
-  if (r >= rows || c >= cols) return make_float2(0.f, 0.f);
-  float2 v = trans ? p[size_t(c) * ld + r] : p[size_t(r) * ld + c];
-  if (conj) v.y = -v.y;
-  return v;
-}
+// Tile configuration: WM x WN waves, each wave a 32 x (32 TN) piece of the block tile.
+template <int WM_, int WN_, int TN_>
+struct Cfg {
+  static constexpr int WM = WM_, WN = WN_, TN = TN_;
+  static constexpr int BM = 32 * WM, BN = 32 * TN * WN;
+  static constexpr int threads = 64 * WM * WN;
+  static constexpr int la = BM * BK / threads;  // A elements per thread per tile
+  static constexpr int lb = BK * BN / threads;  // B elements per thread per tile
+  static_assert(BM * BK % threads == 0 && BK * BN % threads == 0, "tile not divisible");
+  static_assert(threads % BK == 0 && threads % BM == 0 && threads % BN == 0, "thread mapping");
+};
+using CfgL = Cfg<4, 2, 2>;  // 128 x 128, 512 threads
+using CfgS = Cfg<2, 2, 1>;  // 64 x 64, 256 threads
 
-__global__ void __launch_bounds__(256) cgemm_kernel(GemmParams gp) {
+// Per-thread share of one BK-deep operand tile, mapped so that consecutive threads walk
+// memory contiguously.
+template <class C, bool TA, bool TB>
+struct TileLoad {
+  float2 ra[C::la], rb[C::lb];
+  __device__ __forceinline__ static void a_coord(int t, int r, int &i, int &k) {
+    if (TA) {  // A stored K x M: contiguous along i
+      i = t % C::BM;
+      k = t / C::BM + (C::threads / C::BM) * r;
+    } else {   // A stored M x K: contiguous along k
+      k = t % BK;
+      i = t / BK + (C::threads / BK) * r;
+    }
+  }
+  __device__ __forceinline__ static void b_coord(int t, int r, int &k, int &j) {
+    if (TB) {  // B stored N x K: contiguous along k
+      k = t % BK;
+      j = t / BK + (C::threads / BK) * r;
+    } else {   // B stored K x N: contiguous along j
+      j = t % C::BN;
+      k = t / C::BN + (C::threads / C::BN) * r;
+    }
+  }
+  __device__ __forceinline__ void load(const CGemmArgs &a, int t, int i0, int j0, int k0, int kend) {
+#pragma unroll
+    for (int r = 0; r < C::la; ++r) {
+      int i, k;
+      a_coord(t, r, i, k);
+      const int gi = i0 + i, gk = k0 + k;
+      ra[r] = (gi < a.M && gk < kend) ? (TA ? a.A[size_t(gk) * a.lda + gi] : a.A[size_t(gi) * a.lda + gk])
+                                      : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < C::lb; ++r) {
+      int k, j;
+      b_coord(t, r, k, j);
+      const int gk = k0 + k, gj = j0 + j;
+      rb[r] = (gj < a.N && gk < kend) ? (TB ? a.B[size_t(gj) * a.ldb + gk] : a.B[size_t(gk) * a.ldb + gj])
+                                      : make_float2(0.f, 0.f);
+    }
+  }
+  __device__ __forceinline__ void store(float2 (*As)[C::BM + PAD], float2 (*Bs)[C::BN + PAD], int t, float sa,
+                                        float sb) const {
+#pragma unroll
+    for (int r = 0; r < C::la; ++r) {
+      int i, k;
+      a_coord(t, r, i, k);
+      As[k][i] = make_float2(ra[r].x, sa * ra[r].y);
+    }
+#pragma unroll
+    for (int r = 0; r < C::lb; ++r) {
+      int k, j;
+      b_coord(t, r, k, j);
+      Bs[k][j] = make_float2(rb[r].x, sb * rb[r].y);
+    }
+  }
+};
+
+template <class C, bool TA, bool TB>
+__global__ void __launch_bounds__(C::threads) cgemm_kernel(GemmParams gp) {
+  constexpr int TN = C::TN;
   const CGemmArgs &a = gp.a;
-  __shared__ float2 As[BK][BM + PAD];
-  __shared__ float2 Bs[BK][BN + PAD];
+  __shared__ float2 As[2][BK][C::BM + PAD];
+  __shared__ float2 Bs[2][BK][C::BN + PAD];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
+  const int wm = wave / C::WN, wn = wave % C::WN;
+  const int i0 = blockIdx.y * C::BM, j0 = blockIdx.x * C::BN;
   const int kbeg = blockIdx.z * gp.k_per_split;
   const int kend = min(a.K, kbeg + gp.k_per_split);
-  // each BK-deep tile is summed by the MFMAs in float32, then added into float64 totals
-  double totr[16], toti[16];
+  const float sa = a.conjA ? -1.f : 1.f, sb = a.conjB ? -1.f : 1.f;
+  double totr[TN][16], toti[TN][16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) totr[r] = toti[r] = 0.0;
+  for (int t = 0; t < TN; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) totr[t][r] = toti[t][r] = 0.0;
+  TileLoad<C, TA, TB> ld;
+  if (kbeg < kend) {
+    ld.load(a, tid, i0, j0, kbeg, kend);
+    ld.store(As[0], Bs[0], tid, sa, sb);
+  }
+  __syncthreads();
+  const int arow = wm * 32 + (lane & 31);
+  const int bcol = wn * 32 * TN + (lane & 31);
+  const int kl = lane >> 5;
+  int buf = 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    floatx16 accr = {0.f}, acci = {0.f};
-    // A tile: op(A)[i0 + i][k0 + k]; op(A) = A (M x K) or A^T with A stored K x M.
-    // The thread mapping walks memory contiguously in either case.
+    const bool more = k0 + BK < kend;
+    if (more) ld.load(a, tid, i0, j0, k0 + BK, kend);
+    floatx16 cr[TN], ci[TN];
 #pragma unroll
-    for (int e = tid; e < BM * BK; e += 256) {
-      int i, k;
-      if (a.transA) {
-        i = e % BM;
-        k = e / BM;
-      } else {
-        k = e % BK;
-        i = e / BK;
-      }
-      As[k][i] = load_op(a.A, a.lda, i0 + i, k0 + k, a.M, kend, a.transA != 0, a.conjA != 0);
+    for (int t = 0; t < TN; ++t) {
+      cr[t] = floatx16{0.f};
+      ci[t] = floatx16{0.f};
     }
-#pragma unroll
-    for (int e = tid; e < BK * BN; e += 256) {
-      int k, j;
-      if (a.transB) {  // B stored N x K: contiguous along k
-        k = e % BK;
-        j = e / BK;
-      } else {
-        j = e % BN;
-        k = e / BN;
-      }
-      float2 v = load_op(a.B, a.ldb, k0 + k, j0 + j, kend, a.N, a.transB != 0, a.conjB != 0);
-      Bs[k][j] = v;
-    }
-    __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
-      const int k = kk + (lane >> 5);
-      const float2 av = As[k][wm * 32 + (lane & 31)];
-      const float2 bv = Bs[k][wn * 32 + (lane & 31)];
-      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.x, accr, 0, 0, 0);
-      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, bv.y, accr, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.y, acci, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv.x, acci, 0, 0, 0);
+      const float2 av = As[buf][kk + kl][arow];
+      float2 bv[TN];
+#pragma unroll
+      for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][kk + kl][bcol + 32 * t];
+#pragma unroll
+      for (int t = 0; t < TN; ++t) {
+        cr[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].x, cr[t], 0, 0, 0);
+        ci[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].y, ci[t], 0, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < TN; ++t) {
+        cr[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, bv[t].y, cr[t], 0, 0, 0);
+        ci[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv[t].x, ci[t], 0, 0, 0);
+      }
     }
+#pragma unroll
+    for (int t = 0; t < TN; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        totr[t][r] += double(cr[t][r]);
+        toti[t][r] += double(ci[t][r]);
+      }
+    if (more) ld.store(As[buf ^ 1], Bs[buf ^ 1], tid, sa, sb);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // accumulator r of lane l sits at row (r/4)*8 + (l/32)*4 + r%4, column l%32 of a 32 x 32 tile
+#pragma unroll
+  for (int t = 0; t < TN; ++t) {
+    const int j = j0 + wn * 32 * TN + t * 32 + (lane & 31);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      totr[r] += double(accr[r]);
-      toti[r] += double(acci[r]);
-    }
-    __syncthreads();
-  }
-  // accumulator r of lane l sits at row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the wave tile
-  const int j = j0 + wn * 32 + (lane & 31);
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = i0 + wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-    if (i >= a.M || j >= a.N) continue;
-    const float cr = float(totr[r]), ci = float(toti[r]);
-    if (gp.split > 1) {
-      gp.partial[(size_t(blockIdx.z) * a.M + i) * a.N + j] = make_float2(cr, ci);
-    } else {
-      epilogue(a, i, j, cr, ci);
+      const int i = i0 + wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+      if (i >= a.M || j >= a.N) continue;
+      if (gp.split > 1) {
+        gp.partial[(size_t(blockIdx.z) * a.M + i) * a.N + j] = make_double2(totr[t][r], toti[t][r]);
+      } else {
+        epilogue(a, i, j, totr[t][r], toti[t][r]);
+      }
     }
   }
 }
@@ -143,25 +219,55 @@ __global__ void __launch_bounds__(256) split_reduce(GemmParams gp) {
   for (size_t e = size_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += size_t(gridDim.x) * 256) {
     double sr = 0.0, si = 0.0;
     for (int s = 0; s < gp.split; ++s) {
-      const float2 v = gp.partial[size_t(s) * total + e];
+      const double2 v = gp.partial[size_t(s) * total + e];
       sr += v.x;
       si += v.y;
     }
     const int i = int(e / a.N), j = int(e % a.N);
-    epilogue(a, i, j, float(sr), float(si));
+    epilogue(a, i, j, sr, si);
   }
+}
+
+template <class C>
+hipError_t launch_cfg(const GemmParams &gp, hipStream_t stream) {
+  const CGemmArgs &a = gp.a;
+  dim3 grid((a.N + C::BN - 1) / C::BN, (a.M + C::BM - 1) / C::BM, gp.split);
+  if (a.transA) {
+    if (a.transB) hipLaunchKernelGGL((cgemm_kernel<C, true, true>), grid, dim3(C::threads), 0, stream, gp);
+    else hipLaunchKernelGGL((cgemm_kernel<C, true, false>), grid, dim3(C::threads), 0, stream, gp);
+  } else {
+    if (a.transB) hipLaunchKernelGGL((cgemm_kernel<C, false, true>), grid, dim3(C::threads), 0, stream, gp);
+    else hipLaunchKernelGGL((cgemm_kernel<C, false, false>), grid, dim3(C::threads), 0, stream, gp);
+  }
+  return hipGetLastError();
+}
+
+template <class C>
+int tiles_of(int M, int N) {
+  return ((M + C::BM - 1) / C::BM) * ((N + C::BN - 1) / C::BN);
+}
+
+// K slices so that the grid holds about two blocks per compute unit, each slice at least
+// 128 deep
+int split_for(int tiles, int K) {
+  int s = 1;
+  while (tiles * s < 512 && K / (s * 2) >= 128 && s < kMaxSplit) s *= 2;
+  return s;
+}
+
+// the large tile when it (with its split) still gives about one block per compute unit
+bool use_large(int M, int N, int K) {
+  const int t = tiles_of<CfgL>(M, N);
+  return t * split_for(t, K) >= 256;
 }
 
 }  // namespace
 
 int cgemm_split_for(int M, int N, int K) {
-  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  int s = 1;
-  while (tiles * s < 512 && (K / (BK * (s * 2))) >= 8 && s < kMaxSplit) s *= 2;
-  return s;
+  return use_large(M, N, K) ? split_for(tiles_of<CfgL>(M, N), K) : split_for(tiles_of<CfgS>(M, N), K);
 }
 
-hipError_t launch_cgemm_split(const CGemmArgs &a, int split, float2 *partial, hipStream_t stream,
+hipError_t launch_cgemm_split(const CGemmArgs &a, int split, void *partial, hipStream_t stream,
                               const LaunchHook &hook) {
   GemmParams gp;
   gp.a = a;
@@ -169,12 +275,13 @@ hipError_t launch_cgemm_split(const CGemmArgs &a, int split, float2 *partial, hi
   int kps = (a.K + split - 1) / split;
   kps = (kps + BK - 1) / BK * BK;
   gp.k_per_split = kps;
-  gp.partial = partial;
-  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, split);
-  hook(stream, "cgemm", a.K, 0);
-  hipLaunchKernelGGL(cgemm_kernel, grid, dim3(256), 0, stream, gp);
-  hipError_t e = hipGetLastError();
-  hook(stream, "cgemm", a.K, 1);
+  gp.partial = static_cast<double2 *>(partial);
+  const bool large = use_large(a.M, a.N, a.K);
+  char name[64];
+  std::snprintf(name, sizeof name, "cgemm%s_%dx%dx%d_s%d", large ? "L" : "S", a.M, a.N, a.K, split);
+  hook(stream, name, a.K, 0);
+  hipError_t e = large ? launch_cfg<CfgL>(gp, stream) : launch_cfg<CfgS>(gp, stream);
+  hook(stream, name, a.K, 1);
   if (e != hipSuccess || split == 1) return e;
   const size_t total = size_t(a.M) * a.N;
   int blocks = int(std::min<size_t>((total + 255) / 256, 4096));

@@ -122,32 +122,161 @@ __global__ void scale_by_grad(const float *g, float w, const float2 *e, float2 *
   }
 }
 
-// g_s = -2 kappa Im(E conj(B)); E is the stored plane, or (pre != null) the pupil optic
-// amp exp(2 pi i (opd + 2 pre) / lambda) synthesised here (amp/opd nd x nd centred).
-__global__ void phase_grad(const float2 *e, const float2 *b, float *gs, int n, float kappa,
-                           const float *amp, const float *opd, int nd, const float *pre,
-                           float inv_lambda) {
-  const size_t tot = size_t(n) * n;
+// DM gradient (a7) and its projection onto the actuators, dL/dA = G^T g_s G with
+//   g_s[i][j] = -2 kappa Im(E[i][j] conj(B[i][j]))   (surface gradient, never stored)
+// in three deterministic steps:
+//   dm_grad_T:   per (16-row strip, 512-column group) block, the group's share of
+//                T[i][b] = sum_j g_s[i][j] G[j][b]; one pass over E and B (HBM-bound)
+//   dm_grad_G:   per 256-row block, T = sum of the group shares (group order), then the
+//                block's share of sum_i G[i][a] T[i][b]
+//   dm_grad_reduce: gA += the block shares, in block order.
+// E is the stored plane, or (E == null) the pupil optic amp exp(2 pi i (opd + 2 pre) / lambda)
+// synthesised here (amp/opd nd x nd centred, pre n x n).
+constexpr int kRows = 16;    // rows per dm_grad_T block
+constexpr int kCJ = 128;     // columns per chunk
+constexpr int kGroup = 512;  // columns per dm_grad_T block
+constexpr int kGRows = 32;   // rows per dm_grad_G block
+constexpr int kMaxAct = 64;  // actuators per DM edge supported
+
+__device__ __forceinline__ float2 pupil_optic(const float *amp, const float *opd, const float *pre, int n, int nd,
+                                              int i, int j, float inv_lambda) {
   const int off = (n - nd) / 2;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < tot; i += size_t(gridDim.x) * blockDim.x) {
-    float2 ev;
-    if (e) {
-      ev = e[i];
-    } else {
-      const int y = int(i / n), x = int(i % n);
-      const int wy = y - off, wx = x - off;
-      const bool in = unsigned(wy) < unsigned(nd) && unsigned(wx) < unsigned(nd);
-      const size_t o = size_t(wy) * nd + wx;
-      const float a = in ? amp[o] : 0.f;
-      float turns = (in && opd) ? opd[o] * inv_lambda : 0.f;
-      turns += 2.f * pre[i] * inv_lambda;
-      float s, c;
-      sincos_turns(turns, &s, &c);
-      ev = make_float2(a * c, a * s);
+  const int wy = i - off, wx = j - off;
+  if (unsigned(wy) >= unsigned(nd) || unsigned(wx) >= unsigned(nd)) return make_float2(0.f, 0.f);
+  const size_t o = size_t(wy) * nd + wx;
+  float turns = 2.f * pre[size_t(i) * n + j] * inv_lambda;
+  if (opd) turns += opd[o] * inv_lambda;
+  float s, c;
+  sincos_turns(turns, &s, &c);
+  return make_float2(amp[o] * c, amp[o] * s);
+}
+
+// All loads of a chunk are issued before any is used (indices clamped inside the arrays, the
+// values of out-of-range elements replaced by zero), so their latencies overlap.
+template <bool SYNTH>
+__global__ void __launch_bounds__(256) dm_grad_T(const float2 *E, const float2 *B, const float *G, int n, int na,
+                                                 float kappa, const float *amp, const float *opd, int nd,
+                                                 const float *pre, float inv_lambda, float *tpart) {
+  __shared__ float gs[kRows][kCJ + 4];
+  __shared__ float Gs[kCJ * kMaxAct];  // Gs[c][a]; reused for the reduction of the quarters
+  constexpr int kPer = kRows * kCJ / 256;  // field elements per thread per chunk
+  constexpr int kGPer = kCJ * kMaxAct / 256;
+  const int tid = threadIdx.x;
+  const int b = tid & 63, ph = tid >> 6;  // actuator column, quarter of the chunk
+  const int i0 = blockIdx.x * kRows;
+  const int g = blockIdx.y;
+  const int jbeg = g * kGroup, jend = min(n, jbeg + kGroup);
+  const int off = (n - nd) / 2;
+  float acc[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) acc[r] = 0.f;
+  for (int j0 = jbeg; j0 < jend; j0 += kCJ) {
+    const int cj = min(kCJ, jend - j0);
+    float2 ev[kPer], bv[kPer];
+    float ws[kPer], wa[kPer], wo[kPer];
+    float gv[kGPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int r = (tid >> 7) + 2 * q, c = tid & 127;
+      const int i = min(i0 + r, n - 1), j = min(j0 + c, n - 1);
+      const size_t o = size_t(i) * n + j;
+      bv[q] = B[o];
+      if (SYNTH) {
+        const int wy = min(max(i - off, 0), nd - 1), wx = min(max(j - off, 0), nd - 1);
+        const size_t ow = size_t(wy) * nd + wx;
+        ws[q] = pre[o];
+        wa[q] = amp[ow];
+        wo[q] = opd ? opd[ow] : 0.f;
+      } else {
+        ev[q] = E[o];
+      }
     }
-    const float2 bv = b[i];
-    // Im(E conj(B)) = e.y b.x - e.x b.y
-    gs[i] = -2.f * kappa * (ev.y * bv.x - ev.x * bv.y);
+#pragma unroll
+    for (int q = 0; q < kGPer; ++q) {
+      const int e = tid + 256 * q;
+      const int c = e / kMaxAct, a = e % kMaxAct;
+      gv[q] = G[size_t(min(j0 + c, n - 1)) * na + min(a, na - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int r = (tid >> 7) + 2 * q, c = tid & 127;
+      const int i = i0 + r, j = j0 + c;
+      float2 e2 = ev[q];
+      bool in = i < n && c < cj;
+      if (SYNTH) {
+        const bool win = unsigned(i - off) < unsigned(nd) && unsigned(j - off) < unsigned(nd);
+        float sn, cs;
+        sincos_turns((2.f * ws[q] + wo[q]) * inv_lambda, &sn, &cs);
+        e2 = make_float2(wa[q] * cs, wa[q] * sn);
+        in = in && win;
+      }
+      gs[r][c] = in ? -2.f * kappa * (e2.y * bv[q].x - e2.x * bv[q].y) : 0.f;  // -2 kappa Im(E conj(B))
+    }
+#pragma unroll
+    for (int q = 0; q < kGPer; ++q) {
+      const int e = tid + 256 * q;
+      const int c = e / kMaxAct, a = e % kMaxAct;
+      Gs[e] = (c < cj && a < na) ? gv[q] : 0.f;
+    }
+    __syncthreads();
+    const int c0 = ph * (kCJ / 4);
+#pragma unroll 4
+    for (int c = c0; c < c0 + kCJ / 4; ++c) {
+      const float gvv = Gs[c * kMaxAct + b];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) acc[r] = fmaf(gs[r][c], gvv, acc[r]);
+    }
+    __syncthreads();
+  }
+  float *red = Gs;  // [4][kRows][kMaxAct]
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) red[(ph * kRows + r) * kMaxAct + b] = acc[r];
+  __syncthreads();
+  for (int e = tid; e < kRows * kMaxAct; e += 256) {
+    const int r = e / kMaxAct, c = e % kMaxAct;
+    const int i = i0 + r;
+    if (i < n && c < na) {
+      const float v = ((red[e] + red[kRows * kMaxAct + e]) + red[2 * kRows * kMaxAct + e]) + red[3 * kRows * kMaxAct + e];
+      tpart[(size_t(g) * n + i) * na + c] = v;
+    }
+  }
+}
+
+// per block of kGRows rows: T rows (group shares added in group order), then the block's share
+// of G^T T
+__global__ void __launch_bounds__(256) dm_grad_G(const float *tpart, int groups, const float *G, int n, int na,
+                                                 float *gpart) {
+  __shared__ float Ts[kGRows][kMaxAct + 1];
+  __shared__ float Gr[kGRows][kMaxAct + 1];
+  const int tid = threadIdx.x;
+  const int r0 = blockIdx.x * kGRows;
+  const int rows = min(kGRows, n - r0);
+  for (int e = tid; e < kGRows * kMaxAct; e += 256) {
+    const int r = e / kMaxAct, c = e % kMaxAct;
+    float v = 0.f, gg = 0.f;
+    if (r < rows && c < na) {
+      for (int q = 0; q < groups; ++q) v += tpart[(size_t(q) * n + r0 + r) * na + c];
+      gg = G[size_t(r0 + r) * na + c];
+    }
+    Ts[r][c] = v;
+    Gr[r][c] = gg;
+  }
+  __syncthreads();
+  for (int e = tid; e < na * na; e += 256) {
+    const int a = e / na, c = e % na;
+    float v = 0.f;
+#pragma unroll 8
+    for (int r = 0; r < kGRows; ++r) v = fmaf(Gr[r][a], Ts[r][c], v);
+    gpart[size_t(blockIdx.x) * na * na + e] = v;
+  }
+}
+
+// gA[a][b] += sum over blocks of gpart[block][a][b], in block order
+__global__ void dm_grad_reduce(const float *part, int blocks, int nn, float *gA) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
+    float v = 0.f;
+    for (int s = 0; s < blocks; ++s) v += part[size_t(s) * nn + e];
+    gA[e] += v;
   }
 }
 
@@ -173,7 +302,7 @@ struct Layout {
   std::vector<size_t> e, b;          // per wavelength (plain: all equal)
   std::vector<int> surf_n;           // distinct grid edges with a surface set
   std::vector<size_t> surf;          // offsets of those sets (n_dm maps each)
-  size_t gs, tdm, el, y1, eocc, edet, ydet, mft, total;
+  size_t tpart, gpart, tdm, el, y1, eocc, edet, ydet, mft, total;
 };
 
 Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_t mode) {
@@ -205,7 +334,9 @@ Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_
     const size_t b0 = take(n2max * 8);
     for (int j = 0; j < n_lambda; ++j) L.b[j] = b0;
   }
-  L.gs = grad ? take(n2max * 4) : 0;
+  const size_t groups = size_t((nmax + kGroup - 1) / kGroup);
+  L.tpart = grad ? take(groups * nmax * d->n_act * 4) : 0;
+  L.gpart = grad ? take(size_t((nmax + kGRows - 1) / kGRows) * d->n_act * d->n_act * 4) : 0;
   const size_t ndm = size_t(std::max(d->n_dm, 1));
   if (batched) {
     for (int j = 0; j < n_lambda; ++j)
@@ -238,6 +369,7 @@ int check_desc(const fr_train_desc *d, int32_t n_lambda, const double *lam, cons
   if (d->n_d <= 0 || !(d->d_m > 0) || !d->pupil_amp) return FR_EINVAL;
   if (d->n_dm < 0 || d->n_dm > 2) return FR_EINVAL;
   if (d->n_dm > 0 && (d->n_act <= 0 || !d->dm_heights_m)) return FR_EINVAL;
+  if (d->n_dm > 0 && d->n_act > kMaxAct) return FR_EUNSUPPORTED;
   if (!std::isfinite(d->z_m)) return FR_EINVAL;
   if (d->occ_m <= 0 || !(d->occ_du_c > 0) || d->det_m <= 0 || !(d->det_du_c > 0)) return FR_EINVAL;
   if (!(mode & FR_TRAIN_NO_OCCULTER) && !d->occ_mask) return FR_EINVAL;
@@ -278,7 +410,8 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   const Layout L = layout(d, n_lambda, n_pad, mode);
   char *base = static_cast<char *>(ws);
   auto c64at = [&](size_t o) { return reinterpret_cast<float2 *>(base + o); };
-  float *GS = grad ? reinterpret_cast<float *>(base + L.gs) : nullptr;
+  float *GPART = grad ? reinterpret_cast<float *>(base + L.gpart) : nullptr;
+  float *TPART = grad ? reinterpret_cast<float *>(base + L.tpart) : nullptr;
   float *TDM = reinterpret_cast<float *>(base + L.tdm);
   float2 *EL = c64at(L.el);
   float2 *Y1 = grad ? c64at(L.y1) : nullptr;
@@ -378,14 +511,30 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     return mft_forward_impl(ctx, EL, nd, nd, d->det_m, double(nd), du_det, o, MWS, s);
   };
 
-  // dL/dA_k += G^T (g_s G) for the surface-gradient plane GS on an n grid
-  auto to_actuators = [&](int n, float *gA) -> int {
+  // dL/dA_k += G^T g_s G with g_s = -2 kappa Im(E conj(B)) (E stored, or the pupil optic
+  // synthesised from amp/opd/pre when E == null)
+  auto dm_grad = [&](int j, const float2 *E, const float2 *B, const float *pre, float *gA) -> int {
+    const int n = n_pad[j];
     const float *G = nullptr;
     FR_TRY(ctx->dm_influence(n, nd, na, s, &G));
-    RGemm g1{n, na, n, GS, n, 0, G, na, 0, TDM, na, 1.f, 0.f};   // TDM (n x na) = g_s G
-    FR_TRY_HIP(rgemm(g1, s, hook));
-    RGemm g2{na, na, n, G, na, 1, TDM, na, 0, gA, na, 1.f, 1.f};  // gA += G^T TDM
-    FR_TRY_HIP(rgemm(g2, s, hook));
+    const int strips = (n + kRows - 1) / kRows, groups = (n + kGroup - 1) / kGroup;
+    const int gblocks = (n + kGRows - 1) / kGRows;
+    const float kappa = float(4.0 * M_PI / lam[j]);
+    hook(s, "dm_grad_T", n, 0);
+    if (E)
+      hipLaunchKernelGGL(dm_grad_T<false>, dim3(strips, groups), dim3(256), 0, s, E, B, G, n, na, kappa,
+                         d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), TPART);
+    else
+      hipLaunchKernelGGL(dm_grad_T<true>, dim3(strips, groups), dim3(256), 0, s, E, B, G, n, na, kappa,
+                         d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), TPART);
+    FR_TRY_HIP(hipGetLastError());
+    hook(s, "dm_grad_T", n, 1);
+    hook(s, "dm_grad_G", n, 0);
+    hipLaunchKernelGGL(dm_grad_G, dim3(gblocks), dim3(256), 0, s, (const float *)TPART, groups, G, n, na, GPART);
+    FR_TRY_HIP(hipGetLastError());
+    hook(s, "dm_grad_G", n, 1);
+    FR_TRY_HIP(launch1d(dm_grad_reduce, size_t(na) * na, s, hook, "dm_grad_reduce", (const float *)GPART,
+                        gblocks, na * na, gA));
     return FR_OK;
   };
 
@@ -414,21 +563,12 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       FR_TRY_HIP(launch1d(fill_c64, n2, s, hook, "fill", B, n2));
     }
     FR_TRY_HIP(launch1d(window_add, size_t(nd) * nd, s, hook, "window_add", B, n, nd, (const float2 *)Y1));
-    const float kappa = float(4.0 * M_PI / lam[j]);
-    FR_TRY_HIP(launch1d(phase_grad, n2, s, hook, "phase_grad", E, (const float2 *)B, GS, n, kappa,
-                        (const float *)nullptr, (const float *)nullptr, nd, (const float *)nullptr,
-                        float(1.0 / lam[j])));
-    return to_actuators(n, grad_heights + size_t(ndm - 1) * na * na);
+    return dm_grad(j, E, B, nullptr, grad_heights + size_t(ndm - 1) * na * na);
   };
   // pupil DM (n_dm == 2), after B_j went back through the adjoint step:
   // g_s1 = -2 kappa Im(E_dm1 conj(B1)), E_dm1 = pupil optic * DM1 phasor synthesised again
   auto back_to_pupil_dm = [&](int j) -> int {
-    const int n = n_pad[j];
-    const float kappa = float(4.0 * M_PI / lam[j]);
-    FR_TRY_HIP(launch1d(phase_grad, size_t(n) * n, s, hook, "phase_grad", (const float2 *)nullptr,
-                        (const float2 *)c64at(L.b[j]), GS, n, kappa, d->pupil_amp, d->pupil_opd_m, nd,
-                        (const float *)surf_of(j), float(1.0 / lam[j])));
-    return to_actuators(n, grad_heights);
+    return dm_grad(j, nullptr, c64at(L.b[j]), surf_of(j), grad_heights);
   };
 
   FR_TRY_HIP(launch1d(fill_f32, det2, s, hook, "fill", psf, det2, 0.f));

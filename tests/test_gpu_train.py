@@ -161,41 +161,53 @@ def test_autograd_function_matches_direct_call():
     assert torch.allclose(h.grad, gh, rtol=0, atol=0)
 
 
-def test_batched_equals_plain_mixed_grids():
-    # one launch per sweep for all wavelengths gives the same PSF and gradient, bit for bit
+def test_batched_matches_plain_mixed_grids():
+    # a batch of mixed edges runs every plane through the mixed-radix sweeps, so it agrees with
+    # the plain mode to float32 rounding; a batch of one power-of-two edge is bit-identical
     banner("train batched vs plain, 2 DMs, grids 96 / 120 / 128 / 160")
     geom, tr, heights, hg = make(64, 64, 8 / 64, 64, 0.5, 0.05, 8, 2, spider=0.04)
     lams = list(synth.wavelengths(4))
     ns, w = [96, 120, 128, 160], [0.25] * 4
-    dh = to_gpu(synth.dark_hole(64, 0.5, 3.0, 7.0), torch.float32)
+    dhn = synth.dark_hole(64, 0.5, 3.0, 7.0)
+    dh = to_gpu(dhn / dhn.sum(), torch.float32)
     p0, g0 = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh)
     p1, g1 = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh, batched=True)
-    torch.cuda.synchronize()
-    assert torch.equal(p0, p1)
-    assert torch.equal(g0, g1)
+    assert rel_l2(_np(p1), _np(p0)) <= 1e-6
+    assert rel_l2(_np(g1), _np(g0)) <= 1e-5
     ref = oracle.train_psf(geom, lams, ns, w, heights)
     assert rel_l2(_np(p1), ref) <= 1e-5
+    gref = np.stack(oracle.train_grad(geom, lams, ns, w, heights, dhn, 1.0))
+    assert rel_l2(_np(g1), gref) <= 1e-4
+    u0, v0 = fb.propagate_train(tr, lams, [128] * 4, w, hg, grad_psf=dh)
+    u1, v1 = fb.propagate_train(tr, lams, [128] * 4, w, hg, grad_psf=dh, batched=True)
+    torch.cuda.synchronize()
+    assert torch.equal(u0, u1)
+    assert torch.equal(v0, v1)
 
 
 def test_broadband_train_batched_full_size():
     # the broadband model: 1024 pupil, 21 wavelengths over 500-600 nm on per-wavelength grids
-    # 3584 ... 4096; batched equals plain bit for bit, and three of the wavelengths (one per
-    # radix family) are checked against the oracle one by one
+    # 3584 ... 4096 in one batch (equal weights). Batched agrees with plain to float32
+    # rounding; the broadband PSF and normalised contrast C = sum_j w_j I_j / max(sum_j w_j
+    # I_ref,j) are checked against the oracle over all 21 wavelengths
     banner("broadband train: 21 wavelengths, grids 3584..4096, batched vs plain")
     geom, tr, heights, hg = make(1024, 256, 8 / 256, 512, 0.25, 1.0, 48, 1)
     lams = list(synth.wavelengths(21))
     ns = list(synth.padded_sizes(21))
     w = [1.0 / 21] * 21
-    p_plain = fb.propagate_train(tr, lams, ns, w, hg)
-    p_batch = fb.propagate_train(tr, lams, ns, w, hg, batched=True)
-    torch.cuda.synchronize()
-    assert torch.equal(p_plain, p_batch)
+    p_plain = _np(fb.propagate_train(tr, lams, ns, w, hg))
+    p_batch = _np(fb.propagate_train(tr, lams, ns, w, hg, batched=True))
+    p_ref0 = _np(fb.propagate_train(tr, lams, ns, w, hg, batched=True, occulter=False))
+    assert rel_l2(p_batch, p_plain) <= 1e-6
+    banner("broadband train: oracle over 21 wavelengths (about a minute)")
     cache = {}
-    for j in (0, 7, 20):
-        banner(f"broadband train: wavelength {j}, grid {ns[j]} vs oracle")
-        one = _np(fb.propagate_train(tr, [lams[j]], [ns[j]], [1.0], hg, batched=True))
-        ref = oracle.train_psf(geom, [lams[j]], [ns[j]], [1.0], heights, step_cache=cache)
-        assert rel_l2(one, ref) <= 1e-5
+    ref = oracle.train_psf(geom, lams, ns, w, heights, step_cache=cache)
+    ref0 = oracle.train_psf(geom, lams, ns, w, heights, occulter=False, step_cache=cache)
+    assert rel_l2(p_batch, ref) <= 1e-5
+    assert rel_l2(p_ref0, ref0) <= 1e-5
+    err = np.max(np.abs(p_batch / p_ref0.max() - ref / ref0.max()))
+    banner(f"broadband max |dC| = {err:.3e}, peak contrast {np.max(ref / ref0.max()):.3e}")
+    assert err <= 1e-9
 
 
 def test_graph_mode_replays_match_eager():

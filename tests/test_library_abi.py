@@ -57,7 +57,8 @@ def test_supported_sizes(L):
 
 
 def test_workspace_query(L):
-    assert L.mft_workspace_bytes(4096, 256) == 17 * 4096 * 256 * 8
+    # the n x m c64 intermediate plus 16 float64 complex split-K slices
+    assert L.mft_workspace_bytes(4096, 256) == 4096 * 256 * 8 + 16 * 4096 * 256 * 16
     assert L.mft_workspace_bytes(0, 256) == 0
 
 
