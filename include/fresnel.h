@@ -126,7 +126,7 @@ int mft_adjoint(fr_ctx *ctx, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_c
  *   Eo  = MFT(E: whole padded plane -> occ_m^2, du = occ_du_c lambda_c / lambda)
  *   EL  = lyot * ( window_{n_d}(E) - MFT^H(occ_mask * Eo -> n_d^2) )
  *   Ed  = MFT(EL -> det_m^2, du = det_du_c lambda_c / lambda)
- *   psf = sum_j weight_j |Ed_j|^2                           (det_m^2 float, overwritten)
+ *   psf = sum_j weight_j |Ed_j|^2    (det_m^2 float, overwritten; summed in float64, rounded once)
  * FR_TRAIN_NO_OCCULTER skips the occulter term (the reference PSF).
  * FR_TRAIN_GRAD additionally takes grad_psf = dL/dpsf (det_m^2 float) and writes
  * grad_heights = dL/dA (n_dm * n_act^2 float, DM1 first), the chain rule through every

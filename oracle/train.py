@@ -13,8 +13,8 @@ the whole sequence is repeated for every wavelength), reduced to a fixed topolog
 
 Focal grids are fixed in units of lambda_c/D, so the per-wavelength sampling is
 du_lambda = du_c lambda_c / lambda and every mask is one lambda-independent array.
-The deformable mirrors and the gradient are this build's additions on top of the paper's
-forward model; their definitions are the ordinary chain rule of that model.
+The deformable mirrors and the gradient are additions on top of the paper's forward model;
+their definitions are the ordinary chain rule of that model.
 """
 
 from dataclasses import dataclass, field

@@ -291,7 +291,7 @@ size_t mft_ws_bytes(int n, int m) {
 static CGemmArgs gemm_args() {
   CGemmArgs g;
   std::memset(&g, 0, sizeof g);
-  g.alpha_re = 1.0f;
+  g.alpha_re = 1.0;
   return g;
 }
 
@@ -323,7 +323,7 @@ int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out,
   g2.A = w; g2.lda = n_in;
   g2.B = t; g2.ldb = m_out;
   g2.C = o.out; g2.ldc = o.ld_out; g2.skip_c = o.skip_out ? 1 : 0;
-  g2.alpha_re = float(du / n_d);
+  g2.alpha_re = du / n_d;
   g2.mask = o.mask; g2.ldm = m_out;
   g2.intensity = o.intensity; g2.ldi = m_out; g2.weight = o.weight;
   e = run_gemm(ctx, g2, partial, pcap, s);
@@ -353,7 +353,7 @@ int mft_adjoint_impl(Ctx *ctx, const float2 *in, int m_in, int ld_in, float2 *ou
   g2.A = w; g2.lda = n_out; g2.transA = 1; g2.conjA = 1;
   g2.B = t; g2.ldb = n_out;
   g2.C = out; g2.ldc = ld_out;
-  g2.alpha_re = float(alpha * (du / n_d));
+  g2.alpha_re = double(alpha) * (du / n_d);
   g2.beta = beta; g2.Cin = cin; g2.ldcin = ld_cin;
   g2.mask = mask; g2.ldm = n_out;
   e = run_gemm(ctx, g2, partial, pcap, s);

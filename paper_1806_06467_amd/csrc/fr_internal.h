@@ -94,15 +94,15 @@ struct CGemmArgs {
   int transA;       // 1: A is given as K x M (use A^T)
   int transB;       // 1: B is given as N x K (use B^T)
   int conjA, conjB; // conjugate the operand on load
-  float alpha_re, alpha_im;
+  double alpha_re, alpha_im;  // applied in float64 in the epilogue
   float beta;       // real; the beta term reads Cin (row stride ldcin), or C when Cin is null
   const float2 *Cin;
   int ldcin;
   const float *mask;  // M x N (row stride ldm) or null: multiplies the result
   int ldm;
-  float *intensity;   // M x N (row stride ldi) or null: intensity += weight |result|^2
+  double *intensity;  // M x N (row stride ldi) or null: intensity += weight |result|^2 (float64)
   int ldi;
-  float weight;
+  double weight;
   int skip_c;         // 1: do not write C (only the intensity)
 };
 // C = alpha op(A) op(B) (+ beta C) (* mask). split > 1 slices K; the slices' partial sums go

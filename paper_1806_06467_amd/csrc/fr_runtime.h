@@ -70,8 +70,8 @@ struct MftOut {
   float2 *out = nullptr;
   int ld_out = 0;
   const float *mask = nullptr;
-  float *intensity = nullptr;  // + weight |out|^2 (det grid, row stride = width)
-  float weight = 0.f;
+  double *intensity = nullptr;  // + weight |out|^2 in float64 (det grid, row stride = width)
+  double weight = 0.0;
   bool skip_out = false;
 };
 int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out, double n_d,

@@ -37,10 +37,10 @@ struct GemmParams {
 };
 
 // result (i, j) = alpha acc + beta Cin, times mask, in float64; written to C and/or
-// accumulated as weight |result|^2 into the intensity map
+// accumulated as weight |result|^2 into the float64 intensity map
 __device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, double cr, double ci) {
-  double orr = double(a.alpha_re) * cr - double(a.alpha_im) * ci;
-  double oi = double(a.alpha_re) * ci + double(a.alpha_im) * cr;
+  double orr = a.alpha_re * cr - a.alpha_im * ci;
+  double oi = a.alpha_re * ci + a.alpha_im * cr;
   if (a.beta != 0.f) {
     const float2 old = a.Cin ? a.Cin[size_t(i) * a.ldcin + j] : a.C[size_t(i) * a.ldc + j];
     orr += double(a.beta) * double(old.x);
@@ -51,11 +51,10 @@ __device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, doubl
     orr *= mk;
     oi *= mk;
   }
-  const float2 outv = make_float2(float(orr), float(oi));
-  if (!a.skip_c) a.C[size_t(i) * a.ldc + j] = outv;
+  if (!a.skip_c) a.C[size_t(i) * a.ldc + j] = make_float2(float(orr), float(oi));
   if (a.intensity) {
-    float *ip = a.intensity + size_t(i) * a.ldi + j;
-    *ip += a.weight * (outv.x * outv.x + outv.y * outv.y);
+    double *ip = a.intensity + size_t(i) * a.ldi + j;
+    *ip += a.weight * (orr * orr + oi * oi);
   }
 }
 

@@ -25,11 +25,6 @@ namespace {
 constexpr int kT = kMrThreads;    // threads per line
 constexpr int kEM = kMrMaxN / kT;  // slots per thread for the global load / store
 
-__device__ __forceinline__ c32 ld2(const float2 *p) {
-  float2 v = *p;
-  return {v.x, v.y};
-}
-
 struct Buf64 {
   __amdgpu_buffer_rsrc_t r;
   typedef unsigned int raw64 __attribute__((__vector_size__(8)));
@@ -53,37 +48,53 @@ struct Buf32 {
   }
 };
 
-// pre optic amp exp(2 pi i (opd + 2 pre_surf) / lambda) lens[x] lens[y] at (y, x), x < n
-__device__ __forceinline__ c32 mr_pre_optic(const PlaneArgs &pa, int n, int y, int x) {
-  const int win = pa.win;
-  const int off = (n - win) >> 1;
-  const int wy = y - off, wx = x - off;
-  const bool in = unsigned(wy) < unsigned(win) && unsigned(wx) < unsigned(win);
-  float a = 1.0f, turns = 0.0f;
-  if (pa.amp || pa.opd) {
-    const unsigned o = unsigned(min(max(wy, 0), win - 1) * win + min(max(wx, 0), win - 1)) * 4u;
-    const unsigned bytes = unsigned(win) * unsigned(win) * 4u;
-    if (pa.amp) a = in ? Buf32(pa.amp, bytes).load(o) : 0.0f;
-    if (pa.opd && in) turns = Buf32(pa.opd, bytes).load(o) * pa.inv_lambda;
-  }
-  if (pa.pre_surf)
-    turns += 2.0f * Buf32(pa.pre_surf, unsigned(n) * unsigned(n) * 4u).load(unsigned(y * n + x) * 4u) * pa.inv_lambda;
+// The optic maps of a plane as buffer resources. A missing map gets zero records, so its loads
+// return 0 without touching memory: every slot's loads are then issued together, with no
+// branch between them, and the selects below drop the missing terms.
+struct PreMaps {
+  Buf32 amp, opd, pre;
+  Buf64 lens;
+  int n, win, off;
+  float inv_lambda;
+  bool has_amp, has_phase, has_lens;
+  __device__ __forceinline__ PreMaps(const PlaneArgs &pa, int n_)
+      : amp(pa.amp, pa.amp ? unsigned(pa.win) * unsigned(pa.win) * 4u : 0u),
+        opd(pa.opd, pa.opd ? unsigned(pa.win) * unsigned(pa.win) * 4u : 0u),
+        pre(pa.pre_surf, pa.pre_surf ? unsigned(n_) * unsigned(n_) * 4u : 0u),
+        lens(pa.lens, pa.lens ? unsigned(n_) * 8u : 0u),
+        n(n_), win(pa.win), off((n_ - pa.win) >> 1), inv_lambda(pa.inv_lambda), has_amp(pa.amp != nullptr),
+        has_phase(pa.opd != nullptr || pa.pre_surf != nullptr), has_lens(pa.lens != nullptr) {}
+};
+struct PreVals {
+  float a, o, p;
+  c32 lx;
+};
+
+// loads of the pre optic at (y, x), both < n
+__device__ __forceinline__ PreVals pre_fetch(const PreMaps &m, int y, int x) {
+  const int wy = min(max(y - m.off, 0), m.win - 1), wx = min(max(x - m.off, 0), m.win - 1);
+  const unsigned o = unsigned(wy * m.win + wx) * 4u;
+  PreVals v;
+  v.a = m.amp.load(o);
+  v.o = m.opd.load(o);
+  v.p = m.pre.load(unsigned(y * m.n + x) * 4u);
+  v.lx = m.lens.load(unsigned(x) * 8u);
+  return v;
+}
+
+// pre optic amp exp(2 pi i (opd + 2 pre_surf) / lambda) lens[x] lens[y] at (y, x); ly = lens[y]
+__device__ __forceinline__ c32 pre_optic(const PreMaps &m, const PreVals &v, int y, int x, c32 ly) {
+  const bool in = unsigned(y - m.off) < unsigned(m.win) && unsigned(x - m.off) < unsigned(m.win);
+  const float a = m.has_amp ? (in ? v.a : 0.0f) : 1.0f;
   c32 ph = {a, 0.0f};
-  if (pa.opd || pa.pre_surf) {
+  if (m.has_phase) {
+    const float turns = (in ? v.o : 0.0f) * m.inv_lambda + 2.0f * v.p * m.inv_lambda;
     float s, c;
     sincos_turns(turns, &s, &c);
     ph = {a * c, a * s};
   }
-  if (pa.lens) ph = cmul(ph, cmul(ld2(pa.lens + x), ld2(pa.lens + y)));
+  if (m.has_lens) ph = cmul(ph, cmul(v.lx, ly));
   return ph;
-}
-
-__device__ __forceinline__ c32 mr_post_optic(const PlaneArgs &pa, int n, int y, int x) {
-  float s, c;
-  sincos_turns(2.0f * Buf32(pa.post_surf, unsigned(n) * unsigned(n) * 4u).load(unsigned(y * n + x) * 4u) *
-                   pa.inv_lambda,
-               &s, &c);
-  return {c, s};
 }
 
 __device__ __forceinline__ bool mr_has_pre(const PlaneArgs &pa) {
@@ -117,6 +128,28 @@ __device__ __forceinline__ int mr_item(int round) {
   return round * g + local;
 }
 
+// slots of the global load / store handled per batch of optic loads
+constexpr int kOptBatch = 8;
+
+// multiplies v[0..kEM) of row y by the pre optic (conjugated when CONJ), in batches of
+// kOptBatch slots whose loads are issued together
+template <bool CONJ>
+__device__ __forceinline__ void apply_pre(c32 (&v)[kEM], const PlaneArgs &pa, int n, int y, int t, bool source) {
+  const PreMaps pm(pa, n);
+  const c32 ly = pm.lens.load(unsigned(y) * 8u);
+#pragma unroll
+  for (int m0 = 0; m0 < kEM; m0 += kOptBatch) {
+    PreVals pv[kOptBatch];
+#pragma unroll
+    for (int q = 0; q < kOptBatch; ++q) pv[q] = pre_fetch(pm, y, min(t + kT * (m0 + q), n - 1));
+#pragma unroll
+    for (int q = 0; q < kOptBatch; ++q) {
+      const c32 ph = pre_optic(pm, pv[q], y, min(t + kT * (m0 + q), n - 1), ly);
+      v[m0 + q] = source ? ph : (CONJ ? cmulc(v[m0 + q], ph) : cmul(v[m0 + q], ph));
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kT) mr_row_sweep(MrBatch) {
   const MrBatch &args = kernarg_batch();
   __shared__ c32 lds[LdsLine<kMrMaxN>::size];
@@ -130,33 +163,30 @@ __global__ void __launch_bounds__(kT) mr_row_sweep(MrBatch) {
       const int n = mp.n, y = item - mp.first;
       const int t = mr_opaque(t0);
       const bool adj = pa.flags & FR_ADJOINT;
+      const bool source = pa.flags & kSourceOptic;
+      const bool pre = mr_has_pre(pa);
       const Buf64 fb(pa.field, unsigned(n) * unsigned(n) * 8u);
+      c32 v[kEM];
+      if (source) {
 #pragma unroll
-      for (int m = 0; m < kEM; ++m) {
-        const int x = t + kT * m;
-        if (x < n) {
-          c32 v;
-          if (pa.flags & kSourceOptic) {
-            v = mr_has_pre(pa) ? mr_pre_optic(pa, n, y, x) : c32{1.0f, 0.0f};
-          } else {
-            v = fb.load(unsigned(y * n + x) * 8u);
-            if (!adj && mr_has_pre(pa)) v = cmul(v, mr_pre_optic(pa, n, y, x));
-          }
-          lds[lds_pad(x)] = v;
-        }
+        for (int m = 0; m < kEM; ++m) v[m] = {1.0f, 0.0f};
+      } else {
+#pragma unroll
+        for (int m = 0; m < kEM; ++m) v[m] = fb.load(unsigned(y * n + min(t + kT * m, n - 1)) * 8u);
       }
+      if (!adj && pre) apply_pre<false>(v, pa, n, y, t, source);
+#pragma unroll
+      for (int m = 0; m < kEM; ++m)
+        if (t + kT * m < n) lds[lds_pad(t + kT * m)] = v[m];
       __syncthreads();
       plane_fft<false>(lds, mp, t, nullptr, false);
       plane_fft<true>(lds, mp, t, pa.h, adj);
 #pragma unroll
-      for (int m = 0; m < kEM; ++m) {
-        const int x = t + kT * m;
-        if (x < n) {
-          c32 v = lds[lds_pad(x)];
-          if (adj && mr_has_pre(pa)) v = cmulc(v, mr_pre_optic(pa, n, y, x));
-          fb.store(unsigned(y * n + x) * 8u, v);
-        }
-      }
+      for (int m = 0; m < kEM; ++m) v[m] = lds[lds_pad(min(t + kT * m, n - 1))];
+      if (adj && pre) apply_pre<true>(v, pa, n, y, t, false);
+#pragma unroll
+      for (int m = 0; m < kEM; ++m)
+        if (t + kT * m < n) fb.store(unsigned(y * n + t + kT * m) * 8u, v[m]);
       __syncthreads();
     }
   }
@@ -181,27 +211,45 @@ __global__ void __launch_bounds__(kT * 4) mr_col_sweep(MrBatch) {
       const int xc = min(x, n - 1);
       const bool adj = pa.flags & FR_ADJOINT;
       const Buf64 fb(pa.field, unsigned(n) * unsigned(n) * 8u);
+      // a missing post map has zero records (its loads return 0)
+      const Buf32 post(pa.post_surf, pa.post_surf ? unsigned(n) * unsigned(n) * 4u : 0u);
+      const bool has_post = pa.post_surf != nullptr;
+      c32 v[kEM];
 #pragma unroll
-      for (int m = 0; m < kEM; ++m) {
-        const int y = t + kT * m;
-        if (y < n) {
-          c32 v = fb.load(unsigned(y * n + xc) * 8u);
-          if (adj && pa.post_surf) v = cmulc(v, mr_post_optic(pa, n, y, xc));
-          my[lds_pad(y)] = v;
+      for (int m = 0; m < kEM; ++m) v[m] = fb.load(unsigned(min(t + kT * m, n - 1) * n + xc) * 8u);
+      if (adj && has_post) {
+        float sv[kEM];
+#pragma unroll
+        for (int m = 0; m < kEM; ++m) sv[m] = post.load(unsigned(min(t + kT * m, n - 1) * n + xc) * 4u);
+#pragma unroll
+        for (int m = 0; m < kEM; ++m) {
+          float sn, cs;
+          sincos_turns(2.0f * sv[m] * pa.inv_lambda, &sn, &cs);
+          v[m] = cmulc(v[m], c32{cs, sn});
         }
       }
+#pragma unroll
+      for (int m = 0; m < kEM; ++m)
+        if (t + kT * m < n) my[lds_pad(t + kT * m)] = v[m];
       __syncthreads();
       plane_fft<false>(my, mp, t, nullptr, false);
       plane_fft<true>(my, mp, t, pa.h, adj);
 #pragma unroll
-      for (int m = 0; m < kEM; ++m) {
-        const int y = t + kT * m;
-        if (y < n && xin) {
-          c32 v = my[lds_pad(y)];
-          if (!adj && pa.post_surf) v = cmul(v, mr_post_optic(pa, n, y, x));
-          fb.store(unsigned(y * n + x) * 8u, v);
+      for (int m = 0; m < kEM; ++m) v[m] = my[lds_pad(min(t + kT * m, n - 1))];
+      if (!adj && has_post) {
+        float sv[kEM];
+#pragma unroll
+        for (int m = 0; m < kEM; ++m) sv[m] = post.load(unsigned(min(t + kT * m, n - 1) * n + xc) * 4u);
+#pragma unroll
+        for (int m = 0; m < kEM; ++m) {
+          float sn, cs;
+          sincos_turns(2.0f * sv[m] * pa.inv_lambda, &sn, &cs);
+          v[m] = cmul(v[m], c32{cs, sn});
         }
       }
+#pragma unroll
+      for (int m = 0; m < kEM; ++m)
+        if (t + kT * m < n && xin) fb.store(unsigned((t + kT * m) * n + x) * 8u, v[m]);
       __syncthreads();
     }
   }

@@ -85,6 +85,16 @@ __global__ void fill_f32(float *p, size_t n, float v) {
     p[i] = v;
 }
 
+__global__ void fill_f64(double *p, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    p[i] = 0.0;
+}
+
+__global__ void to_f32(const double *src, float *dst, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    dst[i] = float(src[i]);
+}
+
 __global__ void fill_c64(float2 *p, size_t n) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
     p[i] = make_float2(0.f, 0.f);
@@ -302,7 +312,7 @@ struct Layout {
   std::vector<size_t> e, b;          // per wavelength (plain: all equal)
   std::vector<int> surf_n;           // distinct grid edges with a surface set
   std::vector<size_t> surf;          // offsets of those sets (n_dm maps each)
-  size_t tpart, gpart, tdm, el, y1, eocc, edet, ydet, mft, total;
+  size_t tpart, gpart, tdm, el, y1, eocc, edet, ydet, psf64, mft, total;
 };
 
 Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_t mode) {
@@ -354,6 +364,7 @@ Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_
   L.eocc = take(size_t(d->occ_m) * d->occ_m * 8);
   L.edet = take(size_t(d->det_m) * d->det_m * 8);
   L.ydet = grad ? take(size_t(d->det_m) * d->det_m * 8) : 0;
+  L.psf64 = take(size_t(d->det_m) * d->det_m * 8);
   const size_t m1 = mft_ws_bytes(nmax, d->occ_m);
   const size_t m2 = mft_ws_bytes(d->n_d, d->det_m);
   const size_t m3 = mft_ws_bytes(d->n_d, d->occ_m);
@@ -419,6 +430,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   float2 *EDET = c64at(L.edet);
   float2 *YDET = grad ? c64at(L.ydet) : nullptr;
   void *MWS = base + L.mft;
+  double *PSF64 = reinterpret_cast<double *>(base + L.psf64);
   const LaunchHook hook = ctx->hook();
   const int nd = d->n_d, na = d->n_act, ndm = d->n_dm;
   const size_t det2 = size_t(d->det_m) * d->det_m;
@@ -506,7 +518,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     MftOut o;
     o.out = EDET;
     o.ld_out = d->det_m;
-    o.intensity = psf;
+    o.intensity = PSF64;
     o.weight = weight[j];
     return mft_forward_impl(ctx, EL, nd, nd, d->det_m, double(nd), du_det, o, MWS, s);
   };
@@ -571,7 +583,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     return dm_grad(j, nullptr, c64at(L.b[j]), surf_of(j), grad_heights);
   };
 
-  FR_TRY_HIP(launch1d(fill_f32, det2, s, hook, "fill", psf, det2, 0.f));
+  FR_TRY_HIP(launch1d(fill_f64, det2, s, hook, "fill", PSF64, det2));
   if (grad) {
     const size_t ng = size_t(ndm) * na * na;
     FR_TRY_HIP(launch1d(fill_f32, ng, s, hook, "fill", grad_heights, ng, 0.f));
@@ -617,6 +629,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       for (int j = 0; j < n_lambda; ++j) FR_TRY(back_to_pupil_dm(j));
     }
   }
+  FR_TRY_HIP(launch1d(to_f32, det2, s, hook, "psf_to_f32", (const double *)PSF64, psf, det2));
 #undef FR_TRY
 #undef FR_TRY_HIP
   return FR_OK;

@@ -76,7 +76,7 @@ def test_occulter_mft_full_size():
     assert rel_l2(got, ref) <= TOL
 
 
-def test_airy_config1_on_gpu():
+def test_airy_256_aperture_on_gpu():
     ap = synth.circular_aperture(512, 128.0)
     got = to_np(fb.mft_forward(to_gpu(ap), 256.0, 128, 0.25))
     assert abs(got[64, 64] - 0.25 / 256 * 51429) <= 1e-5 * 50.2236

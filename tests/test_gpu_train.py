@@ -53,7 +53,7 @@ def test_train_small_matches_oracle(n_dm, n_lambda):
     ref0 = oracle.train_psf(geom, lams, ns, w, heights, occulter=False)
     assert rel_l2(psf0, ref0) <= 1e-5
     # this toy coronagraph only reaches ~1e-3 contrast, so its contrast error is bounded
-    # relative to the peak contrast; the absolute 1e-9 bar is checked on config 2 below
+    # relative to the peak contrast; the absolute 1e-9 bar is checked on the 4096 train below
     c_ref = ref / ref0.max()
     assert np.max(np.abs(psf / psf0.max() - c_ref)) <= 1e-6 * np.max(c_ref)
 
@@ -75,8 +75,8 @@ def test_train_mixed_radix_grids_matches_oracle():
     assert rel_l2(_np(gh), gref) <= 1e-4
 
 
-def test_train_config2_full_size():
-    banner("train config 2: 1024 pupil padded to 4096, occulter 256, detector 512")
+def test_train_lyot_4096_full_size():
+    banner("train: 1024 pupil padded to 4096, occulter 256, detector 512")
     geom, tr, heights, hg = make(1024, 256, 8 / 256, 512, 0.25, 1.0, 48, 1)
     lams, ns, w = [550e-9], [4096], [1.0]
     psf = _np(fb.propagate_train(tr, lams, ns, w, hg))
@@ -87,7 +87,7 @@ def test_train_config2_full_size():
     assert rel_l2(psf, ref) <= 1e-5
     assert rel_l2(psf0, ref0) <= 1e-5
     contrast_err = np.max(np.abs(psf / psf0.max() - ref / ref0.max()))
-    banner(f"config 2 max |dC| = {contrast_err:.3e}, peak contrast {np.max(ref / ref0.max()):.3e}")
+    banner(f"4096 train max |dC| = {contrast_err:.3e}, peak contrast {np.max(ref / ref0.max()):.3e}")
     assert contrast_err <= 1e-9
 
 
@@ -118,10 +118,10 @@ def test_gradient_small_matches_oracle_and_fd(n_dm, n_lambda):
     assert np.max(np.abs(an - fd)) <= 1e-4 * np.max(np.abs(ref))
 
 
-def test_gradient_config4_full_size():
-    # config 4: 1024 pupil padded 2x, one 48x48 DM, dark hole 3-10 lambda/D right half,
+def test_gradient_lyot_2048_full_size():
+    # 1024 pupil padded 2x, one 48x48 DM, dark hole 3-10 lambda/D right half,
     # 20 actuators inside the clear aperture (seed 3) checked by central differences
-    banner("gradient config 4: 2048 grid, 48x48 DM")
+    banner("gradient: 2048 grid, 48x48 DM")
     geom, tr, heights, hg, lams, ns, w, dh, mref = _grad_setup(1024, 2048, 256, 512, 0.25, 48, 1, 1, 1.0)
     g_psf = to_gpu(dh / (dh.sum() * mref), torch.float32)
     _, gh = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g_psf)
@@ -131,7 +131,7 @@ def test_gradient_config4_full_size():
     g_i = (w[0] / (dh.sum() * mref)) * dh
     ref = np.stack(oracle.train_backward(geom, lams[0], ns[0], heights, fwd, g_i))
     err = rel_l2(gpu, ref)
-    banner(f"config 4 gradient rel L2 vs FP64 adjoint: {err:.3e}")
+    banner(f"2048 gradient rel L2 vs FP64 adjoint: {err:.3e}")
     assert err <= 1e-4
     rng = np.random.default_rng(3)
     p = 1024 / 48
@@ -143,7 +143,7 @@ def test_gradient_config4_full_size():
     an = np.array([gpu[d, r, c] for d, r, c in acts])
     fd_ref = np.array([ref[d, r, c] for d, r, c in acts])
     scale = np.max(np.abs(ref))
-    banner(f"config 4 FD: max |gpu - fd| / max|g| = {np.max(np.abs(an - fd)) / scale:.3e}, "
+    banner(f"2048 gradient FD: max |gpu - fd| / max|g| = {np.max(np.abs(an - fd)) / scale:.3e}, "
            f"max |oracle adjoint - fd| / max|g| = {np.max(np.abs(fd_ref - fd)) / scale:.3e}")
     assert np.max(np.abs(fd_ref - fd)) <= 1e-6 * scale
     assert np.max(np.abs(an - fd)) <= 1e-4 * scale

@@ -48,7 +48,7 @@ def test_mft_reduces_to_centred_dft(n, n_d, rng):
     assert np.max(np.abs(back - e)) <= 1e-13 * np.max(np.abs(e))
 
 
-def test_mft_dc_term_config1():
+def test_mft_dc_term_256_aperture():
     # 256 px circular aperture (r < 128) in a 512 grid, 128^2 focal plane at 0.25 lambda/D
     ap = synth.circular_aperture(512, 128.0)
     assert ap.sum() == 51429
@@ -66,7 +66,7 @@ def test_mft_adjoint_identity(n, m, n_d, du, rng):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
-def test_airy_pattern_config1():
+def test_airy_pattern_256_aperture():
     ap = synth.circular_aperture(512, 128.0)
     eb = oracle.mft(ap, 256.0, 128, 0.25)
     peak = abs(eb[64, 64])
@@ -82,7 +82,7 @@ def test_airy_pattern_config1():
 
 
 def test_as_mft_lattice_invariance():
-    # config 1: z = 1 m, dx = 1e-4 m, lambda = 550 nm; padded-grid lattice = every 2nd sample
+    # 256 px aperture on a 512 grid: z = 1 m, dx = 1e-4 m, lambda = 550 nm; padded-grid lattice = every 2nd sample
     n, n_d, lam, dx, z = 512, 256.0, 550e-9, 1e-4, 1.0
     ap = synth.circular_aperture(n, 128.0)
     e_z = oracle.as_propagate(ap, dx, lam, z)
