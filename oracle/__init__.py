@@ -23,7 +23,7 @@ value in the paper for that system to compare against.
 
 from .core import (  # noqa: F401
     centred, signed_index, dft_matrix, dft2, idft2, transfer_function,
-    as_propagate, optic_phasor, fresnel_step, mft_matrix, mft, mft_adjoint,
+    as_propagate, as_propagate_rows, optic_phasor, fresnel_step, mft_matrix, mft, mft_adjoint,
 )
 from .train import (  # noqa: F401
     embed, extract, dm_influence, dm_surface, TrainGeometry, train_forward,

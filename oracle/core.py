@@ -87,6 +87,27 @@ def as_propagate(u, dx, wavelength, z):
     return idft2(transfer_function(n, dx, wavelength, z) * dft2(np.asarray(u, dtype=np.complex128)))
 
 
+def as_propagate_rows(u, dx, wavelength, z, rows):
+    """Rows `rows` of as_propagate(u, dx, wavelength, z), at O(len(rows) n^2) cost.
+
+    The paraxial H is the outer product h (x) h with h[k] = exp(-i pi lambda z k~^2/(n dx)^2),
+    so IDFT2(H . DFT2(U)) = K U K^T with the circulant K = IDFT diag(h) DFT, whose entries are
+    K[y, r] = kappa[(y - r) mod n] for kappa = IDFT(h) (1-D). Rows of the result are then
+    K[rows, :] U K^T: no 2-D transform of the whole plane is needed.
+    """
+    u = np.asarray(u, dtype=np.complex128)
+    n = u.shape[0]
+    k = signed_index(n)
+    turns = (k * k) * (-float(wavelength) * float(z) / (2.0 * (n * float(dx)) ** 2))
+    turns = turns - np.round(turns)
+    h = np.exp(2j * np.pi * turns)
+    kappa = (dft_matrix(n).conj() @ h) / n
+    rows = np.asarray(rows, dtype=np.int64)
+    i = np.arange(n, dtype=np.int64)
+    left = kappa[(rows[:, None] - i[None, :]) % n] @ u
+    return left @ kappa[(i[:, None] - i[None, :]) % n].T
+
+
 # --------------------------------------------------------------------------------------------
 # O2. Optic multiply: the complex phasor of Eq. (3), A exp(2 pi i phi / lambda), plus a
 #     reflective surface (OPD = 2 x surface) and a thin lens exp(-i pi r^2 / (lambda f))

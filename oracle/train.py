@@ -97,9 +97,9 @@ def train_forward(geom: TrainGeometry, wavelength, n, heights: Sequence[np.ndarr
 
     heights: one array (the DM after the Fresnel step) or two (DM1 at the pupil, DM2 after
     the step), each n_act x n_act surface heights in m.
-    step_cache: optional dict; with zero or one DM the Fresnel step does not depend on the
-    heights, so its result is remembered there per (wavelength, n) and reused (memoisation
-    only: the arithmetic is unchanged).
+    step_cache: optional dict; the Fresnel step's result is remembered there per (wavelength,
+    n) and, with two DMs, the pupil DM's heights (the only heights it depends on), and reused
+    (memoisation only: the arithmetic is unchanged).
     """
     lam = float(wavelength)
     nd = geom.n_d
@@ -115,12 +115,12 @@ def train_forward(geom: TrainGeometry, wavelength, n, heights: Sequence[np.ndarr
         e = e * ph1
         out.e_dm.append(e)
         out.dm_phasors.append(ph1)
-    key = (lam, n)
-    if step_cache is not None and len(hs) < 2 and key in step_cache:
+    key = (lam, n) if len(hs) < 2 else (lam, n, np.asarray(hs[0], dtype=np.float64).tobytes())
+    if step_cache is not None and key in step_cache:
         e = step_cache[key]
     else:
         e = as_propagate(e, geom.dx, lam, geom.z_m)
-        if step_cache is not None and len(hs) < 2:
+        if step_cache is not None:
             step_cache[key] = e
     if hs:
         ph = _dm_phasor(dm_surface(hs[-1], n, nd), lam)

@@ -5,8 +5,9 @@
 //
 // Complex product with real MFMA: per complex k-step, Cr += Ar Br - Ai Bi and
 // Ci += Ar Bi + Ai Br (four v_mfma_f32_32x32x2f32 per 32 x 32 tile, fragments from LDS).
-// Block tile 128 x 128, eight waves in 4 x 2, each wave a 32 x 64 piece (two 32 x 32 MFMA
-// tiles). Operand tiles 16 deep are staged through double-buffered LDS, the next tile's
+// Block tile 64 x 128 (four waves in 2 x 2, each a 32 x 64 piece made of two 32 x 32 MFMA
+// tiles) or 64 x 64 for small outputs. Two or three blocks share a compute unit; as their
+// barriers are independent, one block's float64 folds overlap another block's MFMAs. Operand tiles 16 deep are staged through double-buffered LDS, the next tile's
 // global loads in flight while the current one is multiplied (one barrier per tile). Each
 // 16-deep tile is summed by the MFMAs in float32 and then added into float64 totals (the long
 // Fourier sums of the coronagraph cancel to tiny values in the dark hole, so their rounding
@@ -17,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 
 #include "fr_internal.h"
 
@@ -69,8 +71,9 @@ struct Cfg {
   static_assert(BM * BK % threads == 0 && BK * BN % threads == 0, "tile not divisible");
   static_assert(threads % BK == 0 && threads % BM == 0 && threads % BN == 0, "thread mapping");
 };
-using CfgL = Cfg<4, 2, 2>;  // 128 x 128, 512 threads
+using CfgL = Cfg<2, 2, 2>;  // 64 x 128, 256 threads: two blocks share a compute unit
 using CfgS = Cfg<2, 2, 1>;  // 64 x 64, 256 threads
+using CfgX = Cfg<4, 2, 2>;  // 128 x 128, 512 threads
 
 // Per-thread share of one BK-deep operand tile, mapped so that consecutive threads walk
 // memory contiguously.
@@ -131,7 +134,9 @@ struct TileLoad {
 };
 
 template <class C, bool TA, bool TB>
-__global__ void __launch_bounds__(C::threads) cgemm_kernel(GemmParams gp) {
+__global__ void __launch_bounds__(C::threads) __attribute__((amdgpu_waves_per_eu(2)))
+cgemm_kernel(GemmParams gp) {
+  static_assert(C::threads <= 512, "block too large");
   constexpr int TN = C::TN;
   const CGemmArgs &a = gp.a;
   __shared__ float2 As[2][BK][C::BM + PAD];
@@ -260,10 +265,26 @@ bool use_large(int M, int N, int K) {
   return t * split_for(t, K) >= 256;
 }
 
+// tile configuration: 0 small, 1 large, 2 extra large; FR_GEMM_TILE (s, l, x) overrides the
+// choice for tuning runs
+int tile_choice(int M, int N, int K) {
+  static const int forced = [] {
+    const char *v = std::getenv("FR_GEMM_TILE");
+    if (!v) return -1;
+    return v[0] == 's' ? 0 : v[0] == 'l' ? 1 : v[0] == 'x' ? 2 : -1;
+  }();
+  if (forced >= 0) return forced;
+  return use_large(M, N, K) ? 1 : 0;
+}
+
 }  // namespace
 
 int cgemm_split_for(int M, int N, int K) {
-  return use_large(M, N, K) ? split_for(tiles_of<CfgL>(M, N), K) : split_for(tiles_of<CfgS>(M, N), K);
+  switch (tile_choice(M, N, K)) {
+    case 1: return split_for(tiles_of<CfgL>(M, N), K);
+    case 2: return split_for(tiles_of<CfgX>(M, N), K);
+    default: return split_for(tiles_of<CfgS>(M, N), K);
+  }
 }
 
 hipError_t launch_cgemm_split(const CGemmArgs &a, int split, void *partial, hipStream_t stream,
@@ -275,11 +296,14 @@ hipError_t launch_cgemm_split(const CGemmArgs &a, int split, void *partial, hipS
   kps = (kps + BK - 1) / BK * BK;
   gp.k_per_split = kps;
   gp.partial = static_cast<double2 *>(partial);
-  const bool large = use_large(a.M, a.N, a.K);
+  const int cfg = tile_choice(a.M, a.N, a.K);
   char name[64];
-  std::snprintf(name, sizeof name, "cgemm%s_%dx%dx%d_s%d", large ? "L" : "S", a.M, a.N, a.K, split);
+  std::snprintf(name, sizeof name, "cgemm%s_%dx%dx%d_s%d", cfg == 1 ? "L" : cfg == 2 ? "X" : "S", a.M, a.N, a.K,
+                split);
   hook(stream, name, a.K, 0);
-  hipError_t e = large ? launch_cfg<CfgL>(gp, stream) : launch_cfg<CfgS>(gp, stream);
+  hipError_t e = cfg == 1 ? launch_cfg<CfgL>(gp, stream)
+                 : cfg == 2 ? launch_cfg<CfgX>(gp, stream)
+                            : launch_cfg<CfgS>(gp, stream);
   hook(stream, name, a.K, 1);
   if (e != hipSuccess || split == 1) return e;
   const size_t total = size_t(a.M) * a.N;

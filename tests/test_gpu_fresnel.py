@@ -204,3 +204,28 @@ def test_broadband_batch_equals_single_calls():
         r2 = (synth.radius_grid(m) * dx) ** 2
         ref = np.exp(-r2 / (w0 * w0 * (1 + 1.5j))) / (1 + 1.5j)
         assert rel_l2(to_np(t), ref) <= TOL, m
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_fresnel_step_8192_sampled_rows(adjoint):
+    # the full 8192^2 plane against the oracle on sampled output rows (the separable form of the
+    # paraxial step gives single rows at O(n^2) each)
+    n = 8192
+    banner(f"fresnel_step n=8192 adjoint={adjoint}: sampled rows vs oracle")
+    rng = np.random.default_rng(81 + adjoint)
+    field = f32(synth.random_field(n, 81 + adjoint))
+    amp = f32(rng.uniform(0.3, 1.0, (n, n)))
+    opd = f32(rng.normal(0.0, 60e-9, (n, n)))
+    dx, lam, z = 1.25e-5, 550e-9, 1.0
+    t = to_gpu(field)
+    fb.fresnel_step(t, dx, lam, z, amp=to_gpu(amp, torch.float32), opd=to_gpu(opd, torch.float32),
+                    adjoint=adjoint)
+    rows = [0, 1, 1234, n // 2, 5000, n - 1]
+    torch.cuda.synchronize()
+    got = t[rows].cpu().numpy().astype(np.complex128)
+    ph = oracle.optic_phasor(n, dx, lam, amp=amp, opd=opd)
+    if adjoint:
+        ref = oracle.as_propagate_rows(field, dx, lam, -z, rows) * np.conj(ph[rows])
+    else:
+        ref = oracle.as_propagate_rows(field * ph, dx, lam, z, rows)
+    assert rel_l2(got, ref) <= TOL

@@ -17,13 +17,13 @@ from tests.gpu_common import banner, f32, rel_l2, to_gpu
 pytestmark = pytest.mark.gpu
 
 
-def make(n_d, occ_m, occ_du, det_m, det_du, z, n_act, n_dm, spider=0.01, seed=0):
+def make(n_d, occ_m, occ_du, det_m, det_du, z, n_act, n_dm, spider=0.01, seed=0, dx=25e-6):
     amp = f32(synth.pupil_amplitude(n_d, 0.1, spider))
     opd = f32(synth.power_law_opd(n_d, amp, 10e-9, -3.0, seed))
     occ = f32(synth.occulter_spot(occ_m, occ_du, 3.0))
     lyot = f32(synth.lyot_stop(n_d, 0.9))
     heights = [f32(synth.dm_heights(n_act, 1 + k)) for k in range(n_dm)]
-    d_m = n_d * 25e-6
+    d_m = n_d * dx
     geom = oracle.TrainGeometry(n_d=n_d, d_m=d_m, z_m=z, occ_m=occ_m, occ_du_c=occ_du, det_m=det_m,
                                 det_du_c=det_du, lambda_c=550e-9, pupil_amp=amp, occ_mask=occ,
                                 lyot=lyot, pupil_opd=opd)
@@ -232,3 +232,40 @@ def test_graph_mode_replays_match_eager():
         assert torch.equal(out, p_ref), rep
         assert torch.equal(gout, g_ref), rep
         assert torch.isfinite(junk)
+
+
+def test_large_train_8192_two_dms():
+    # 2048 pupil (dx 12.5 um) padded 4x to 8192, two 64 x 64 DMs (pupil and after 1 m),
+    # 8 wavelengths over 500-600 nm, PSF and gradient. Batched equals plain bit for bit (one
+    # power-of-two edge); the first wavelength, taken out of the full batch with one-hot weights,
+    # is checked against the oracle: PSF, normalised contrast and the gradient.
+    banner("large train: 8192 grid, two 64x64 DMs, 8 wavelengths")
+    geom, tr, heights, hg = make(2048, 256, 8 / 256, 512, 0.25, 1.0, 64, 2, dx=12.5e-6)
+    lams = list(synth.wavelengths(8))
+    ns, w = [8192] * 8, [1.0 / 8] * 8
+    dhn = synth.dark_hole(512, 0.25, 3.0, 10.0)
+    dh = to_gpu(dhn / dhn.sum(), torch.float32)
+    p0, g0 = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh)
+    p1, g1 = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh, batched=True)
+    torch.cuda.synchronize()
+    assert torch.equal(p0, p1)
+    assert torch.equal(g0, g1)
+    one_hot = [1.0] + [0.0] * 7
+    pj, gj = fb.propagate_train(tr, lams, ns, one_hot, hg, grad_psf=dh, batched=True)
+    pj0 = _np(fb.propagate_train(tr, lams, ns, one_hot, hg, batched=True, occulter=False))
+    pj, gj = _np(pj), _np(gj)
+    banner("large train: oracle for 500 nm at 8192 (two Fresnel steps, a minute or two)")
+    cache = {}
+    fwd = oracle.train_forward(geom, lams[0], 8192, heights, True, cache)
+    ref = fwd.e_det.real ** 2 + fwd.e_det.imag ** 2
+    e0 = oracle.train_forward(geom, lams[0], 8192, heights, False, cache).e_det
+    ref0 = e0.real ** 2 + e0.imag ** 2
+    assert rel_l2(pj, ref) <= 1e-5
+    assert rel_l2(pj0, ref0) <= 1e-5
+    err = np.max(np.abs(pj / pj0.max() - ref / ref0.max()))
+    banner(f"large train max |dC| = {err:.3e}")
+    assert err <= 1e-9
+    gref = np.stack(oracle.train_backward(geom, lams[0], 8192, heights, fwd, dhn / dhn.sum()))
+    gerr = rel_l2(gj, gref)
+    banner(f"large train gradient rel L2 vs FP64 adjoint: {gerr:.3e}")
+    assert gerr <= 1e-4

@@ -159,3 +159,28 @@ def test_fresnel_step_adjoint_identity(rng):
     lhs = np.vdot(fx, y)
     rhs = np.vdot(x, fhy)
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_as_propagate_rows_equals_full_step():
+    # the separable (circulant) form of the paraxial step gives the same rows as the 2-D
+    # definition, on even and odd edges and at distances whose phases wrap many turns
+    rng = np.random.default_rng(5)
+    for n, z in ((64, 0.3), (100, 2.0), (45, 7.5)):
+        u = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+        rows = [0, 1, n // 2, n - 1]
+        full = oracle.as_propagate(u, 2e-5, 600e-9, z)[rows]
+        part = oracle.as_propagate_rows(u, 2e-5, 600e-9, z, rows)
+        assert np.max(np.abs(part - full)) <= 1e-12 * np.max(np.abs(full))
+
+
+def test_as_propagate_rows_gaussian_closed_form():
+    # rows of a propagated Gaussian beam against the closed form (independent of the 2-D path)
+    n, dx, lam, w0px = 256, 1e-5, 550e-9, 12.0
+    w0 = w0px * dx
+    zr = np.pi * w0 * w0 / lam
+    u = synth.gaussian_beam(n, w0px)
+    rows = [n // 2, n // 2 + 7, n // 2 - 20, 3]
+    got = oracle.as_propagate_rows(u, dx, lam, 1.5 * zr, rows)
+    r2 = (synth.radius_grid(n) * dx) ** 2
+    ref = (np.exp(-r2 / (w0 * w0 * (1 + 1.5j))) / (1 + 1.5j))[rows]
+    assert np.linalg.norm(got - ref) <= 1e-6 * np.linalg.norm(ref)
