@@ -163,34 +163,63 @@ def main():
     psf_sum = float(psf.sum())
     n_plain = max(1, steps // 4)
     ms_plain, _ = timed(plain_step, n_plain, 1)
-    _, prof_plain = timed(plain_step, n_plain, 0, profile=True)
     ms_per_step = ms_batched / steps
     value = planes_per_step * steps / (ms_batched * 1e-3)
     plain_value = planes_per_step * n_plain / (ms_plain * 1e-3)
 
-    # per-kernel times of one step, from the plain form (the same kernels, launched one
-    # wavelength at a time; the graph form is timed as a whole)
+    # per-kernel times of one step: the batched form run eagerly (the graph replays exactly
+    # these launches), each launch bracketed by events
+    def eager_batched():
+        fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g_psf, batched=True, out=psf, grad_out=gh)
+
+    n_prof = 2
+    _, prof = timed(eager_batched, n_prof, 1, profile=True)
     agg = {}
-    for k, (tot, cnt) in prof_plain.items():
+    for k, (tot, cnt) in prof.items():
         name = k.split("/")[0]
         a = agg.setdefault(name, [0.0, 0])
         a[0] += tot
         a[1] += cnt
-    kernels_ms_per_step = {k: v[0] / n_plain for k, v in sorted(agg.items(), key=lambda kv: -kv[1][0])}
+    kernels_ms_per_step = {k: v[0] / n_prof for k, v in sorted(agg.items(), key=lambda kv: -kv[1][0])}
 
-    # dominant kernel of the step; a complex GEMM launch is tagged with its M x N x K
-    dom = next(iter(kernels_ms_per_step))
-    dom_ms = agg[dom][0] / agg[dom][1]
-    if dom.startswith("cgemm"):
-        m, n_, k = (int(x) for x in dom.split("_")[1].split("x"))
-        flops = 8.0 * m * n_ * k
-        achieved = flops / (dom_ms * 1e-3) / 1e12
-        roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
-                    "flops_per_launch": flops, "avg_launch_ms": dom_ms,
-                    "note": "8 real flops per complex multiply-add over the launch's M x N x K"}
-    else:
-        roofline = {"bound": "unmodelled", "kernel": dom, "avg_launch_ms": dom_ms}
+    # algorithmic cost per launch of the step's kernels (21 planes per sweep launch):
+    #   forward row sweep: the pupil optic is synthesised (no field read): write the field,
+    #     read the pupil DM map and the two N_D^2 pupil windows;
+    #   adjoint row sweep: read + write the field, the same maps (conjugate optic);
+    #   column sweeps: read + write the field and the DM map after the step;
+    #   dm_grad_T: read E and B (last DM) or B, the pupil DM map and the windows (pupil DM);
+    #   cgemm M x N x K: 8 M N K flops.
+    n2, nd2 = N * N, N_D * N_D
+    hbm_model = {
+        "row_sweep": N_LAMBDA * (8 * n2 + 4 * n2 + 8 * nd2),
+        "row_sweep_adj": N_LAMBDA * (16 * n2 + 4 * n2 + 8 * nd2),
+        "col_sweep": N_LAMBDA * (16 * n2 + 4 * n2),
+        "col_sweep_adj": N_LAMBDA * (16 * n2 + 4 * n2),
+        "dm_grad_T": 16 * n2,
+        "dm_grad_T_pupil": 8 * n2 + 4 * n2 + 8 * nd2,
+    }
+
+    def roofline_of(name):
+        tot, cnt = agg[name]
+        ms = tot / cnt
+        if name in hbm_model:
+            gbs = hbm_model[name] / (ms * 1e-3) / 1e9
+            return {"bound": "hbm", "kernel": name, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": hbm_model[name],
+                    "avg_launch_ms": ms}
+        if name.startswith("cgemm"):
+            m, n_, k = (int(x) for x in name.split("_")[1].split("x"))
+            flops = 8.0 * m * n_ * k
+            tf = flops / (ms * 1e-3) / 1e12
+            return {"bound": "mfma", "kernel": name, "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": tf / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                    "flops_per_launch": flops, "avg_launch_ms": ms}
+        return None
+
+    # the dominant kernel: the largest share of the step that has a cost model
+    modelled = [k for k in kernels_ms_per_step if roofline_of(k) is not None]
+    roofline = roofline_of(modelled[0])
+    kernel_rooflines = {k: roofline_of(k) for k in modelled[:6]}
 
     # the Fresnel sweeps alone: 42 planes (21 forward, 21 adjoint) of 4096^2 with a dense
     # amplitude + OPD optic in one batched call; per-launch HBM roofline of the sweep kernels
@@ -209,7 +238,8 @@ def main():
                                                            adjoints=adjs), fr_calls, 2, profile=True)
     # each sweep launch covers the 21 planes of one direction; both row launches apply the
     # amplitude and OPD maps (prologue forward, conjugate epilogue adjoint)
-    per_launch = {"row_sweep": N_LAMBDA * sweep_bytes(N, 2), "col_sweep": N_LAMBDA * sweep_bytes(N, 0)}
+    per_launch = {"row_sweep": N_LAMBDA * sweep_bytes(N, 2), "row_sweep_adj": N_LAMBDA * sweep_bytes(N, 2),
+                  "col_sweep": N_LAMBDA * sweep_bytes(N, 0), "col_sweep_adj": N_LAMBDA * sweep_bytes(N, 0)}
     fr_rl = {}
     for key, (tot, cnt) in prof_fr.items():
         name = key.split("/")[0]
@@ -251,6 +281,7 @@ def main():
         },
         "plain": {"value": plain_value, "unit": "Fresnel planes/s", "ms_per_step": ms_plain / n_plain},
         "roofline": roofline,
+        "kernel_rooflines": kernel_rooflines,
         "kernels_ms_per_step": kernels_ms_per_step,
         "fresnel_only": {
             "value": 2 * N_LAMBDA * fr_calls / (ms_fr * 1e-3), "unit": "Fresnel planes/s",

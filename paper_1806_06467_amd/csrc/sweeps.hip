@@ -264,27 +264,28 @@ hipError_t launch_sweeps(const BatchArgs &fwd, int nf, const BatchArgs &adj, int
                          const float2 *tw, hipStream_t s, const LaunchHook &hook) {
   constexpr int N = PL::N;
   static_assert(N % ROW_LINES == 0 && N % COL_LINES == 0, "tile must divide n");
-  auto rows = [&](const BatchArgs &a, int count) {
-    hook(s, "row_sweep", N, 0);
+  // timing names carry the direction (the optic maps read differ)
+  auto rows = [&](const BatchArgs &a, int count, const char *name) {
+    hook(s, name, N, 0);
     hipLaunchKernelGGL((row_sweep<PL, ROW_LINES>), dim3(N / ROW_LINES, count),
                        dim3(PL::T * ROW_LINES), 0, s, a, tw);
     hipError_t e = hipGetLastError();
-    hook(s, "row_sweep", N, 1);
+    hook(s, name, N, 1);
     return e;
   };
-  auto cols = [&](const BatchArgs &a, int count) {
-    hook(s, "col_sweep", N, 0);
+  auto cols = [&](const BatchArgs &a, int count, const char *name) {
+    hook(s, name, N, 0);
     hipLaunchKernelGGL((col_sweep<PL, COL_LINES>), dim3(N / COL_LINES, count),
                        dim3(PL::T * COL_LINES), 0, s, a, tw);
     hipError_t e = hipGetLastError();
-    hook(s, "col_sweep", N, 1);
+    hook(s, name, N, 1);
     return e;
   };
   hipError_t e = hipSuccess;
-  if (nf && (e = rows(fwd, nf)) != hipSuccess) return e;
-  if (nf && (e = cols(fwd, nf)) != hipSuccess) return e;
-  if (na && (e = cols(adj, na)) != hipSuccess) return e;
-  if (na && (e = rows(adj, na)) != hipSuccess) return e;
+  if (nf && (e = rows(fwd, nf, "row_sweep")) != hipSuccess) return e;
+  if (nf && (e = cols(fwd, nf, "col_sweep")) != hipSuccess) return e;
+  if (na && (e = cols(adj, na, "col_sweep_adj")) != hipSuccess) return e;
+  if (na && (e = rows(adj, na, "row_sweep_adj")) != hipSuccess) return e;
   return e;
 }
 

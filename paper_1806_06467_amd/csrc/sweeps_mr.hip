@@ -289,27 +289,27 @@ hipError_t launch_mr_batch(const MrBatch &all, int blocks_rows, int blocks_cols,
     }
     b.total = acc;
   };
-  auto rows = [&](MrBatch b) {
+  auto rows = [&](MrBatch b, const char *name) {
     rows_list(b);
-    hook(s, "mr_row_sweep", b.count, 0);
+    hook(s, name, b.count, 0);
     hipLaunchKernelGGL(mr_row_sweep, dim3(std::max(1, std::min(blocks_rows, b.total))), dim3(kT), 0, s, b);
     hipError_t e = hipGetLastError();
-    hook(s, "mr_row_sweep", b.count, 1);
+    hook(s, name, b.count, 1);
     return e;
   };
-  auto cols = [&](MrBatch b) {
+  auto cols = [&](MrBatch b, const char *name) {
     cols_list(b);
-    hook(s, "mr_col_sweep", b.count, 0);
+    hook(s, name, b.count, 0);
     hipLaunchKernelGGL(mr_col_sweep, dim3(std::max(1, std::min(blocks_cols, b.total))), dim3(4 * kT), 0, s, b);
     hipError_t e = hipGetLastError();
-    hook(s, "mr_col_sweep", b.count, 1);
+    hook(s, name, b.count, 1);
     return e;
   };
   hipError_t e = hipSuccess;
-  if (fwd.count && (e = rows(fwd)) != hipSuccess) return e;
-  if (fwd.count && (e = cols(fwd)) != hipSuccess) return e;
-  if (adj.count && (e = cols(adj)) != hipSuccess) return e;
-  if (adj.count && (e = rows(adj)) != hipSuccess) return e;
+  if (fwd.count && (e = rows(fwd, "mr_row_sweep")) != hipSuccess) return e;
+  if (fwd.count && (e = cols(fwd, "mr_col_sweep")) != hipSuccess) return e;
+  if (adj.count && (e = cols(adj, "mr_col_sweep_adj")) != hipSuccess) return e;
+  if (adj.count && (e = rows(adj, "mr_row_sweep_adj")) != hipSuccess) return e;
   return e;
 }
 

@@ -532,7 +532,8 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     const int strips = (n + kRows - 1) / kRows, groups = (n + kGroup - 1) / kGroup;
     const int gblocks = (n + kGRows - 1) / kGRows;
     const float kappa = float(4.0 * M_PI / lam[j]);
-    hook(s, "dm_grad_T", n, 0);
+    const char *tname = E ? "dm_grad_T" : "dm_grad_T_pupil";
+    hook(s, tname, n, 0);
     if (E)
       hipLaunchKernelGGL(dm_grad_T<false>, dim3(strips, groups), dim3(256), 0, s, E, B, G, n, na, kappa,
                          d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), TPART);
@@ -540,7 +541,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       hipLaunchKernelGGL(dm_grad_T<true>, dim3(strips, groups), dim3(256), 0, s, E, B, G, n, na, kappa,
                          d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), TPART);
     FR_TRY_HIP(hipGetLastError());
-    hook(s, "dm_grad_T", n, 1);
+    hook(s, tname, n, 1);
     hook(s, "dm_grad_G", n, 0);
     hipLaunchKernelGGL(dm_grad_G, dim3(gblocks), dim3(256), 0, s, (const float *)TPART, groups, G, n, na, GPART);
     FR_TRY_HIP(hipGetLastError());
