@@ -116,6 +116,17 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    # autotune (untimed): sweep tiles for the plane edge, GEMM tiles for the train's MFT shapes
+    t_tune = time.perf_counter()
+    fb.autotune_fresnel(N)
+    for n_, m_ in ((N, OCC_M), (N_D, OCC_M), (N_D, DET_M)):
+        fb.autotune_mft(n_, m_)
+    tune_file = os.path.join(os.environ.get("TMPDIR", "/tmp"), "fresnel_bench_tune_%d.txt" % os.getpid())
+    fb.autotune_save(tune_file)
+    with open(tune_file) as f:
+        tuned = [l.strip() for l in f if not l.startswith("#")]
+    os.remove(tune_file)
+    t_tune = time.perf_counter() - t_tune
     inp = train_inputs(torch, np, synth, dev)
     lams = inp["lams"]
     tr = fb.Train(N_D, D_M, Z, inp["pupil"], inp["lyot"], inp["occ"], OCC_DU, DET_M, DET_DU,
@@ -288,6 +299,7 @@ def main():
             "planes_per_call": 2 * N_LAMBDA, "ms_per_call": ms_fr / fr_calls,
             "roofline": fr_rl,
         },
+        "autotuned": {"choices": tuned, "seconds": t_tune},
         "checksum_psf_sum": psf_sum,
         "wall_s": t_wall,
     }

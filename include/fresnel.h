@@ -170,6 +170,25 @@ int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda,
                     int32_t mode, float *psf, const float *grad_psf, float *grad_heights,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* ---- autotuner (Sec. 2.1: measurement decides among equivalent implementations) ---------
+ * fr_autotune times the candidate kernel configurations of one workload shape on `stream` and
+ * keeps the fastest in the context; later calls of every entry point use it:
+ *   FR_TUNE_FRESNEL, a = plane edge n (b unused): the tile variants of the power-of-two sweeps
+ *     (rows per block, columns per tile) and the pass orders of the mixed-radix plan of n;
+ *   FR_TUNE_MFT, a = pupil-side edge n, b = focal edge m: the GEMM tile configuration of each of
+ *     the two GEMMs of mft_forward (n -> m) and mft_adjoint (m -> n).
+ * Every candidate computes the same result up to the order of float32 roundings. The call
+ * allocates scratch device memory for its duration, synchronises `stream`, and is not meant for
+ * a hot loop or a graph capture. Errors: FR_EINVAL, FR_EUNSUPPORTED, FR_ENOMEM, FR_EHIP.
+ * fr_autotune_save / fr_autotune_load write / read the tuned choices as a text file (one
+ * "sweep n variant", "plan n packed_order" or "gemm M N K transA transB tile" per line); a
+ * malformed or inconsistent line makes load return FR_EINVAL (valid lines are still taken). */
+#define FR_TUNE_FRESNEL 1
+#define FR_TUNE_MFT 2
+int fr_autotune(fr_ctx *ctx, int32_t kind, int32_t a, int32_t b, void *stream);
+int fr_autotune_save(fr_ctx *ctx, const char *path);
+int fr_autotune_load(fr_ctx *ctx, const char *path);
+
 /* ---- kernel timing (profiling aid; Sec. 2.1: profiling decides what to optimise) -------
  * While enabled, every kernel the context launches is bracketed by two HIP events recorded
  * on the launch stream. fr_profile_read waits for the recorded events, returns per-kernel

@@ -88,11 +88,21 @@ static void timing_hook(void *user, hipStream_t s, const char *name, int tag, in
 }
 
 int Ctx::sweep_variant(int n) const {
-  // FR_SWEEP_VARIANT overrides the tile configuration of the plane sweeps (for tuning runs)
-  const char *v = std::getenv("FR_SWEEP_VARIANT");
-  int k = v ? std::atoi(v) : 0;
+  // FR_SWEEP_VARIANT overrides the tile configuration of the plane sweeps (manual tuning runs);
+  // else the autotuner's choice, else variant 0
+  int k = 0;
+  if (const char *v = std::getenv("FR_SWEEP_VARIANT")) {
+    k = std::atoi(v);
+  } else if (auto it = tuned_variant.find(n); it != tuned_variant.end()) {
+    k = it->second;
+  }
   if (k < 0 || k >= fr::fresnel_variants(n)) k = 0;
   return k;
+}
+
+int Ctx::gemm_tile(const CGemmArgs &g) const {
+  auto it = tuned_gemm.find({g.M, g.N, g.K, g.transA, g.transB});
+  return it == tuned_gemm.end() ? -1 : it->second;
 }
 
 LaunchHook Ctx::hook() {
@@ -176,10 +186,16 @@ int Ctx::twiddles(int n, hipStream_t s, const float2 **out) {
   return st;
 }
 
-int Ctx::mr(int n, hipStream_t s, MrPlane *out) {
+int Ctx::mr(int n, hipStream_t s, MrPlane *out, unsigned plan) {
   int np = 0, rad[kMrMaxPass];
   if (!mr_plan(n, &np, rad)) return FR_EUNSUPPORTED;
-  TableKey key{kMrTw, n, 0, 0, 0, 0};
+  if (plan == 0)
+    if (auto it = tuned_plan.find(n); it != tuned_plan.end()) plan = it->second;
+  if (plan != 0) {
+    // a reordering of the same radices (validated by the caller that chose it)
+    for (int i = 0; i < np; ++i) rad[i] = int((plan >> (5 * i)) & 31u);
+  }
+  TableKey key{kMrTw, n, uint64_t(mr_pack(np, rad)), 0, 0, 0};
   void *d = nullptr;
   if (auto it = tables.find(key); it != tables.end()) {
     d = it->second;
@@ -295,10 +311,11 @@ static CGemmArgs gemm_args() {
   return g;
 }
 
-static hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, void *partial, size_t partial_elems, hipStream_t s) {
-  int split = cgemm_split_for(g.M, g.N, g.K);
+hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, void *partial, size_t partial_elems, hipStream_t s, int cfg) {
+  if (cfg < 0) cfg = ctx->gemm_tile(g);
+  int split = cgemm_split_for(g.M, g.N, g.K, cfg);
   while (split > 1 && size_t(split) * size_t(g.M) * size_t(g.N) > partial_elems) split /= 2;
-  return launch_cgemm_split(g, split, partial, s, ctx->hook());
+  return launch_cgemm_split(g, split, cfg, partial, s, ctx->hook());
 }
 
 int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out, double n_d,

@@ -73,6 +73,8 @@ struct MrBatch {
   MrPlane p[kMrMaxBatch];
 };
 bool mr_plan(int n, int *npass, int *radix);
+// distinct orders of the greedy plan's radices (the first is the greedy plan), at most `max`
+int mr_plan_orders(int n, int max, unsigned *plans, int *npass);
 unsigned mr_pack(int npass, const int *radix);
 int mr_twiddle_count(int npass, const int *radix);
 void mr_twiddle_build(int npass, const int *radix, float2 *out);  // host
@@ -109,8 +111,11 @@ struct CGemmArgs {
 // to `partial` (split x M x N complex float64, 16-byte aligned) and are added in a fixed order
 // by a second kernel.
 constexpr int kMaxSplit = 16;
-int cgemm_split_for(int M, int N, int K);
-hipError_t launch_cgemm_split(const CGemmArgs &a, int split, void *partial, hipStream_t stream,
+// cfg: tile configuration (0 small 64 x 64, 1 large 64 x 128, 2 extra large 128 x 128), or -1
+// for the default choice by shape
+constexpr int kGemmTiles = 3;
+int cgemm_split_for(int M, int N, int K, int cfg);
+hipError_t launch_cgemm_split(const CGemmArgs &a, int split, int cfg, void *partial, hipStream_t stream,
                               const LaunchHook &hook);
 
 }  // namespace fr

@@ -53,8 +53,15 @@ struct Ctx {
   // copy `bytes` of host data to a new cached device buffer (waits on `s` for the copy)
   int upload(const TableKey &key, const void *host, size_t bytes, hipStream_t s, void **out);
   int twiddles(int n, hipStream_t s, const float2 **out);
-  // mixed-radix plan of edge n (radices and device twiddle table); FR_EUNSUPPORTED if none
-  int mr(int n, hipStream_t s, MrPlane *out);
+  // mixed-radix plan of edge n (radices and device twiddle table); FR_EUNSUPPORTED if none.
+  // plan != 0 asks for that packed pass order instead of the tuned or default one.
+  int mr(int n, hipStream_t s, MrPlane *out, unsigned plan = 0);
+
+  // choices made by the autotuner (fr_autotune), consulted by every later call
+  std::map<int, int> tuned_variant;                 // power-of-two sweep tile variant per edge
+  std::map<int, unsigned> tuned_plan;               // mixed-radix pass order per edge
+  std::map<std::tuple<int, int, int, int, int>, int> tuned_gemm;  // (M, N, K, transA, transB) -> tile
+  int gemm_tile(const CGemmArgs &g) const;
   int transfer(int n, double dx, double lam, double z, hipStream_t s, const float2 **out);
   int lens(int n, double dx, double lam, double f, hipStream_t s, const float2 **out);
   int mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out);
@@ -74,6 +81,9 @@ struct MftOut {
   double weight = 0.0;
   bool skip_out = false;
 };
+// one complex GEMM with the tuned (or, cfg >= 0, the given) tile configuration and a split-K
+// that fits `partial_elems` float64 complex partial sums
+hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, void *partial, size_t partial_elems, hipStream_t s, int cfg = -1);
 int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out, double n_d,
                      double du, const MftOut &o, void *ws, hipStream_t s);
 // out = alpha (du/n_d) W^H in conj(W) + beta cin, * mask  (cin may alias out)

@@ -144,8 +144,22 @@ cgemm_kernel(GemmParams gp) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = wave / C::WN, wn = wave % C::WN;
-  const int i0 = blockIdx.y * C::BM, j0 = blockIdx.x * C::BN;
-  const int kbeg = blockIdx.z * gp.k_per_split;
+  // Blocks are dealt round-robin to the 8 XCDs (each with its own L2). Renumber them so that
+  // each XCD runs a contiguous range of tiles, x (the output column tile) fastest: the tiles
+  // that share the rows of A (and the K slice) then share that XCD's L2.
+  int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  {
+    const int total = gridDim.x * gridDim.y * gridDim.z;
+    if (total % 8 == 0) {
+      const int lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+      const int tile = (lin & 7) * (total >> 3) + (lin >> 3);
+      bx = tile % gridDim.x;
+      by = (tile / gridDim.x) % gridDim.y;
+      bz = tile / (gridDim.x * gridDim.y);
+    }
+  }
+  const int i0 = by * C::BM, j0 = bx * C::BN;
+  const int kbeg = bz * gp.k_per_split;
   const int kend = min(a.K, kbeg + gp.k_per_split);
   const float sa = a.conjA ? -1.f : 1.f, sb = a.conjB ? -1.f : 1.f;
   double totr[TN][16], toti[TN][16];
@@ -209,7 +223,7 @@ cgemm_kernel(GemmParams gp) {
       const int i = i0 + wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
       if (i >= a.M || j >= a.N) continue;
       if (gp.split > 1) {
-        gp.partial[(size_t(blockIdx.z) * a.M + i) * a.N + j] = make_double2(totr[t][r], toti[t][r]);
+        gp.partial[(size_t(bz) * a.M + i) * a.N + j] = make_double2(totr[t][r], toti[t][r]);
       } else {
         epilogue(a, i, j, totr[t][r], toti[t][r]);
       }
@@ -265,9 +279,10 @@ bool use_large(int M, int N, int K) {
   return t * split_for(t, K) >= 256;
 }
 
-// tile configuration: 0 small, 1 large, 2 extra large; FR_GEMM_TILE (s, l, x) overrides the
-// choice for tuning runs
-int tile_choice(int M, int N, int K) {
+// tile configuration: 0 small, 1 large, 2 extra large; `cfg` >= 0 is a choice made by the
+// autotuner, else FR_GEMM_TILE (s, l, x) overrides the default for manual tuning runs
+int tile_choice(int M, int N, int K, int cfg) {
+  if (cfg >= 0 && cfg < kGemmTiles) return cfg;
   static const int forced = [] {
     const char *v = std::getenv("FR_GEMM_TILE");
     if (!v) return -1;
@@ -279,15 +294,15 @@ int tile_choice(int M, int N, int K) {
 
 }  // namespace
 
-int cgemm_split_for(int M, int N, int K) {
-  switch (tile_choice(M, N, K)) {
+int cgemm_split_for(int M, int N, int K, int cfg) {
+  switch (tile_choice(M, N, K, cfg)) {
     case 1: return split_for(tiles_of<CfgL>(M, N), K);
     case 2: return split_for(tiles_of<CfgX>(M, N), K);
     default: return split_for(tiles_of<CfgS>(M, N), K);
   }
 }
 
-hipError_t launch_cgemm_split(const CGemmArgs &a, int split, void *partial, hipStream_t stream,
+hipError_t launch_cgemm_split(const CGemmArgs &a, int split, int cfg_choice, void *partial, hipStream_t stream,
                               const LaunchHook &hook) {
   GemmParams gp;
   gp.a = a;
@@ -296,7 +311,7 @@ hipError_t launch_cgemm_split(const CGemmArgs &a, int split, void *partial, hipS
   kps = (kps + BK - 1) / BK * BK;
   gp.k_per_split = kps;
   gp.partial = static_cast<double2 *>(partial);
-  const int cfg = tile_choice(a.M, a.N, a.K);
+  const int cfg = tile_choice(a.M, a.N, a.K, cfg_choice);
   char name[64];
   std::snprintf(name, sizeof name, "cgemm%s_%dx%dx%d_s%d", cfg == 1 ? "L" : cfg == 2 ? "X" : "S", a.M, a.N, a.K,
                 split);

@@ -259,6 +259,16 @@ __global__ void __launch_bounds__(kT * 4) mr_col_sweep(MrBatch) {
 
 bool mr_plan(int n, int *npass, int *radix) { return mr_plan_build(n, kMrMaxN, kMrMaxPass, npass, radix); }
 unsigned mr_pack(int npass, const int *radix) { return mr_plan_pack(npass, radix); }
+int mr_plan_orders(int n, int max, unsigned *plans, int *npass) {
+  int rad[kMrMaxPass];
+  if (!mr_plan_build(n, kMrMaxN, kMrMaxPass, npass, rad)) return 0;
+  std::sort(rad, rad + *npass, [](int a, int b) { return a > b; });
+  int count = 0;
+  do {
+    plans[count++] = mr_plan_pack(*npass, rad);
+  } while (count < max && std::next_permutation(rad, rad + *npass, [](int a, int b) { return a > b; }));
+  return count;
+}
 int mr_twiddle_count(int npass, const int *radix) { return mr_twiddle_size(npass, radix); }
 void mr_twiddle_build(int npass, const int *radix, float2 *out) { mr_twiddle_fill(npass, radix, out); }
 

@@ -139,7 +139,7 @@ __global__ void scale_by_grad(const float *g, float w, const float2 *e, float2 *
 //                T[i][b] = sum_j g_s[i][j] G[j][b]; one pass over E and B (HBM-bound)
 //   dm_grad_G:   per 256-row block, T = sum of the group shares (group order), then the
 //                block's share of sum_i G[i][a] T[i][b]
-//   dm_grad_reduce: gA += the block shares, in block order.
+//   dm_grad_reduce: gA += the block shares, in a fixed order.
 // E is the stored plane, or (E == null) the pupil optic amp exp(2 pi i (opd + 2 pre) / lambda)
 // synthesised here (amp/opd nd x nd centred, pre n x n).
 constexpr int kRows = 16;    // rows per dm_grad_T block
@@ -253,7 +253,8 @@ __global__ void __launch_bounds__(256) dm_grad_T(const float2 *E, const float2 *
 }
 
 // per block of kGRows rows: T rows (group shares added in group order), then the block's share
-// of G^T T
+// of G^T T. All group shares of an element are loaded before they are added.
+constexpr int kMaxGroups = 16;  // n <= 8192
 __global__ void __launch_bounds__(256) dm_grad_G(const float *tpart, int groups, const float *G, int n, int na,
                                                  float *gpart) {
   __shared__ float Ts[kGRows][kMaxAct + 1];
@@ -263,13 +264,16 @@ __global__ void __launch_bounds__(256) dm_grad_G(const float *tpart, int groups,
   const int rows = min(kGRows, n - r0);
   for (int e = tid; e < kGRows * kMaxAct; e += 256) {
     const int r = e / kMaxAct, c = e % kMaxAct;
-    float v = 0.f, gg = 0.f;
-    if (r < rows && c < na) {
-      for (int q = 0; q < groups; ++q) v += tpart[(size_t(q) * n + r0 + r) * na + c];
-      gg = G[size_t(r0 + r) * na + c];
-    }
-    Ts[r][c] = v;
-    Gr[r][c] = gg;
+    const bool in = r < rows && c < na;
+    const size_t o = size_t(r0 + min(r, rows - 1)) * na + min(c, na - 1);
+    float part[kMaxGroups];
+#pragma unroll
+    for (int q = 0; q < kMaxGroups; ++q) part[q] = q < groups ? tpart[size_t(q) * n * na + o] : 0.f;
+    float v = 0.f;
+#pragma unroll
+    for (int q = 0; q < kMaxGroups; ++q) v += part[q];
+    Ts[r][c] = in ? v : 0.f;
+    Gr[r][c] = in ? G[o] : 0.f;
   }
   __syncthreads();
   for (int e = tid; e < na * na; e += 256) {
@@ -281,13 +285,19 @@ __global__ void __launch_bounds__(256) dm_grad_G(const float *tpart, int groups,
   }
 }
 
-// gA[a][b] += sum over blocks of gpart[block][a][b], in block order
-__global__ void dm_grad_reduce(const float *part, int blocks, int nn, float *gA) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
-    float v = 0.f;
-    for (int s = 0; s < blocks; ++s) v += part[size_t(s) * nn + e];
-    gA[e] += v;
-  }
+// gA[a][b] += sum over blocks of gpart[block][a][b]: each output's terms are split over the
+// four waves of a block (wave q takes blocks q, q + 4, ...), and the four partial sums are added
+// in wave order, so the result does not depend on scheduling
+__global__ void __launch_bounds__(256) dm_grad_reduce(const float *part, int blocks, int nn, float *gA) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  float v = 0.f;
+  if (e < nn)
+    for (int s = q; s < blocks; s += 4) v += part[size_t(s) * nn + e];
+  red[q][lane] = v;
+  __syncthreads();
+  if (q == 0 && e < nn) gA[e] += ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 template <typename K, typename... Args>
@@ -381,6 +391,8 @@ int check_desc(const fr_train_desc *d, int32_t n_lambda, const double *lam, cons
   if (d->n_dm < 0 || d->n_dm > 2) return FR_EINVAL;
   if (d->n_dm > 0 && (d->n_act <= 0 || !d->dm_heights_m)) return FR_EINVAL;
   if (d->n_dm > 0 && d->n_act > kMaxAct) return FR_EUNSUPPORTED;
+  for (int j = 0; j < n_lambda; ++j)
+    if ((n_pad[j] + kGroup - 1) / kGroup > kMaxGroups) return FR_EUNSUPPORTED;
   if (!std::isfinite(d->z_m)) return FR_EINVAL;
   if (d->occ_m <= 0 || !(d->occ_du_c > 0) || d->det_m <= 0 || !(d->det_du_c > 0)) return FR_EINVAL;
   if (!(mode & FR_TRAIN_NO_OCCULTER) && !d->occ_mask) return FR_EINVAL;
@@ -546,8 +558,11 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     hipLaunchKernelGGL(dm_grad_G, dim3(gblocks), dim3(256), 0, s, (const float *)TPART, groups, G, n, na, GPART);
     FR_TRY_HIP(hipGetLastError());
     hook(s, "dm_grad_G", n, 1);
-    FR_TRY_HIP(launch1d(dm_grad_reduce, size_t(na) * na, s, hook, "dm_grad_reduce", (const float *)GPART,
-                        gblocks, na * na, gA));
+    hook(s, "dm_grad_reduce", n, 0);
+    hipLaunchKernelGGL(dm_grad_reduce, dim3((na * na + 63) / 64), dim3(256), 0, s, (const float *)GPART, gblocks,
+                       na * na, gA);
+    FR_TRY_HIP(hipGetLastError());
+    hook(s, "dm_grad_reduce", n, 1);
     return FR_OK;
   };
 

@@ -85,6 +85,9 @@ def lib():
             "fr_profile_enable": (_c.c_int, [_vp, _c.c_int]),
             "fr_profile_read": (_c.c_int, [_vp, i32, _c.c_char_p, i32, _c.POINTER(f64),
                                            _c.POINTER(_c.c_int64), _c.POINTER(i32)]),
+            "fr_autotune": (_c.c_int, [_vp, i32, i32, i32, _vp]),
+            "fr_autotune_save": (_c.c_int, [_vp, _c.c_char_p]),
+            "fr_autotune_load": (_c.c_int, [_vp, _c.c_char_p]),
             "propagate_train_workspace_bytes": (sz, [_c.POINTER(FrTrainDesc), i32, _c.POINTER(i32), i32]),
             "propagate_train": (_c.c_int, [_vp, _c.POINTER(FrTrainDesc), i32, _c.POINTER(f64),
                                            _c.POINTER(i32), _c.POINTER(f32), i32, _vp, _vp, _vp, _vp,
@@ -293,6 +296,34 @@ def mft_adjoint(inp, n_d, n_out, du, alpha=1.0, beta=0.0, mask=None, out=None, s
                        ws.numel(), _stream_handle(dev, stream))
     _check(st, "mft_adjoint")
     return out
+
+
+# ---- autotuner -------------------------------------------------------------------------------
+
+FR_TUNE_FRESNEL = 1
+FR_TUNE_MFT = 2
+
+
+def autotune_fresnel(n, device=None, stream=None):
+    """Time the sweep configurations for plane edge n and keep the fastest in the context."""
+    dev = torch.cuda.current_device() if device is None else device
+    _check(lib().fr_autotune(context(dev).handle, FR_TUNE_FRESNEL, int(n), 0, _stream_handle(dev, stream)),
+           "fr_autotune")
+
+
+def autotune_mft(n, m, device=None, stream=None):
+    """Time the GEMM tile configurations of the n <-> m MFTs and keep the fastest."""
+    dev = torch.cuda.current_device() if device is None else device
+    _check(lib().fr_autotune(context(dev).handle, FR_TUNE_MFT, int(n), int(m), _stream_handle(dev, stream)),
+           "fr_autotune")
+
+
+def autotune_save(path, device=None):
+    _check(lib().fr_autotune_save(context(device).handle, os.fsencode(path)), "fr_autotune_save")
+
+
+def autotune_load(path, device=None):
+    _check(lib().fr_autotune_load(context(device).handle, os.fsencode(path)), "fr_autotune_load")
 
 
 # ---- kernel timing ---------------------------------------------------------------------------

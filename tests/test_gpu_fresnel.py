@@ -229,3 +229,33 @@ def test_fresnel_step_8192_sampled_rows(adjoint):
     else:
         ref = oracle.as_propagate_rows(field * ph, dx, lam, z, rows)
     assert rel_l2(got, ref) <= TOL
+
+
+def test_autotuner_choices_keep_parity(tmp_path):
+    # tune the sweeps for a power-of-two and a mixed-radix edge and the MFT GEMMs, then the
+    # tuned kernels still match the oracle; the choices survive a save / load round trip and a
+    # corrupted file is refused
+    banner("autotune: sweeps 4096 and 3840, MFT 4096 <-> 256")
+    fb.autotune_fresnel(4096)
+    fb.autotune_fresnel(3840)
+    fb.autotune_mft(4096, 256)
+    for n, adjoint in ((3840, False), (4096, True)):
+        field, amp, opd, dx, lam, z, f = _case(n, 7 * n + adjoint)
+        got = _run_gpu(field, amp, opd, dx, lam, z, f, adjoint)
+        ref = oracle.fresnel_step(f32(field), dx, lam, z, amp=f32(amp), opd=f32(opd), lens_focal=f,
+                                  adjoint=adjoint)
+        assert rel_l2(got, ref) <= TOL
+    # a mixed batch uses the tuned mixed-radix order
+    t1, t2 = to_gpu(synth.random_field(3840, 5)), to_gpu(synth.random_field(96, 6))
+    fb.fresnel_step_batched([t1, t2], 2.5e-5, 550e-9, 0.3)
+    ref = oracle.fresnel_step(f32(synth.random_field(3840, 5)), 2.5e-5, 550e-9, 0.3)
+    assert rel_l2(to_np(t1), ref) <= TOL
+    path = tmp_path / "tune.txt"
+    fb.autotune_save(str(path))
+    text = path.read_text()
+    assert "sweep 4096" in text and "plan 3840" in text and "gemm 4096 256 4096" in text
+    fb.autotune_load(str(path))
+    bad = tmp_path / "bad.txt"
+    bad.write_text("plan 3840 17\n")  # not an order of 3840's radices
+    with pytest.raises(fb.FrError):
+        fb.autotune_load(str(bad))
