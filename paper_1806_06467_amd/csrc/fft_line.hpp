@@ -47,9 +47,12 @@ struct PassOut {
 // entries (the table is built in float64 on the host; each entry is within half an ulp).
 template <int P, int R, int NB, int T>
 struct PassTw {
-  c32 w[NB][R > 1 ? R - 1 : 1];
+  // with several butterflies per thread and long lines (32 elements per thread) the twiddles
+  // are read per butterfly inside the pass instead (register budget)
+  static constexpr bool lazy = NB > 1 && NB * R >= 32;
+  c32 w[lazy ? 1 : NB][R > 1 ? R - 1 : 1];
   __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) {
-    if constexpr (P > 1) {
+    if constexpr (P > 1 && !lazy) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         const int k = (t + j * T) % P;
@@ -70,7 +73,13 @@ struct FirstOf {
 
 // Pass with radix R after span P. The twiddles of the next pass are loaded before this
 // pass's LDS exchange, so their latency overlaps the exchange.
-template <bool INV, int N, int E, int P, int R, int... Rest>
+//
+// HALF exchanges move the line through an LDS buffer of N/2 (+ padding) in two rounds: the
+// outputs at positions below N/2 (butterflies b < N/(2R): threads t < T/2 when each thread owns
+// one butterfly, else the first half of each thread's butterflies), then the upper half. Every
+// non-last pass has P R <= N/2, so the N/2 boundary never splits a butterfly's outputs, and the
+// reading slots split the same way (slot m < E/2 is position t + T m < N/2).
+template <bool INV, bool HALF, int N, int E, int P, int R, int... Rest>
 __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, int t,
                                            const float2* __restrict__ tw,
                                            const PassTw<P, R, E / R, N / E>& cur) {
@@ -78,7 +87,24 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide the elements per thread");
   static_assert(N % (P * R) == 0, "plan does not factor N");
+  static_assert(!HALF || NB == 1 || NB % 2 == 0, "half exchanges split each thread's butterflies in two");
   constexpr bool last = sizeof...(Rest) == 0;
+  constexpr bool lazy = PassTw<P, R, NB, T>::lazy;
+  // outputs of the second half-round, held until the first half has been exchanged
+  constexpr int HOLD = !HALF || last ? 1 : (NB == 1 ? 1 : NB / 2);
+  c32 hold[HOLD][R];
+  // write output r of butterfly b (positions shifted down by `shift`)
+  auto put = [&](int b, int shift, const c32 (&u)[R]) {
+    if constexpr (PassOut<P, R>::exact) {
+      const PassOut<P, R> o(b - shift / R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[o.base + PassOut<P, R>::off(r)] = u[r];
+    } else {
+      const int base = (b / P) * (P * R) + (b % P) - shift;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lds_pad(base + r * P)] = u[r];
+    }
+  };
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     c32 u[R];
@@ -86,22 +112,37 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
     for (int r = 0; r < R; ++r) u[r] = v[j + r * NB];
     const int b = t + j * T;
     if constexpr (P > 1) {
+      if constexpr (lazy) {
+        const int k = b % P;
 #pragma unroll
-      for (int r = 1; r < R; ++r) u[r] = INV ? cmulc(u[r], cur.w[j][r - 1]) : cmul(u[r], cur.w[j][r - 1]);
+        for (int r = 1; r < R; ++r) {
+          const float2 q = tw[(r - 1) * P + k];
+          u[r] = INV ? cmulc(u[r], c32{q.x, q.y}) : cmul(u[r], c32{q.x, q.y});
+        }
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) u[r] = INV ? cmulc(u[r], cur.w[j][r - 1]) : cmul(u[r], cur.w[j][r - 1]);
+      }
     }
     DftDir<R, INV>::run(u);
     if constexpr (last) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[j + r * NB] = u[r];
-    } else {
-      if constexpr (PassOut<P, R>::exact) {
-        const PassOut<P, R> o(b);
-#pragma unroll
-        for (int r = 0; r < R; ++r) lds[o.base + PassOut<P, R>::off(r)] = u[r];
+    } else if constexpr (!HALF) {
+      put(b, 0, u);
+    } else if constexpr (NB == 1) {
+      if (t < T / 2) {
+        put(b, 0, u);
       } else {
-        const int base = (b / P) * (P * R) + (b % P);
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[lds_pad(base + r * P)] = u[r];
+        for (int r = 0; r < R; ++r) hold[0][r] = u[r];
+      }
+    } else {
+      if (j < NB / 2) {
+        put(b, 0, u);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) hold[j - NB / 2][r] = u[r];
       }
     }
   }
@@ -110,18 +151,36 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
     const float2* tw_next = tw + (P > 1 ? (R - 1) * P : 0);
     PassTw<P * R, R2, E / R2, T> nxt;
     nxt.load(tw_next, t);
-    __syncthreads();
-    if constexpr (T % 16 == 0) {
-      // pad(t + T m) = pad(t) + 17 T m / 16
-      const int base = lds_pad(t);
+    // read slots [m0, m1), whose positions start at T m0
+    auto get = [&](int m0, int m1) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = lds[base + m * (T + T / 16)];
+      for (int m = 0; m < E; ++m) {
+        if (m < m0 || m >= m1) continue;
+        if constexpr (T % 16 == 0) {
+          v[m] = lds[lds_pad(t) + (m - m0) * (T + T / 16)];
+        } else {
+          v[m] = lds[lds_pad(t + T * (m - m0))];
+        }
+      }
+    };
+    __syncthreads();
+    if constexpr (!HALF) {
+      get(0, E);
+      __syncthreads();
     } else {
+      get(0, E / 2);
+      __syncthreads();
+      if constexpr (NB == 1) {
+        if (t >= T / 2) put(t, N / 2, hold[0]);
+      } else {
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = lds[lds_pad(t + T * m)];
+        for (int j = NB / 2; j < NB; ++j) put(t + j * T, N / 2, hold[j - NB / 2]);
+      }
+      __syncthreads();
+      get(E / 2, E);
+      __syncthreads();
     }
-    __syncthreads();
-    fft_passes<INV, N, E, P * R, Rest...>(v, lds, t, tw_next, nxt);
+    fft_passes<INV, HALF, N, E, P * R, Rest...>(v, lds, t, tw_next, nxt);
   }
 }
 
@@ -157,15 +216,18 @@ struct Plan {
   static constexpr int twiddles = TwiddleTable<N_, 1, Rs...>::size();
   static constexpr int R0 = FirstOf<Rs...>::value;
   static void build_twiddles(float2* out) { TwiddleTable<N_, 1, Rs...>::build(out); }
-  // unnormalised DFT of the line, kernel exp(-2 pi i nk/N); tw = the plan's twiddle table
+  // unnormalised DFT of the line, kernel exp(-2 pi i nk/N); tw = the plan's twiddle table.
+  // HALF: exchanges through an LDS line of N/2 (LdsLine<N/2>), in two rounds each.
+  template <bool HALF = false>
   __device__ __forceinline__ static void forward(c32 (&v)[E_], c32* lds, int t, const float2* tw) {
     PassTw<1, R0, E_ / R0, N_ / E_> none;
-    fft_passes<false, N_, E_, 1, Rs...>(v, lds, t, tw, none);
+    fft_passes<false, HALF, N_, E_, 1, Rs...>(v, lds, t, tw, none);
   }
   // unnormalised inverse DFT, kernel exp(+2 pi i nk/N)
+  template <bool HALF = false>
   __device__ __forceinline__ static void inverse(c32 (&v)[E_], c32* lds, int t, const float2* tw) {
     PassTw<1, R0, E_ / R0, N_ / E_> none;
-    fft_passes<true, N_, E_, 1, Rs...>(v, lds, t, tw, none);
+    fft_passes<true, HALF, N_, E_, 1, Rs...>(v, lds, t, tw, none);
   }
 };
 

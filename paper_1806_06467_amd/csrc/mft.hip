@@ -60,10 +60,12 @@ __device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, doubl
   }
 }
 
-// Tile configuration: WM x WN waves, each wave a 32 x (32 TN) piece of the block tile.
-template <int WM_, int WN_, int TN_>
+// Tile configuration: WM x WN waves, each wave a 32 x (32 TN) piece of the block tile; the
+// operand tiles of the next PD stages are in flight while a stage is multiplied.
+template <int WM_, int WN_, int TN_, int PD_ = 1>
 struct Cfg {
-  static constexpr int WM = WM_, WN = WN_, TN = TN_;
+  static constexpr int WM = WM_, WN = WN_, TN = TN_, PD = PD_;
+  static constexpr int waves = TN == 1 ? 3 : 2;  // waves per SIMD the register budget targets
   static constexpr int BM = 32 * WM, BN = 32 * TN * WN;
   static constexpr int threads = 64 * WM * WN;
   static constexpr int la = BM * BK / threads;  // A elements per thread per tile
@@ -74,6 +76,7 @@ struct Cfg {
 using CfgL = Cfg<2, 2, 2>;  // 64 x 128, 256 threads: two blocks share a compute unit
 using CfgS = Cfg<2, 2, 1>;  // 64 x 64, 256 threads
 using CfgX = Cfg<4, 2, 2>;  // 128 x 128, 512 threads
+using CfgP = Cfg<2, 2, 1, 2>;  // 64 x 64, 256 threads, two stages of loads in flight
 
 // Per-thread share of one BK-deep operand tile, mapped so that consecutive threads walk
 // memory contiguously.
@@ -134,7 +137,7 @@ struct TileLoad {
 };
 
 template <class C, bool TA, bool TB>
-__global__ void __launch_bounds__(C::threads) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(C::threads) __attribute__((amdgpu_waves_per_eu(C::waves)))
 cgemm_kernel(GemmParams gp) {
   static_assert(C::threads <= 512, "block too large");
   constexpr int TN = C::TN;
@@ -167,19 +170,11 @@ cgemm_kernel(GemmParams gp) {
   for (int t = 0; t < TN; ++t)
 #pragma unroll
     for (int r = 0; r < 16; ++r) totr[t][r] = toti[t][r] = 0.0;
-  TileLoad<C, TA, TB> ld;
-  if (kbeg < kend) {
-    ld.load(a, tid, i0, j0, kbeg, kend);
-    ld.store(As[0], Bs[0], tid, sa, sb);
-  }
-  __syncthreads();
   const int arow = wm * 32 + (lane & 31);
   const int bcol = wn * 32 * TN + (lane & 31);
   const int kl = lane >> 5;
-  int buf = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    const bool more = k0 + BK < kend;
-    if (more) ld.load(a, tid, i0, j0, k0 + BK, kend);
+  // one stage: multiply the LDS tile `buf`, fold into the float64 totals
+  auto multiply = [&](int buf) {
     floatx16 cr[TN], ci[TN];
 #pragma unroll
     for (int t = 0; t < TN; ++t) {
@@ -210,10 +205,45 @@ cgemm_kernel(GemmParams gp) {
         totr[t][r] += double(cr[t][r]);
         toti[t][r] += double(ci[t][r]);
       }
-    if (more) ld.store(As[buf ^ 1], Bs[buf ^ 1], tid, sa, sb);
+  };
+  if constexpr (C::PD == 1) {
+    TileLoad<C, TA, TB> ld;
+    if (kbeg < kend) {
+      ld.load(a, tid, i0, j0, kbeg, kend);
+      ld.store(As[0], Bs[0], tid, sa, sb);
+    }
     __syncthreads();
-    buf ^= 1;
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      const bool more = k0 + BK < kend;
+      if (more) ld.load(a, tid, i0, j0, k0 + BK, kend);
+      multiply(buf);
+      if (more) ld.store(As[buf ^ 1], Bs[buf ^ 1], tid, sa, sb);
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
+    // two register sets: while stage s is multiplied, one set receives stage s + 2 and the
+    // other holds stage s + 1 (stored to the other LDS buffer at the end of the stage)
+    TileLoad<C, TA, TB> l0, l1;
+    if (kbeg < kend) {
+      l0.load(a, tid, i0, j0, kbeg, kend);
+      l0.store(As[0], Bs[0], tid, sa, sb);
+    }
+    if (kbeg + BK < kend) l1.load(a, tid, i0, j0, kbeg + BK, kend);
+    __syncthreads();
+    auto step = [&](int k0, int buf, TileLoad<C, TA, TB> &fill, const TileLoad<C, TA, TB> &ready) {
+      if (k0 + 2 * BK < kend) fill.load(a, tid, i0, j0, k0 + 2 * BK, kend);
+      multiply(buf);
+      if (k0 + BK < kend) ready.store(As[buf ^ 1], Bs[buf ^ 1], tid, sa, sb);
+      __syncthreads();
+    };
+    for (int k0 = kbeg; k0 < kend; k0 += 2 * BK) {
+      step(k0, 0, l0, l1);
+      if (k0 + BK < kend) step(k0 + BK, 1, l1, l0);
+    }
   }
+  // what the float32 accumulators still hold was folded at the end of each stage
   // accumulator r of lane l sits at row (r/4)*8 + (l/32)*4 + r%4, column l%32 of a 32 x 32 tile
 #pragma unroll
   for (int t = 0; t < TN; ++t) {
@@ -279,14 +309,15 @@ bool use_large(int M, int N, int K) {
   return t * split_for(t, K) >= 256;
 }
 
-// tile configuration: 0 small, 1 large, 2 extra large; `cfg` >= 0 is a choice made by the
-// autotuner, else FR_GEMM_TILE (s, l, x) overrides the default for manual tuning runs
+// tile configuration: 0 small, 1 large, 2 extra large, 3 small with deeper prefetch; `cfg` >= 0
+// is a choice made by the autotuner, else FR_GEMM_TILE (s, l, x, p) overrides the default for
+// manual tuning runs
 int tile_choice(int M, int N, int K, int cfg) {
   if (cfg >= 0 && cfg < kGemmTiles) return cfg;
   static const int forced = [] {
     const char *v = std::getenv("FR_GEMM_TILE");
     if (!v) return -1;
-    return v[0] == 's' ? 0 : v[0] == 'l' ? 1 : v[0] == 'x' ? 2 : -1;
+    return v[0] == 's' ? 0 : v[0] == 'l' ? 1 : v[0] == 'x' ? 2 : v[0] == 'p' ? 3 : -1;
   }();
   if (forced >= 0) return forced;
   return use_large(M, N, K) ? 1 : 0;
@@ -298,6 +329,7 @@ int cgemm_split_for(int M, int N, int K, int cfg) {
   switch (tile_choice(M, N, K, cfg)) {
     case 1: return split_for(tiles_of<CfgL>(M, N), K);
     case 2: return split_for(tiles_of<CfgX>(M, N), K);
+    case 3: return split_for(tiles_of<CfgP>(M, N), K);
     default: return split_for(tiles_of<CfgS>(M, N), K);
   }
 }
@@ -313,11 +345,12 @@ hipError_t launch_cgemm_split(const CGemmArgs &a, int split, int cfg_choice, voi
   gp.partial = static_cast<double2 *>(partial);
   const int cfg = tile_choice(a.M, a.N, a.K, cfg_choice);
   char name[64];
-  std::snprintf(name, sizeof name, "cgemm%s_%dx%dx%d_s%d", cfg == 1 ? "L" : cfg == 2 ? "X" : "S", a.M, a.N, a.K,
+  std::snprintf(name, sizeof name, "cgemm%s_%dx%dx%d_s%d", cfg == 1 ? "L" : cfg == 2 ? "X" : cfg == 3 ? "P" : "S", a.M, a.N, a.K,
                 split);
   hook(stream, name, a.K, 0);
   hipError_t e = cfg == 1 ? launch_cfg<CfgL>(gp, stream)
                  : cfg == 2 ? launch_cfg<CfgX>(gp, stream)
+                 : cfg == 3 ? launch_cfg<CfgP>(gp, stream)
                             : launch_cfg<CfgS>(gp, stream);
   hook(stream, name, a.K, 1);
   if (e != hipSuccess || split == 1) return e;

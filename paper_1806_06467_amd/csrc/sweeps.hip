@@ -220,11 +220,14 @@ __global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const 
   for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * 8u, v[m]);
 }
 
-template <class PL, int LINES>
+// HALF: the FFT exchanges go through half-size LDS lines in two rounds, so that two blocks fit
+// on a compute unit
+template <class PL, int LINES, bool HALF = false>
 __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const float2 *tw) {
   constexpr int N = PL::N, E = PL::E, T = PL::T;
   constexpr int G = N / LINES;  // column groups per plane
-  __shared__ c32 lds[LINES * (LdsLine<N>::size + 4)];
+  constexpr int LINE = (HALF ? LdsLine<N / 2>::size : LdsLine<N>::size) + 4;
+  __shared__ c32 lds[LINES * LINE];
   const PlaneArgs &pa = args.p[blockIdx.y];
   const int c = threadIdx.x % LINES;
   const int t = threadIdx.x / LINES;
@@ -242,10 +245,10 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], post_optic(pa, N, t + T * m, x));
   }
-  c32 *my = lds + c * (LdsLine<N>::size + 4);
-  PL::forward(v, my, t, tw);
+  c32 *my = lds + c * LINE;
+  PL::template forward<HALF>(v, my, t, tw);
   freq_product<E, T>(v, pa.h, t, adj);
-  PL::inverse(v, my, t, tw);
+  PL::template inverse<HALF>(v, my, t, tw);
   if (!adj && pa.post_surf) {
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = cmul(v[m], post_optic(pa, N, t + T * m, x));
@@ -259,10 +262,11 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
 // prologue) and the row sweep second (conjugate optic epilogue). The two halves of the
 // angular-spectrum step commute, so only the placement of the optics sets the order, and the
 // amplitude/OPD maps are always read along rows.
-template <class PL, int ROW_LINES, int COL_LINES>
+template <class PL, int ROW_LINES, int COL_LINES, class PC = PL, bool CHALF = false>
 hipError_t launch_sweeps(const BatchArgs &fwd, int nf, const BatchArgs &adj, int na,
                          const float2 *tw, hipStream_t s, const LaunchHook &hook) {
   constexpr int N = PL::N;
+  static_assert(PC::N == N, "row and column plans of one edge");
   static_assert(N % ROW_LINES == 0 && N % COL_LINES == 0, "tile must divide n");
   // timing names carry the direction (the optic maps read differ)
   auto rows = [&](const BatchArgs &a, int count, const char *name) {
@@ -275,8 +279,8 @@ hipError_t launch_sweeps(const BatchArgs &fwd, int nf, const BatchArgs &adj, int
   };
   auto cols = [&](const BatchArgs &a, int count, const char *name) {
     hook(s, name, N, 0);
-    hipLaunchKernelGGL((col_sweep<PL, COL_LINES>), dim3(N / COL_LINES, count),
-                       dim3(PL::T * COL_LINES), 0, s, a, tw);
+    hipLaunchKernelGGL((col_sweep<PC, COL_LINES, CHALF>), dim3(N / COL_LINES, count),
+                       dim3(PC::T * COL_LINES), 0, s, a, tw);
     hipError_t e = hipGetLastError();
     hook(s, name, N, 1);
     return e;
@@ -328,7 +332,7 @@ void fresnel_twiddle_build(int n, float2 *out) {
   }
 }
 
-int fresnel_variants(int n) { return n == 4096 || n == 2048 || n == 8192 ? 3 : 1; }
+int fresnel_variants(int n) { return n == 4096 ? 4 : n == 2048 || n == 8192 ? 3 : 1; }
 
 hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const float2 *root,
                                 hipStream_t s, const LaunchHook &hook, int variant) {
@@ -372,6 +376,8 @@ hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const
       using P4 = Plan<4096, 16, 16, 16, 16>;
       if (variant == 1) FR_SWEEPS(P4, 1, 2);
       if (variant == 2) FR_SWEEPS(P4, 2, 2);
+      // column exchanges through half-size LDS lines
+      if (variant == 3) return launch_sweeps<P4, 1, 4, P4, true>(fwd, nf, adj, na, root, s, hook);
       FR_SWEEPS(P4, 1, 4);
     }
     case 8192: {

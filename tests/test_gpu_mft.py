@@ -86,3 +86,21 @@ def test_airy_256_aperture_on_gpu():
     core = rho <= 3.0
     cut = np.abs(got[64, :]) / abs(got[64, 64])
     assert np.max(np.abs(cut - np.abs(airy))[core]) <= 1.5e-3
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+def test_every_gemm_tile_configuration_matches_oracle(tile, tmp_path):
+    # force one tile configuration on all four GEMMs of a ragged forward and adjoint MFT (through
+    # the autotuner's file format) and check both transforms against the oracle
+    n, m, n_d, du = 1000, 130, 500.0, 0.3
+    banner(f"mft with GEMM tile configuration {tile}")
+    shapes = [(n, m, n, 0, 1), (m, m, n, 0, 0), (m, n, m, 0, 0), (n, n, m, 1, 0)]
+    f = tmp_path / "tiles.txt"
+    f.write_text("".join("gemm %d %d %d %d %d %d\n" % (s + (tile,)) for s in shapes))
+    fb.autotune_load(str(f))
+    e = synth.random_field(n, 31)
+    got = to_np(fb.mft_forward(to_gpu(e), n_d, m, du))
+    assert rel_l2(got, oracle.mft(f32(e), n_d, m, du)) <= TOL
+    eb = synth.random_field(m, 32)
+    got = to_np(fb.mft_adjoint(to_gpu(eb), n_d, n, du))
+    assert rel_l2(got, oracle.mft_adjoint(f32(eb), n_d, n, du)) <= TOL
