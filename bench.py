@@ -185,15 +185,18 @@ def main():
 
     n_prof = 2
     _, prof = timed(eager_batched, n_prof, 1, profile=True)
+    # per kernel name: total ms, launches, and the planes the launches covered (sweep timing
+    # tags carry the planes per launch)
     agg = {}
     for k, (tot, cnt) in prof.items():
-        name = k.split("/")[0]
-        a = agg.setdefault(name, [0.0, 0])
+        name, _, tag = k.partition("/")
+        a = agg.setdefault(name, [0.0, 0, 0])
         a[0] += tot
         a[1] += cnt
+        a[2] += cnt * (int(tag) if tag.isdigit() else 0)
     kernels_ms_per_step = {k: v[0] / n_prof for k, v in sorted(agg.items(), key=lambda kv: -kv[1][0])}
 
-    # algorithmic cost per launch of the step's kernels (21 planes per sweep launch):
+    # algorithmic cost (per plane for the sweeps, per launch otherwise):
     #   forward row sweep: the pupil optic is synthesised (no field read): write the field,
     #     read the pupil DM map and the two N_D^2 pupil windows;
     #   adjoint row sweep: read + write the field, the same maps (conjugate optic);
@@ -201,22 +204,22 @@ def main():
     #   dm_grad_T: read E and B (last DM) or B, the pupil DM map and the windows (pupil DM);
     #   cgemm M x N x K: 8 M N K flops.
     n2, nd2 = N * N, N_D * N_D
-    hbm_model = {
-        "row_sweep": N_LAMBDA * (8 * n2 + 4 * n2 + 8 * nd2),
-        "row_sweep_adj": N_LAMBDA * (16 * n2 + 4 * n2 + 8 * nd2),
-        "col_sweep": N_LAMBDA * (16 * n2 + 4 * n2),
-        "col_sweep_adj": N_LAMBDA * (16 * n2 + 4 * n2),
-        "dm_grad_T": 16 * n2,
-        "dm_grad_T_pupil": 8 * n2 + 4 * n2 + 8 * nd2,
+    per_plane = {
+        "row_sweep": 8 * n2 + 4 * n2 + 8 * nd2,
+        "row_sweep_adj": 16 * n2 + 4 * n2 + 8 * nd2,
+        "col_sweep": 16 * n2 + 4 * n2,
+        "col_sweep_adj": 16 * n2 + 4 * n2,
     }
+    per_launch = {"dm_grad_T": 16 * n2, "dm_grad_T_pupil": 8 * n2 + 4 * n2 + 8 * nd2}
 
     def roofline_of(name):
-        tot, cnt = agg[name]
+        tot, cnt, planes = agg[name]
         ms = tot / cnt
-        if name in hbm_model:
-            gbs = hbm_model[name] / (ms * 1e-3) / 1e9
+        if name in per_plane or name in per_launch:
+            nbytes = per_plane[name] * planes / cnt if name in per_plane else per_launch[name]
+            gbs = nbytes / (ms * 1e-3) / 1e9
             return {"bound": "hbm", "kernel": name, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": hbm_model[name],
+                    "frac": gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nbytes,
                     "avg_launch_ms": ms}
         if name.startswith("cgemm"):
             m, n_, k = (int(x) for x in name.split("_")[1].split("x"))
@@ -247,20 +250,28 @@ def main():
     fr_calls = 10
     ms_fr, prof_fr = timed(lambda: fb.fresnel_step_batched(fields, DX, lam_pl, Z, amps=amp, opds=opd,
                                                            adjoints=adjs), fr_calls, 2, profile=True)
-    # each sweep launch covers the 21 planes of one direction; both row launches apply the
-    # amplitude and OPD maps (prologue forward, conjugate epilogue adjoint)
-    per_launch = {"row_sweep": N_LAMBDA * sweep_bytes(N, 2), "row_sweep_adj": N_LAMBDA * sweep_bytes(N, 2),
-                  "col_sweep": N_LAMBDA * sweep_bytes(N, 0), "col_sweep_adj": N_LAMBDA * sweep_bytes(N, 0)}
-    fr_rl = {}
+    # both row sweeps apply the amplitude and OPD maps (prologue forward, conjugate epilogue
+    # adjoint); the column sweeps move only the fields. Timing tags carry the planes per launch.
+    fr_plane = {"row_sweep": sweep_bytes(N, 2), "row_sweep_adj": sweep_bytes(N, 2),
+                "col_sweep": sweep_bytes(N, 0), "col_sweep_adj": sweep_bytes(N, 0)}
+    fr_agg = {}
     for key, (tot, cnt) in prof_fr.items():
-        name = key.split("/")[0]
-        if name not in per_launch:
-            continue
+        name, _, tag = key.partition("/")
+        if name in fr_plane:
+            a = fr_agg.setdefault(name, [0.0, 0, 0])
+            a[0] += tot
+            a[1] += cnt
+            a[2] += cnt * int(tag)
+    fr_rl = {}
+    for name, (tot, cnt, planes) in fr_agg.items():
         ms = tot / cnt
-        gbs = per_launch[name] / (ms * 1e-3) / 1e9
+        nbytes = fr_plane[name] * planes / cnt
+        gbs = nbytes / (ms * 1e-3) / 1e9
         fr_rl[name] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": per_launch[name],
-                       "avg_launch_ms": ms}
+                       "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "avg_launch_ms": ms}
+    # the whole Fresnel plane (both sweeps) against the two-pass model, maps included
+    fr_bytes = 2 * N_LAMBDA * (2 * sweep_bytes(N, 0) + 2 * N * N * 4)
+    fr_plane_frac = fr_bytes / (ms_fr / fr_calls * 1e-3) / 1e9 / HBM_PEAK_GBS
     del fields
     if args.copy_calibration:
         src = torch.randn((N, N), dtype=torch.complex64, device=dev)
@@ -297,6 +308,7 @@ def main():
         "fresnel_only": {
             "value": 2 * N_LAMBDA * fr_calls / (ms_fr * 1e-3), "unit": "Fresnel planes/s",
             "planes_per_call": 2 * N_LAMBDA, "ms_per_call": ms_fr / fr_calls,
+            "hbm_frac_whole_plane": fr_plane_frac,
             "roofline": fr_rl,
         },
         "autotuned": {"choices": tuned, "seconds": t_tune},

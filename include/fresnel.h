@@ -132,8 +132,10 @@ int mft_adjoint(fr_ctx *ctx, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_c
  * grad_heights = dL/dA (n_dm * n_act^2 float, DM1 first), the chain rule through every
  * adjoint above. Arrays lambda_m, n_pad, weight are HOST arrays of n_lambda entries.
  * FR_TRAIN_BATCHED keeps one field plane per wavelength in the workspace and runs the Fresnel
- * steps of all wavelengths (grids of different edges allowed) in one launch per sweep; the
- * focal-plane chains and all sums still go in wavelength order. With one power-of-two edge
+ * steps of a group of wavelengths (grids of different edges allowed) in one launch per sweep;
+ * groups are as many wavelengths as fit the last-level cache together (one 4096^2 plane,
+ * several smaller ones), each followed by its focal-plane chains; all sums still go in
+ * wavelength order. With one power-of-two edge
  * for all wavelengths, psf and grad_heights are bit-identical to the plain (wavelength after
  * wavelength) mode; with mixed edges every plane takes the mixed-radix sweeps and the results
  * agree with the plain mode to float32 rounding. Its workspace grows with sum_j n_pad[j]^2.

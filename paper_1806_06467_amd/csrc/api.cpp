@@ -382,9 +382,33 @@ bool plane_size_supported(int n) {
   return fresnel_size_supported(n) || mr_plan(n, &np, rad);
 }
 
+// Planes are swept in groups whose fields fit the last-level cache together (at least one plane
+// per group), both sweeps of a group before the next group: the second sweep of a plane then
+// reads what the first one has just written from that cache instead of from HBM.
+constexpr size_t kCacheGroupBytes = size_t(160) << 20;
+
+// end of the group that starts at plane i (at most `cap` planes); FR_PLANE_GROUPS=0 turns the
+// grouping off (one group of up to `cap` planes) for tuning runs
+static int group_end(const PlaneArgs *args, int count, int i, int cap) {
+  static const bool grouping = [] {
+    const char *v = std::getenv("FR_PLANE_GROUPS");
+    return !(v && v[0] == '0');
+  }();
+  if (!grouping) return std::min(count, i + cap);
+  size_t bytes = 0;
+  int j = i;
+  while (j < count && j - i < cap) {
+    const size_t b = size_t(args[j].n) * size_t(args[j].n) * sizeof(float2);
+    if (j > i && bytes + b > kCacheGroupBytes) break;
+    bytes += b;
+    ++j;
+  }
+  return j;
+}
+
 // All planes share edge n (a power of two with a tuned register-resident plan): the two-sweep
 // kernels. Otherwise (mixed edges or a mixed-radix edge): the persistent mixed-radix kernels,
-// one launch per sweep for the whole batch.
+// one launch per sweep for each group of planes.
 int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s) {
   bool uniform = fresnel_size_supported(n);
   for (int i = 0; i < count && uniform; ++i) uniform = (args[i].n == n);
@@ -392,16 +416,18 @@ int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s) {
     const float2 *root;
     int st = ctx->twiddles(n, s, &root);
     if (st != FR_OK) return st;
-    for (int i = 0; i < count; i += kMaxBatch) {
-      const int c = std::min(count - i, kMaxBatch);
-      hipError_t e = launch_fresnel_batch(args + i, c, n, root, s, ctx->hook(), ctx->sweep_variant(n));
+    for (int i = 0; i < count;) {
+      const int j = group_end(args, count, i, kMaxBatch);
+      hipError_t e = launch_fresnel_batch(args + i, j - i, n, root, s, ctx->hook(), ctx->sweep_variant(n));
       if (e != hipSuccess) return record_hip(e);
+      i = j;
     }
     return FR_OK;
   }
-  for (int i = 0; i < count; i += kMrMaxBatch) {
+  for (int i = 0; i < count;) {
+    const int j = group_end(args, count, i, kMrMaxBatch);
     MrBatch b;
-    b.count = std::min(count - i, kMrMaxBatch);
+    b.count = j - i;
     b.total = 0;
     for (int k = 0; k < b.count; ++k) {
       int st = ctx->mr(args[i + k].n, s, &b.p[k]);
@@ -410,6 +436,7 @@ int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s) {
     }
     hipError_t e = launch_mr_batch(b, ctx->cus * 4, ctx->cus, s, ctx->hook());
     if (e != hipSuccess) return record_hip(e);
+    i = j;
   }
   return FR_OK;
 }

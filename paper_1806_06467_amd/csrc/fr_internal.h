@@ -24,7 +24,9 @@ struct LaunchHook {
 //   pre  = amp * exp(2 pi i (opd + 2 pre_surf) / lambda) * lens[x] lens[y]
 //   post = exp(2 pi i 2 post_surf / lambda)               (reflective DM after the step)
 // amp and opd are win x win maps centred in the plane (offset (n - win)/2); outside the
-// window amp is 0 when given. pre_surf / post_surf are n x n surface maps [m].
+// window amp is 0 when given. pre_surf is an n x n surface map [m], row-major; post_surf is the
+// same kind of map stored in 4-column tiles (post_tiled_index) so that the column sweep, which
+// applies it, reads it contiguously.
 constexpr int kSourceOptic = 2;  // forward only: the input field is 1 (it is not read)
 struct PlaneArgs {
   float2 *field;             // n x n, in place
@@ -39,6 +41,13 @@ struct PlaneArgs {
   int win;                   // window edge of amp / opd (n for full maps)
   int flags;                 // FR_ADJOINT | kSourceOptic
 };
+
+// element (y, x) of an n x n map stored in 4-column tiles: tile x/4 holds rows 0..n-1 of its
+// 4 columns, row-major within the tile (post_tiled_size(n) floats in all)
+__host__ __device__ inline size_t post_tiled_index(int n, int y, int x) {
+  return (size_t(x >> 2) * size_t(n) + size_t(y)) * 4 + size_t(x & 3);
+}
+__host__ __device__ inline size_t post_tiled_size(int n) { return size_t((n + 3) / 4) * 4 * size_t(n); }
 
 constexpr int kMaxBatch = 64;
 struct BatchArgs {

@@ -138,11 +138,20 @@ __device__ __forceinline__ bool pre_optic_row(const PlaneArgs &pa, int n, int y,
   return true;
 }
 
-// post optic at (y, x): exp(2 pi i 2 post_surf / lambda)
-__device__ __forceinline__ c32 post_optic(const PlaneArgs &pa, int n, int y, int x) {
-  float s, c;
-  sincos_turns(2.0f * pa.post_surf[size_t(y) * n + x] * pa.inv_lambda, &s, &c);
-  return {c, s};
+// post optic exp(2 pi i 2 post_surf / lambda) at rows y = t + T m of column x, for all slots:
+// the map (4-column tiles) is read for every slot before any phasor is formed
+template <int E, int T>
+__device__ __forceinline__ void post_optic_col(const PlaneArgs &pa, int n, int t, int x, c32 (&ph)[E]) {
+  const MapBuf map(pa.post_surf, unsigned(post_tiled_size(n)) * 4u);
+  float sv[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) sv[m] = map.load(unsigned(post_tiled_index(n, t + T * m, x)) * 4u, 0u);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    float s, c;
+    sincos_turns(2.0f * sv[m] * pa.inv_lambda, &s, &c);
+    ph[m] = {c, s};
+  }
 }
 
 __device__ __forceinline__ bool has_pre(const PlaneArgs &pa) {
@@ -242,16 +251,20 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = buf.load(vo, unsigned(T * m) * unsigned(N) * 8u);
   if (adj && pa.post_surf) {
+    c32 ph[E];
+    post_optic_col<E, T>(pa, N, t, x, ph);
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], post_optic(pa, N, t + T * m, x));
+    for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], ph[m]);
   }
   c32 *my = lds + c * LINE;
   PL::template forward<HALF>(v, my, t, tw);
   freq_product<E, T>(v, pa.h, t, adj);
   PL::template inverse<HALF>(v, my, t, tw);
   if (!adj && pa.post_surf) {
+    c32 ph[E];
+    post_optic_col<E, T>(pa, N, t, x, ph);
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], post_optic(pa, N, t + T * m, x));
+    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], ph[m]);
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
@@ -268,21 +281,21 @@ hipError_t launch_sweeps(const BatchArgs &fwd, int nf, const BatchArgs &adj, int
   constexpr int N = PL::N;
   static_assert(PC::N == N, "row and column plans of one edge");
   static_assert(N % ROW_LINES == 0 && N % COL_LINES == 0, "tile must divide n");
-  // timing names carry the direction (the optic maps read differ)
+  // timing names carry the direction (the optic maps read differ), tags the planes per launch
   auto rows = [&](const BatchArgs &a, int count, const char *name) {
-    hook(s, name, N, 0);
+    hook(s, name, count, 0);
     hipLaunchKernelGGL((row_sweep<PL, ROW_LINES>), dim3(N / ROW_LINES, count),
                        dim3(PL::T * ROW_LINES), 0, s, a, tw);
     hipError_t e = hipGetLastError();
-    hook(s, name, N, 1);
+    hook(s, name, count, 1);
     return e;
   };
   auto cols = [&](const BatchArgs &a, int count, const char *name) {
-    hook(s, name, N, 0);
+    hook(s, name, count, 0);
     hipLaunchKernelGGL((col_sweep<PC, COL_LINES, CHALF>), dim3(N / COL_LINES, count),
                        dim3(PC::T * COL_LINES), 0, s, a, tw);
     hipError_t e = hipGetLastError();
-    hook(s, name, N, 1);
+    hook(s, name, count, 1);
     return e;
   };
   hipError_t e = hipSuccess;

@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(kT * 4) mr_col_sweep(MrBatch) {
       const bool adj = pa.flags & FR_ADJOINT;
       const Buf64 fb(pa.field, unsigned(n) * unsigned(n) * 8u);
       // a missing post map has zero records (its loads return 0)
-      const Buf32 post(pa.post_surf, pa.post_surf ? unsigned(n) * unsigned(n) * 4u : 0u);
+      const Buf32 post(pa.post_surf, pa.post_surf ? unsigned(post_tiled_size(n)) * 4u : 0u);
       const bool has_post = pa.post_surf != nullptr;
       c32 v[kEM];
 #pragma unroll
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(kT * 4) mr_col_sweep(MrBatch) {
       if (adj && has_post) {
         float sv[kEM];
 #pragma unroll
-        for (int m = 0; m < kEM; ++m) sv[m] = post.load(unsigned(min(t + kT * m, n - 1) * n + xc) * 4u);
+        for (int m = 0; m < kEM; ++m) sv[m] = post.load(unsigned(post_tiled_index(n, min(t + kT * m, n - 1), xc)) * 4u);
 #pragma unroll
         for (int m = 0; m < kEM; ++m) {
           float sn, cs;
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(kT * 4) mr_col_sweep(MrBatch) {
       if (!adj && has_post) {
         float sv[kEM];
 #pragma unroll
-        for (int m = 0; m < kEM; ++m) sv[m] = post.load(unsigned(min(t + kT * m, n - 1) * n + xc) * 4u);
+        for (int m = 0; m < kEM; ++m) sv[m] = post.load(unsigned(post_tiled_index(n, min(t + kT * m, n - 1), xc)) * 4u);
 #pragma unroll
         for (int m = 0; m < kEM; ++m) {
           float sn, cs;

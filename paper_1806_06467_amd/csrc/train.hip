@@ -40,6 +40,7 @@ struct RGemm {
   float *C;
   int ldc;
   float alpha, beta;
+  int tiled;  // 1: C is an M x M map stored in 4-column tiles (post_tiled_index), ldc unused
 };
 
 __global__ void __launch_bounds__(256) rgemm_kernel(RGemm g) {
@@ -67,7 +68,7 @@ __global__ void __launch_bounds__(256) rgemm_kernel(RGemm g) {
     __syncthreads();
   }
   if (i < g.M && j < g.N) {
-    float *cp = g.C + size_t(i) * g.ldc + j;
+    float *cp = g.tiled ? g.C + post_tiled_index(g.M, i, j) : g.C + size_t(i) * g.ldc + j;
     *cp = g.alpha * acc + (g.beta != 0.f ? g.beta * *cp : 0.f);
   }
 }
@@ -313,6 +314,9 @@ hipError_t launch1d(K kern, size_t work, hipStream_t s, const LaunchHook &hook, 
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// floats per DM surface map on an n grid (room for either layout)
+size_t surf_stride(int n) { return std::max(size_t(n) * size_t(n), post_tiled_size(n)); }
+
 // Workspace layout. Plain mode: one field plane E (and one adjoint plane B) of the largest
 // grid, reused wavelength after wavelength. Batched mode: one E plane per wavelength (and one B
 // plane per wavelength when the pupil DM needs the adjoint Fresnel step), so that the Fresnel
@@ -362,11 +366,11 @@ Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_
     for (int j = 0; j < n_lambda; ++j)
       if (std::find(L.surf_n.begin(), L.surf_n.end(), int(n_pad[j])) == L.surf_n.end()) {
         L.surf_n.push_back(n_pad[j]);
-        L.surf.push_back(take(ndm * size_t(n_pad[j]) * n_pad[j] * 4));
+        L.surf.push_back(take(ndm * surf_stride(n_pad[j]) * 4));
       }
   } else {
     L.surf_n.push_back(0);
-    L.surf.push_back(take(ndm * n2max * 4));
+    L.surf.push_back(take(ndm * surf_stride(nmax) * 4));
   }
   L.tdm = take(size_t(std::max(d->n_act, 1)) * nmax * 4);
   L.el = take(nd2 * 8);
@@ -463,11 +467,12 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   auto surfaces = [&](int n, float *surf) -> int {
     const float *G = nullptr;
     FR_TRY(ctx->dm_influence(n, nd, na, s, &G));
-    const size_t n2 = size_t(n) * n;
     for (int k = 0; k < ndm; ++k) {
-      RGemm g1{na, n, na, d->dm_heights_m + size_t(k) * na * na, na, 0, G, na, 1, TDM, n, 1.f, 0.f};
+      RGemm g1{na, n, na, d->dm_heights_m + size_t(k) * na * na, na, 0, G, na, 1, TDM, n, 1.f, 0.f, 0};
       FR_TRY_HIP(rgemm(g1, s, hook));
-      RGemm g2{n, n, na, G, na, 0, TDM, n, 0, surf + size_t(k) * n2, n, 1.f, 0.f};
+      // the DM after the step is applied by the column sweep: 4-column tiles
+      const int tiled = k == ndm - 1 ? 1 : 0;
+      RGemm g2{n, n, na, G, na, 0, TDM, n, 0, surf + size_t(k) * surf_stride(n), n, 1.f, 0.f, tiled};
       FR_TRY_HIP(rgemm(g2, s, hook));
     }
     return FR_OK;
@@ -490,7 +495,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     pa->opd = d->pupil_opd_m;
     pa->win = nd;
     pa->pre_surf = ndm == 2 ? surf : nullptr;
-    pa->post_surf = ndm >= 1 ? surf + size_t(ndm - 1) * n * n : nullptr;
+    pa->post_surf = ndm >= 1 ? surf + size_t(ndm - 1) * surf_stride(n) : nullptr;
     pa->inv_lambda = float(1.0 / lam[j]);
     pa->flags = kSourceOptic;
     return ctx->transfer(n, dx, lam[j], d->z_m, s, &pa->h);
@@ -501,7 +506,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     std::memset(pb, 0, sizeof *pb);
     pb->field = c64at(L.b[j]);
     pb->n = n;
-    pb->post_surf = surf_of(j) + size_t(ndm - 1) * n * n;
+    pb->post_surf = surf_of(j) + size_t(ndm - 1) * surf_stride(n);
     pb->inv_lambda = float(1.0 / lam[j]);
     pb->win = n;
     pb->flags = FR_ADJOINT;
@@ -627,22 +632,35 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       }
     }
   } else {
-    // batched: the Fresnel planes of all wavelengths in one launch per sweep; the focal
-    // chains and gradient sums still run in wavelength order (identical results)
+    // batched: wavelengths in groups whose planes fit the last-level cache together (one 4096^2
+    // plane, several smaller ones); each group's Fresnel planes in one launch per sweep, then
+    // its focal chains while its planes are still cached. Sums still run in wavelength order.
     if (ndm > 0)
       for (size_t i = 0; i < L.surf_n.size(); ++i)
         FR_TRY(surfaces(L.surf_n[i], reinterpret_cast<float *>(base + L.surf[i])));
+    constexpr size_t kGroupBytes = size_t(160) << 20;
     std::vector<PlaneArgs> planes(n_lambda);
-    for (int j = 0; j < n_lambda; ++j) FR_TRY(fwd_plane(j, &planes[j]));
-    FR_TRY(run_planes(ctx, planes.data(), n_lambda, n_pad[0], s));
-    for (int j = 0; j < n_lambda; ++j) {
-      FR_TRY(focal_chain(j));
-      if (grad) FR_TRY(back_to_last_dm(j));
-    }
-    if (grad && ndm == 2) {
-      for (int j = 0; j < n_lambda; ++j) FR_TRY(adj_plane(j, &planes[j]));
-      FR_TRY(run_planes(ctx, planes.data(), n_lambda, n_pad[0], s));
-      for (int j = 0; j < n_lambda; ++j) FR_TRY(back_to_pupil_dm(j));
+    for (int g0 = 0; g0 < n_lambda;) {
+      int g1 = g0;
+      size_t bytes = 0;
+      while (g1 < n_lambda) {
+        const size_t b = size_t(n_pad[g1]) * n_pad[g1] * sizeof(float2);
+        if (g1 > g0 && bytes + b > kGroupBytes) break;
+        bytes += b;
+        ++g1;
+      }
+      for (int j = g0; j < g1; ++j) FR_TRY(fwd_plane(j, &planes[j]));
+      FR_TRY(run_planes(ctx, planes.data() + g0, g1 - g0, n_pad[g0], s));
+      for (int j = g0; j < g1; ++j) {
+        FR_TRY(focal_chain(j));
+        if (grad) FR_TRY(back_to_last_dm(j));
+      }
+      if (grad && ndm == 2) {
+        for (int j = g0; j < g1; ++j) FR_TRY(adj_plane(j, &planes[j]));
+        FR_TRY(run_planes(ctx, planes.data() + g0, g1 - g0, n_pad[g0], s));
+        for (int j = g0; j < g1; ++j) FR_TRY(back_to_pupil_dm(j));
+      }
+      g0 = g1;
     }
   }
   FR_TRY_HIP(launch1d(to_f32, det2, s, hook, "psf_to_f32", (const double *)PSF64, psf, det2));
