@@ -177,13 +177,13 @@ int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda,
  * keeps the fastest in the context; later calls of every entry point use it:
  *   FR_TUNE_FRESNEL, a = plane edge n (b unused): the tile variants of the power-of-two sweeps
  *     (rows per block, columns per tile) and the pass orders of the mixed-radix plan of n;
- *   FR_TUNE_MFT, a = pupil-side edge n, b = focal edge m: the GEMM tile configuration of each of
- *     the two GEMMs of mft_forward (n -> m) and mft_adjoint (m -> n).
+ *   FR_TUNE_MFT, a = pupil-side edge n, b = focal edge m: the GEMM tile configuration and split-K
+ *     factor of each of the two GEMMs of mft_forward (n -> m) and mft_adjoint (m -> n).
  * Every candidate computes the same result up to the order of float32 roundings. The call
  * allocates scratch device memory for its duration, synchronises `stream`, and is not meant for
  * a hot loop or a graph capture. Errors: FR_EINVAL, FR_EUNSUPPORTED, FR_ENOMEM, FR_EHIP.
  * fr_autotune_save / fr_autotune_load write / read the tuned choices as a text file (one
- * "sweep n variant", "plan n packed_order" or "gemm M N K transA transB tile" per line); a
+ * "sweep n variant", "plan n packed_order" or "gemm M N K transA transB tile [split]" per line); a
  * malformed or inconsistent line makes load return FR_EINVAL (valid lines are still taken). */
 #define FR_TUNE_FRESNEL 1
 #define FR_TUNE_MFT 2

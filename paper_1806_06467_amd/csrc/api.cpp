@@ -100,9 +100,9 @@ int Ctx::sweep_variant(int n) const {
   return k;
 }
 
-int Ctx::gemm_tile(const CGemmArgs &g) const {
+Ctx::GemmChoice Ctx::gemm_choice(const CGemmArgs &g) const {
   auto it = tuned_gemm.find({g.M, g.N, g.K, g.transA, g.transB});
-  return it == tuned_gemm.end() ? -1 : it->second;
+  return it == tuned_gemm.end() ? GemmChoice{-1, 0} : it->second;
 }
 
 LaunchHook Ctx::hook() {
@@ -311,9 +311,15 @@ static CGemmArgs gemm_args() {
   return g;
 }
 
-hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, void *partial, size_t partial_elems, hipStream_t s, int cfg) {
-  if (cfg < 0) cfg = ctx->gemm_tile(g);
-  int split = cgemm_split_for(g.M, g.N, g.K, cfg);
+hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, void *partial, size_t partial_elems, hipStream_t s, int cfg,
+                    int split) {
+  if (cfg < 0) {
+    const Ctx::GemmChoice c = ctx->gemm_choice(g);
+    cfg = c.tile;
+    split = c.split;
+  }
+  if (split <= 0) split = cgemm_split_for(g.M, g.N, g.K, cfg);
+  split = std::min(split, kMaxSplit);
   while (split > 1 && size_t(split) * size_t(g.M) * size_t(g.N) > partial_elems) split /= 2;
   return launch_cgemm_split(g, split, cfg, partial, s, ctx->hook());
 }

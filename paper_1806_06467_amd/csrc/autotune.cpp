@@ -154,14 +154,21 @@ int tune_mft(Ctx *ctx, int n, int m, hipStream_t s) {
   add(m, n, m, a, m, 0, w, n, 0, t, n);  // adjoint: E_B conj(W)
   add(n, n, m, w, n, 1, t, n, 0, c, n);  // adjoint: W^H T
   for (CGemmArgs &g : shapes) {
-    int best = 0;
+    Ctx::GemmChoice best{0, 0};
     float best_ms = -1.f;
     for (int cfg = 0; cfg < kGemmTiles; ++cfg) {
-      const float ms = time_min(s, [&] { return run_gemm(ctx, g, partial, pcap, s, cfg); });
-      if (ms < 0.f) return record_hip(hipGetLastError());
-      if (best_ms < 0.f || ms < best_ms) {
-        best_ms = ms;
-        best = cfg;
+      // the tile's default split, and every power of two up to kMaxSplit that leaves slices of
+      // at least 64 (the default is tried first, so it wins ties)
+      std::vector<int> splits{0};
+      for (int sp = 1; sp <= kMaxSplit && g.K / sp >= 64; sp *= 2)
+        if (size_t(sp) * size_t(g.M) * size_t(g.N) <= pcap) splits.push_back(sp);
+      for (int sp : splits) {
+        const float ms = time_min(s, [&] { return run_gemm(ctx, g, partial, pcap, s, cfg, sp); });
+        if (ms < 0.f) return record_hip(hipGetLastError());
+        if (best_ms < 0.f || ms < best_ms) {
+          best_ms = ms;
+          best = {cfg, sp};
+        }
       }
     }
     ctx->tuned_gemm[{g.M, g.N, g.K, g.transA, g.transB}] = best;
@@ -214,8 +221,8 @@ int fr_autotune_save(fr_ctx *ctx_, const char *path) {
   for (auto &kv : ctx->tuned_plan) std::fprintf(f, "plan %d %u\n", kv.first, kv.second);
   for (auto &kv : ctx->tuned_gemm) {
     const auto &k = kv.first;
-    std::fprintf(f, "gemm %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
-                 std::get<4>(k), kv.second);
+    std::fprintf(f, "gemm %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                 std::get<4>(k), kv.second.tile, kv.second.split);
   }
   const bool ok = std::fclose(f) == 0;
   return ok ? FR_OK : FR_EINVAL;
@@ -230,17 +237,22 @@ int fr_autotune_load(fr_ctx *ctx_, const char *path) {
   int st = FR_OK;
   while (std::fgets(line, sizeof line, f)) {
     if (line[0] == '#' || line[0] == '\n') continue;
-    int n = 0, v = 0, M = 0, N = 0, K = 0, ta = 0, tb = 0;
+    int n = 0, v = 0, M = 0, N = 0, K = 0, ta = 0, tb = 0, sp = 0;
     unsigned plan = 0;
+    int fields = 0;
     if (std::sscanf(line, "sweep %d %d", &n, &v) == 2) {
       if (!fr::fresnel_size_supported(n) || v < 0 || v >= fr::fresnel_variants(n)) st = FR_EINVAL;
       else ctx->tuned_variant[n] = v;
     } else if (std::sscanf(line, "plan %d %u", &n, &plan) == 2) {
       if (!fr::valid_plan(n, plan)) st = FR_EINVAL;
       else ctx->tuned_plan[n] = plan;
-    } else if (std::sscanf(line, "gemm %d %d %d %d %d %d", &M, &N, &K, &ta, &tb, &v) == 6) {
-      if (M <= 0 || N <= 0 || K <= 0 || v < 0 || v >= fr::kGemmTiles || (ta & ~1) || (tb & ~1)) st = FR_EINVAL;
-      else ctx->tuned_gemm[{M, N, K, ta, tb}] = v;
+    } else if ((fields = std::sscanf(line, "gemm %d %d %d %d %d %d %d", &M, &N, &K, &ta, &tb, &v, &sp)) >= 6) {
+      if (fields == 6) sp = 0;
+      if (M <= 0 || N <= 0 || K <= 0 || v < 0 || v >= fr::kGemmTiles || (ta & ~1) || (tb & ~1) || sp < 0 ||
+          sp > fr::kMaxSplit)
+        st = FR_EINVAL;
+      else
+        ctx->tuned_gemm[{M, N, K, ta, tb}] = {v, sp};
     } else {
       st = FR_EINVAL;
     }

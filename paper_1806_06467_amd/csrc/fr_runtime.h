@@ -60,8 +60,12 @@ struct Ctx {
   // choices made by the autotuner (fr_autotune), consulted by every later call
   std::map<int, int> tuned_variant;                 // power-of-two sweep tile variant per edge
   std::map<int, unsigned> tuned_plan;               // mixed-radix pass order per edge
-  std::map<std::tuple<int, int, int, int, int>, int> tuned_gemm;  // (M, N, K, transA, transB) -> tile
-  int gemm_tile(const CGemmArgs &g) const;
+  struct GemmChoice {
+    int tile;   // tile configuration
+    int split;  // K slices (0: the default for the tile)
+  };
+  std::map<std::tuple<int, int, int, int, int>, GemmChoice> tuned_gemm;  // (M, N, K, transA, transB)
+  GemmChoice gemm_choice(const CGemmArgs &g) const;
   int transfer(int n, double dx, double lam, double z, hipStream_t s, const float2 **out);
   int lens(int n, double dx, double lam, double f, hipStream_t s, const float2 **out);
   int mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out);
@@ -83,7 +87,9 @@ struct MftOut {
 };
 // one complex GEMM with the tuned (or, cfg >= 0, the given) tile configuration and a split-K
 // that fits `partial_elems` float64 complex partial sums
-hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, void *partial, size_t partial_elems, hipStream_t s, int cfg = -1);
+// split > 0 forces that many K slices (at most kMaxSplit, reduced to fit partial_elems)
+hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, void *partial, size_t partial_elems, hipStream_t s, int cfg = -1,
+                    int split = 0);
 int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out, double n_d,
                      double du, const MftOut &o, void *ws, hipStream_t s);
 // out = alpha (du/n_d) W^H in conj(W) + beta cin, * mask  (cin may alias out)

@@ -88,15 +88,17 @@ def test_airy_256_aperture_on_gpu():
     assert np.max(np.abs(cut - np.abs(airy))[core]) <= 1.5e-3
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
-def test_every_gemm_tile_configuration_matches_oracle(tile, tmp_path):
-    # force one tile configuration on all four GEMMs of a ragged forward and adjoint MFT (through
-    # the autotuner's file format) and check both transforms against the oracle
+@pytest.mark.parametrize("tile,split", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 1), (1, 3), (2, 16),
+                                        (3, 7)])
+def test_every_gemm_tile_configuration_matches_oracle(tile, split, tmp_path):
+    # force one tile configuration and split-K factor (0: the tile's default) on all four GEMMs
+    # of a ragged forward and adjoint MFT (through the autotuner's file format) and check both
+    # transforms against the oracle; 16 slices of K = 130 leave trailing slices empty
     n, m, n_d, du = 1000, 130, 500.0, 0.3
-    banner(f"mft with GEMM tile configuration {tile}")
+    banner(f"mft with GEMM tile configuration {tile}, split {split}")
     shapes = [(n, m, n, 0, 1), (m, m, n, 0, 0), (m, n, m, 0, 0), (n, n, m, 1, 0)]
     f = tmp_path / "tiles.txt"
-    f.write_text("".join("gemm %d %d %d %d %d %d\n" % (s + (tile,)) for s in shapes))
+    f.write_text("".join("gemm %d %d %d %d %d %d %d\n" % (s + (tile, split)) for s in shapes))
     fb.autotune_load(str(f))
     e = synth.random_field(n, 31)
     got = to_np(fb.mft_forward(to_gpu(e), n_d, m, du))
@@ -104,3 +106,10 @@ def test_every_gemm_tile_configuration_matches_oracle(tile, tmp_path):
     eb = synth.random_field(m, 32)
     got = to_np(fb.mft_adjoint(to_gpu(eb), n_d, n, du))
     assert rel_l2(got, oracle.mft_adjoint(f32(eb), n_d, n, du)) <= TOL
+
+
+def test_autotune_file_refuses_a_split_beyond_the_limit(tmp_path):
+    f = tmp_path / "bad.txt"
+    f.write_text("gemm 1000 130 1000 0 1 0 17\n")
+    with pytest.raises(fb.FrError):
+        fb.autotune_load(str(f))
