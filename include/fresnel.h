@@ -178,13 +178,17 @@ int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda,
  *   FR_TUNE_FRESNEL, a = plane edge n (b unused): the tile variants of the power-of-two sweeps
  *     (rows per block, columns per tile) and the pass orders of the mixed-radix plan of n;
  *   FR_TUNE_MFT, a = pupil-side edge n, b = focal edge m: the GEMM tile configuration and split-K
- *     factor of each of the two GEMMs of mft_forward (n -> m) and mft_adjoint (m -> n).
+ *     factor of each of the two GEMMs of mft_forward (n -> m) and mft_adjoint (m -> n). Tiles
+ *     0-3 form each complex k-step from four real products, tiles 4-5 from three (Gauss; the
+ *     three sums are combined in float64 at every 16-deep stage).
  * Every candidate computes the same result up to the order of float32 roundings. The call
  * allocates scratch device memory for its duration, synchronises `stream`, and is not meant for
  * a hot loop or a graph capture. Errors: FR_EINVAL, FR_EUNSUPPORTED, FR_ENOMEM, FR_EHIP.
  * fr_autotune_save / fr_autotune_load write / read the tuned choices as a text file (one
- * "sweep n variant", "plan n packed_order" or "gemm M N K transA transB tile [split]" per line); a
- * malformed or inconsistent line makes load return FR_EINVAL (valid lines are still taken). */
+ * "sweep n variant", "plan n packed_order", "gemm M N K transA transB tile [split]" or
+ * "gemm_default tile split" per line; the default applies to GEMM shapes without their own line,
+ * tile -1 restoring the choice by shape); a malformed or inconsistent line makes load return
+ * FR_EINVAL (valid lines are still taken). */
 #define FR_TUNE_FRESNEL 1
 #define FR_TUNE_MFT 2
 int fr_autotune(fr_ctx *ctx, int32_t kind, int32_t a, int32_t b, void *stream);

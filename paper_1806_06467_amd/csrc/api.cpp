@@ -102,7 +102,7 @@ int Ctx::sweep_variant(int n) const {
 
 Ctx::GemmChoice Ctx::gemm_choice(const CGemmArgs &g) const {
   auto it = tuned_gemm.find({g.M, g.N, g.K, g.transA, g.transB});
-  return it == tuned_gemm.end() ? GemmChoice{-1, 0} : it->second;
+  return it == tuned_gemm.end() ? default_gemm : it->second;
 }
 
 LaunchHook Ctx::hook() {

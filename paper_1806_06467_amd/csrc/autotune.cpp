@@ -219,6 +219,8 @@ int fr_autotune_save(fr_ctx *ctx_, const char *path) {
   std::fprintf(f, "# fresnel autotune v1\n");
   for (auto &kv : ctx->tuned_variant) std::fprintf(f, "sweep %d %d\n", kv.first, kv.second);
   for (auto &kv : ctx->tuned_plan) std::fprintf(f, "plan %d %u\n", kv.first, kv.second);
+  if (ctx->default_gemm.tile >= 0)
+    std::fprintf(f, "gemm_default %d %d\n", ctx->default_gemm.tile, ctx->default_gemm.split);
   for (auto &kv : ctx->tuned_gemm) {
     const auto &k = kv.first;
     std::fprintf(f, "gemm %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
@@ -240,7 +242,10 @@ int fr_autotune_load(fr_ctx *ctx_, const char *path) {
     int n = 0, v = 0, M = 0, N = 0, K = 0, ta = 0, tb = 0, sp = 0;
     unsigned plan = 0;
     int fields = 0;
-    if (std::sscanf(line, "sweep %d %d", &n, &v) == 2) {
+    if (std::sscanf(line, "gemm_default %d %d", &v, &sp) == 2) {
+      if (v < -1 || v >= fr::kGemmTiles || sp < 0 || sp > fr::kMaxSplit) st = FR_EINVAL;
+      else ctx->default_gemm = {v, sp};
+    } else if (std::sscanf(line, "sweep %d %d", &n, &v) == 2) {
       if (!fr::fresnel_size_supported(n) || v < 0 || v >= fr::fresnel_variants(n)) st = FR_EINVAL;
       else ctx->tuned_variant[n] = v;
     } else if (std::sscanf(line, "plan %d %u", &n, &plan) == 2) {

@@ -65,6 +65,7 @@ struct Ctx {
     int split;  // K slices (0: the default for the tile)
   };
   std::map<std::tuple<int, int, int, int, int>, GemmChoice> tuned_gemm;  // (M, N, K, transA, transB)
+  GemmChoice default_gemm{-1, 0};  // for shapes without an entry (tile -1: chosen by shape)
   GemmChoice gemm_choice(const CGemmArgs &g) const;
   int transfer(int n, double dx, double lam, double z, hipStream_t s, const float2 **out);
   int lens(int n, double dx, double lam, double f, hipStream_t s, const float2 **out);

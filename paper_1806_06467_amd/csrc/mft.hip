@@ -61,11 +61,16 @@ __device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, doubl
 }
 
 // Tile configuration: WM x WN waves, each wave a 32 x (32 TN) piece of the block tile; the
-// operand tiles of the next PD stages are in flight while a stage is multiplied.
-template <int WM_, int WN_, int TN_, int PD_ = 1>
+// operand tiles of the next PD stages are in flight while a stage is multiplied. G3: three real
+// products per complex k-step instead of four (Gauss): P1 = sum Ar Br, P2 = sum Ai Bi,
+// P3 = sum (Ar + Ai)(Br + Bi), combined per stage in float64 as Cr = P1 - P2, Ci = P3 - P1 - P2.
+template <int WM_, int WN_, int TN_, int PD_ = 1, bool G3_ = false>
 struct Cfg {
   static constexpr int WM = WM_, WN = WN_, TN = TN_, PD = PD_;
-  static constexpr int waves = TN == 1 ? 3 : 2;  // waves per SIMD the register budget targets
+  static constexpr bool G3 = G3_;
+  // waves per SIMD the register budget targets (the three-product 32 x 64 wave tile holds three
+  // float32 and two float64 accumulator sets, so it gets the whole register file)
+  static constexpr int waves = TN == 1 ? 3 : (G3 ? 1 : 2);
   static constexpr int BM = 32 * WM, BN = 32 * TN * WN;
   static constexpr int threads = 64 * WM * WN;
   static constexpr int la = BM * BK / threads;  // A elements per thread per tile
@@ -77,6 +82,8 @@ using CfgL = Cfg<2, 2, 2>;  // 64 x 128, 256 threads: two blocks share a compute
 using CfgS = Cfg<2, 2, 1>;  // 64 x 64, 256 threads
 using CfgX = Cfg<4, 2, 2>;  // 128 x 128, 512 threads
 using CfgP = Cfg<2, 2, 1, 2>;  // 64 x 64, 256 threads, two stages of loads in flight
+using CfgS3 = Cfg<2, 2, 1, 1, true>;  // 64 x 64, three products per complex step
+using CfgL3 = Cfg<2, 2, 2, 1, true>;  // 64 x 128, three products per complex step
 
 // Per-thread share of one BK-deep operand tile, mapped so that consecutive threads walk
 // memory contiguously.
@@ -175,36 +182,68 @@ cgemm_kernel(GemmParams gp) {
   const int kl = lane >> 5;
   // one stage: multiply the LDS tile `buf`, fold into the float64 totals
   auto multiply = [&](int buf) {
-    floatx16 cr[TN], ci[TN];
-#pragma unroll
-    for (int t = 0; t < TN; ++t) {
-      cr[t] = floatx16{0.f};
-      ci[t] = floatx16{0.f};
-    }
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 2) {
-      const float2 av = As[buf][kk + kl][arow];
-      float2 bv[TN];
-#pragma unroll
-      for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][kk + kl][bcol + 32 * t];
+    if constexpr (C::G3) {
+      floatx16 p1[TN], p2[TN], p3[TN];
 #pragma unroll
       for (int t = 0; t < TN; ++t) {
-        cr[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].x, cr[t], 0, 0, 0);
-        ci[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].y, ci[t], 0, 0, 0);
+        p1[t] = floatx16{0.f};
+        p2[t] = floatx16{0.f};
+        p3[t] = floatx16{0.f};
       }
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        const float2 av = As[buf][kk + kl][arow];
+        const float as = av.x + av.y;
+        float2 bv[TN];
+#pragma unroll
+        for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][kk + kl][bcol + 32 * t];
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+          p1[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].x, p1[t], 0, 0, 0);
+          p2[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv[t].y, p2[t], 0, 0, 0);
+          p3[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(as, bv[t].x + bv[t].y, p3[t], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TN; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const double d1 = double(p1[t][r]), d2 = double(p2[t][r]);
+          totr[t][r] += d1 - d2;
+          toti[t][r] += double(p3[t][r]) - d1 - d2;
+        }
+    } else {
+      floatx16 cr[TN], ci[TN];
 #pragma unroll
       for (int t = 0; t < TN; ++t) {
-        cr[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, bv[t].y, cr[t], 0, 0, 0);
-        ci[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv[t].x, ci[t], 0, 0, 0);
+        cr[t] = floatx16{0.f};
+        ci[t] = floatx16{0.f};
       }
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        const float2 av = As[buf][kk + kl][arow];
+        float2 bv[TN];
+#pragma unroll
+        for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][kk + kl][bcol + 32 * t];
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+          cr[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].x, cr[t], 0, 0, 0);
+          ci[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].y, ci[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+          cr[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, bv[t].y, cr[t], 0, 0, 0);
+          ci[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv[t].x, ci[t], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TN; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          totr[t][r] += double(cr[t][r]);
+          toti[t][r] += double(ci[t][r]);
+        }
     }
-#pragma unroll
-    for (int t = 0; t < TN; ++t)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        totr[t][r] += double(cr[t][r]);
-        toti[t][r] += double(ci[t][r]);
-      }
   };
   if constexpr (C::PD == 1) {
     TileLoad<C, TA, TB> ld;
@@ -309,15 +348,15 @@ bool use_large(int M, int N, int K) {
   return t * split_for(t, K) >= 256;
 }
 
-// tile configuration: 0 small, 1 large, 2 extra large, 3 small with deeper prefetch; `cfg` >= 0
-// is a choice made by the autotuner, else FR_GEMM_TILE (s, l, x, p) overrides the default for
-// manual tuning runs
+// tile configuration: 0 small, 1 large, 2 extra large, 3 small with deeper prefetch, 4 small and
+// 5 large with three products per complex step; `cfg` >= 0 is a choice made by the autotuner,
+// else FR_GEMM_TILE (s, l, x, p, t, u) overrides the default for manual tuning runs
 int tile_choice(int M, int N, int K, int cfg) {
   if (cfg >= 0 && cfg < kGemmTiles) return cfg;
   static const int forced = [] {
     const char *v = std::getenv("FR_GEMM_TILE");
     if (!v) return -1;
-    return v[0] == 's' ? 0 : v[0] == 'l' ? 1 : v[0] == 'x' ? 2 : v[0] == 'p' ? 3 : -1;
+    return v[0] == 's' ? 0 : v[0] == 'l' ? 1 : v[0] == 'x' ? 2 : v[0] == 'p' ? 3 : v[0] == 't' ? 4 : v[0] == 'u' ? 5 : -1;
   }();
   if (forced >= 0) return forced;
   return use_large(M, N, K) ? 1 : 0;
@@ -330,6 +369,8 @@ int cgemm_split_for(int M, int N, int K, int cfg) {
     case 1: return split_for(tiles_of<CfgL>(M, N), K);
     case 2: return split_for(tiles_of<CfgX>(M, N), K);
     case 3: return split_for(tiles_of<CfgP>(M, N), K);
+    case 4: return split_for(tiles_of<CfgS3>(M, N), K);
+    case 5: return split_for(tiles_of<CfgL3>(M, N), K);
     default: return split_for(tiles_of<CfgS>(M, N), K);
   }
 }
@@ -345,12 +386,14 @@ hipError_t launch_cgemm_split(const CGemmArgs &a, int split, int cfg_choice, voi
   gp.partial = static_cast<double2 *>(partial);
   const int cfg = tile_choice(a.M, a.N, a.K, cfg_choice);
   char name[64];
-  std::snprintf(name, sizeof name, "cgemm%s_%dx%dx%d_s%d", cfg == 1 ? "L" : cfg == 2 ? "X" : cfg == 3 ? "P" : "S", a.M, a.N, a.K,
-                split);
+  static const char *const tag[kGemmTiles] = {"S", "L", "X", "P", "S3", "L3"};
+  std::snprintf(name, sizeof name, "cgemm%s_%dx%dx%d_s%d", tag[cfg], a.M, a.N, a.K, split);
   hook(stream, name, a.K, 0);
   hipError_t e = cfg == 1 ? launch_cfg<CfgL>(gp, stream)
                  : cfg == 2 ? launch_cfg<CfgX>(gp, stream)
                  : cfg == 3 ? launch_cfg<CfgP>(gp, stream)
+                 : cfg == 4 ? launch_cfg<CfgS3>(gp, stream)
+                 : cfg == 5 ? launch_cfg<CfgL3>(gp, stream)
                             : launch_cfg<CfgS>(gp, stream);
   hook(stream, name, a.K, 1);
   if (e != hipSuccess || split == 1) return e;

@@ -136,119 +136,156 @@ __global__ void scale_by_grad(const float *g, float w, const float2 *e, float2 *
 // DM gradient (a7) and its projection onto the actuators, dL/dA = G^T g_s G with
 //   g_s[i][j] = -2 kappa Im(E[i][j] conj(B[i][j]))   (surface gradient, never stored)
 // in three deterministic steps:
-//   dm_grad_T:   per (16-row strip, 512-column group) block, the group's share of
-//                T[i][b] = sum_j g_s[i][j] G[j][b]; one pass over E and B (HBM-bound)
-//   dm_grad_G:   per 256-row block, T = sum of the group shares (group order), then the
+//   dm_grad_T:   per (32-row strip, 512-column group) block, the group's share of
+//                T[i][b] = sum_j g_s[i][j] G[j][b] on FP32 MFMA; one pass over E and B
+//                (HBM-bound)
+//   dm_grad_G:   per 32-row block, T = sum of the group shares (group order), then the
 //                block's share of sum_i G[i][a] T[i][b]
 //   dm_grad_reduce: gA += the block shares, in a fixed order.
 // E is the stored plane, or (E == null) the pupil optic amp exp(2 pi i (opd + 2 pre) / lambda)
 // synthesised here (amp/opd nd x nd centred, pre n x n).
-constexpr int kRows = 16;    // rows per dm_grad_T block
-constexpr int kCJ = 128;     // columns per chunk
+constexpr int kRows = 32;    // rows per dm_grad_T block (one MFMA tile)
+constexpr int kCJ = 64;      // columns per chunk
 constexpr int kGroup = 512;  // columns per dm_grad_T block
 constexpr int kGRows = 32;   // rows per dm_grad_G block
 constexpr int kMaxAct = 64;  // actuators per DM edge supported
 
-__device__ __forceinline__ float2 pupil_optic(const float *amp, const float *opd, const float *pre, int n, int nd,
-                                              int i, int j, float inv_lambda) {
-  const int off = (n - nd) / 2;
-  const int wy = i - off, wx = j - off;
-  if (unsigned(wy) >= unsigned(nd) || unsigned(wx) >= unsigned(nd)) return make_float2(0.f, 0.f);
-  const size_t o = size_t(wy) * nd + wx;
-  float turns = 2.f * pre[size_t(i) * n + j] * inv_lambda;
-  if (opd) turns += opd[o] * inv_lambda;
-  float s, c;
-  sincos_turns(turns, &s, &c);
-  return make_float2(amp[o] * c, amp[o] * s);
-}
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-// All loads of a chunk are issued before any is used (indices clamped inside the arrays, the
-// values of out-of-range elements replaced by zero), so their latencies overlap.
+// The loads of one chunk (the field values, or the optic maps when SYNTH, and the chunk's
+// influence rows) with indices clamped inside the arrays; values outside the plane or the
+// chunk are replaced by zero when they are used.
+template <bool SYNTH>
+struct GradChunk {
+  static constexpr int kPer = kRows * kCJ / 256;     // field elements per thread
+  static constexpr int kGPer = kCJ * kMaxAct / 256;  // influence values per thread
+  float2 ev[kPer], bv[kPer];
+  float ws[SYNTH ? kPer : 1], wa[SYNTH ? kPer : 1], wo[SYNTH ? kPer : 1];
+  float gv[kGPer];
+  // raw buffer loads: one 32-bit per-lane offset per access (planes up to 8192^2 c64 = 512 MiB)
+  static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, 0x7fffffff, 0x00020000);
+  }
+  static __device__ __forceinline__ float2 ld64(__amdgpu_buffer_rsrc_t r, unsigned o) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+  }
+  static __device__ __forceinline__ float ld32(__amdgpu_buffer_rsrc_t r, unsigned o) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+  }
+  __device__ __forceinline__ void load(const float2 *E, const float2 *B, const float *G, int n, int na,
+                                       const float *amp, const float *opd, int nd, const float *pre, int i0,
+                                       int j0, int tid) {
+    const int off = (n - nd) / 2;
+    const int c = tid & (kCJ - 1);
+    const __amdgpu_buffer_rsrc_t rb = rsrc(B), rg = rsrc(G);
+    const int j = min(j0 + c, n - 1);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int r = (tid >> 6) + 4 * q;
+      const int i = min(i0 + r, n - 1);
+      const unsigned o = unsigned(i * n + j);
+      bv[q] = ld64(rb, o * 8u);
+      if constexpr (SYNTH) {
+        const int wy = min(max(i - off, 0), nd - 1), wx = min(max(j - off, 0), nd - 1);
+        const unsigned ow = unsigned(wy * nd + wx);
+        ws[q] = ld32(rsrc(pre), o * 4u);
+        wa[q] = ld32(rsrc(amp), ow * 4u);
+        wo[q] = opd ? ld32(rsrc(opd), ow * 4u) : 0.f;
+        ev[q] = make_float2(0.f, 0.f);
+      } else {
+        ev[q] = ld64(rsrc(E), o * 8u);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kGPer; ++q) {
+      const int e = tid + 256 * q;
+      const int cc = e / kMaxAct, a = e % kMaxAct;
+      gv[q] = ld32(rg, unsigned(min(j0 + cc, n - 1) * na + min(a, na - 1)) * 4u);
+    }
+  }
+};
+
+// Block: 4 waves over a 32-row strip and one column group. Per 64-column chunk the surface
+// gradient g_s (32 x 64) and the influence rows G (64 x 64) are staged k-major in LDS; wave w
+// multiplies actuator tile w & 1 over chunk columns [32 (w >> 1), 32 (w >> 1) + 32) with
+// v_mfma_f32_32x32x2f32, accumulating in float32 across the group's chunks; the two column
+// halves are added at the end. The next chunk's loads are issued before this chunk's products.
 template <bool SYNTH>
 __global__ void __launch_bounds__(256) dm_grad_T(const float2 *E, const float2 *B, const float *G, int n, int na,
                                                  float kappa, const float *amp, const float *opd, int nd,
                                                  const float *pre, float inv_lambda, float *tpart) {
-  __shared__ float gs[kRows][kCJ + 4];
-  __shared__ float Gs[kCJ * kMaxAct];  // Gs[c][a]; reused for the reduction of the quarters
-  constexpr int kPer = kRows * kCJ / 256;  // field elements per thread per chunk
-  constexpr int kGPer = kCJ * kMaxAct / 256;
+  // g_s [column][row] and G [column][actuator] per chunk; after the last chunk the same memory
+  // holds the column-half sums
+  __shared__ union {
+    struct {
+      float As[kCJ][kRows + 1];
+      float Bs[kCJ][kMaxAct + 1];
+    } s;
+    float red[2][kRows][kMaxAct / 2 + 1];
+  } sm;
+  using Chunk = GradChunk<SYNTH>;
   const int tid = threadIdx.x;
-  const int b = tid & 63, ph = tid >> 6;  // actuator column, quarter of the chunk
+  const int lane = tid & 63, w = tid >> 6;
+  const int tile = w & 1, half = w >> 1;
   const int i0 = blockIdx.x * kRows;
   const int g = blockIdx.y;
   const int jbeg = g * kGroup, jend = min(n, jbeg + kGroup);
   const int off = (n - nd) / 2;
-  float acc[kRows];
-#pragma unroll
-  for (int r = 0; r < kRows; ++r) acc[r] = 0.f;
+  floatx16 acc = floatx16{0.f};
+  Chunk cur;
+  cur.load(E, B, G, n, na, amp, opd, nd, pre, i0, jbeg, tid);
   for (int j0 = jbeg; j0 < jend; j0 += kCJ) {
     const int cj = min(kCJ, jend - j0);
-    float2 ev[kPer], bv[kPer];
-    float ws[kPer], wa[kPer], wo[kPer];
-    float gv[kGPer];
+    const int c = tid & (kCJ - 1);
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int r = (tid >> 7) + 2 * q, c = tid & 127;
-      const int i = min(i0 + r, n - 1), j = min(j0 + c, n - 1);
-      const size_t o = size_t(i) * n + j;
-      bv[q] = B[o];
-      if (SYNTH) {
-        const int wy = min(max(i - off, 0), nd - 1), wx = min(max(j - off, 0), nd - 1);
-        const size_t ow = size_t(wy) * nd + wx;
-        ws[q] = pre[o];
-        wa[q] = amp[ow];
-        wo[q] = opd ? opd[ow] : 0.f;
-      } else {
-        ev[q] = E[o];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kGPer; ++q) {
-      const int e = tid + 256 * q;
-      const int c = e / kMaxAct, a = e % kMaxAct;
-      gv[q] = G[size_t(min(j0 + c, n - 1)) * na + min(a, na - 1)];
-    }
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int r = (tid >> 7) + 2 * q, c = tid & 127;
+    for (int q = 0; q < Chunk::kPer; ++q) {
+      const int r = (tid >> 6) + 4 * q;
       const int i = i0 + r, j = j0 + c;
-      float2 e2 = ev[q];
+      float2 e2 = cur.ev[q];
       bool in = i < n && c < cj;
-      if (SYNTH) {
+      if constexpr (SYNTH) {
         const bool win = unsigned(i - off) < unsigned(nd) && unsigned(j - off) < unsigned(nd);
         float sn, cs;
-        sincos_turns((2.f * ws[q] + wo[q]) * inv_lambda, &sn, &cs);
-        e2 = make_float2(wa[q] * cs, wa[q] * sn);
+        sincos_turns((2.f * cur.ws[q] + cur.wo[q]) * inv_lambda, &sn, &cs);
+        e2 = make_float2(cur.wa[q] * cs, cur.wa[q] * sn);
         in = in && win;
       }
-      gs[r][c] = in ? -2.f * kappa * (e2.y * bv[q].x - e2.x * bv[q].y) : 0.f;  // -2 kappa Im(E conj(B))
+      // -2 kappa Im(E conj(B))
+      sm.s.As[c][r] = in ? -2.f * kappa * (e2.y * cur.bv[q].x - e2.x * cur.bv[q].y) : 0.f;
     }
 #pragma unroll
-    for (int q = 0; q < kGPer; ++q) {
+    for (int q = 0; q < Chunk::kGPer; ++q) {
       const int e = tid + 256 * q;
-      const int c = e / kMaxAct, a = e % kMaxAct;
-      Gs[e] = (c < cj && a < na) ? gv[q] : 0.f;
+      const int cc = e / kMaxAct, a = e % kMaxAct;
+      sm.s.Bs[cc][a] = (cc < cj && a < na) ? cur.gv[q] : 0.f;
     }
     __syncthreads();
-    const int c0 = ph * (kCJ / 4);
-#pragma unroll 4
-    for (int c = c0; c < c0 + kCJ / 4; ++c) {
-      const float gvv = Gs[c * kMaxAct + b];
+    if (j0 + kCJ < jend) cur.load(E, B, G, n, na, amp, opd, nd, pre, i0, j0 + kCJ, tid);
+    // A operand: lane supplies g_s[row lane % 32][k]; B operand: G[k][actuator lane % 32]
+    const int kl = lane >> 5, rl = lane & 31;
 #pragma unroll
-      for (int r = 0; r < kRows; ++r) acc[r] = fmaf(gs[r][c], gvv, acc[r]);
+    for (int k0 = 0; k0 < kCJ / 2; k0 += 8) {
+#pragma unroll
+      for (int kk = k0; kk < k0 + 8; kk += 2) {
+        const int k = half * (kCJ / 2) + kk + kl;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sm.s.As[k][rl], sm.s.Bs[k][tile * 32 + rl], acc, 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
   }
-  float *red = Gs;  // [4][kRows][kMaxAct]
+  // accumulator r of lane l: row (r / 4) 8 + (l / 32) 4 + r % 4, actuator tile * 32 + l % 32
+  if (half == 1) {
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) red[(ph * kRows + r) * kMaxAct + b] = acc[r];
+    for (int r = 0; r < 16; ++r) sm.red[tile][(r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)][lane & 31] = acc[r];
+  }
   __syncthreads();
-  for (int e = tid; e < kRows * kMaxAct; e += 256) {
-    const int r = e / kMaxAct, c = e % kMaxAct;
-    const int i = i0 + r;
-    if (i < n && c < na) {
-      const float v = ((red[e] + red[kRows * kMaxAct + e]) + red[2 * kRows * kMaxAct + e]) + red[3 * kRows * kMaxAct + e];
-      tpart[(size_t(g) * n + i) * na + c] = v;
+  if (half == 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+      const int i = i0 + row, a = tile * 32 + (lane & 31);
+      if (i < n && a < na) tpart[(size_t(g) * n + i) * na + a] = acc[r] + sm.red[tile][row][lane & 31];
     }
   }
 }

@@ -88,10 +88,11 @@ def test_airy_256_aperture_on_gpu():
     assert np.max(np.abs(cut - np.abs(airy))[core]) <= 1.5e-3
 
 
-@pytest.mark.parametrize("tile,split", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 1), (1, 3), (2, 16),
-                                        (3, 7)])
+@pytest.mark.parametrize("tile,split", [(0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (0, 1), (1, 3),
+                                        (2, 16), (3, 7), (4, 5), (5, 2)])
 def test_every_gemm_tile_configuration_matches_oracle(tile, split, tmp_path):
-    # force one tile configuration and split-K factor (0: the tile's default) on all four GEMMs
+    # force one tile configuration (4 and 5: three real products per complex step) and split-K
+    # factor (0: the tile's default) on all four GEMMs
     # of a ragged forward and adjoint MFT (through the autotuner's file format) and check both
     # transforms against the oracle; 16 slices of K = 130 leave trailing slices empty
     n, m, n_d, du = 1000, 130, 500.0, 0.3
@@ -112,4 +113,29 @@ def test_autotune_file_refuses_a_split_beyond_the_limit(tmp_path):
     f = tmp_path / "bad.txt"
     f.write_text("gemm 1000 130 1000 0 1 0 17\n")
     with pytest.raises(fb.FrError):
+        fb.autotune_load(str(f))
+    f.write_text("gemm_default 6 0\n")   # no tile configuration 6
+    with pytest.raises(fb.FrError):
+        fb.autotune_load(str(f))
+
+
+def test_default_gemm_choice_applies_to_untuned_shapes(tmp_path):
+    # a default tile / split for every shape without its own line: the three-product tile on a
+    # ragged pair of transforms, then back to the choice by shape
+    n, m, n_d, du = 700, 90, 350.0, 0.45
+    f = tmp_path / "default.txt"
+    f.write_text("gemm_default 4 3\n")
+    fb.autotune_load(str(f))
+    try:
+        e = synth.random_field(n, 41)
+        got = to_np(fb.mft_forward(to_gpu(e), n_d, m, du))
+        assert rel_l2(got, oracle.mft(f32(e), n_d, m, du)) <= TOL
+        eb = synth.random_field(m, 42)
+        got = to_np(fb.mft_adjoint(to_gpu(eb), n_d, n, du))
+        assert rel_l2(got, oracle.mft_adjoint(f32(eb), n_d, n, du)) <= TOL
+        saved = tmp_path / "saved.txt"
+        fb.autotune_save(str(saved))
+        assert "gemm_default 4 3" in saved.read_text()
+    finally:
+        f.write_text("gemm_default -1 0\n")
         fb.autotune_load(str(f))

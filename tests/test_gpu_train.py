@@ -5,6 +5,8 @@ Bars: PSF relative L2 <= 1e-5 and max |contrast difference| <= 1e-9 (stated for 
 gradient relative L2 <= 1e-4 against the FP64 adjoint and per-actuator agreement with central
 differences (h = 1e-3 nm) within 1e-4 of the largest gradient component."""
 
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -185,6 +187,20 @@ def test_batched_matches_plain_mixed_grids():
     assert torch.equal(v0, v1)
 
 
+@functools.lru_cache(maxsize=1)
+def _broadband_oracle():
+    # the oracle's broadband PSF with and without the occulting spot (shared by the tests below)
+    banner("broadband train: oracle over 21 wavelengths (about a minute)")
+    geom, _, heights, _ = make(1024, 256, 8 / 256, 512, 0.25, 1.0, 48, 1)
+    lams = list(synth.wavelengths(21))
+    ns = list(synth.padded_sizes(21))
+    w = [1.0 / 21] * 21
+    cache = {}
+    ref = oracle.train_psf(geom, lams, ns, w, heights, step_cache=cache)
+    ref0 = oracle.train_psf(geom, lams, ns, w, heights, occulter=False, step_cache=cache)
+    return ref, ref0
+
+
 def test_broadband_train_batched_full_size():
     # the broadband model: 1024 pupil, 21 wavelengths over 500-600 nm on per-wavelength grids
     # 3584 ... 4096 in one batch (equal weights). Batched agrees with plain to float32
@@ -199,14 +215,36 @@ def test_broadband_train_batched_full_size():
     p_batch = _np(fb.propagate_train(tr, lams, ns, w, hg, batched=True))
     p_ref0 = _np(fb.propagate_train(tr, lams, ns, w, hg, batched=True, occulter=False))
     assert rel_l2(p_batch, p_plain) <= 1e-6
-    banner("broadband train: oracle over 21 wavelengths (about a minute)")
-    cache = {}
-    ref = oracle.train_psf(geom, lams, ns, w, heights, step_cache=cache)
-    ref0 = oracle.train_psf(geom, lams, ns, w, heights, occulter=False, step_cache=cache)
+    ref, ref0 = _broadband_oracle()
     assert rel_l2(p_batch, ref) <= 1e-5
     assert rel_l2(p_ref0, ref0) <= 1e-5
     err = np.max(np.abs(p_batch / p_ref0.max() - ref / ref0.max()))
     banner(f"broadband max |dC| = {err:.3e}, peak contrast {np.max(ref / ref0.max()):.3e}")
+    assert err <= 1e-9
+
+
+def test_broadband_contrast_with_three_product_gemms(tmp_path):
+    # the same broadband train with every MFT GEMM on the three-product tile (Gauss: the
+    # imaginary part is a difference of three float32 sums, combined in float64 per stage):
+    # the normalised contrast still meets the 1e-9 bar against the oracle
+    banner("broadband train with three-product GEMM tiles")
+    geom, tr, heights, hg = make(1024, 256, 8 / 256, 512, 0.25, 1.0, 48, 1)
+    lams = list(synth.wavelengths(21))
+    ns = list(synth.padded_sizes(21))
+    w = [1.0 / 21] * 21
+    f = tmp_path / "g3.txt"
+    f.write_text("gemm_default 4 0\n")
+    fb.autotune_load(str(f))
+    try:
+        p = _np(fb.propagate_train(tr, lams, ns, w, hg, batched=True))
+        p0 = _np(fb.propagate_train(tr, lams, ns, w, hg, batched=True, occulter=False))
+    finally:
+        f.write_text("gemm_default -1 0\n")
+        fb.autotune_load(str(f))
+    ref, ref0 = _broadband_oracle()
+    assert rel_l2(p, ref) <= 1e-5
+    err = np.max(np.abs(p / p0.max() - ref / ref0.max()))
+    banner(f"three-product GEMMs: broadband max |dC| = {err:.3e}")
     assert err <= 1e-9
 
 
