@@ -4,14 +4,17 @@
 // the matrix cores.
 //
 // Complex product with real MFMA: per complex k-step, Cr += Ar Br - Ai Bi and
-// Ci += Ar Bi + Ai Br (four v_mfma_f32_32x32x2f32 per 32 x 32 tile, fragments from LDS).
+// Ci += Ar Bi + Ai Br (four v_mfma_f32_32x32x2f32 per 32 x 32 tile, fragments from LDS), or
+// with three products (Gauss) P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), Cr = P1 - P2,
+// Ci = P3 - P1 - P2, the differences taken in float64 at each fold.
 // Block tile 64 x 128 (four waves in 2 x 2, each a 32 x 64 piece made of two 32 x 32 MFMA
 // tiles) or 64 x 64 for small outputs. Two or three blocks share a compute unit; as their
 // barriers are independent, one block's float64 folds overlap another block's MFMAs. Operand tiles 16 deep are staged through double-buffered LDS, the next tile's
 // global loads in flight while the current one is multiplied (one barrier per tile). Each
-// 16-deep tile is summed by the MFMAs in float32 and then added into float64 totals (the long
-// Fourier sums of the coronagraph cancel to tiny values in the dark hole, so their rounding
-// must not grow with K); the epilogue (alpha, beta, mask, intensity) runs in float64.
+// 16-deep tile (32-deep group for the three-product tiles) is summed by the MFMAs in float32 and
+// then added into float64 totals (the long Fourier sums of the coronagraph cancel to tiny values
+// in the dark hole, so their rounding must not grow with K); the epilogue (alpha, beta, mask,
+// intensity) runs in float64.
 // Operands may be transposed (template) and/or conjugated (on the LDS store). Outputs with few
 // tiles and long K are split over K; the float64 partial sums go to the workspace and one
 // epilogue kernel adds them in a fixed order (deterministic).
@@ -64,10 +67,11 @@ __device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, doubl
 // operand tiles of the next PD stages are in flight while a stage is multiplied. G3: three real
 // products per complex k-step instead of four (Gauss): P1 = sum Ar Br, P2 = sum Ai Bi,
 // P3 = sum (Ar + Ai)(Br + Bi), combined per stage in float64 as Cr = P1 - P2, Ci = P3 - P1 - P2.
-template <int WM_, int WN_, int TN_, int PD_ = 1, bool G3_ = false>
+template <int WM_, int WN_, int TN_, int PD_ = 1, bool G3_ = false, int FOLD_ = 1>
 struct Cfg {
   static constexpr int WM = WM_, WN = WN_, TN = TN_, PD = PD_;
   static constexpr bool G3 = G3_;
+  static constexpr int FOLD = FOLD_;  // 16-deep stages summed in float32 between float64 folds
   // waves per SIMD the register budget targets (the three-product 32 x 64 wave tile holds three
   // float32 and two float64 accumulator sets, so it gets the whole register file)
   static constexpr int waves = TN == 1 ? 3 : (G3 ? 1 : 2);
@@ -82,8 +86,9 @@ using CfgL = Cfg<2, 2, 2>;  // 64 x 128, 256 threads: two blocks share a compute
 using CfgS = Cfg<2, 2, 1>;  // 64 x 64, 256 threads
 using CfgX = Cfg<4, 2, 2>;  // 128 x 128, 512 threads
 using CfgP = Cfg<2, 2, 1, 2>;  // 64 x 64, 256 threads, two stages of loads in flight
-using CfgS3 = Cfg<2, 2, 1, 1, true>;  // 64 x 64, three products per complex step
-using CfgL3 = Cfg<2, 2, 2, 1, true>;  // 64 x 128, three products per complex step
+// three products per complex step, float32 sums over 32-deep groups between float64 folds
+using CfgS3 = Cfg<2, 2, 1, 1, true, 2>;  // 64 x 64
+using CfgL3 = Cfg<2, 2, 2, 1, true, 2>;  // 64 x 128
 
 // Per-thread share of one BK-deep operand tile, mapped so that consecutive threads walk
 // memory contiguously.
@@ -180,69 +185,67 @@ cgemm_kernel(GemmParams gp) {
   const int arow = wm * 32 + (lane & 31);
   const int bcol = wn * 32 * TN + (lane & 31);
   const int kl = lane >> 5;
-  // one stage: multiply the LDS tile `buf`, fold into the float64 totals
+  // float32 sums of the current fold group: (P1, P2, P3) for three products, (Cr, Ci) else
+  floatx16 acc[C::G3 ? 3 : 2][TN];
+  auto clear = [&] {
+#pragma unroll
+    for (int q = 0; q < (C::G3 ? 3 : 2); ++q)
+#pragma unroll
+      for (int t = 0; t < TN; ++t) acc[q][t] = floatx16{0.f};
+  };
+  clear();
+  // one stage: multiply the LDS tile `buf` into the float32 sums
   auto multiply = [&](int buf) {
-    if constexpr (C::G3) {
-      floatx16 p1[TN], p2[TN], p3[TN];
 #pragma unroll
-      for (int t = 0; t < TN; ++t) {
-        p1[t] = floatx16{0.f};
-        p2[t] = floatx16{0.f};
-        p3[t] = floatx16{0.f};
-      }
+    for (int kk = 0; kk < BK; kk += 2) {
+      const float2 av = As[buf][kk + kl][arow];
+      float2 bv[TN];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 2) {
-        const float2 av = As[buf][kk + kl][arow];
+      for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][kk + kl][bcol + 32 * t];
+      if constexpr (C::G3) {
         const float as = av.x + av.y;
-        float2 bv[TN];
-#pragma unroll
-        for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][kk + kl][bcol + 32 * t];
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
-          p1[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].x, p1[t], 0, 0, 0);
-          p2[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv[t].y, p2[t], 0, 0, 0);
-          p3[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(as, bv[t].x + bv[t].y, p3[t], 0, 0, 0);
+          acc[0][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].x, acc[0][t], 0, 0, 0);
+          acc[1][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv[t].y, acc[1][t], 0, 0, 0);
+          acc[2][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(as, bv[t].x + bv[t].y, acc[2][t], 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+          acc[0][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].x, acc[0][t], 0, 0, 0);
+          acc[1][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].y, acc[1][t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+          acc[0][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, bv[t].y, acc[0][t], 0, 0, 0);
+          acc[1][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv[t].x, acc[1][t], 0, 0, 0);
         }
       }
+    }
+  };
+  // add the float32 sums into the float64 totals and restart them
+  auto fold = [&] {
 #pragma unroll
-      for (int t = 0; t < TN; ++t)
+    for (int t = 0; t < TN; ++t)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const double d1 = double(p1[t][r]), d2 = double(p2[t][r]);
+      for (int r = 0; r < 16; ++r) {
+        if constexpr (C::G3) {
+          const double d1 = double(acc[0][t][r]), d2 = double(acc[1][t][r]);
           totr[t][r] += d1 - d2;
-          toti[t][r] += double(p3[t][r]) - d1 - d2;
-        }
-    } else {
-      floatx16 cr[TN], ci[TN];
-#pragma unroll
-      for (int t = 0; t < TN; ++t) {
-        cr[t] = floatx16{0.f};
-        ci[t] = floatx16{0.f};
-      }
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 2) {
-        const float2 av = As[buf][kk + kl][arow];
-        float2 bv[TN];
-#pragma unroll
-        for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][kk + kl][bcol + 32 * t];
-#pragma unroll
-        for (int t = 0; t < TN; ++t) {
-          cr[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].x, cr[t], 0, 0, 0);
-          ci[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv[t].y, ci[t], 0, 0, 0);
-        }
-#pragma unroll
-        for (int t = 0; t < TN; ++t) {
-          cr[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, bv[t].y, cr[t], 0, 0, 0);
-          ci[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv[t].x, ci[t], 0, 0, 0);
+          toti[t][r] += double(acc[2][t][r]) - d1 - d2;
+        } else {
+          totr[t][r] += double(acc[0][t][r]);
+          toti[t][r] += double(acc[1][t][r]);
         }
       }
-#pragma unroll
-      for (int t = 0; t < TN; ++t)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          totr[t][r] += double(cr[t][r]);
-          toti[t][r] += double(ci[t][r]);
-        }
+    clear();
+  };
+  int pending = 0;  // stages multiplied since the last fold
+  auto after_stage = [&](bool last) {
+    if (++pending == C::FOLD || last) {
+      fold();
+      pending = 0;
     }
   };
   if constexpr (C::PD == 1) {
@@ -257,6 +260,7 @@ cgemm_kernel(GemmParams gp) {
       const bool more = k0 + BK < kend;
       if (more) ld.load(a, tid, i0, j0, k0 + BK, kend);
       multiply(buf);
+      after_stage(!more);
       if (more) ld.store(As[buf ^ 1], Bs[buf ^ 1], tid, sa, sb);
       __syncthreads();
       buf ^= 1;
@@ -274,6 +278,7 @@ cgemm_kernel(GemmParams gp) {
     auto step = [&](int k0, int buf, TileLoad<C, TA, TB> &fill, const TileLoad<C, TA, TB> &ready) {
       if (k0 + 2 * BK < kend) fill.load(a, tid, i0, j0, k0 + 2 * BK, kend);
       multiply(buf);
+      after_stage(k0 + BK >= kend);
       if (k0 + BK < kend) ready.store(As[buf ^ 1], Bs[buf ^ 1], tid, sa, sb);
       __syncthreads();
     };
@@ -282,7 +287,7 @@ cgemm_kernel(GemmParams gp) {
       if (k0 + BK < kend) step(k0 + BK, 1, l1, l0);
     }
   }
-  // what the float32 accumulators still hold was folded at the end of each stage
+  // the last stage of the slice ended with a fold, so the float64 totals hold everything
   // accumulator r of lane l sits at row (r/4)*8 + (l/32)*4 + r%4, column l%32 of a 32 x 32 tile
 #pragma unroll
   for (int t = 0; t < TN; ++t) {
