@@ -43,6 +43,38 @@ LAMBDA_C = 550e-9
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
+# HBM bytes per launch from two rocprofv3 --pmc runs of this bench (FETCH_SIZE, then WRITE_SIZE,
+# KiB per dispatch), scaled by what the counters read for a device copy of one 128 MiB plane in
+# the same runs (FETCH x 2.0, WRITE x 1.0); each entry carries the SHA-256 of the sources of the
+# kernel it was measured on, and reads as unknown (null) once those sources change.
+HERE = os.path.dirname(os.path.abspath(__file__))
+MEASURED_TRAFFIC = {
+    # kernel: (fetch bytes, write bytes)
+    "cgemmS3_4096x256x4096_s8": (2.0 * 84173.9 * 1024, 131072.0 * 1024),
+    "cgemmS3_4096x4096x256_s1": (2.0 * 38122.4 * 1024, 131072.0 * 1024),
+}
+TRAFFIC_SOURCES = {
+    "paper_1806_06467_amd/csrc/mft.hip": "1e4a5e73838001050c75e8963365c333d72e2643b3c7b2760a2e76db1ebe7f79",
+    "paper_1806_06467_amd/csrc/fr_internal.h": "b49aa7f98e3cc75117d00a2e716cc0c955e3b7e9db516c787d217b3c8b719390",
+}
+
+
+def measured_traffic(kernel):
+    """Counter-measured HBM bytes per launch of `kernel`, or None (not measured, or measured on
+    sources that have changed since)."""
+    import hashlib
+    if kernel not in MEASURED_TRAFFIC:
+        return None
+    for rel, digest in TRAFFIC_SOURCES.items():
+        try:
+            with open(os.path.join(HERE, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    fetch, write = MEASURED_TRAFFIC[kernel]
+    return fetch + write
+
 
 def sweep_bytes(n, optic_maps):
     """Algorithmic HBM bytes of one sweep of one plane: the n^2 c64 field read and written once,
@@ -97,6 +129,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-file", default=None,
+                    help="load tuned kernel choices from this file (written by --save-tune) instead "
+                         "of running the autotuner, so that repeated runs launch the same kernels")
+    ap.add_argument("--save-tune", default=None, help="write the tuned kernel choices to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of one 4096^2 c64 plane (134217728 B read, "
                          "134217728 B written) so HBM byte counters can be scaled")
@@ -116,16 +152,22 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    # autotune (untimed): sweep tiles for the plane edge, GEMM tiles for the train's MFT shapes
+    # autotune (untimed): sweep tiles for the plane edge, GEMM tiles (and split-K factors) for
+    # the train's MFT shapes; or the choices of an earlier run
     t_tune = time.perf_counter()
-    fb.autotune_fresnel(N)
-    for n_, m_ in ((N, OCC_M), (N_D, OCC_M), (N_D, DET_M)):
-        fb.autotune_mft(n_, m_)
-    tune_file = os.path.join(os.environ.get("TMPDIR", "/tmp"), "fresnel_bench_tune_%d.txt" % os.getpid())
+    if args.tune_file:
+        fb.autotune_load(args.tune_file)
+    else:
+        fb.autotune_fresnel(N)
+        for n_, m_ in ((N, OCC_M), (N_D, OCC_M), (N_D, DET_M)):
+            fb.autotune_mft(n_, m_)
+    tune_file = args.save_tune or os.path.join(os.environ.get("TMPDIR", "/tmp"),
+                                               "fresnel_bench_tune_%d.txt" % os.getpid())
     fb.autotune_save(tune_file)
     with open(tune_file) as f:
         tuned = [l.strip() for l in f if not l.startswith("#")]
-    os.remove(tune_file)
+    if not args.save_tune:
+        os.remove(tune_file)
     t_tune = time.perf_counter() - t_tune
     inp = train_inputs(torch, np, synth, dev)
     lams = inp["lams"]
@@ -226,8 +268,8 @@ def main():
             flops = 8.0 * m * n_ * k
             tf = flops / (ms * 1e-3) / 1e12
             return {"bound": "mfma", "kernel": name, "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": tf / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
-                    "flops_per_launch": flops, "avg_launch_ms": ms}
+                    "unit": "TFLOP/s", "frac": tf / FP32_MFMA_PEAK_TFLOPS,
+                    "traffic": measured_traffic(name), "flops_per_launch": flops, "avg_launch_ms": ms}
         return None
 
     # the dominant kernel: the largest share of the step that has a cost model
@@ -311,7 +353,7 @@ def main():
             "hbm_frac_whole_plane": fr_plane_frac,
             "roofline": fr_rl,
         },
-        "autotuned": {"choices": tuned, "seconds": t_tune},
+        "autotuned": {"choices": tuned, "seconds": t_tune, "loaded_from_file": bool(args.tune_file)},
         "checksum_psf_sum": psf_sum,
         "wall_s": t_wall,
     }

@@ -160,18 +160,24 @@ cgemm_kernel(GemmParams gp) {
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = wave / C::WN, wn = wave % C::WN;
   // Blocks are dealt round-robin to the 8 XCDs (each with its own L2). Renumber them so that
-  // each XCD runs a contiguous range of tiles, x (the output column tile) fastest: the tiles
-  // that share the rows of A (and the K slice) then share that XCD's L2.
-  int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  // each XCD runs a contiguous range of tiles; inside a K slice the range is walked in groups of
+  // kGroupRows tile rows, column by column, so that the blocks resident on an XCD at one time
+  // share a few operand row panels of A and column panels of B in that XCD's L2 (walking whole
+  // tile rows instead streams all of B once per tile row).
+  int bx, by, bz;
   {
-    const int total = gridDim.x * gridDim.y * gridDim.z;
-    if (total % 8 == 0) {
-      const int lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-      const int tile = (lin & 7) * (total >> 3) + (lin >> 3);
-      bx = tile % gridDim.x;
-      by = (tile / gridDim.x) % gridDim.y;
-      bz = tile / (gridDim.x * gridDim.y);
-    }
+    constexpr int kGroupRows = 8;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int total = gx * gy * gridDim.z;
+    const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int tile = total % 8 == 0 ? (lin & 7) * (total >> 3) + (lin >> 3) : lin;
+    bz = tile / (gx * gy);
+    const int t = tile % (gx * gy);
+    const int g = t / (kGroupRows * gx);             // group of tile rows
+    const int rows = min(kGroupRows, gy - g * kGroupRows);
+    const int u = t % (kGroupRows * gx);             // position inside the group
+    bx = u / rows;
+    by = g * kGroupRows + u % rows;
   }
   const int i0 = by * C::BM, j0 = bx * C::BN;
   const int kbeg = bz * gp.k_per_split;
