@@ -67,14 +67,20 @@ __device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, doubl
 // operand tiles of the next PD stages are in flight while a stage is multiplied. G3: three real
 // products per complex k-step instead of four (Gauss): P1 = sum Ar Br, P2 = sum Ai Bi,
 // P3 = sum (Ar + Ai)(Br + Bi), combined per stage in float64 as Cr = P1 - P2, Ci = P3 - P1 - P2.
-template <int WM_, int WN_, int TN_, int PD_ = 1, bool G3_ = false, int FOLD_ = 1>
+template <int WM_, int WN_, int TN_, int PD_ = 1, bool G3_ = false, int FOLD_ = 1, bool BF_ = false>
 struct Cfg {
   static constexpr int WM = WM_, WN = WN_, TN = TN_, PD = PD_;
   static constexpr bool G3 = G3_;
   static constexpr int FOLD = FOLD_;  // 16-deep stages summed in float32 between float64 folds
+  // BF: the three real operand streams (re, im, re + im) are split exactly into three bfloat16
+  // pieces each (hi, mid below 2^-7 and lo below 2^-15 of the value) and multiplied on
+  // v_mfma_f32_32x32x16_bf16: every piece product except lo lo (below 2^-30 of the leading
+  // one), each exact in float32
+  static constexpr bool BF = BF_;
+  static_assert(!BF || (G3 && TN == 1), "bfloat16 split tiles: three products, 32 x 32 per wave");
   // waves per SIMD the register budget targets (the three-product 32 x 64 wave tile holds three
   // float32 and two float64 accumulator sets, so it gets the whole register file)
-  static constexpr int waves = TN == 1 ? 3 : (G3 ? 1 : 2);
+  static constexpr int waves = BF ? 2 : TN == 1 ? 3 : (G3 ? 1 : 2);
   static constexpr int BM = 32 * WM, BN = 32 * TN * WN;
   static constexpr int threads = 64 * WM * WN;
   static constexpr int la = BM * BK / threads;  // A elements per thread per tile
@@ -89,16 +95,31 @@ using CfgP = Cfg<2, 2, 1, 2>;  // 64 x 64, 256 threads, two stages of loads in f
 // three products per complex step, float32 sums over 32-deep groups between float64 folds
 using CfgS3 = Cfg<2, 2, 1, 1, true, 2>;  // 64 x 64
 using CfgL3 = Cfg<2, 2, 2, 1, true, 2>;  // 64 x 128
+// three products on bfloat16 pieces, 64 x 64
+#ifndef FR_BF_FOLD
+#define FR_BF_FOLD 4
+#endif
+using CfgB = Cfg<2, 2, 1, 1, true, FR_BF_FOLD, true>;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Per-thread share of one BK-deep operand tile, mapped so that consecutive threads walk
 // memory contiguously.
 template <class C, bool TA, bool TB>
 struct TileLoad {
   float2 ra[C::la], rb[C::lb];
+  // For the bfloat16 tiles every thread holds la (lb) consecutive k of one row (column), so that
+  // each of its pieces goes to LDS as one 8-byte write: an operand stored with i (j) contiguous
+  // keeps its loads contiguous along i (j) for every r; one stored with k contiguous is read as
+  // 32-byte runs (four threads per 16-deep row).
+  static constexpr int kRun = BK / 4;  // threads per row of a k-contiguous bfloat16 operand
   __device__ __forceinline__ static void a_coord(int t, int r, int &i, int &k) {
     if (TA) {  // A stored K x M: contiguous along i
       i = t % C::BM;
-      k = t / C::BM + (C::threads / C::BM) * r;
+      k = C::BF ? (t / C::BM) * C::la + r : t / C::BM + (C::threads / C::BM) * r;
+    } else if (C::BF) {
+      i = t / kRun;
+      k = (t % kRun) * 4 + r;
     } else {   // A stored M x K: contiguous along k
       k = t % BK;
       i = t / BK + (C::threads / BK) * r;
@@ -106,29 +127,77 @@ struct TileLoad {
   }
   __device__ __forceinline__ static void b_coord(int t, int r, int &k, int &j) {
     if (TB) {  // B stored N x K: contiguous along k
-      k = t % BK;
-      j = t / BK + (C::threads / BK) * r;
+      if (C::BF) {
+        j = t / kRun;
+        k = (t % kRun) * 4 + r;
+      } else {
+        k = t % BK;
+        j = t / BK + (C::threads / BK) * r;
+      }
     } else {   // B stored K x N: contiguous along j
       j = t % C::BN;
-      k = t / C::BN + (C::threads / C::BN) * r;
+      k = C::BF ? (t / C::BN) * C::lb + r : t / C::BN + (C::threads / C::BN) * r;
     }
   }
+  // four consecutive complex values base[e .. e + 3] (32 bytes, 8-byte aligned) as two 16-byte
+  // buffer loads; the descriptor is the operand's (wave-uniform), e the per-lane element offset
+  // (operands up to 2^28 elements, so the byte offset fits 32 bits)
+  __device__ __forceinline__ static void load_run(const float2 *base, size_t e, float2 *dst) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(base), (short)0, 0x7fffffff, 0x00020000);
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const unsigned o = unsigned(e) * 8u;
+    const f4 lo = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0));
+    const f4 hi = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u, 0, 0));
+    dst[0] = make_float2(lo[0], lo[1]);
+    dst[1] = make_float2(lo[2], lo[3]);
+    dst[2] = make_float2(hi[0], hi[1]);
+    dst[3] = make_float2(hi[2], hi[3]);
+  }
   __device__ __forceinline__ void load(const CGemmArgs &a, int t, int i0, int j0, int k0, int kend) {
-#pragma unroll
-    for (int r = 0; r < C::la; ++r) {
+    if constexpr (C::BF && !TA) {
+      static_assert(C::la == 4, "one 4-run per thread");
       int i, k;
-      a_coord(t, r, i, k);
+      a_coord(t, 0, i, k);
       const int gi = i0 + i, gk = k0 + k;
-      ra[r] = (gi < a.M && gk < kend) ? (TA ? a.A[size_t(gk) * a.lda + gi] : a.A[size_t(gi) * a.lda + gk])
-                                      : make_float2(0.f, 0.f);
-    }
+      if (gi < a.M && gk + 4 <= kend) {
+        load_run(a.A, size_t(gi) * a.lda + gk, ra);
+      } else {
 #pragma unroll
-    for (int r = 0; r < C::lb; ++r) {
+        for (int r = 0; r < 4; ++r)
+          ra[r] = (gi < a.M && gk + r < kend) ? a.A[size_t(gi) * a.lda + gk + r] : make_float2(0.f, 0.f);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < C::la; ++r) {
+        int i, k;
+        a_coord(t, r, i, k);
+        const int gi = i0 + i, gk = k0 + k;
+        ra[r] = (gi < a.M && gk < kend) ? (TA ? a.A[size_t(gk) * a.lda + gi] : a.A[size_t(gi) * a.lda + gk])
+                                        : make_float2(0.f, 0.f);
+      }
+    }
+    if constexpr (C::BF && TB) {
+      static_assert(C::lb == 4, "one 4-run per thread");
       int k, j;
-      b_coord(t, r, k, j);
+      b_coord(t, 0, k, j);
       const int gk = k0 + k, gj = j0 + j;
-      rb[r] = (gj < a.N && gk < kend) ? (TB ? a.B[size_t(gj) * a.ldb + gk] : a.B[size_t(gk) * a.ldb + gj])
-                                      : make_float2(0.f, 0.f);
+      if (gj < a.N && gk + 4 <= kend) {
+        load_run(a.B, size_t(gj) * a.ldb + gk, rb);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          rb[r] = (gj < a.N && gk + r < kend) ? a.B[size_t(gj) * a.ldb + gk + r] : make_float2(0.f, 0.f);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < C::lb; ++r) {
+        int k, j;
+        b_coord(t, r, k, j);
+        const int gk = k0 + k, gj = j0 + j;
+        rb[r] = (gj < a.N && gk < kend) ? (TB ? a.B[size_t(gj) * a.ldb + gk] : a.B[size_t(gk) * a.ldb + gj])
+                                        : make_float2(0.f, 0.f);
+      }
     }
   }
   __device__ __forceinline__ void store(float2 (*As)[C::BM + PAD], float2 (*Bs)[C::BN + PAD], int t, float sa,
@@ -154,8 +223,13 @@ cgemm_kernel(GemmParams gp) {
   static_assert(C::threads <= 512, "block too large");
   constexpr int TN = C::TN;
   const CGemmArgs &a = gp.a;
-  __shared__ float2 As[2][BK][C::BM + PAD];
-  __shared__ float2 Bs[2][BK][C::BN + PAD];
+  __shared__ float2 As[C::BF ? 1 : 2][BK][C::BM + PAD];
+  __shared__ float2 Bs[C::BF ? 1 : 2][BK][C::BN + PAD];
+  // bfloat16 pieces, [buffer][stream * 3 + level][row or column][k], k contiguous so that a
+  // lane's eight k values of one piece are one 16-byte read
+  constexpr int kPieces = 9;
+  __shared__ __attribute__((aligned(16))) unsigned short Ab[C::BF ? 2 : 1][C::BF ? kPieces : 1][C::BF ? C::BM : 1][BK];
+  __shared__ __attribute__((aligned(16))) unsigned short Bb[C::BF ? 2 : 1][C::BF ? kPieces : 1][C::BF ? C::BN : 1][BK];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = wave / C::WN, wn = wave % C::WN;
@@ -191,17 +265,47 @@ cgemm_kernel(GemmParams gp) {
   const int arow = wm * 32 + (lane & 31);
   const int bcol = wn * 32 * TN + (lane & 31);
   const int kl = lane >> 5;
-  // float32 sums of the current fold group: (P1, P2, P3) for three products, (Cr, Ci) else
-  floatx16 acc[C::G3 ? 3 : 2][TN];
+  // float32 sums of the current fold group: (P1, P2, P3) for three products, (Cr, Ci) else; the
+  // bfloat16 tile keeps each P in two sums, the hi hi products and the (at least 2^-7 smaller)
+  // correction products, so that the correction terms are not rounded at the scale of the total
+  constexpr int kSums = C::BF ? 6 : (C::G3 ? 3 : 2);
+  floatx16 acc[kSums][TN];
   auto clear = [&] {
 #pragma unroll
-    for (int q = 0; q < (C::G3 ? 3 : 2); ++q)
+    for (int q = 0; q < kSums; ++q)
 #pragma unroll
       for (int t = 0; t < TN; ++t) acc[q][t] = floatx16{0.f};
   };
   clear();
   // one stage: multiply the LDS tile `buf` into the float32 sums
   auto multiply = [&](int buf) {
+    if constexpr (C::BF) {
+      // lane: row (column) lane % 32 of the wave's piece, k = 8 (lane / 32) .. + 7
+      const int kh = 8 * (lane >> 5);
+      bf16x8 ap[3][3], bp[3][3];
+#pragma unroll
+      for (int st = 0; st < 3; ++st)
+#pragma unroll
+        for (int lv = 0; lv < 3; ++lv) {
+          ap[st][lv] = *reinterpret_cast<const bf16x8 *>(&Ab[buf][st * 3 + lv][arow][kh]);
+          bp[st][lv] = *reinterpret_cast<const bf16x8 *>(&Bb[buf][st * 3 + lv][bcol][kh]);
+        }
+      // eight piece products: the seven corrections smallest first (lo mid, mid lo, lo hi,
+      // mid mid, hi lo, mid hi, hi mid) into the correction sum, then hi hi into the main sum;
+      // only lo lo (below 2^-28 of the leading product) is left out. The three streams' chains
+      // are interleaved so that consecutive MFMAs are independent.
+      constexpr int la_[7] = {2, 1, 2, 1, 0, 1, 0}, lb_[7] = {1, 2, 0, 1, 2, 0, 1};
+#pragma unroll
+      for (int q = 0; q < 7; ++q)
+#pragma unroll
+        for (int st = 0; st < 3; ++st)
+          acc[2 * st + 1][0] =
+              __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[st][la_[q]], bp[st][lb_[q]], acc[2 * st + 1][0], 0, 0, 0);
+#pragma unroll
+      for (int st = 0; st < 3; ++st)
+        acc[2 * st][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[st][0], bp[st][0], acc[2 * st][0], 0, 0, 0);
+      return;
+    }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
       const float2 av = As[buf][kk + kl][arow];
@@ -230,13 +334,71 @@ cgemm_kernel(GemmParams gp) {
       }
     }
   };
+  // operand tile from the loader's registers into LDS: float32 complex, or for BF the three
+  // streams (re, im, re + im; imaginary parts conjugated as asked) in bfloat16 pieces
+  auto stage_store = [&](const TileLoad<C, TA, TB> &ld, int buf) {
+    if constexpr (C::BF) {
+      // one operand's elements: pieces of the three streams, as 2-byte writes (k contiguous
+      // across lanes) or, when a thread holds n consecutive k of one row, as one 2n-byte write
+      // the four consecutive-k values v[0..3] of one row. Each stream value x = hi + mid + lo
+      // exactly, each piece a bfloat16 (the upper 16 bits of a float32 bit pattern): hi and mid
+      // by truncation, the remainders r = x - hi and r - mid being exact in float32, lo holding
+      // the last at most eight significant bits. Pairs of upper halves are packed by one byte
+      // permute each and written as one 8-byte store per piece.
+      auto put = [&](unsigned short(*dst)[C::BF ? C::BM : 1][BK], const float2 *v, float sc, int row, int k0) {
+        unsigned bits[3][3][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float re = v[r].x, im = sc * v[r].y;
+          const float x3[3] = {re, im, re + im};
+#pragma unroll
+          for (int st = 0; st < 3; ++st) {
+            const unsigned xb = __float_as_uint(x3[st]);
+            const float rr = x3[st] - __uint_as_float(xb & 0xffff0000u);
+            const unsigned rb = __float_as_uint(rr);
+            bits[st][0][r] = xb;
+            bits[st][1][r] = rb;
+            bits[st][2][r] = __float_as_uint(rr - __uint_as_float(rb & 0xffff0000u));
+          }
+        }
+#pragma unroll
+        for (int st = 0; st < 3; ++st)
+#pragma unroll
+          for (int lv = 0; lv < 3; ++lv) {
+            // upper half of the second operand in the low half, of the first in the high half
+            const unsigned w0 = __builtin_amdgcn_perm(bits[st][lv][1], bits[st][lv][0], 0x07060302u);
+            const unsigned w1 = __builtin_amdgcn_perm(bits[st][lv][3], bits[st][lv][2], 0x07060302u);
+            *reinterpret_cast<uint2 *>(&dst[st * 3 + lv][row][k0]) = make_uint2(w0, w1);
+          }
+      };
+      static_assert(C::la == 4 && C::lb == 4, "bfloat16 tiles: four elements per thread per operand");
+      {
+        int i, k;
+        TileLoad<C, TA, TB>::a_coord(tid, 0, i, k);
+        put(Ab[buf], ld.ra, sa, i, k);
+      }
+      {
+        int k, j;
+        TileLoad<C, TA, TB>::b_coord(tid, 0, k, j);
+        put(Bb[buf], ld.rb, sb, j, k);
+      }
+    } else {
+      ld.store(As[buf], Bs[buf], tid, sa, sb);
+    }
+  };
   // add the float32 sums into the float64 totals and restart them
   auto fold = [&] {
 #pragma unroll
     for (int t = 0; t < TN; ++t)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        if constexpr (C::G3) {
+        if constexpr (C::BF) {
+          const double d1 = double(acc[0][t][r]) + double(acc[1][t][r]);
+          const double d2 = double(acc[2][t][r]) + double(acc[3][t][r]);
+          const double d3 = double(acc[4][t][r]) + double(acc[5][t][r]);
+          totr[t][r] += d1 - d2;
+          toti[t][r] += d3 - d1 - d2;
+        } else if constexpr (C::G3) {
           const double d1 = double(acc[0][t][r]), d2 = double(acc[1][t][r]);
           totr[t][r] += d1 - d2;
           toti[t][r] += double(acc[2][t][r]) - d1 - d2;
@@ -258,7 +420,7 @@ cgemm_kernel(GemmParams gp) {
     TileLoad<C, TA, TB> ld;
     if (kbeg < kend) {
       ld.load(a, tid, i0, j0, kbeg, kend);
-      ld.store(As[0], Bs[0], tid, sa, sb);
+      stage_store(ld, 0);
     }
     __syncthreads();
     int buf = 0;
@@ -267,7 +429,7 @@ cgemm_kernel(GemmParams gp) {
       if (more) ld.load(a, tid, i0, j0, k0 + BK, kend);
       multiply(buf);
       after_stage(!more);
-      if (more) ld.store(As[buf ^ 1], Bs[buf ^ 1], tid, sa, sb);
+      if (more) stage_store(ld, buf ^ 1);
       __syncthreads();
       buf ^= 1;
     }
@@ -277,7 +439,7 @@ cgemm_kernel(GemmParams gp) {
     TileLoad<C, TA, TB> l0, l1;
     if (kbeg < kend) {
       l0.load(a, tid, i0, j0, kbeg, kend);
-      l0.store(As[0], Bs[0], tid, sa, sb);
+      stage_store(l0, 0);
     }
     if (kbeg + BK < kend) l1.load(a, tid, i0, j0, kbeg + BK, kend);
     __syncthreads();
@@ -285,7 +447,7 @@ cgemm_kernel(GemmParams gp) {
       if (k0 + 2 * BK < kend) fill.load(a, tid, i0, j0, k0 + 2 * BK, kend);
       multiply(buf);
       after_stage(k0 + BK >= kend);
-      if (k0 + BK < kend) ready.store(As[buf ^ 1], Bs[buf ^ 1], tid, sa, sb);
+      if (k0 + BK < kend) stage_store(ready, buf ^ 1);
       __syncthreads();
     };
     for (int k0 = kbeg; k0 < kend; k0 += 2 * BK) {
@@ -360,14 +522,15 @@ bool use_large(int M, int N, int K) {
 }
 
 // tile configuration: 0 small, 1 large, 2 extra large, 3 small with deeper prefetch, 4 small and
-// 5 large with three products per complex step; `cfg` >= 0 is a choice made by the autotuner,
-// else FR_GEMM_TILE (s, l, x, p, t, u) overrides the default for manual tuning runs
+// 5 large with three products per complex step, 6 small with three products on bfloat16 pieces;
+// `cfg` >= 0 is a choice made by the autotuner, else FR_GEMM_TILE (s, l, x, p, t, u, b)
+// overrides the default for manual tuning runs
 int tile_choice(int M, int N, int K, int cfg) {
   if (cfg >= 0 && cfg < kGemmTiles) return cfg;
   static const int forced = [] {
     const char *v = std::getenv("FR_GEMM_TILE");
     if (!v) return -1;
-    return v[0] == 's' ? 0 : v[0] == 'l' ? 1 : v[0] == 'x' ? 2 : v[0] == 'p' ? 3 : v[0] == 't' ? 4 : v[0] == 'u' ? 5 : -1;
+    return v[0] == 's' ? 0 : v[0] == 'l' ? 1 : v[0] == 'x' ? 2 : v[0] == 'p' ? 3 : v[0] == 't' ? 4 : v[0] == 'u' ? 5 : v[0] == 'b' ? 6 : -1;
   }();
   if (forced >= 0) return forced;
   return use_large(M, N, K) ? 1 : 0;
@@ -382,8 +545,17 @@ int cgemm_split_for(int M, int N, int K, int cfg) {
     case 3: return split_for(tiles_of<CfgP>(M, N), K);
     case 4: return split_for(tiles_of<CfgS3>(M, N), K);
     case 5: return split_for(tiles_of<CfgL3>(M, N), K);
+    case 6: return split_for(tiles_of<CfgB>(M, N), K);
     default: return split_for(tiles_of<CfgS>(M, N), K);
   }
+}
+
+// the bfloat16 tile reads k-contiguous operands through a buffer descriptor with 32-bit byte
+// offsets: both operands' extents must stay below 2^31 bytes
+bool bf_offsets_fit(const CGemmArgs &a) {
+  const long long ea = (a.transA ? (long long)(a.K - 1) * a.lda + a.M : (long long)(a.M - 1) * a.lda + a.K);
+  const long long eb = (a.transB ? (long long)(a.N - 1) * a.ldb + a.K : (long long)(a.K - 1) * a.ldb + a.N);
+  return ea * 8 < (1ll << 31) - 64 && eb * 8 < (1ll << 31) - 64;
 }
 
 hipError_t launch_cgemm_split(const CGemmArgs &a, int split, int cfg_choice, void *partial, hipStream_t stream,
@@ -395,9 +567,10 @@ hipError_t launch_cgemm_split(const CGemmArgs &a, int split, int cfg_choice, voi
   kps = (kps + BK - 1) / BK * BK;
   gp.k_per_split = kps;
   gp.partial = static_cast<double2 *>(partial);
-  const int cfg = tile_choice(a.M, a.N, a.K, cfg_choice);
+  int cfg = tile_choice(a.M, a.N, a.K, cfg_choice);
+  if (cfg == 6 && !bf_offsets_fit(a)) cfg = 4;  // the same products on float32 operands
   char name[64];
-  static const char *const tag[kGemmTiles] = {"S", "L", "X", "P", "S3", "L3"};
+  static const char *const tag[kGemmTiles] = {"S", "L", "X", "P", "S3", "L3", "B"};
   std::snprintf(name, sizeof name, "cgemm%s_%dx%dx%d_s%d", tag[cfg], a.M, a.N, a.K, split);
   hook(stream, name, a.K, 0);
   hipError_t e = cfg == 1 ? launch_cfg<CfgL>(gp, stream)
@@ -405,6 +578,7 @@ hipError_t launch_cgemm_split(const CGemmArgs &a, int split, int cfg_choice, voi
                  : cfg == 3 ? launch_cfg<CfgP>(gp, stream)
                  : cfg == 4 ? launch_cfg<CfgS3>(gp, stream)
                  : cfg == 5 ? launch_cfg<CfgL3>(gp, stream)
+                 : cfg == 6 ? launch_cfg<CfgB>(gp, stream)
                             : launch_cfg<CfgS>(gp, stream);
   hook(stream, name, a.K, 1);
   if (e != hipSuccess || split == 1) return e;

@@ -88,10 +88,11 @@ def test_airy_256_aperture_on_gpu():
     assert np.max(np.abs(cut - np.abs(airy))[core]) <= 1.5e-3
 
 
-@pytest.mark.parametrize("tile,split", [(0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (0, 1), (1, 3),
-                                        (2, 16), (3, 7), (4, 5), (5, 2)])
+@pytest.mark.parametrize("tile,split", [(0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (6, 0), (0, 1),
+                                        (1, 3), (2, 16), (3, 7), (4, 5), (5, 2), (6, 3)])
 def test_every_gemm_tile_configuration_matches_oracle(tile, split, tmp_path):
-    # force one tile configuration (4 and 5: three real products per complex step) and split-K
+    # force one tile configuration (4 and 5: three real products per complex step; 6: the same on
+    # bfloat16 pieces of the operands) and split-K
     # factor (0: the tile's default) on all four GEMMs
     # of a ragged forward and adjoint MFT (through the autotuner's file format) and check both
     # transforms against the oracle; 16 slices of K = 130 leave trailing slices empty
@@ -114,7 +115,7 @@ def test_autotune_file_refuses_a_split_beyond_the_limit(tmp_path):
     f.write_text("gemm 1000 130 1000 0 1 0 17\n")
     with pytest.raises(fb.FrError):
         fb.autotune_load(str(f))
-    f.write_text("gemm_default 6 0\n")   # no tile configuration 6
+    f.write_text("gemm_default 7 0\n")   # no tile configuration 7
     with pytest.raises(fb.FrError):
         fb.autotune_load(str(f))
 

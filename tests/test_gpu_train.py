@@ -223,17 +223,19 @@ def test_broadband_train_batched_full_size():
     assert err <= 1e-9
 
 
-def test_broadband_contrast_with_three_product_gemms(tmp_path):
-    # the same broadband train with every MFT GEMM on the three-product tile (Gauss: the
-    # imaginary part is a difference of three float32 sums, combined in float64 per stage):
-    # the normalised contrast still meets the 1e-9 bar against the oracle
-    banner("broadband train with three-product GEMM tiles")
+@pytest.mark.parametrize("tile", [4, 6])
+def test_broadband_contrast_with_three_product_gemms(tile, tmp_path):
+    # the same broadband train with every MFT GEMM on a three-product tile (Gauss: the
+    # imaginary part is a difference of three float32 sums, combined in float64 per stage;
+    # tile 6 forms the products from exact bfloat16 pieces of the operands): the normalised
+    # contrast still meets the 1e-9 bar against the oracle
+    banner(f"broadband train with three-product GEMM tile {tile}")
     geom, tr, heights, hg = make(1024, 256, 8 / 256, 512, 0.25, 1.0, 48, 1)
     lams = list(synth.wavelengths(21))
     ns = list(synth.padded_sizes(21))
     w = [1.0 / 21] * 21
     f = tmp_path / "g3.txt"
-    f.write_text("gemm_default 4 0\n")
+    f.write_text("gemm_default %d 0\n" % tile)
     fb.autotune_load(str(f))
     try:
         p = _np(fb.propagate_train(tr, lams, ns, w, hg, batched=True))
@@ -244,7 +246,7 @@ def test_broadband_contrast_with_three_product_gemms(tmp_path):
     ref, ref0 = _broadband_oracle()
     assert rel_l2(p, ref) <= 1e-5
     err = np.max(np.abs(p / p0.max() - ref / ref0.max()))
-    banner(f"three-product GEMMs: broadband max |dC| = {err:.3e}")
+    banner(f"three-product GEMM tile {tile}: broadband max |dC| = {err:.3e}")
     assert err <= 1e-9
 
 
