@@ -42,6 +42,7 @@ DET_M, DET_DU = 512, 0.25
 LAMBDA_C = 550e-9
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 
 # HBM bytes per launch from two rocprofv3 --pmc runs of this bench (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch), scaled by what the counters read for a device copy of one 128 MiB plane in
@@ -50,12 +51,12 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 HERE = os.path.dirname(os.path.abspath(__file__))
 MEASURED_TRAFFIC = {
     # kernel: (fetch bytes, write bytes)
-    "cgemmS3_4096x256x4096_s8": (2.0 * 84173.9 * 1024, 131072.0 * 1024),
-    "cgemmS3_4096x4096x256_s1": (2.0 * 38122.4 * 1024, 131072.0 * 1024),
+    "cgemmS3_4096x4096x256_s1": (2.0 * 38125.2 * 1024, 131072.0 * 1024),
+    "cgemmB_4096x256x4096_s2": (2.0 * 83065.0 * 1024, 32768.0 * 1024),
 }
 TRAFFIC_SOURCES = {
-    "paper_1806_06467_amd/csrc/mft.hip": "1e4a5e73838001050c75e8963365c333d72e2643b3c7b2760a2e76db1ebe7f79",
-    "paper_1806_06467_amd/csrc/fr_internal.h": "b49aa7f98e3cc75117d00a2e716cc0c955e3b7e9db516c787d217b3c8b719390",
+    "paper_1806_06467_amd/csrc/mft.hip": "e18f0dbd64b8f4bb18e0312be1bdcaea563ee622d1aab7a4f5d9e24f8458aeaf",
+    "paper_1806_06467_amd/csrc/fr_internal.h": "b3666a943644d3c73a368da0c5416f6d6c58d760565c0fa4f759323b4461f064",
 }
 
 
@@ -244,7 +245,8 @@ def main():
     #   adjoint row sweep: read + write the field, the same maps (conjugate optic);
     #   column sweeps: read + write the field and the DM map after the step;
     #   dm_grad_T: read E and B (last DM) or B, the pupil DM map and the windows (pupil DM);
-    #   cgemm M x N x K: 8 M N K flops.
+    #   cgemm M x N x K: 8 M N K flops (float32 MFMA tiles); the bfloat16-split tile executes
+    #     48 M N K flops on the bf16 matrix cores.
     n2, nd2 = N * N, N_D * N_D
     per_plane = {
         "row_sweep": 8 * n2 + 4 * n2 + 8 * nd2,
@@ -263,6 +265,20 @@ def main():
             return {"bound": "hbm", "kernel": name, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nbytes,
                     "avg_launch_ms": ms}
+        if name.startswith("cgemmB"):
+            # bfloat16-split tile: three real products (Gauss), each from 8 bfloat16 piece
+            # products on the bf16 matrix cores: 3 x 8 x 2 M N K executed flops, priced against
+            # the dense bf16 MFMA peak; the conventional 8 M N K complex count against the FP32
+            # MFMA peak is reported beside it
+            m, n_, k = (int(x) for x in name.split("_")[1].split("x"))
+            flops = 48.0 * m * n_ * k
+            tf = flops / (ms * 1e-3) / 1e12
+            tf32 = 8.0 * m * n_ * k / (ms * 1e-3) / 1e12
+            return {"bound": "mfma", "kernel": name, "achieved": tf, "peak": BF16_MFMA_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": tf / BF16_MFMA_PEAK_TFLOPS,
+                    "traffic": measured_traffic(name), "flops_per_launch": flops, "avg_launch_ms": ms,
+                    "dtype": "bf16 pieces of f32 operands",
+                    "complex_8mnk_tflops": tf32, "complex_8mnk_frac_of_fp32_peak": tf32 / FP32_MFMA_PEAK_TFLOPS}
         if name.startswith("cgemm"):
             m, n_, k = (int(x) for x in name.split("_")[1].split("x"))
             flops = 8.0 * m * n_ * k
