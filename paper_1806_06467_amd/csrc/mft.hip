@@ -11,7 +11,8 @@
 // tiles) or 64 x 64 for small outputs. Two or three blocks share a compute unit; as their
 // barriers are independent, one block's float64 folds overlap another block's MFMAs. Operand tiles 16 deep are staged through double-buffered LDS, the next tile's
 // global loads in flight while the current one is multiplied (one barrier per tile). Each
-// 16-deep tile (32-deep group for the three-product tiles) is summed by the MFMAs in float32 and
+// 16-deep tile (32-deep group for the float32 three-product tiles, 128-deep for the bfloat16-split
+// tile, whose leading sum rounds once per 16 k) is summed by the MFMAs in float32 and
 // then added into float64 totals (the long Fourier sums of the coronagraph cancel to tiny values
 // in the dark hole, so their rounding must not grow with K); the epilogue (alpha, beta, mask,
 // intensity) runs in float64.
@@ -96,10 +97,7 @@ using CfgP = Cfg<2, 2, 1, 2>;  // 64 x 64, 256 threads, two stages of loads in f
 using CfgS3 = Cfg<2, 2, 1, 1, true, 2>;  // 64 x 64
 using CfgL3 = Cfg<2, 2, 2, 1, true, 2>;  // 64 x 128
 // three products on bfloat16 pieces, 64 x 64
-#ifndef FR_BF_FOLD
-#define FR_BF_FOLD 4
-#endif
-using CfgB = Cfg<2, 2, 1, 1, true, FR_BF_FOLD, true>;
+using CfgB = Cfg<2, 2, 1, 1, true, 8, true>;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
