@@ -140,3 +140,22 @@ def test_default_gemm_choice_applies_to_untuned_shapes(tmp_path):
     finally:
         f.write_text("gemm_default -1 0\n")
         fb.autotune_load(str(f))
+
+
+def test_bfloat16_split_tile_on_8192_field(tmp_path):
+    # the bfloat16-split tile reads the 512 MiB field through 32-bit buffer offsets: the
+    # occulter MFT of an 8192^2 field (the large train's grid) against the oracle, every GEMM on
+    # that tile
+    n, nd, m, du = 8192, 2048.0, 256, 8 / 256
+    banner("bfloat16-split tile: occulter mft 8192 -> 256")
+    f = tmp_path / "bf.txt"
+    f.write_text("gemm_default 6 0\n")
+    fb.autotune_load(str(f))
+    try:
+        e = synth.random_field(n, 21)
+        got = to_np(fb.mft_forward(to_gpu(e), nd, m, du))
+    finally:
+        f.write_text("gemm_default -1 0\n")
+        fb.autotune_load(str(f))
+    ref = oracle.mft(f32(e), nd, m, du)
+    assert rel_l2(got, ref) <= TOL
