@@ -251,9 +251,10 @@ int Ctx::lens(int n, double dx, double lam, double f, hipStream_t s, const float
   return st;
 }
 
-// W[k][m] = exp(-2 pi i (k - M/2)(m - N/2) du / n_d), M x N row-major
-int Ctx::mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out) {
-  TableKey key{kMft, m_out, uint64_t(n_in), bits(n_d), bits(du), 0};
+// W[k][m] = exp(-2 pi i (k - M/2)(m - N/2) du / n_d), M x N row-major (or its transpose, N x M)
+int Ctx::mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out,
+                    bool transposed) {
+  TableKey key{kMft, m_out, uint64_t(n_in), bits(n_d), bits(du), transposed ? 1u : 0u};
   if (auto it = tables.find(key); it != tables.end()) {
     *out = static_cast<const float2 *>(it->second);
     return FR_OK;
@@ -264,7 +265,7 @@ int Ctx::mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, c
     const long long a = k - m_out / 2;
     for (int m = 0; m < n_in; ++m) {
       const long long b = m - n_in / 2;
-      h[size_t(k) * n_in + m] = turn_to_c64(double(a * b) * coef, 1.0);
+      h[transposed ? size_t(m) * m_out + k : size_t(k) * n_in + m] = turn_to_c64(double(a * b) * coef, 1.0);
     }
   }
   void *d;
@@ -356,24 +357,26 @@ int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out,
 int mft_adjoint_impl(Ctx *ctx, const float2 *in, int m_in, int ld_in, float2 *out, int n_out,
                      int ld_out, double n_d, double du, float alpha, float beta,
                      const float2 *cin, int ld_cin, const float *mask, void *ws, hipStream_t s) {
-  const float2 *w;
-  int st = ctx->mft_matrix(m_in, n_out, n_d, du, s, &w);
+  // with Wt = W^T (n_out x m_in): conj(W) = conj(Wt)^T and W^H = conj(Wt), so both GEMMs read
+  // the matrix with k contiguous
+  const float2 *wt;
+  int st = ctx->mft_matrix(m_in, n_out, n_d, du, s, &wt, true);
   if (st != FR_OK) return st;
   float2 *t = static_cast<float2 *>(ws);
   void *partial = static_cast<char *>(ws) + mft_t_bytes(n_out, m_in);
   const size_t pcap = size_t(kMaxSplit) * n_out * m_in;
-  // T = E_B conj(W)  (m_in x n_out)
+  // T = E_B conj(W) = E_B conj(Wt)^T  (m_in x n_out)
   CGemmArgs g1 = gemm_args();
   g1.M = m_in; g1.N = n_out; g1.K = m_in;
   g1.A = in; g1.lda = ld_in;
-  g1.B = w; g1.ldb = n_out; g1.conjB = 1;
+  g1.B = wt; g1.ldb = m_in; g1.transB = 1; g1.conjB = 1;
   g1.C = t; g1.ldc = n_out;
   hipError_t e = run_gemm(ctx, g1, partial, pcap, s);
   if (e != hipSuccess) return record_hip(e);
-  // out = alpha (du / n_d) W^H T + beta cin (* mask)
+  // out = alpha (du / n_d) conj(Wt) T + beta cin (* mask)
   CGemmArgs g2 = gemm_args();
   g2.M = n_out; g2.N = n_out; g2.K = m_in;
-  g2.A = w; g2.lda = n_out; g2.transA = 1; g2.conjA = 1;
+  g2.A = wt; g2.lda = m_in; g2.conjA = 1;
   g2.B = t; g2.ldb = n_out;
   g2.C = out; g2.ldc = ld_out;
   g2.alpha_re = double(alpha) * (du / n_d);

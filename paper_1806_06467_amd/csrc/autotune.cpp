@@ -151,8 +151,8 @@ int tune_mft(Ctx *ctx, int n, int m, hipStream_t s) {
   };
   add(n, m, n, a, n, 0, w, n, 1, t, m);  // forward: T = E W^T
   add(m, m, n, w, n, 0, t, m, 0, c, m);  // forward: W T
-  add(m, n, m, a, m, 0, w, n, 0, t, n);  // adjoint: E_B conj(W)
-  add(n, n, m, w, n, 1, t, n, 0, c, n);  // adjoint: W^H T
+  add(m, n, m, a, m, 0, w, m, 1, t, n);  // adjoint: E_B conj(Wt)^T (Wt = W^T, n x m)
+  add(n, n, m, w, m, 0, t, n, 0, c, n);  // adjoint: conj(Wt) T
   for (CGemmArgs &g : shapes) {
     Ctx::GemmChoice best{0, 0};
     float best_ms = -1.f;

@@ -69,7 +69,8 @@ struct Ctx {
   GemmChoice gemm_choice(const CGemmArgs &g) const;
   int transfer(int n, double dx, double lam, double z, hipStream_t s, const float2 **out);
   int lens(int n, double dx, double lam, double f, hipStream_t s, const float2 **out);
-  int mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out);
+  int mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out,
+                 bool transposed = false);
   int dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **out);
 };
 

@@ -98,7 +98,7 @@ def test_every_gemm_tile_configuration_matches_oracle(tile, split, tmp_path):
     # transforms against the oracle; 16 slices of K = 130 leave trailing slices empty
     n, m, n_d, du = 1000, 130, 500.0, 0.3
     banner(f"mft with GEMM tile configuration {tile}, split {split}")
-    shapes = [(n, m, n, 0, 1), (m, m, n, 0, 0), (m, n, m, 0, 0), (n, n, m, 1, 0)]
+    shapes = [(n, m, n, 0, 1), (m, m, n, 0, 0), (m, n, m, 0, 1), (n, n, m, 0, 0)]
     f = tmp_path / "tiles.txt"
     f.write_text("".join("gemm %d %d %d %d %d %d %d\n" % (s + (tile, split)) for s in shapes))
     fb.autotune_load(str(f))
