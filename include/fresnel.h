@@ -180,7 +180,9 @@ int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda,
  *   FR_TUNE_MFT, a = pupil-side edge n, b = focal edge m: the GEMM tile configuration and split-K
  *     factor of each of the two GEMMs of mft_forward (n -> m) and mft_adjoint (m -> n). Tiles
  *     0-3 form each complex k-step from four real products, tiles 4-5 from three (Gauss; the
- *     three sums are combined in float64 at every 16-deep stage).
+ *     three sums are combined in float64 at every 32-deep group), tile 6 from four real products
+ *     each summed from six products of exact bfloat16 pieces of the float32 operands on the
+ *     bf16 matrix cores.
  * Every candidate computes the same result up to the order of float32 roundings. The call
  * allocates scratch device memory for its duration, synchronises `stream`, and is not meant for
  * a hot loop or a graph capture. Errors: FR_EINVAL, FR_EUNSUPPORTED, FR_ENOMEM, FR_EHIP.

@@ -122,8 +122,8 @@ struct CGemmArgs {
 constexpr int kMaxSplit = 16;
 // cfg: tile configuration (0 small 64 x 64, 1 large 64 x 128, 2 extra large 128 x 128, 3 small
 // with two stages of operand loads in flight, 4 small and 5 large with three real products per
-// complex step, 6 small with three products on bfloat16 pieces of the operands), or -1 for the
-// default choice by shape
+// complex step, 6 small with the four real products formed from bfloat16 pieces of the
+// operands on the bf16 matrix cores), or -1 for the default choice by shape
 constexpr int kGemmTiles = 7;
 int cgemm_split_for(int M, int N, int K, int cfg);
 hipError_t launch_cgemm_split(const CGemmArgs &a, int split, int cfg, void *partial, hipStream_t stream,

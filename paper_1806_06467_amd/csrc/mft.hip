@@ -1,21 +1,23 @@
-// Matrix Fourier transform as two complex GEMMs on FP32 MFMA (Sec. 1.1: the semi-analytic
-// coronagraph of Soummer et al. uses matrix DFTs; Sec. 2.3: the sin/cos arrays of that
-// matrix DFT). Unlike the FFT sweeps this step really is a dense contraction, so it runs on
-// the matrix cores.
+// Matrix Fourier transform as two complex GEMMs on the matrix cores (Sec. 1.1: the
+// semi-analytic coronagraph of Soummer et al. uses matrix DFTs; Sec. 2.3: the sin/cos arrays of
+// that matrix DFT). Unlike the FFT sweeps this step really is a dense contraction, so it runs on
+// MFMA.
 //
 // Complex product with real MFMA: per complex k-step, Cr += Ar Br - Ai Bi and
 // Ci += Ar Bi + Ai Br (four v_mfma_f32_32x32x2f32 per 32 x 32 tile, fragments from LDS), or
 // with three products (Gauss) P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), Cr = P1 - P2,
-// Ci = P3 - P1 - P2, the differences taken in float64 at each fold.
+// Ci = P3 - P1 - P2, the differences taken in float64 at each fold; or (tile 6) the four real
+// products formed on v_mfma_f32_32x32x16_bf16 from exact bfloat16 pieces of the float32
+// operands (cgemm_bf_kernel).
 // Block tile 64 x 128 (four waves in 2 x 2, each a 32 x 64 piece made of two 32 x 32 MFMA
 // tiles) or 64 x 64 for small outputs. Two or three blocks share a compute unit; as their
-// barriers are independent, one block's float64 folds overlap another block's MFMAs. Operand tiles 16 deep are staged through double-buffered LDS, the next tile's
-// global loads in flight while the current one is multiplied (one barrier per tile). Each
-// 16-deep tile (32-deep group for the float32 three-product tiles, 128-deep for the bfloat16-split
-// tile, whose leading sum rounds once per 16 k) is summed by the MFMAs in float32 and
-// then added into float64 totals (the long Fourier sums of the coronagraph cancel to tiny values
-// in the dark hole, so their rounding must not grow with K); the epilogue (alpha, beta, mask,
-// intensity) runs in float64.
+// barriers are independent, one block's float64 folds overlap another block's MFMAs. Operand
+// tiles 16 deep are staged through double-buffered LDS, the next tile's global loads in flight
+// while the current one is multiplied (one barrier per tile). Each 16-deep tile (32-deep group
+// for the float32 three-product tiles, 128-deep for the bfloat16-split tile, whose sums round
+// once per 16 k) is summed by the MFMAs in float32 and then added into float64 totals (the long
+// Fourier sums of the coronagraph cancel to tiny values in the dark hole, so their rounding must
+// not grow with K); the epilogue (alpha, beta, mask, intensity) runs in float64.
 // Operands may be transposed (template) and/or conjugated (on the LDS store). Outputs with few
 // tiles and long K are split over K; the float64 partial sums go to the workspace and one
 // epilogue kernel adds them in a fixed order (deterministic).
@@ -23,6 +25,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "fr_internal.h"
 
@@ -68,20 +71,14 @@ __device__ __forceinline__ void epilogue(const CGemmArgs &a, int i, int j, doubl
 // operand tiles of the next PD stages are in flight while a stage is multiplied. G3: three real
 // products per complex k-step instead of four (Gauss): P1 = sum Ar Br, P2 = sum Ai Bi,
 // P3 = sum (Ar + Ai)(Br + Bi), combined per stage in float64 as Cr = P1 - P2, Ci = P3 - P1 - P2.
-template <int WM_, int WN_, int TN_, int PD_ = 1, bool G3_ = false, int FOLD_ = 1, bool BF_ = false>
+template <int WM_, int WN_, int TN_, int PD_ = 1, bool G3_ = false, int FOLD_ = 1>
 struct Cfg {
   static constexpr int WM = WM_, WN = WN_, TN = TN_, PD = PD_;
   static constexpr bool G3 = G3_;
   static constexpr int FOLD = FOLD_;  // 16-deep stages summed in float32 between float64 folds
-  // BF: the three real operand streams (re, im, re + im) are split exactly into three bfloat16
-  // pieces each (hi, mid below 2^-7 and lo below 2^-15 of the value) and multiplied on
-  // v_mfma_f32_32x32x16_bf16: every piece product except lo lo (below 2^-30 of the leading
-  // one), each exact in float32
-  static constexpr bool BF = BF_;
-  static_assert(!BF || (G3 && TN == 1), "bfloat16 split tiles: three products, 32 x 32 per wave");
   // waves per SIMD the register budget targets (the three-product 32 x 64 wave tile holds three
   // float32 and two float64 accumulator sets, so it gets the whole register file)
-  static constexpr int waves = BF ? 2 : TN == 1 ? 3 : (G3 ? 1 : 2);
+  static constexpr int waves = TN == 1 ? 3 : (G3 ? 1 : 2);
   static constexpr int BM = 32 * WM, BN = 32 * TN * WN;
   static constexpr int threads = 64 * WM * WN;
   static constexpr int la = BM * BK / threads;  // A elements per thread per tile
@@ -96,8 +93,6 @@ using CfgP = Cfg<2, 2, 1, 2>;  // 64 x 64, 256 threads, two stages of loads in f
 // three products per complex step, float32 sums over 32-deep groups between float64 folds
 using CfgS3 = Cfg<2, 2, 1, 1, true, 2>;  // 64 x 64
 using CfgL3 = Cfg<2, 2, 2, 1, true, 2>;  // 64 x 128
-// three products on bfloat16 pieces, 64 x 64
-using CfgB = Cfg<2, 2, 1, 1, true, 8, true>;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -106,18 +101,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 template <class C, bool TA, bool TB>
 struct TileLoad {
   float2 ra[C::la], rb[C::lb];
-  // For the bfloat16 tiles every thread holds la (lb) consecutive k of one row (column), so that
-  // each of its pieces goes to LDS as one 8-byte write: an operand stored with i (j) contiguous
-  // keeps its loads contiguous along i (j) for every r; one stored with k contiguous is read as
-  // 32-byte runs (four threads per 16-deep row).
-  static constexpr int kRun = BK / 4;  // threads per row of a k-contiguous bfloat16 operand
   __device__ __forceinline__ static void a_coord(int t, int r, int &i, int &k) {
     if (TA) {  // A stored K x M: contiguous along i
       i = t % C::BM;
-      k = C::BF ? (t / C::BM) * C::la + r : t / C::BM + (C::threads / C::BM) * r;
-    } else if (C::BF) {
-      i = t / kRun;
-      k = (t % kRun) * 4 + r;
+      k = t / C::BM + (C::threads / C::BM) * r;
     } else {   // A stored M x K: contiguous along k
       k = t % BK;
       i = t / BK + (C::threads / BK) * r;
@@ -125,77 +112,29 @@ struct TileLoad {
   }
   __device__ __forceinline__ static void b_coord(int t, int r, int &k, int &j) {
     if (TB) {  // B stored N x K: contiguous along k
-      if (C::BF) {
-        j = t / kRun;
-        k = (t % kRun) * 4 + r;
-      } else {
-        k = t % BK;
-        j = t / BK + (C::threads / BK) * r;
-      }
+      k = t % BK;
+      j = t / BK + (C::threads / BK) * r;
     } else {   // B stored K x N: contiguous along j
       j = t % C::BN;
-      k = C::BF ? (t / C::BN) * C::lb + r : t / C::BN + (C::threads / C::BN) * r;
+      k = t / C::BN + (C::threads / C::BN) * r;
     }
-  }
-  // four consecutive complex values base[e .. e + 3] (32 bytes, 8-byte aligned) as two 16-byte
-  // buffer loads; the descriptor is the operand's (wave-uniform), e the per-lane element offset
-  // (operands up to 2^28 elements, so the byte offset fits 32 bits)
-  __device__ __forceinline__ static void load_run(const float2 *base, size_t e, float2 *dst) {
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(base), (short)0, 0x7fffffff, 0x00020000);
-    typedef float f4 __attribute__((ext_vector_type(4)));
-    const unsigned o = unsigned(e) * 8u;
-    const f4 lo = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0));
-    const f4 hi = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u, 0, 0));
-    dst[0] = make_float2(lo[0], lo[1]);
-    dst[1] = make_float2(lo[2], lo[3]);
-    dst[2] = make_float2(hi[0], hi[1]);
-    dst[3] = make_float2(hi[2], hi[3]);
   }
   __device__ __forceinline__ void load(const CGemmArgs &a, int t, int i0, int j0, int k0, int kend) {
-    if constexpr (C::BF && !TA) {
-      static_assert(C::la == 4, "one 4-run per thread");
+#pragma unroll
+    for (int r = 0; r < C::la; ++r) {
       int i, k;
-      a_coord(t, 0, i, k);
+      a_coord(t, r, i, k);
       const int gi = i0 + i, gk = k0 + k;
-      if (gi < a.M && gk + 4 <= kend) {
-        load_run(a.A, size_t(gi) * a.lda + gk, ra);
-      } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          ra[r] = (gi < a.M && gk + r < kend) ? a.A[size_t(gi) * a.lda + gk + r] : make_float2(0.f, 0.f);
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < C::la; ++r) {
-        int i, k;
-        a_coord(t, r, i, k);
-        const int gi = i0 + i, gk = k0 + k;
-        ra[r] = (gi < a.M && gk < kend) ? (TA ? a.A[size_t(gk) * a.lda + gi] : a.A[size_t(gi) * a.lda + gk])
-                                        : make_float2(0.f, 0.f);
-      }
+      ra[r] = (gi < a.M && gk < kend) ? (TA ? a.A[size_t(gk) * a.lda + gi] : a.A[size_t(gi) * a.lda + gk])
+                                      : make_float2(0.f, 0.f);
     }
-    if constexpr (C::BF && TB) {
-      static_assert(C::lb == 4, "one 4-run per thread");
+#pragma unroll
+    for (int r = 0; r < C::lb; ++r) {
       int k, j;
-      b_coord(t, 0, k, j);
+      b_coord(t, r, k, j);
       const int gk = k0 + k, gj = j0 + j;
-      if (gj < a.N && gk + 4 <= kend) {
-        load_run(a.B, size_t(gj) * a.ldb + gk, rb);
-      } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          rb[r] = (gj < a.N && gk + r < kend) ? a.B[size_t(gj) * a.ldb + gk + r] : make_float2(0.f, 0.f);
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < C::lb; ++r) {
-        int k, j;
-        b_coord(t, r, k, j);
-        const int gk = k0 + k, gj = j0 + j;
-        rb[r] = (gj < a.N && gk < kend) ? (TB ? a.B[size_t(gj) * a.ldb + gk] : a.B[size_t(gk) * a.ldb + gj])
-                                        : make_float2(0.f, 0.f);
-      }
+      rb[r] = (gj < a.N && gk < kend) ? (TB ? a.B[size_t(gj) * a.ldb + gk] : a.B[size_t(gk) * a.ldb + gj])
+                                      : make_float2(0.f, 0.f);
     }
   }
   __device__ __forceinline__ void store(float2 (*As)[C::BM + PAD], float2 (*Bs)[C::BN + PAD], int t, float sa,
@@ -215,42 +154,39 @@ struct TileLoad {
   }
 };
 
+// Blocks are dealt round-robin to the 8 XCDs (each with its own L2). Renumber them so that each
+// XCD runs a contiguous range of tiles; inside a K slice the range is walked in groups of
+// kGroupRows tile rows, column by column, so that the blocks resident on an XCD at one time share
+// a few operand row panels of A and column panels of B in that XCD's L2 (walking whole tile rows
+// instead streams all of B once per tile row).
+__device__ __forceinline__ void block_tile(int &bx, int &by, int &bz) {
+  constexpr int kGroupRows = 8;
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy * gridDim.z;
+  const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int tile = total % 8 == 0 ? (lin & 7) * (total >> 3) + (lin >> 3) : lin;
+  bz = tile / (gx * gy);
+  const int t = tile % (gx * gy);
+  const int g = t / (kGroupRows * gx);             // group of tile rows
+  const int rows = min(kGroupRows, gy - g * kGroupRows);
+  const int u = t % (kGroupRows * gx);             // position inside the group
+  bx = u / rows;
+  by = g * kGroupRows + u % rows;
+}
+
 template <class C, bool TA, bool TB>
 __global__ void __launch_bounds__(C::threads) __attribute__((amdgpu_waves_per_eu(C::waves)))
 cgemm_kernel(GemmParams gp) {
   static_assert(C::threads <= 512, "block too large");
   constexpr int TN = C::TN;
   const CGemmArgs &a = gp.a;
-  __shared__ float2 As[C::BF ? 1 : 2][BK][C::BM + PAD];
-  __shared__ float2 Bs[C::BF ? 1 : 2][BK][C::BN + PAD];
-  // bfloat16 pieces, [buffer][stream * 3 + level][row or column][k], k contiguous so that a
-  // lane's eight k values of one piece are one 16-byte read
-  constexpr int kPieces = 9;
-  __shared__ __attribute__((aligned(16))) unsigned short Ab[C::BF ? 2 : 1][C::BF ? kPieces : 1][C::BF ? C::BM : 1][BK];
-  __shared__ __attribute__((aligned(16))) unsigned short Bb[C::BF ? 2 : 1][C::BF ? kPieces : 1][C::BF ? C::BN : 1][BK];
+  __shared__ float2 As[2][BK][C::BM + PAD];
+  __shared__ float2 Bs[2][BK][C::BN + PAD];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = wave / C::WN, wn = wave % C::WN;
-  // Blocks are dealt round-robin to the 8 XCDs (each with its own L2). Renumber them so that
-  // each XCD runs a contiguous range of tiles; inside a K slice the range is walked in groups of
-  // kGroupRows tile rows, column by column, so that the blocks resident on an XCD at one time
-  // share a few operand row panels of A and column panels of B in that XCD's L2 (walking whole
-  // tile rows instead streams all of B once per tile row).
   int bx, by, bz;
-  {
-    constexpr int kGroupRows = 8;
-    const int gx = gridDim.x, gy = gridDim.y;
-    const int total = gx * gy * gridDim.z;
-    const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    const int tile = total % 8 == 0 ? (lin & 7) * (total >> 3) + (lin >> 3) : lin;
-    bz = tile / (gx * gy);
-    const int t = tile % (gx * gy);
-    const int g = t / (kGroupRows * gx);             // group of tile rows
-    const int rows = min(kGroupRows, gy - g * kGroupRows);
-    const int u = t % (kGroupRows * gx);             // position inside the group
-    bx = u / rows;
-    by = g * kGroupRows + u % rows;
-  }
+  block_tile(bx, by, bz);
   const int i0 = by * C::BM, j0 = bx * C::BN;
   const int kbeg = bz * gp.k_per_split;
   const int kend = min(a.K, kbeg + gp.k_per_split);
@@ -263,10 +199,8 @@ cgemm_kernel(GemmParams gp) {
   const int arow = wm * 32 + (lane & 31);
   const int bcol = wn * 32 * TN + (lane & 31);
   const int kl = lane >> 5;
-  // float32 sums of the current fold group: (P1, P2, P3) for three products, (Cr, Ci) else; the
-  // bfloat16 tile keeps each P in two sums, the hi hi products and the (at least 2^-7 smaller)
-  // correction products, so that the correction terms are not rounded at the scale of the total
-  constexpr int kSums = C::BF ? 6 : (C::G3 ? 3 : 2);
+  // float32 sums of the current fold group: (P1, P2, P3) for three products, (Cr, Ci) else
+  constexpr int kSums = C::G3 ? 3 : 2;
   floatx16 acc[kSums][TN];
   auto clear = [&] {
 #pragma unroll
@@ -277,33 +211,6 @@ cgemm_kernel(GemmParams gp) {
   clear();
   // one stage: multiply the LDS tile `buf` into the float32 sums
   auto multiply = [&](int buf) {
-    if constexpr (C::BF) {
-      // lane: row (column) lane % 32 of the wave's piece, k = 8 (lane / 32) .. + 7
-      const int kh = 8 * (lane >> 5);
-      bf16x8 ap[3][3], bp[3][3];
-#pragma unroll
-      for (int st = 0; st < 3; ++st)
-#pragma unroll
-        for (int lv = 0; lv < 3; ++lv) {
-          ap[st][lv] = *reinterpret_cast<const bf16x8 *>(&Ab[buf][st * 3 + lv][arow][kh]);
-          bp[st][lv] = *reinterpret_cast<const bf16x8 *>(&Bb[buf][st * 3 + lv][bcol][kh]);
-        }
-      // eight piece products: the seven corrections smallest first (lo mid, mid lo, lo hi,
-      // mid mid, hi lo, mid hi, hi mid) into the correction sum, then hi hi into the main sum;
-      // only lo lo (below 2^-28 of the leading product) is left out. The three streams' chains
-      // are interleaved so that consecutive MFMAs are independent.
-      constexpr int la_[7] = {2, 1, 2, 1, 0, 1, 0}, lb_[7] = {1, 2, 0, 1, 2, 0, 1};
-#pragma unroll
-      for (int q = 0; q < 7; ++q)
-#pragma unroll
-        for (int st = 0; st < 3; ++st)
-          acc[2 * st + 1][0] =
-              __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[st][la_[q]], bp[st][lb_[q]], acc[2 * st + 1][0], 0, 0, 0);
-#pragma unroll
-      for (int st = 0; st < 3; ++st)
-        acc[2 * st][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[st][0], bp[st][0], acc[2 * st][0], 0, 0, 0);
-      return;
-    }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
       const float2 av = As[buf][kk + kl][arow];
@@ -332,71 +239,15 @@ cgemm_kernel(GemmParams gp) {
       }
     }
   };
-  // operand tile from the loader's registers into LDS: float32 complex, or for BF the three
-  // streams (re, im, re + im; imaginary parts conjugated as asked) in bfloat16 pieces
-  auto stage_store = [&](const TileLoad<C, TA, TB> &ld, int buf) {
-    if constexpr (C::BF) {
-      // one operand's elements: pieces of the three streams, as 2-byte writes (k contiguous
-      // across lanes) or, when a thread holds n consecutive k of one row, as one 2n-byte write
-      // the four consecutive-k values v[0..3] of one row. Each stream value x = hi + mid + lo
-      // exactly, each piece a bfloat16 (the upper 16 bits of a float32 bit pattern): hi and mid
-      // by truncation, the remainders r = x - hi and r - mid being exact in float32, lo holding
-      // the last at most eight significant bits. Pairs of upper halves are packed by one byte
-      // permute each and written as one 8-byte store per piece.
-      auto put = [&](unsigned short(*dst)[C::BF ? C::BM : 1][BK], const float2 *v, float sc, int row, int k0) {
-        unsigned bits[3][3][4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float re = v[r].x, im = sc * v[r].y;
-          const float x3[3] = {re, im, re + im};
-#pragma unroll
-          for (int st = 0; st < 3; ++st) {
-            const unsigned xb = __float_as_uint(x3[st]);
-            const float rr = x3[st] - __uint_as_float(xb & 0xffff0000u);
-            const unsigned rb = __float_as_uint(rr);
-            bits[st][0][r] = xb;
-            bits[st][1][r] = rb;
-            bits[st][2][r] = __float_as_uint(rr - __uint_as_float(rb & 0xffff0000u));
-          }
-        }
-#pragma unroll
-        for (int st = 0; st < 3; ++st)
-#pragma unroll
-          for (int lv = 0; lv < 3; ++lv) {
-            // upper half of the second operand in the low half, of the first in the high half
-            const unsigned w0 = __builtin_amdgcn_perm(bits[st][lv][1], bits[st][lv][0], 0x07060302u);
-            const unsigned w1 = __builtin_amdgcn_perm(bits[st][lv][3], bits[st][lv][2], 0x07060302u);
-            *reinterpret_cast<uint2 *>(&dst[st * 3 + lv][row][k0]) = make_uint2(w0, w1);
-          }
-      };
-      static_assert(C::la == 4 && C::lb == 4, "bfloat16 tiles: four elements per thread per operand");
-      {
-        int i, k;
-        TileLoad<C, TA, TB>::a_coord(tid, 0, i, k);
-        put(Ab[buf], ld.ra, sa, i, k);
-      }
-      {
-        int k, j;
-        TileLoad<C, TA, TB>::b_coord(tid, 0, k, j);
-        put(Bb[buf], ld.rb, sb, j, k);
-      }
-    } else {
-      ld.store(As[buf], Bs[buf], tid, sa, sb);
-    }
-  };
+  // operand tile from the loader's registers into LDS (imaginary parts conjugated as asked)
+  auto stage_store = [&](const TileLoad<C, TA, TB> &ld, int buf) { ld.store(As[buf], Bs[buf], tid, sa, sb); };
   // add the float32 sums into the float64 totals and restart them
   auto fold = [&] {
 #pragma unroll
     for (int t = 0; t < TN; ++t)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        if constexpr (C::BF) {
-          const double d1 = double(acc[0][t][r]) + double(acc[1][t][r]);
-          const double d2 = double(acc[2][t][r]) + double(acc[3][t][r]);
-          const double d3 = double(acc[4][t][r]) + double(acc[5][t][r]);
-          totr[t][r] += d1 - d2;
-          toti[t][r] += d3 - d1 - d2;
-        } else if constexpr (C::G3) {
+        if constexpr (C::G3) {
           const double d1 = double(acc[0][t][r]), d2 = double(acc[1][t][r]);
           totr[t][r] += d1 - d2;
           toti[t][r] += double(acc[2][t][r]) - d1 - d2;
@@ -471,6 +322,241 @@ cgemm_kernel(GemmParams gp) {
   }
 }
 
+// The bfloat16-split tile (tile 6). Each float32 operand value x (real and imaginary parts, the
+// imaginary part's sign flipped when the operand is conjugated) is split exactly into three
+// bfloat16 pieces x = hi + mid + lo by rounding to nearest: hi = bf16(x), mid = bf16(x - hi),
+// lo = x - hi - mid. Both differences are exact in float32 (each operand pair is within a factor
+// of two), and lo has at most eight significant bits, so it is a bfloat16 too; |mid| <= 2^-8 |x|
+// and |lo| <= 2^-16 |x|. A real product a b is the sum of the nine piece products, each exact in
+// float32; the tile forms the six down to 2^-16 |a b| (hi hi, hi mid, mid hi, mid mid, hi lo,
+// lo hi) on v_mfma_f32_32x32x16_bf16, which sums each 16-term dot fused and rounds once. The
+// three left out (mid lo, lo mid, lo lo) are below 2^-23 |a b| together and, as round-to-nearest
+// residuals, of either sign. The complex product takes four real products per k
+// (Cr = Ar Br - Ai Bi, Ci = Ar Bi + Ai Br; -Ai by a sign flip of its pieces), so only two real
+// streams per operand are split. The hi hi products and the correction products go to separate
+// float32 sums, so that the corrections are never rounded at the scale of the running total;
+// every kBfFold stages the sums are added into float64 totals.
+// Block tile 64 x 64, four waves of 32 x 32, 16-deep stages through double-buffered LDS. Each
+// thread loads four consecutive k of one operand row per stage, two stages ahead of the one
+// being multiplied, and while the MFMAs of stage s run it splits stage s + 1 and writes its
+// pieces to the other LDS buffer (one 8-byte store per piece, contiguous across the wave).
+constexpr int kBfRows = 64;     // block tile edge (M and N)
+constexpr int kBfThreads = 256;
+constexpr int kBfFold = 8;      // 16-deep stages per float64 fold
+constexpr int kBfPieces = 6;    // re hi, re mid, re lo, im hi, im mid, im lo
+
+struct BfRegs {
+  float2 a[4], b[4];
+};
+
+// LDS row of 16 k as two 8-k halves; rows alternate the halves' order in a pattern that keeps a
+// wave's 16-byte fragment reads free of bank conflicts
+__device__ __forceinline__ int bf_swz(int row) { return (((row >> 2) ^ (row >> 3)) & 1) * 8; }
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
+// two values as packed bfloat16 pairs of their pieces (first value in the low half), x = hi +
+// mid + lo exactly for each (see above)
+__device__ __forceinline__ void bf_split2(float x0, float x1, unsigned &hi, unsigned &mid, unsigned &lo) {
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(floatx2{x0, x1}, bf16x2));
+  const float r0 = x0 - __uint_as_float(hi << 16), r1 = x1 - __uint_as_float(hi & 0xffff0000u);
+  mid = __builtin_bit_cast(unsigned, __builtin_convertvector(floatx2{r0, r1}, bf16x2));
+  const float l0 = r0 - __uint_as_float(mid << 16), l1 = r1 - __uint_as_float(mid & 0xffff0000u);
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(floatx2{l0, l1}, bf16x2));
+}
+
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(kBfThreads) __attribute__((amdgpu_waves_per_eu(2)))
+cgemm_bf_kernel(GemmParams gp) {
+  const CGemmArgs &a = gp.a;
+  // pieces [buffer][piece][row or column][k], k contiguous (with the half swizzle), so that a
+  // lane's eight k values of one piece are one 16-byte read
+  __shared__ __attribute__((aligned(16))) unsigned short Ap[2][kBfPieces][kBfRows][BK];
+  __shared__ __attribute__((aligned(16))) unsigned short Bp[2][kBfPieces][kBfRows][BK];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  int bx, by, bz;
+  block_tile(bx, by, bz);
+  const int i0 = by * kBfRows, j0 = bx * kBfRows;
+  const int kbeg = bz * gp.k_per_split;
+  const int kend = min(a.K, kbeg + gp.k_per_split);
+  const int nst = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  const unsigned sma = a.conjA ? 0x80000000u : 0u, smb = a.conjB ? 0x80000000u : 0u;
+  // this thread's operand row (A) / column (B) in the tile and its first k of four
+  const int lrow = tid >> 2, lk = (tid & 3) * 4;
+
+  // four consecutive complex values base[e .. e + 3] as two 16-byte buffer loads (wave-uniform
+  // descriptor, per-lane byte offset; operands below 2^31 bytes)
+  auto load_run = [](const float2 *base, unsigned e, float2 *dst) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(base), (short)0, 0x7fffffff, 0x00020000);
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const unsigned o = e * 8u;
+    const f4 lo = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0));
+    const f4 hi = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u, 0, 0));
+    dst[0] = make_float2(lo[0], lo[1]);
+    dst[1] = make_float2(lo[2], lo[3]);
+    dst[2] = make_float2(hi[0], hi[1]);
+    dst[3] = make_float2(hi[2], hi[3]);
+  };
+  // `full`: the block's tile lies inside M x N and its K slice is a whole number of stages, so
+  // no load needs a bounds check (and every path issues the same loads, which keeps the
+  // prefetch's wait counts exact)
+  auto load = [&](auto full, BfRegs &rg, int k0) {
+    constexpr bool F = decltype(full)::value;
+    const int gk = k0 + lk;
+    const int gi = i0 + lrow, gj = j0 + lrow;
+    if (F) {
+      if (!TA) {
+        load_run(a.A, unsigned(gi) * unsigned(a.lda) + unsigned(gk), rg.a);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rg.a[r] = a.A[size_t(gk + r) * a.lda + gi];
+      }
+      if (TB) {
+        load_run(a.B, unsigned(gj) * unsigned(a.ldb) + unsigned(gk), rg.b);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rg.b[r] = a.B[size_t(gk + r) * a.ldb + gj];
+      }
+      return;
+    }
+    if (!TA && gi < a.M && gk + 4 <= kend) {
+      load_run(a.A, unsigned(gi) * unsigned(a.lda) + unsigned(gk), rg.a);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        rg.a[r] = (gi < a.M && gk + r < kend)
+                      ? (TA ? a.A[size_t(gk + r) * a.lda + gi] : a.A[size_t(gi) * a.lda + gk + r])
+                      : make_float2(0.f, 0.f);
+    }
+    if (TB && gj < a.N && gk + 4 <= kend) {
+      load_run(a.B, unsigned(gj) * unsigned(a.ldb) + unsigned(gk), rg.b);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        rg.b[r] = (gj < a.N && gk + r < kend)
+                      ? (TB ? a.B[size_t(gj) * a.ldb + gk + r] : a.B[size_t(gk + r) * a.ldb + gj])
+                      : make_float2(0.f, 0.f);
+    }
+  };
+  // split four values of one operand row and write the six pieces (8 bytes each) to LDS
+  auto put = [&](unsigned short (*dst)[kBfRows][BK], const float2 *v, unsigned sm) {
+    unsigned w[kBfPieces][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      bf_split2(v[2 * h].x, v[2 * h + 1].x, w[0][h], w[1][h], w[2][h]);
+      bf_split2(__uint_as_float(__float_as_uint(v[2 * h].y) ^ sm), __uint_as_float(__float_as_uint(v[2 * h + 1].y) ^ sm),
+                w[3][h], w[4][h], w[5][h]);
+    }
+    const int k = lk ^ bf_swz(lrow);
+#pragma unroll
+    for (int q = 0; q < kBfPieces; ++q) *reinterpret_cast<uint2 *>(&dst[q][lrow][k]) = make_uint2(w[q][0], w[q][1]);
+  };
+
+  // float32 sums of the current fold group: Cr and Ci, each as hi hi and correction sums
+  floatx16 crh, crc, cih, cic;
+  double totr[16], toti[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) totr[r] = toti[r] = 0.0;
+  auto clear = [&] {
+    crh = floatx16{0.f};
+    crc = floatx16{0.f};
+    cih = floatx16{0.f};
+    cic = floatx16{0.f};
+  };
+  clear();
+  // fragment rows: lane % 32 of the wave's 32 rows (columns), k = 8 (lane / 32) .. + 7
+  const int ra = wm * 32 + (lane & 31), rb = wn * 32 + (lane & 31);
+  const int ka = 8 * (lane >> 5) ^ bf_swz(ra), kb = 8 * (lane >> 5) ^ bf_swz(rb);
+  auto multiply = [&](int buf) {
+    bf16x8 fa[kBfPieces], fb[kBfPieces], na[3];
+#pragma unroll
+    for (int q = 0; q < kBfPieces; ++q) {
+      fa[q] = *reinterpret_cast<const bf16x8 *>(&Ap[buf][q][ra][ka]);
+      fb[q] = *reinterpret_cast<const bf16x8 *>(&Bp[buf][q][rb][kb]);
+    }
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      na[q] = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u4, fa[3 + q]) ^ u4{0x80008000u, 0x80008000u,
+                                                                                 0x80008000u, 0x80008000u});
+    // the five corrections smallest first (mid mid, lo hi, hi lo, mid hi, hi mid), then hi hi;
+    // the Cr and Ci chains alternate so consecutive MFMAs are independent
+    constexpr int lx[5] = {1, 2, 0, 1, 0}, ly[5] = {1, 0, 2, 0, 1};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const int x = lx[q], y = ly[q];
+      crc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fb[y], crc, 0, 0, 0);
+      cic = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fb[3 + y], cic, 0, 0, 0);
+      crc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(na[x], fb[3 + y], crc, 0, 0, 0);
+      cic = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[3 + x], fb[y], cic, 0, 0, 0);
+    }
+    crh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], fb[0], crh, 0, 0, 0);
+    cih = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], fb[3], cih, 0, 0, 0);
+    crh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(na[0], fb[3], crh, 0, 0, 0);
+    cih = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[3], fb[0], cih, 0, 0, 0);
+  };
+  auto fold = [&] {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      totr[r] += double(crh[r]) + double(crc[r]);
+      toti[r] += double(cih[r]) + double(cic[r]);
+    }
+    clear();
+  };
+
+  // stage s: multiply LDS buffer `buf` while `ready` (stage s + 1) is split into the other
+  // buffer and `fill` receives stage s + 2. At the last stage the split writes a repeated stage
+  // to a buffer nobody reads again.
+  auto run = [&](auto full) {
+    BfRegs r0, r1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) r0.a[r] = r0.b[r] = r1.a[r] = r1.b[r] = make_float2(0.f, 0.f);
+    if (nst == 0) return;
+    load(full, r0, kbeg);
+    put(Ap[0], r0.a, sma);
+    put(Bp[0], r0.b, smb);
+    load(full, r1, kbeg + min(1, nst - 1) * BK);
+    __syncthreads();
+    int pending = 0;
+    // the loads are issued unconditionally (the last stages reload the last stage) so that the
+    // wait before the split counts only the previous stage's loads
+    auto stage = [&](int s, int buf, BfRegs &fill, const BfRegs &ready) {
+      load(full, fill, kbeg + min(s + 2, nst - 1) * BK);
+      multiply(buf);
+      put(Ap[buf ^ 1], ready.a, sma);
+      put(Bp[buf ^ 1], ready.b, smb);
+      if (++pending == kBfFold || s + 1 == nst) {
+        fold();
+        pending = 0;
+      }
+      __syncthreads();
+    };
+    for (int s = 0; s < nst; s += 2) {
+      stage(s, 0, r0, r1);
+      if (s + 1 < nst) stage(s + 1, 1, r1, r0);
+    }
+  };
+  const bool full = i0 + kBfRows <= a.M && j0 + kBfRows <= a.N && (kend - kbeg) % BK == 0;
+  if (full) run(std::true_type{});
+  else run(std::false_type{});
+  // accumulator r of lane l sits at row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the wave's tile
+  const int j = j0 + wn * 32 + (lane & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = i0 + wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+    if (i >= a.M || j >= a.N) continue;
+    if (gp.split > 1) {
+      gp.partial[(size_t(bz) * a.M + i) * a.N + j] = make_double2(totr[r], toti[r]);
+    } else {
+      epilogue(a, i, j, totr[r], toti[r]);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) split_reduce(GemmParams gp) {
   const CGemmArgs &a = gp.a;
   const size_t total = size_t(a.M) * a.N;
@@ -500,6 +586,19 @@ hipError_t launch_cfg(const GemmParams &gp, hipStream_t stream) {
   return hipGetLastError();
 }
 
+hipError_t launch_bf(const GemmParams &gp, hipStream_t stream) {
+  const CGemmArgs &a = gp.a;
+  dim3 grid((a.N + kBfRows - 1) / kBfRows, (a.M + kBfRows - 1) / kBfRows, gp.split);
+  if (a.transA) {
+    if (a.transB) hipLaunchKernelGGL((cgemm_bf_kernel<true, true>), grid, dim3(kBfThreads), 0, stream, gp);
+    else hipLaunchKernelGGL((cgemm_bf_kernel<true, false>), grid, dim3(kBfThreads), 0, stream, gp);
+  } else {
+    if (a.transB) hipLaunchKernelGGL((cgemm_bf_kernel<false, true>), grid, dim3(kBfThreads), 0, stream, gp);
+    else hipLaunchKernelGGL((cgemm_bf_kernel<false, false>), grid, dim3(kBfThreads), 0, stream, gp);
+  }
+  return hipGetLastError();
+}
+
 template <class C>
 int tiles_of(int M, int N) {
   return ((M + C::BM - 1) / C::BM) * ((N + C::BN - 1) / C::BN);
@@ -520,7 +619,7 @@ bool use_large(int M, int N, int K) {
 }
 
 // tile configuration: 0 small, 1 large, 2 extra large, 3 small with deeper prefetch, 4 small and
-// 5 large with three products per complex step, 6 small with three products on bfloat16 pieces;
+// 5 large with three products per complex step, 6 small on bfloat16 pieces;
 // `cfg` >= 0 is a choice made by the autotuner, else FR_GEMM_TILE (s, l, x, p, t, u, b)
 // overrides the default for manual tuning runs
 int tile_choice(int M, int N, int K, int cfg) {
@@ -543,7 +642,7 @@ int cgemm_split_for(int M, int N, int K, int cfg) {
     case 3: return split_for(tiles_of<CfgP>(M, N), K);
     case 4: return split_for(tiles_of<CfgS3>(M, N), K);
     case 5: return split_for(tiles_of<CfgL3>(M, N), K);
-    case 6: return split_for(tiles_of<CfgB>(M, N), K);
+    case 6: return split_for(tiles_of<CfgS>(M, N), K);  // 64 x 64 like the small tile
     default: return split_for(tiles_of<CfgS>(M, N), K);
   }
 }
@@ -576,7 +675,7 @@ hipError_t launch_cgemm_split(const CGemmArgs &a, int split, int cfg_choice, voi
                  : cfg == 3 ? launch_cfg<CfgP>(gp, stream)
                  : cfg == 4 ? launch_cfg<CfgS3>(gp, stream)
                  : cfg == 5 ? launch_cfg<CfgL3>(gp, stream)
-                 : cfg == 6 ? launch_cfg<CfgB>(gp, stream)
+                 : cfg == 6 ? launch_bf(gp, stream)
                             : launch_cfg<CfgS>(gp, stream);
   hook(stream, name, a.K, 1);
   if (e != hipSuccess || split == 1) return e;

@@ -1,6 +1,8 @@
 """Shared helpers of the GPU parity tests (inputs come from the seeded generators; expected
 values from the oracle or closed forms only)."""
 
+import contextlib
+
 import numpy as np
 import torch
 
@@ -30,3 +32,26 @@ def f32(a):
 
 def banner(msg):
     print(f"[gpu-test] {msg}", flush=True)
+
+
+@contextlib.contextmanager
+def forced_gemm_tile(tile, tmp_path):
+    """Every MFT GEMM on one tile configuration for the duration: the default choice and every
+    shape an earlier autotune call gave its own line. Restores the previous choices after."""
+    from paper_1806_06467_amd import fresnel as fb
+    saved = tmp_path / "gemm_saved.txt"
+    fb.autotune_save(str(saved))
+    lines = ["gemm_default %d 0" % tile]
+    for ln in saved.read_text().splitlines():
+        t = ln.split()
+        if t and t[0] == "gemm":
+            lines.append(" ".join(t[:6] + [str(tile), "0"]))
+    forced = tmp_path / "gemm_forced.txt"
+    forced.write_text("\n".join(lines) + "\n")
+    fb.autotune_load(str(forced))
+    try:
+        yield
+    finally:
+        forced.write_text("gemm_default -1 0\n")
+        fb.autotune_load(str(forced))
+        fb.autotune_load(str(saved))

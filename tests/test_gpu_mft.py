@@ -9,7 +9,7 @@ from scipy.special import j1
 import oracle
 from paper_1806_06467_amd import fresnel as fb
 from paper_1806_06467_amd import synth
-from tests.gpu_common import banner, f32, rel_l2, to_gpu, to_np
+from tests.gpu_common import banner, f32, forced_gemm_tile, rel_l2, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -148,14 +148,8 @@ def test_bfloat16_split_tile_on_8192_field(tmp_path):
     # that tile
     n, nd, m, du = 8192, 2048.0, 256, 8 / 256
     banner("bfloat16-split tile: occulter mft 8192 -> 256")
-    f = tmp_path / "bf.txt"
-    f.write_text("gemm_default 6 0\n")
-    fb.autotune_load(str(f))
-    try:
+    with forced_gemm_tile(6, tmp_path):
         e = synth.random_field(n, 21)
         got = to_np(fb.mft_forward(to_gpu(e), nd, m, du))
-    finally:
-        f.write_text("gemm_default -1 0\n")
-        fb.autotune_load(str(f))
     ref = oracle.mft(f32(e), nd, m, du)
     assert rel_l2(got, ref) <= TOL
