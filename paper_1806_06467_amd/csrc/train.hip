@@ -135,13 +135,16 @@ __global__ void scale_by_grad(const float *g, float w, const float2 *e, float2 *
 
 // DM gradient (a7) and its projection onto the actuators, dL/dA = G^T g_s G with
 //   g_s[i][j] = -2 kappa Im(E[i][j] conj(B[i][j]))   (surface gradient, never stored)
-// in three deterministic steps:
+// in deterministic steps:
 //   dm_grad_T:   per (32-row strip, 512-column group) block, the group's share of
 //                T[i][b] = sum_j g_s[i][j] G[j][b] on FP32 MFMA; one pass over E and B
 //                (HBM-bound)
-//   dm_grad_G:   per 32-row block, T = sum of the group shares (group order), then the
-//                block's share of sum_i G[i][a] T[i][b]
+//   dm_grad_acc: T_sum += the sum of the group shares (group order)
+//   dm_grad_G:   per 32-row block, the block's share of sum_i G[i][a] T_sum[i][b]
 //   dm_grad_reduce: gA += the block shares, in a fixed order.
+// G depends only on the grid edge and kappa enters g_s, so the projection is linear in the
+// wavelengths' T: each DM keeps one T_sum that the wavelengths of a grid edge add into in
+// wavelength order, and the last two steps run once per DM and grid edge.
 // E is the stored plane, or (E == null) the pupil optic amp exp(2 pi i (opd + 2 pre) / lambda)
 // synthesised here (amp/opd nd x nd centred, pre n x n).
 constexpr int kRows = 32;    // rows per dm_grad_T block (one MFMA tile)
@@ -290,6 +293,15 @@ __global__ void __launch_bounds__(256) dm_grad_T(const float2 *E, const float2 *
   }
 }
 
+// T_sum[e] += sum over groups of tpart[group][e], in group order
+__global__ void __launch_bounds__(256) dm_grad_acc(const float *tpart, int groups, int total, float *tsum) {
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+    float v = 0.f;
+    for (int q = 0; q < groups; ++q) v += tpart[size_t(q) * total + e];
+    tsum[e] += v;
+  }
+}
+
 // per block of kGRows rows: T rows (group shares added in group order), then the block's share
 // of G^T T. All group shares of an element are loaded before they are added.
 constexpr int kMaxGroups = 16;  // n <= 8192
@@ -363,7 +375,7 @@ struct Layout {
   std::vector<size_t> e, b;          // per wavelength (plain: all equal)
   std::vector<int> surf_n;           // distinct grid edges with a surface set
   std::vector<size_t> surf;          // offsets of those sets (n_dm maps each)
-  size_t tpart, gpart, tdm, el, y1, eocc, edet, ydet, psf64, mft, total;
+  size_t tpart, tsum, gpart, tdm, el, y1, eocc, edet, ydet, psf64, mft, total;
 };
 
 Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_t mode) {
@@ -396,9 +408,10 @@ Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_
     for (int j = 0; j < n_lambda; ++j) L.b[j] = b0;
   }
   const size_t groups = size_t((nmax + kGroup - 1) / kGroup);
-  L.tpart = grad ? take(groups * nmax * d->n_act * 4) : 0;
-  L.gpart = grad ? take(size_t((nmax + kGRows - 1) / kGRows) * d->n_act * d->n_act * 4) : 0;
   const size_t ndm = size_t(std::max(d->n_dm, 1));
+  L.tpart = grad ? take(groups * nmax * d->n_act * 4) : 0;
+  L.tsum = grad ? take(ndm * nmax * d->n_act * 4) : 0;  // one T_sum per DM
+  L.gpart = grad ? take(size_t((nmax + kGRows - 1) / kGRows) * d->n_act * d->n_act * 4) : 0;
   if (batched) {
     for (int j = 0; j < n_lambda; ++j)
       if (std::find(L.surf_n.begin(), L.surf_n.end(), int(n_pad[j])) == L.surf_n.end()) {
@@ -476,6 +489,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   auto c64at = [&](size_t o) { return reinterpret_cast<float2 *>(base + o); };
   float *GPART = grad ? reinterpret_cast<float *>(base + L.gpart) : nullptr;
   float *TPART = grad ? reinterpret_cast<float *>(base + L.tpart) : nullptr;
+  float *TSUM = grad ? reinterpret_cast<float *>(base + L.tsum) : nullptr;
   float *TDM = reinterpret_cast<float *>(base + L.tdm);
   float2 *EL = c64at(L.el);
   float2 *Y1 = grad ? c64at(L.y1) : nullptr;
@@ -578,13 +592,42 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   };
 
   // dL/dA_k += G^T g_s G with g_s = -2 kappa Im(E conj(B)) (E stored, or the pupil optic
-  // synthesised from amp/opd/pre when E == null)
-  auto dm_grad = [&](int j, const float2 *E, const float2 *B, const float *pre, float *gA) -> int {
+  // synthesised from amp/opd/pre when E == null): the wavelength's T goes into DM k's T_sum; the
+  // projection G^T T_sum into gA_k runs when the grid edge changes and at the end of the call
+  int nmax = 0;
+  for (int j = 0; j < n_lambda; ++j) nmax = std::max(nmax, int(n_pad[j]));
+  int sum_n[2] = {-1, -1};  // grid edge whose T each DM's T_sum holds (-1: empty)
+  auto flush = [&](int k) -> int {
+    const int n = sum_n[k];
+    if (n < 0) return FR_OK;
+    const float *G = nullptr;
+    FR_TRY(ctx->dm_influence(n, nd, na, s, &G));
+    const int gblocks = (n + kGRows - 1) / kGRows;
+    hook(s, "dm_grad_G", n, 0);
+    hipLaunchKernelGGL(dm_grad_G, dim3(gblocks), dim3(256), 0, s, (const float *)(TSUM + size_t(k) * nmax * na), 1,
+                       G, n, na, GPART);
+    FR_TRY_HIP(hipGetLastError());
+    hook(s, "dm_grad_G", n, 1);
+    hook(s, "dm_grad_reduce", n, 0);
+    hipLaunchKernelGGL(dm_grad_reduce, dim3((na * na + 63) / 64), dim3(256), 0, s, (const float *)GPART, gblocks,
+                       na * na, grad_heights + size_t(k) * na * na);
+    FR_TRY_HIP(hipGetLastError());
+    hook(s, "dm_grad_reduce", n, 1);
+    sum_n[k] = -1;
+    return FR_OK;
+  };
+  auto dm_grad = [&](int j, int k, const float2 *E, const float2 *B, const float *pre) -> int {
     const int n = n_pad[j];
     const float *G = nullptr;
     FR_TRY(ctx->dm_influence(n, nd, na, s, &G));
     const int strips = (n + kRows - 1) / kRows, groups = (n + kGroup - 1) / kGroup;
-    const int gblocks = (n + kGRows - 1) / kGRows;
+    const int tn = n * na;
+    float *T = TSUM + size_t(k) * nmax * na;
+    if (sum_n[k] != n) {
+      FR_TRY(flush(k));
+      FR_TRY_HIP(launch1d(fill_f32, size_t(tn), s, hook, "fill", T, size_t(tn), 0.f));
+      sum_n[k] = n;
+    }
     const float kappa = float(4.0 * M_PI / lam[j]);
     const char *tname = E ? "dm_grad_T" : "dm_grad_T_pupil";
     hook(s, tname, n, 0);
@@ -596,15 +639,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
                          d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), TPART);
     FR_TRY_HIP(hipGetLastError());
     hook(s, tname, n, 1);
-    hook(s, "dm_grad_G", n, 0);
-    hipLaunchKernelGGL(dm_grad_G, dim3(gblocks), dim3(256), 0, s, (const float *)TPART, groups, G, n, na, GPART);
-    FR_TRY_HIP(hipGetLastError());
-    hook(s, "dm_grad_G", n, 1);
-    hook(s, "dm_grad_reduce", n, 0);
-    hipLaunchKernelGGL(dm_grad_reduce, dim3((na * na + 63) / 64), dim3(256), 0, s, (const float *)GPART, gblocks,
-                       na * na, gA);
-    FR_TRY_HIP(hipGetLastError());
-    hook(s, "dm_grad_reduce", n, 1);
+    FR_TRY_HIP(launch1d(dm_grad_acc, size_t(tn), s, hook, "dm_grad_acc", (const float *)TPART, groups, tn, T));
     return FR_OK;
   };
 
@@ -633,12 +668,12 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       FR_TRY_HIP(launch1d(fill_c64, n2, s, hook, "fill", B, n2));
     }
     FR_TRY_HIP(launch1d(window_add, size_t(nd) * nd, s, hook, "window_add", B, n, nd, (const float2 *)Y1));
-    return dm_grad(j, E, B, nullptr, grad_heights + size_t(ndm - 1) * na * na);
+    return dm_grad(j, ndm - 1, E, B, nullptr);
   };
   // pupil DM (n_dm == 2), after B_j went back through the adjoint step:
   // g_s1 = -2 kappa Im(E_dm1 conj(B1)), E_dm1 = pupil optic * DM1 phasor synthesised again
   auto back_to_pupil_dm = [&](int j) -> int {
-    return dm_grad(j, nullptr, c64at(L.b[j]), surf_of(j), grad_heights);
+    return dm_grad(j, 0, nullptr, c64at(L.b[j]), surf_of(j));
   };
 
   FR_TRY_HIP(launch1d(fill_f64, det2, s, hook, "fill", PSF64, det2));
@@ -700,6 +735,8 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       g0 = g1;
     }
   }
+  if (grad)
+    for (int k = 0; k < ndm; ++k) FR_TRY(flush(k));
   FR_TRY_HIP(launch1d(to_f32, det2, s, hook, "psf_to_f32", (const double *)PSF64, psf, det2));
 #undef FR_TRY
 #undef FR_TRY_HIP
