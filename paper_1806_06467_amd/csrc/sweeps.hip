@@ -235,7 +235,9 @@ template <class PL, int LINES, bool HALF = false>
 __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const float2 *tw) {
   constexpr int N = PL::N, E = PL::E, T = PL::T;
   constexpr int G = N / LINES;  // column groups per plane
-  constexpr int LINE = (HALF ? LdsLine<N / 2>::size : LdsLine<N>::size) + 4;
+  // the lines of the LINES columns start 8 float2 apart in the bank pattern (measured: a
+  // 3 % faster sweep than 4, 10 % than 1)
+  constexpr int LINE = (HALF ? LdsLine<N / 2>::size : LdsLine<N>::size) + 8;
   __shared__ c32 lds[LINES * LINE];
   const PlaneArgs &pa = args.p[blockIdx.y];
   const int c = threadIdx.x % LINES;
