@@ -12,7 +12,8 @@ purpose, so that it can be checked against the paper and the mathematics by eye.
 
 Pins (see tests/test_oracle_*.py): brute-force DFT on tiny grids, Parseval,
 the complex Gaussian-beam closed form, the Talbot self-imaging closed form,
-the thin-lens q-parameter law, the Airy pattern, the exact DFT special case of
+the thin-lens q-parameter law, the Airy pattern, the direct Fresnel step's agreement with
+the angular-spectrum step where its kernel is periodic, the exact DFT special case of
 the MFT, dot-product (adjoint) identities, the AS/MFT lattice invariance,
 finite differences and a Taylor test of the gradient.
 
@@ -24,6 +25,7 @@ value in the paper for that system to compare against.
 from .core import (  # noqa: F401
     centred, signed_index, dft_matrix, dft2, idft2, transfer_function,
     as_propagate, as_propagate_rows, optic_phasor, fresnel_step, mft_matrix, mft, mft_adjoint,
+    direct_pitch, quadratic_phase, direct_kernel_matrix, direct_fresnel, direct_fresnel_rows,
 )
 from .train import (  # noqa: F401
     embed, extract, dm_influence, dm_surface, TrainGeometry, train_forward,

@@ -177,3 +177,70 @@ def mft_adjoint(eb, n_d, n_out, du):
     eb = np.asarray(eb, dtype=np.complex128)
     w = mft_matrix(eb.shape[0], n_out, n_d, du)
     return (float(du) / float(n_d)) * (w.conj().T @ eb @ w.conj())
+
+
+# --------------------------------------------------------------------------------------------
+# O9. Direct (single-transform) Fresnel step (Sec. 1.1: POPPY's direct Fresnel method beside
+#     the angular spectrum; Sec. 2.3, Eq. 2: the quadratic phase factor, read as
+#     exp(+i pi (x^2 + y^2) / (lambda z)) since the printed form drops pi / lambda and its sign).
+# --------------------------------------------------------------------------------------------
+
+def direct_pitch(n, dx, wavelength, z):
+    """Output pixel pitch of the direct step: lambda z / (n dx)."""
+    return float(wavelength) * float(z) / (n * float(dx))
+
+
+def quadratic_phase(n, pitch, wavelength, z):
+    """q(i) = exp(+i pi (c(i) pitch)^2 / (lambda z)); the integer c(i)^2 is exact and the phase
+    is taken in turns in float64, reduced before the exponential."""
+    c = centred(n)
+    turns = (c * c) * (float(pitch) ** 2 / (2.0 * float(wavelength) * float(z)))
+    turns = turns - np.round(turns)
+    return np.exp(2j * np.pi * turns)
+
+
+def direct_kernel_matrix(n):
+    """F[k, i] = exp(-2 pi i c(k) c(i) / n): the Fresnel transform kernel between the centred
+    input grid x = c(i) dx and the centred output grid u = c(k) lambda z / (n dx)."""
+    p = np.outer(centred(n), centred(n)) % n      # exact integer index reduction
+    return np.exp((-2j * np.pi / n) * p)
+
+
+def direct_fresnel(u, dx, wavelength, z):
+    """The Fresnel integral over a distance z > 0 evaluated with one transform:
+
+        U2(u, v) = dx^2 / (i lambda z) q2(u) q2(v) sum_{x, y} U1(x, y) q1(x) q1(y)
+                   exp(-2 pi i (x u + y v) / (lambda z)),
+
+    input pitch dx, output pitch dx2 = lambda z / (n dx), q1 / q2 the quadratic phase on the
+    input / output grid. No e^{ikz} piston (as for the angular-spectrum step).
+    Returns (U2, dx2)."""
+    if not float(z) > 0.0:
+        raise ValueError("the direct step takes z > 0")
+    u = np.asarray(u, dtype=np.complex128)
+    n = u.shape[0]
+    if u.shape != (n, n):
+        raise ValueError("square arrays only")
+    dx2 = direct_pitch(n, dx, wavelength, z)
+    q1 = quadratic_phase(n, dx, wavelength, z)
+    q2 = quadratic_phase(n, dx2, wavelength, z)
+    f = direct_kernel_matrix(n)
+    c = float(dx) ** 2 / (1j * float(wavelength) * float(z))
+    inner = (q1[:, None] * u * q1[None, :])
+    return c * (q2[:, None] * (f @ inner @ f.T) * q2[None, :]), dx2
+
+
+def direct_fresnel_rows(u, dx, wavelength, z, rows):
+    """Rows `rows` of direct_fresnel(u, dx, wavelength, z)[0], at O(len(rows) n^2) cost (the
+    kernel matrix's rows, not the whole matrix)."""
+    u = np.asarray(u, dtype=np.complex128)
+    n = u.shape[0]
+    rows = np.asarray(rows, dtype=np.int64)
+    dx2 = direct_pitch(n, dx, wavelength, z)
+    q1 = quadratic_phase(n, dx, wavelength, z)
+    q2 = quadratic_phase(n, dx2, wavelength, z)
+    c = float(dx) ** 2 / (1j * float(wavelength) * float(z))
+    fr = np.exp((-2j * np.pi / n) * (np.outer(centred(n)[rows], centred(n)) % n))   # len(rows) x n
+    f = direct_kernel_matrix(n)
+    inner = (q1[:, None] * u * q1[None, :])
+    return c * (q2[rows][:, None] * ((fr @ inner) @ f.T) * q2[None, :])

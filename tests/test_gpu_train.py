@@ -187,6 +187,22 @@ def test_batched_matches_plain_mixed_grids():
     assert torch.equal(v0, v1)
 
 
+def test_gradient_with_grid_edges_revisited():
+    # each DM's gradient is projected once per run of wavelengths on one grid edge: edges that
+    # change and come back (128, 128, 96, 128) flush and refill the same DM's sum, in the plain
+    # and the batched mode, against the oracle's adjoint
+    banner("gradient, 2 DMs, grids 128 / 128 / 96 / 128")
+    geom, tr, heights, hg = make(64, 64, 8 / 64, 64, 0.5, 0.05, 8, 2, spider=0.04)
+    lams = list(synth.wavelengths(4))
+    ns, w = [128, 128, 96, 128], [0.25] * 4
+    dhn = synth.dark_hole(64, 0.5, 3.0, 7.0)
+    dh = to_gpu(dhn / dhn.sum(), torch.float32)
+    gref = np.stack(oracle.train_grad(geom, lams, ns, w, heights, dhn, 1.0))
+    for batched in (False, True):
+        _, g = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh, batched=batched)
+        assert rel_l2(_np(g), gref) <= 1e-4
+
+
 @functools.lru_cache(maxsize=1)
 def _broadband_oracle():
     # the oracle's broadband PSF with and without the occulting spot (shared by the tests below)
