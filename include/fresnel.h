@@ -6,6 +6,8 @@
  *   - fresnel_step: one plane-to-plane step, i.e. the optic multiply of Eq. (3) (and a thin
  *     lens, Sec. 1.1 after Goodman Eq. 5-10) followed by angular-spectrum propagation
  *     (Sec. 1.1, after Lawrence Eqs. 82-89): 2-D FFT, transfer function, inverse 2-D FFT;
+ *   - fresnel_direct: the direct Fresnel step (Sec. 1.1; the quadratic phase of Sec. 2.3):
+ *     quadratic phase, one 2-D FFT, quadratic phase, to a grid of pitch lambda z / (n dx);
  *   - mft_forward / mft_adjoint: the matrix Fourier transform between pupil and focal planes
  *     used by the semi-analytic Lyot coronagraph (Sec. 1.1, Soummer et al.; Sec. 2.3, the
  *     sin/cos arrays of the matrix DFT);
@@ -49,6 +51,7 @@ extern "C" {
 
 #define FR_W_AS_UNDERSAMPLED 1 /* |z| > n dx^2 / lambda: the transfer function aliases     */
 #define FR_W_MFT_ALIASED 2     /* du > n_d / n_in: focal sampling beyond the input lattice */
+#define FR_W_DIRECT_UNDERSAMPLED 4 /* z < n dx^2 / lambda: the direct step's input chirp aliases */
 
 /* flags of fresnel_step */
 #define FR_ADJOINT 1 /* apply the adjoint: AS over -z first, then the conjugate optic      */
@@ -82,6 +85,26 @@ int fr_fft_size_supported(int32_t n);
 int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wavelength_m,
                  double z_m, const float *amp, const float *opd_m, double lens_focal_m,
                  int32_t flags, void *stream);
+
+/* ---- direct (single-transform) Fresnel step (Sec. 1.1: the direct Fresnel method beside the
+ * angular spectrum; Sec. 2.3, Eq. 2: the quadratic phase factor, read as
+ * exp(+i pi (x^2 + y^2) / (lambda z))) -----------------------------------------------------
+ * field : n x n c64, in place. With U = field * optic (optic exactly as for fresnel_step,
+ *         lens included), on return
+ *           field[ky][kx] <- dx^2 / (i lambda z) q2(kx) q2(ky) sum_{y, x} U[y][x] q1(x) q1(y)
+ *                            exp(-2 pi i ((x - n/2)(kx - n/2) + (y - n/2)(ky - n/2)) / n),
+ *         q1(i) = exp(i pi ((i - n/2) dx)^2 / (lambda z)) on the input grid and
+ *         q2(k) = exp(i pi ((k - n/2) dx2)^2 / (lambda z)) on the output grid of pitch
+ *         dx2 = lambda z / (n dx): the Fresnel integral over z evaluated with one 2-D FFT (no
+ *         e^{ikz} piston, as for fresnel_step). The output plane is centred on pixel n/2 too.
+ * z_m   : > 0.   dx_out_m : receives dx2 (written only on success).
+ * Implemented edges: powers of two from 64 to 8192. Errors: FR_EINVAL (null field or dx_out_m,
+ * n <= 0, dx / lambda / z <= 0 or not finite), FR_EUNSUPPORTED (edge). Warning:
+ * FR_W_DIRECT_UNDERSAMPLED (z < n dx^2 / lambda, where the angular-spectrum step is the sampled
+ * one). Uses no workspace (in place, two sweeps). */
+int fresnel_direct(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wavelength_m, double z_m,
+                   const float *amp, const float *opd_m, double lens_focal_m, double *dx_out_m,
+                   void *stream);
 
 /* Many independent planes in one launch per sweep (e.g. the wavelengths of a broadband
  * model, Sec. 1.2). Each entry has the meaning of the fresnel_step arguments. `planes` is a

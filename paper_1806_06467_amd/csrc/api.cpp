@@ -251,6 +251,43 @@ int Ctx::lens(int n, double dx, double lam, double f, hipStream_t s, const float
   return st;
 }
 
+// Direct Fresnel step (Sec. 1.1; Sec. 2.3, Eq. 2, the quadratic phase read as
+// exp(+i pi r^2 / (lambda z))):
+//   pre[i]  = (-1)^i exp(i pi c(i)^2 dx^2 (1/z - 1/f) / lambda)  (a thin lens of focal f folded
+//             in; 1/f = 0 without one)
+//   post[k] = (-1)^k exp(i pi c(k)^2 dx2^2 / (lambda z)) (dx / sqrt(lambda z)) e^{-i pi/4},
+//             dx2 = lambda z / (n dx)
+// so that post[ky] post[kx] DFT2(pre[y] pre[x] U)[ky][kx] is the step: the signs centre the
+// transform on pixel n/2 (exp(-2 pi i c(k) c(i) / n) = W^{ki} (-1)^{k + i} (-1)^{n/2}, the last
+// factor squaring to 1 over the two axes) and the two roots make the constant dx^2/(i lambda z).
+int Ctx::direct_phases(int n, double dx, double lam, double z, double f, hipStream_t s, const float2 **pre,
+                       const float2 **post) {
+  const TableKey kpre{kDirectPre, n, bits(dx), bits(lam), bits(z), bits(f)};
+  const TableKey kpost{kDirectPost, n, bits(dx), bits(lam), bits(z), 0};
+  auto build = [&](const TableKey &key, bool input, const float2 **out) -> int {
+    if (auto it = tables.find(key); it != tables.end()) {
+      *out = static_cast<const float2 *>(it->second);
+      return FR_OK;
+    }
+    std::vector<float2> h(n);
+    const double dx2 = lam * z / (double(n) * dx);
+    const double coef = input ? dx * dx * (1.0 / z - (f != 0.0 ? 1.0 / f : 0.0)) / (2.0 * lam)
+                              : dx2 * dx2 / (2.0 * lam * z);
+    const double scale = input ? 1.0 : dx / std::sqrt(lam * z);
+    for (int i = 0; i < n; ++i) {
+      const long long c = i - n / 2;
+      const double turns = double(c * c) * coef + 0.5 * double(i & 1) - (input ? 0.0 : 0.125);
+      h[i] = turn_to_c64(turns, scale);
+    }
+    void *d;
+    const int st = upload(key, h.data(), h.size() * sizeof(float2), s, &d);
+    *out = static_cast<const float2 *>(d);
+    return st;
+  };
+  const int st = build(kpre, true, pre);
+  return st != FR_OK ? st : build(kpost, false, post);
+}
+
 // W[k][m] = exp(-2 pi i (k - M/2)(m - N/2) du / n_d), M x N row-major (or its transpose, N x M)
 int Ctx::mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out,
                     bool transposed) {
@@ -567,6 +604,37 @@ int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wave
   p.n = n;
   p.flags = flags;
   return fresnel_step_batched(ctx, &p, 1, stream);
+}
+
+int fresnel_direct(fr_ctx *ctx_, fr_c64 *field, int32_t n, double dx_m, double wavelength_m, double z_m,
+                   const float *amp, const float *opd_m, double lens_focal_m, double *dx_out_m, void *stream) {
+  if (!field || !dx_out_m || n <= 0) return FR_EINVAL;
+  if (!(dx_m > 0) || !(wavelength_m > 0) || !(z_m > 0) || !std::isfinite(dx_m) || !std::isfinite(wavelength_m) ||
+      !std::isfinite(z_m) || !std::isfinite(lens_focal_m))
+    return FR_EINVAL;
+  if (!fr::fresnel_size_supported(n)) return FR_EUNSUPPORTED;
+  Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
+  if (!ctx) return FR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fr::record_hip(e);
+  PlaneArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.field = reinterpret_cast<float2 *>(field);
+  a.amp = amp;
+  a.opd = opd_m;
+  a.n = n;
+  a.win = n;
+  a.inv_lambda = float(1.0 / wavelength_m);
+  int st = ctx->direct_phases(n, dx_m, wavelength_m, z_m, lens_focal_m, s, &a.lens, &a.h);
+  if (st != FR_OK) return st;
+  const float2 *root;
+  st = ctx->twiddles(n, s, &root);
+  if (st != FR_OK) return st;
+  e = fr::launch_direct_batch(&a, 1, n, root, s, ctx->hook());
+  if (e != hipSuccess) return fr::record_hip(e);
+  *dx_out_m = wavelength_m * z_m / (double(n) * dx_m);
+  return z_m < double(n) * dx_m * dx_m / wavelength_m ? FR_W_DIRECT_UNDERSAMPLED : FR_OK;
 }
 
 }  // extern "C"

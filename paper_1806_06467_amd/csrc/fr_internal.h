@@ -60,6 +60,12 @@ struct BatchArgs {
 // variant computes the same result. fresnel_variants(n) = number of variants for edge n.
 hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const float2 *tw,
                                 hipStream_t stream, const LaunchHook &hook, int variant);
+// The direct (single-transform) Fresnel step of `count` planes of power-of-two edge n
+// (count <= kMaxBatch): the row sweep applies the optic times the input quadratic phase (lens
+// slot) and the forward transform, the column sweep the forward transform and the output
+// quadratic phase (h slot). Same tiles as variant 0 of launch_fresnel_batch.
+hipError_t launch_direct_batch(const PlaneArgs *planes, int count, int n, const float2 *tw, hipStream_t s,
+                               const LaunchHook &hook);
 int fresnel_variants(int n);
 int fresnel_twiddle_count(int n);
 void fresnel_twiddle_build(int n, float2 *out);  // host

@@ -12,7 +12,7 @@
 
 namespace fr {
 
-enum TableKind : int { kRoots = 1, kTransfer, kLens, kMft, kDm, kMrTw };
+enum TableKind : int { kRoots = 1, kTransfer, kLens, kMft, kDm, kMrTw, kDirectPre, kDirectPost };
 // (kind, size, then up to four parameter words: sizes or the bits of float64 parameters)
 using TableKey = std::tuple<int, int, uint64_t, uint64_t, uint64_t, uint64_t>;
 
@@ -69,6 +69,8 @@ struct Ctx {
   GemmChoice gemm_choice(const CGemmArgs &g) const;
   int transfer(int n, double dx, double lam, double z, hipStream_t s, const float2 **out);
   int lens(int n, double dx, double lam, double f, hipStream_t s, const float2 **out);
+  int direct_phases(int n, double dx, double lam, double z, double f, hipStream_t s, const float2 **pre,
+                    const float2 **post);
   int mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out,
                  bool transposed = false);
   int dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **out);

@@ -171,7 +171,9 @@ __device__ __forceinline__ void freq_product(c32 (&v)[E], const float2 *h, int t
   }
 }
 
-template <class PL, int LINES>
+// DIRECT: the row half of the direct (single-transform) Fresnel step: the prologue applies the
+// optic times the input quadratic phase (held in the lens slot), then the forward transform only
+template <class PL, int LINES, bool DIRECT = false>
 __global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const float2 *tw) {
   constexpr int N = PL::N, E = PL::E, T = PL::T;
   __shared__ c32 lds[LINES * LdsLine<N>::size];
@@ -214,6 +216,11 @@ __global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const 
   }
   c32 *my = lds + line * LdsLine<N>::size;
   PL::forward(v, my, t, tw);
+  if constexpr (DIRECT) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * 8u, v[m]);
+    return;
+  }
   freq_product<E, T>(v, pa.h, t, adj);
   PL::inverse(v, my, t, tw);
   if (adj && has_pre(pa)) {
@@ -230,8 +237,9 @@ __global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const 
 }
 
 // HALF: the FFT exchanges go through half-size LDS lines in two rounds, so that two blocks fit
-// on a compute unit
-template <class PL, int LINES, bool HALF = false>
+// on a compute unit. DIRECT: the column half of the direct Fresnel step: the forward transform,
+// then the output quadratic phase of both axes (h holds it per index, with the constant's root).
+template <class PL, int LINES, bool HALF = false, bool DIRECT = false>
 __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const float2 *tw) {
   constexpr int N = PL::N, E = PL::E, T = PL::T;
   constexpr int G = N / LINES;  // column groups per plane
@@ -260,6 +268,15 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   }
   c32 *my = lds + c * LINE;
   PL::template forward<HALF>(v, my, t, tw);
+  if constexpr (DIRECT) {
+    // slot m holds frequency row ky = t + T m of column kx = x
+    const c32 px = ld2(pa.h + x);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], cmul(ld2(pa.h + t + T * m), px));
+#pragma unroll
+    for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
+    return;
+  }
   freq_product<E, T>(v, pa.h, t, adj);
   PL::template inverse<HALF>(v, my, t, tw);
   if (!adj && pa.post_surf) {
@@ -277,7 +294,7 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
 // prologue) and the row sweep second (conjugate optic epilogue). The two halves of the
 // angular-spectrum step commute, so only the placement of the optics sets the order, and the
 // amplitude/OPD maps are always read along rows.
-template <class PL, int ROW_LINES, int COL_LINES, class PC = PL, bool CHALF = false>
+template <class PL, int ROW_LINES, int COL_LINES, class PC = PL, bool CHALF = false, bool DIRECT = false>
 hipError_t launch_sweeps(const BatchArgs &fwd, int nf, const BatchArgs &adj, int na,
                          const float2 *tw, hipStream_t s, const LaunchHook &hook) {
   constexpr int N = PL::N;
@@ -286,7 +303,7 @@ hipError_t launch_sweeps(const BatchArgs &fwd, int nf, const BatchArgs &adj, int
   // timing names carry the direction (the optic maps read differ), tags the planes per launch
   auto rows = [&](const BatchArgs &a, int count, const char *name) {
     hook(s, name, count, 0);
-    hipLaunchKernelGGL((row_sweep<PL, ROW_LINES>), dim3(N / ROW_LINES, count),
+    hipLaunchKernelGGL((row_sweep<PL, ROW_LINES, DIRECT>), dim3(N / ROW_LINES, count),
                        dim3(PL::T * ROW_LINES), 0, s, a, tw);
     hipError_t e = hipGetLastError();
     hook(s, name, count, 1);
@@ -294,15 +311,15 @@ hipError_t launch_sweeps(const BatchArgs &fwd, int nf, const BatchArgs &adj, int
   };
   auto cols = [&](const BatchArgs &a, int count, const char *name) {
     hook(s, name, count, 0);
-    hipLaunchKernelGGL((col_sweep<PC, COL_LINES, CHALF>), dim3(N / COL_LINES, count),
+    hipLaunchKernelGGL((col_sweep<PC, COL_LINES, CHALF, DIRECT>), dim3(N / COL_LINES, count),
                        dim3(PC::T * COL_LINES), 0, s, a, tw);
     hipError_t e = hipGetLastError();
     hook(s, name, count, 1);
     return e;
   };
   hipError_t e = hipSuccess;
-  if (nf && (e = rows(fwd, nf, "row_sweep")) != hipSuccess) return e;
-  if (nf && (e = cols(fwd, nf, "col_sweep")) != hipSuccess) return e;
+  if (nf && (e = rows(fwd, nf, DIRECT ? "direct_rows" : "row_sweep")) != hipSuccess) return e;
+  if (nf && (e = cols(fwd, nf, DIRECT ? "direct_cols" : "col_sweep")) != hipSuccess) return e;
   if (na && (e = cols(adj, na, "col_sweep_adj")) != hipSuccess) return e;
   if (na && (e = rows(adj, na, "row_sweep_adj")) != hipSuccess) return e;
   return e;
@@ -404,6 +421,25 @@ hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const
     default: return hipErrorInvalidValue;
   }
 #undef FR_SWEEPS
+}
+
+hipError_t launch_direct_batch(const PlaneArgs *planes, int count, int n, const float2 *root, hipStream_t s,
+                               const LaunchHook &hook) {
+  BatchArgs fwd, none;
+  for (int i = 0; i < count; ++i) fwd.p[i] = planes[i];
+#define FR_DIRECT(PL, RL, CL) return launch_sweeps<PL, RL, CL, PL, false, true>(fwd, count, none, 0, root, s, hook)
+  switch (n) {
+    case 64: { using P = Plan<64, 8, 8, 8>; FR_DIRECT(P, 8, 16); }
+    case 128: { using P = Plan<128, 16, 16, 8>; FR_DIRECT(P, 16, 32); }
+    case 256: { using P = Plan<256, 16, 16, 16>; FR_DIRECT(P, 16, 32); }
+    case 512: { using P = Plan<512, 8, 8, 8, 8>; FR_DIRECT(P, 4, 16); }
+    case 1024: { using P = Plan<1024, 16, 16, 8, 8>; FR_DIRECT(P, 4, 8); }
+    case 2048: { using P = Plan<2048, 16, 16, 16, 8>; FR_DIRECT(P, 2, 8); }
+    case 4096: { using P = Plan<4096, 16, 16, 16, 16>; FR_DIRECT(P, 1, 4); }
+    case 8192: { using P = Plan<8192, 16, 16, 16, 16, 2>; FR_DIRECT(P, 1, 2); }
+    default: return hipErrorInvalidValue;
+  }
+#undef FR_DIRECT
 }
 
 }  // namespace fr

@@ -25,6 +25,7 @@ FR_ENOMEM = -5
 FR_ESTATE = -6
 FR_W_AS_UNDERSAMPLED = 1
 FR_W_MFT_ALIASED = 2
+FR_W_DIRECT_UNDERSAMPLED = 4
 FR_ADJOINT = 1
 FR_TRAIN_NO_OCCULTER = 1
 FR_TRAIN_GRAD = 2
@@ -78,6 +79,7 @@ def lib():
             "fr_fft_size_supported": (_c.c_int, [i32]),
             "fresnel_step": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
             "fresnel_step_batched": (_c.c_int, [_vp, _c.POINTER(FrPlane), i32, _vp]),
+            "fresnel_direct": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, _c.POINTER(f64), _vp]),
             "mft_workspace_bytes": (sz, [i32, i32]),
             "mft_forward": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, _vp, _vp, sz, _vp]),
             "mft_adjoint": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, f32, f32, _vp,
@@ -208,6 +210,22 @@ def fresnel_step(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, a
                             float(z), _ptr(amp), _ptr(opd), float(lens_focal),
                             FR_ADJOINT if adjoint else 0, _stream_handle(dev, stream))
     return _check(st, "fresnel_step")
+
+
+def fresnel_direct(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, stream=None):
+    """In place: field <- the direct (single-transform) Fresnel step of field * optic over z > 0.
+    Returns (output pitch lambda z / (n dx), warning bits)."""
+    _need(field, torch.complex64, None, "field")
+    n = field.shape[0]
+    _need(field, torch.complex64, (n, n), "field")
+    for t, nm in ((amp, "amp"), (opd, "opd")):
+        if t is not None:
+            _need(t, torch.float32, (n, n), nm)
+    dev = field.device.index
+    out = _c.c_double(0.0)
+    st = lib().fresnel_direct(context(dev).handle, _ptr(field), n, float(dx), float(wavelength), float(z),
+                              _ptr(amp), _ptr(opd), float(lens_focal), _c.byref(out), _stream_handle(dev, stream))
+    return out.value, _check(st, "fresnel_direct")
 
 
 def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens_focals=None,

@@ -1,0 +1,108 @@
+"""GPU parity of fresnel_direct (the direct, single-transform Fresnel step) against the FP64
+oracle (O9) and the Gaussian-beam closed form; at the distance n dx^2 / lambda it must also agree
+with the angular-spectrum step run on the GPU. Bar: field and intensity relative L2 <= 1e-5 (the
+same float32 FFT error budget as fresnel_step); the output pitch is returned exactly."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1806_06467_amd import fresnel as fb
+from paper_1806_06467_amd import synth
+from tests.gpu_common import banner, f32, rel_l2, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _case(n, seed, z_mult, optics):
+    rng = np.random.default_rng(seed)
+    field = synth.random_field(n, seed)
+    lam = 550e-9 + 10e-9 * (seed % 5)
+    dx = 2.0e-5
+    z = z_mult * n * dx * dx / lam
+    amp = rng.uniform(0.3, 1.0, (n, n)) if optics else None
+    opd = rng.normal(0.0, 60e-9, (n, n)) if optics else None
+    f = 5.0 * n * dx * dx / lam if optics else 0.0
+    return field, amp, opd, dx, lam, z, f
+
+
+def _gpu(field, dx, lam, z, amp=None, opd=None, f=0.0):
+    t = to_gpu(field)
+    dx2, st = fb.fresnel_direct(t, dx, lam, z, amp=None if amp is None else to_gpu(amp, torch.float32),
+                                opd=None if opd is None else to_gpu(opd, torch.float32), lens_focal=f)
+    return to_np(t), dx2, st
+
+
+def _ref(field, dx, lam, z, amp=None, opd=None, f=0.0):
+    u = f32(field)
+    if amp is not None or opd is not None or f:
+        n = u.shape[0]
+        u = u * oracle.optic_phasor(n, dx, lam, amp=None if amp is None else f32(amp),
+                                    opd=None if opd is None else f32(opd), lens_focal=f)
+    return oracle.direct_fresnel(u, dx, lam, z)
+
+
+@pytest.mark.parametrize("optics", [False, True])
+@pytest.mark.parametrize("n,z_mult", [(64, 1.0), (128, 2.5), (256, 1.7), (512, 4.0), (1024, 1.2), (2048, 3.0)])
+def test_direct_matches_oracle(n, z_mult, optics):
+    banner(f"fresnel_direct n={n} z={z_mult} n dx^2/lambda optics={optics}")
+    field, amp, opd, dx, lam, z, f = _case(n, n + optics, z_mult, optics)
+    got, dx2, st = _gpu(field, dx, lam, z, amp, opd, f)
+    ref, rdx2 = _ref(field, dx, lam, z, amp, opd, f)
+    assert st == 0
+    assert dx2 == lam * z / (n * dx) and abs(dx2 - rdx2) <= 1e-15 * rdx2
+    assert rel_l2(got, ref) <= TOL
+    assert rel_l2(np.abs(got) ** 2, np.abs(ref) ** 2) <= TOL
+
+
+def test_direct_4096_matches_oracle():
+    n = 4096
+    banner("fresnel_direct n=4096 with optics (oracle takes a few seconds)")
+    field, amp, opd, dx, lam, z, f = _case(n, 11, 1.5, True)
+    got, _, _ = _gpu(field, dx, lam, z, amp, opd, f)
+    ref, _ = _ref(field, dx, lam, z, amp, opd, f)
+    assert rel_l2(got, ref) <= TOL
+    assert rel_l2(np.abs(got) ** 2, np.abs(ref) ** 2) <= TOL
+
+
+@pytest.mark.parametrize("n", [512, 4096])
+def test_direct_gaussian_beam_closed_form(n):
+    banner(f"fresnel_direct Gaussian beam n={n}")
+    dx, lam, w0px = 1e-5, 550e-9, n / 40.0
+    w0 = w0px * dx
+    z = 4.0 * math.pi * w0 * w0 / lam
+    got, dx2, _ = _gpu(synth.gaussian_beam(n, w0px), dx, lam, z)
+    zeta = z / (math.pi * w0 * w0 / lam)
+    r2 = (synth.radius_grid(n) * dx2) ** 2
+    ref = np.exp(-r2 / (w0 * w0 * (1 + 1j * zeta))) / (1 + 1j * zeta)
+    assert rel_l2(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("n", [256, 4096])
+def test_direct_equals_angular_spectrum_at_periodic_distance(n):
+    # at z = n dx^2 / lambda the output pitch is dx and both steps evaluate the same discrete sum
+    banner(f"fresnel_direct vs fresnel_step at n dx^2/lambda, n={n}")
+    dx, lam = 1.5e-5, 600e-9
+    z = n * dx * dx / lam
+    field = synth.random_field(n, 3)
+    a = to_gpu(field)
+    b = to_gpu(field)
+    fb.fresnel_step(a, dx, lam, z)
+    dx2, _ = fb.fresnel_direct(b, dx, lam, z)
+    assert abs(dx2 - dx) <= 1e-15 * dx
+    assert rel_l2(to_np(b), to_np(a)) <= 2 * TOL
+
+
+def test_direct_warning_below_the_sampled_distance_and_zero_rows():
+    n, dx, lam = 256, 2e-5, 550e-9
+    t = to_gpu(np.zeros((n, n), dtype=np.complex128))
+    dx2, st = fb.fresnel_direct(t, dx, lam, 0.5 * n * dx * dx / lam)
+    assert st == fb.FR_W_DIRECT_UNDERSAMPLED
+    assert np.count_nonzero(to_np(t)) == 0
+    with pytest.raises(fb.FrError):
+        fb.fresnel_direct(t, dx, lam, -1.0)
