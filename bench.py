@@ -52,13 +52,13 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 HERE = os.path.dirname(os.path.abspath(__file__))
 MEASURED_TRAFFIC = {
     # kernel: (fetch bytes, write bytes)
-    "cgemmB_4096x4096x256_s1": (2.0 * 37232.3 * 1024, 131072.0 * 1024),
-    "cgemmB_4096x256x4096_s2": (2.0 * 93325.4 * 1024, 32768.0 * 1024),
+    "cgemmB_4096x4096x256_s1": (2.0 * 37124.6 * 1024, 131072.0 * 1024),
+    "cgemmB_4096x256x4096_s2": (2.0 * 93313.1 * 1024, 32768.0 * 1024),
 }
 TRAFFIC_SOURCES = {
     "paper_1806_06467_amd/csrc/mft.hip": "bfc10b5635141374e216a49597db38fc3f4e7fb412e6e860e39b274f731c50fd",
-    "paper_1806_06467_amd/csrc/fr_internal.h": "c1c9ae9960bfcfb4cdfb3e7cebdf1b3503942a108483803833338aaf59a70c68",
-    "paper_1806_06467_amd/csrc/api.cpp": "ad74c9bd09f4d8dbfb36bc013d45496c11db6fdf9a8abba908aa73b329fa43ff",
+    "paper_1806_06467_amd/csrc/fr_internal.h": "14a3551b0afc45d9b76d48c9739e1140a929ac5990a512fc68a09876b42d37be",
+    "paper_1806_06467_amd/csrc/api.cpp": "546b022776fa24cfaba954c16eb21ba6f8f69a7b405fc41bc9b91b68cc511f51",
 }
 
 
@@ -332,6 +332,26 @@ def main():
     # the whole Fresnel plane (both sweeps) against the two-pass model, maps included
     fr_bytes = 2 * N_LAMBDA * (2 * sweep_bytes(N, 0) + 2 * N * N * 4)
     fr_plane_frac = fr_bytes / (ms_fr / fr_calls * 1e-3) / 1e9 / HBM_PEAK_GBS
+    # the direct (single-transform) Fresnel step on the forward fields, one plane per call, at
+    # twice the distance beyond which its input phase is sampled; both sweeps move only the field
+    z_dir = 2.0 * N * DX * DX / min(lams)
+    dr_calls = 3
+
+    def direct_all():
+        for i in range(N_LAMBDA):
+            fb.fresnel_direct(fields[i], DX, lam_pl[i], z_dir)
+    ms_dr, prof_dr = timed(direct_all, dr_calls, 1, profile=True)
+    dr_rl = {}
+    for name in ("direct_rows", "direct_cols"):
+        tot = sum(v[0] for k, v in prof_dr.items() if k.partition("/")[0] == name)
+        cnt = sum(v[1] for k, v in prof_dr.items() if k.partition("/")[0] == name)
+        if cnt:
+            ms = tot / cnt
+            gbs = sweep_bytes(N, 0) / (ms * 1e-3) / 1e9
+            dr_rl[name] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": sweep_bytes(N, 0), "avg_launch_ms": ms}
+    dr_planes = N_LAMBDA * dr_calls
+    dr_frac = dr_planes * 2 * sweep_bytes(N, 0) / (ms_dr * 1e-3) / 1e9 / HBM_PEAK_GBS
     del fields
     if args.copy_calibration:
         src = torch.randn((N, N), dtype=torch.complex64, device=dev)
@@ -370,6 +390,10 @@ def main():
             "planes_per_call": 2 * N_LAMBDA, "ms_per_call": ms_fr / fr_calls,
             "hbm_frac_whole_plane": fr_plane_frac,
             "roofline": fr_rl,
+        },
+        "direct_fresnel": {
+            "value": dr_planes / (ms_dr * 1e-3), "unit": "Fresnel planes/s", "z_m": z_dir,
+            "planes_per_call": 1, "hbm_frac_whole_plane": dr_frac, "roofline": dr_rl,
         },
         "autotuned": {"choices": tuned, "seconds": t_tune, "loaded_from_file": bool(args.tune_file)},
         "checksum_psf_sum": psf_sum,
