@@ -244,3 +244,27 @@ def direct_fresnel_rows(u, dx, wavelength, z, rows):
     f = direct_kernel_matrix(n)
     inner = (q1[:, None] * u * q1[None, :])
     return c * (q2[rows][:, None] * ((fr @ inner) @ f.T) * q2[None, :])
+
+
+def direct_fresnel_adjoint(v, dx, wavelength, z):
+    """Exact adjoint of direct_fresnel over the same (dx, wavelength, z): from the output grid
+    (pitch lambda z / (n dx)) back to the input grid,
+
+        U1(x, y) = conj(dx^2 / (i lambda z)) conj(q1(x) q1(y)) sum_{u, v} V(u, v) conj(q2(u) q2(v))
+                   exp(+2 pi i (x u + y v) / (lambda z)),
+
+    so that <direct_fresnel(u), v> = <u, direct_fresnel_adjoint(v)>. Scaled by (dx2 / dx)^2 it
+    is the inverse step (the forward one is unitary up to the pitch change)."""
+    if not float(z) > 0.0:
+        raise ValueError("the direct step takes z > 0")
+    v = np.asarray(v, dtype=np.complex128)
+    n = v.shape[0]
+    if v.shape != (n, n):
+        raise ValueError("square arrays only")
+    dx2 = direct_pitch(n, dx, wavelength, z)
+    q1 = quadratic_phase(n, dx, wavelength, z)
+    q2 = quadratic_phase(n, dx2, wavelength, z)
+    fh = direct_kernel_matrix(n).conj()          # the kernel matrix is symmetric: F^H = conj(F)
+    c = float(dx) ** 2 / (1j * float(wavelength) * float(z))
+    inner = q2.conj()[:, None] * v * q2.conj()[None, :]
+    return np.conj(c) * (q1.conj()[:, None] * (fh @ inner @ fh.T) * q1.conj()[None, :])

@@ -65,3 +65,19 @@ def test_direct_rows_and_argument_checks():
     assert np.max(np.abs(oracle.direct_fresnel_rows(u, dx, lam, z, rows) - full[rows])) <= 1e-13
     with pytest.raises(ValueError):
         oracle.direct_fresnel(u, dx, lam, -z)
+
+
+@pytest.mark.parametrize("n,z", [(32, 0.02), (48, 0.7)])
+def test_direct_adjoint_identity_and_inverse(n, z):
+    # the adjoint by the dot-product identity against the (pinned) forward step, and the inverse
+    # (adjoint times (dx2/dx)^2) undoing the forward step
+    dx, lam = 9e-6, 700e-9
+    rng = np.random.default_rng(n)
+    u = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    v = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    du, dx2 = oracle.direct_fresnel(u, dx, lam, z)
+    lhs = np.vdot(v, du)
+    rhs = np.vdot(oracle.direct_fresnel_adjoint(v, dx, lam, z), u)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    back = oracle.direct_fresnel_adjoint(du, dx, lam, z) * (dx2 / dx) ** 2
+    assert np.max(np.abs(back - u)) <= 1e-12 * np.max(np.abs(u))
