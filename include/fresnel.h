@@ -53,8 +53,8 @@ extern "C" {
 #define FR_W_MFT_ALIASED 2     /* du > n_d / n_in: focal sampling beyond the input lattice */
 #define FR_W_DIRECT_UNDERSAMPLED 4 /* z < n dx^2 / lambda: the direct step's input chirp aliases */
 
-/* flags of fresnel_step */
-#define FR_ADJOINT 1 /* apply the adjoint: AS over -z first, then the conjugate optic      */
+/* flags of fresnel_step and fresnel_direct */
+#define FR_ADJOINT 1 /* apply the adjoint: the step's adjoint first, then the conjugate optic */
 
 typedef struct fr_ctx fr_ctx;
 typedef struct {
@@ -97,14 +97,19 @@ int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wave
  *         q2(k) = exp(i pi ((k - n/2) dx2)^2 / (lambda z)) on the output grid of pitch
  *         dx2 = lambda z / (n dx): the Fresnel integral over z evaluated with one 2-D FFT (no
  *         e^{ikz} piston, as for fresnel_step). The output plane is centred on pixel n/2 too.
- * z_m   : > 0.   dx_out_m : receives dx2 (written only on success).
+ * flags : 0, or FR_ADJOINT: the exact adjoint of the call with the same arguments, from the
+ *         output grid back to the input grid: field <- conj(optic) D^H(field), with D^H the
+ *         conjugate transpose of the step above (conjugate phases and constant, exp(+2 pi i ...)).
+ *         Scaled by (dx2 / dx)^2 it undoes the forward step (the step is unitary up to the
+ *         pitch change), i.e. it propagates a far-field plane back over -z.
+ * z_m   : > 0.   dx_out_m : receives dx2 (written only on success), for either direction.
  * Implemented edges: powers of two from 64 to 8192. Errors: FR_EINVAL (null field or dx_out_m,
- * n <= 0, dx / lambda / z <= 0 or not finite), FR_EUNSUPPORTED (edge). Warning:
+ * n <= 0, dx / lambda / z <= 0 or not finite, unknown flag), FR_EUNSUPPORTED (edge). Warning:
  * FR_W_DIRECT_UNDERSAMPLED (z < n dx^2 / lambda, where the angular-spectrum step is the sampled
  * one). Uses no workspace (in place, two sweeps). */
 int fresnel_direct(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wavelength_m, double z_m,
-                   const float *amp, const float *opd_m, double lens_focal_m, double *dx_out_m,
-                   void *stream);
+                   const float *amp, const float *opd_m, double lens_focal_m, int32_t flags,
+                   double *dx_out_m, void *stream);
 
 /* Many independent planes in one launch per sweep (e.g. the wavelengths of a broadband
  * model, Sec. 1.2). Each entry has the meaning of the fresnel_step arguments. `planes` is a

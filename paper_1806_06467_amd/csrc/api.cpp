@@ -607,8 +607,9 @@ int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wave
 }
 
 int fresnel_direct(fr_ctx *ctx_, fr_c64 *field, int32_t n, double dx_m, double wavelength_m, double z_m,
-                   const float *amp, const float *opd_m, double lens_focal_m, double *dx_out_m, void *stream) {
-  if (!field || !dx_out_m || n <= 0) return FR_EINVAL;
+                   const float *amp, const float *opd_m, double lens_focal_m, int32_t flags, double *dx_out_m,
+                   void *stream) {
+  if (!field || !dx_out_m || n <= 0 || (flags & ~FR_ADJOINT)) return FR_EINVAL;
   if (!(dx_m > 0) || !(wavelength_m > 0) || !(z_m > 0) || !std::isfinite(dx_m) || !std::isfinite(wavelength_m) ||
       !std::isfinite(z_m) || !std::isfinite(lens_focal_m))
     return FR_EINVAL;
@@ -626,6 +627,7 @@ int fresnel_direct(fr_ctx *ctx_, fr_c64 *field, int32_t n, double dx_m, double w
   a.n = n;
   a.win = n;
   a.inv_lambda = float(1.0 / wavelength_m);
+  a.flags = flags;
   int st = ctx->direct_phases(n, dx_m, wavelength_m, z_m, lens_focal_m, s, &a.lens, &a.h);
   if (st != FR_OK) return st;
   const float2 *root;

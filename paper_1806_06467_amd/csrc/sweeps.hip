@@ -172,7 +172,8 @@ __device__ __forceinline__ void freq_product(c32 (&v)[E], const float2 *h, int t
 }
 
 // DIRECT: the row half of the direct (single-transform) Fresnel step: the prologue applies the
-// optic times the input quadratic phase (held in the lens slot), then the forward transform only
+// optic times the input quadratic phase (held in the lens slot), then the forward transform only;
+// for its adjoint the inverse transform, then the conjugate of both
 template <class PL, int LINES, bool DIRECT = false>
 __global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const float2 *tw) {
   constexpr int N = PL::N, E = PL::E, T = PL::T;
@@ -215,14 +216,16 @@ __global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const 
     for (int m = 0; m < E; ++m) v[m] = buf.load(vo, unsigned(T * m) * 8u);
   }
   c32 *my = lds + line * LdsLine<N>::size;
-  PL::forward(v, my, t, tw);
   if constexpr (DIRECT) {
-#pragma unroll
-    for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * 8u, v[m]);
-    return;
+    // the adjoint direct step runs this sweep second: inverse transform, then the conjugate
+    // optic and input phase below
+    if (adj) PL::inverse(v, my, t, tw);
+    else PL::forward(v, my, t, tw);
+  } else {
+    PL::forward(v, my, t, tw);
+    freq_product<E, T>(v, pa.h, t, adj);
+    PL::inverse(v, my, t, tw);
   }
-  freq_product<E, T>(v, pa.h, t, adj);
-  PL::inverse(v, my, t, tw);
   if (adj && has_pre(pa)) {
     c32 ph[E];
     if (!pre_optic_row<E, T>(pa, N, y, t, ph)) {
@@ -267,16 +270,25 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
     for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], ph[m]);
   }
   c32 *my = lds + c * LINE;
-  PL::template forward<HALF>(v, my, t, tw);
   if constexpr (DIRECT) {
-    // slot m holds frequency row ky = t + T m of column kx = x
+    // slot m holds frequency row ky = t + T m of column kx = x (after the forward transform;
+    // the adjoint, which runs this sweep first, multiplies the conjugate phases before its
+    // inverse transform)
     const c32 px = ld2(pa.h + x);
+    if (adj) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], cmul(ld2(pa.h + t + T * m), px));
+      for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], cmul(ld2(pa.h + t + T * m), px));
+      PL::template inverse<HALF>(v, my, t, tw);
+    } else {
+      PL::template forward<HALF>(v, my, t, tw);
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cmul(v[m], cmul(ld2(pa.h + t + T * m), px));
+    }
 #pragma unroll
     for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
     return;
   }
+  PL::template forward<HALF>(v, my, t, tw);
   freq_product<E, T>(v, pa.h, t, adj);
   PL::template inverse<HALF>(v, my, t, tw);
   if (!adj && pa.post_surf) {
@@ -320,8 +332,8 @@ hipError_t launch_sweeps(const BatchArgs &fwd, int nf, const BatchArgs &adj, int
   hipError_t e = hipSuccess;
   if (nf && (e = rows(fwd, nf, DIRECT ? "direct_rows" : "row_sweep")) != hipSuccess) return e;
   if (nf && (e = cols(fwd, nf, DIRECT ? "direct_cols" : "col_sweep")) != hipSuccess) return e;
-  if (na && (e = cols(adj, na, "col_sweep_adj")) != hipSuccess) return e;
-  if (na && (e = rows(adj, na, "row_sweep_adj")) != hipSuccess) return e;
+  if (na && (e = cols(adj, na, DIRECT ? "direct_cols_adj" : "col_sweep_adj")) != hipSuccess) return e;
+  if (na && (e = rows(adj, na, DIRECT ? "direct_rows_adj" : "row_sweep_adj")) != hipSuccess) return e;
   return e;
 }
 
@@ -425,9 +437,15 @@ hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const
 
 hipError_t launch_direct_batch(const PlaneArgs *planes, int count, int n, const float2 *root, hipStream_t s,
                                const LaunchHook &hook) {
-  BatchArgs fwd, none;
-  for (int i = 0; i < count; ++i) fwd.p[i] = planes[i];
-#define FR_DIRECT(PL, RL, CL) return launch_sweeps<PL, RL, CL, PL, false, true>(fwd, count, none, 0, root, s, hook)
+  BatchArgs fwd, adj;
+  int nf = 0, na = 0;
+  for (int i = 0; i < count; ++i) {
+    if (planes[i].flags & FR_ADJOINT)
+      adj.p[na++] = planes[i];
+    else
+      fwd.p[nf++] = planes[i];
+  }
+#define FR_DIRECT(PL, RL, CL) return launch_sweeps<PL, RL, CL, PL, false, true>(fwd, nf, adj, na, root, s, hook)
   switch (n) {
     case 64: { using P = Plan<64, 8, 8, 8>; FR_DIRECT(P, 8, 16); }
     case 128: { using P = Plan<128, 16, 16, 8>; FR_DIRECT(P, 16, 32); }

@@ -79,7 +79,7 @@ def lib():
             "fr_fft_size_supported": (_c.c_int, [i32]),
             "fresnel_step": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
             "fresnel_step_batched": (_c.c_int, [_vp, _c.POINTER(FrPlane), i32, _vp]),
-            "fresnel_direct": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, _c.POINTER(f64), _vp]),
+            "fresnel_direct": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _c.POINTER(f64), _vp]),
             "mft_workspace_bytes": (sz, [i32, i32]),
             "mft_forward": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, _vp, _vp, sz, _vp]),
             "mft_adjoint": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, f32, f32, _vp,
@@ -212,9 +212,11 @@ def fresnel_step(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, a
     return _check(st, "fresnel_step")
 
 
-def fresnel_direct(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, stream=None):
-    """In place: field <- the direct (single-transform) Fresnel step of field * optic over z > 0.
-    Returns (output pitch lambda z / (n dx), warning bits)."""
+def fresnel_direct(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, adjoint=False,
+                   stream=None):
+    """In place: field <- the direct (single-transform) Fresnel step of field * optic over z > 0
+    (or its exact adjoint, from the output grid back). Returns (output pitch lambda z / (n dx),
+    warning bits)."""
     _need(field, torch.complex64, None, "field")
     n = field.shape[0]
     _need(field, torch.complex64, (n, n), "field")
@@ -224,7 +226,8 @@ def fresnel_direct(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0,
     dev = field.device.index
     out = _c.c_double(0.0)
     st = lib().fresnel_direct(context(dev).handle, _ptr(field), n, float(dx), float(wavelength), float(z),
-                              _ptr(amp), _ptr(opd), float(lens_focal), _c.byref(out), _stream_handle(dev, stream))
+                              _ptr(amp), _ptr(opd), float(lens_focal), FR_ADJOINT if adjoint else 0,
+                              _c.byref(out), _stream_handle(dev, stream))
     return out.value, _check(st, "fresnel_direct")
 
 

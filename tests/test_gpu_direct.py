@@ -106,3 +106,31 @@ def test_direct_warning_below_the_sampled_distance_and_zero_rows():
     assert np.count_nonzero(to_np(t)) == 0
     with pytest.raises(fb.FrError):
         fb.fresnel_direct(t, dx, lam, -1.0)
+
+
+@pytest.mark.parametrize("optics", [False, True])
+@pytest.mark.parametrize("n,z_mult", [(256, 2.0), (1024, 1.3)])
+def test_direct_adjoint_matches_oracle(n, z_mult, optics):
+    banner(f"fresnel_direct adjoint n={n} optics={optics}")
+    field, amp, opd, dx, lam, z, f = _case(n, 3 * n + optics, z_mult, optics)
+    t = to_gpu(field)
+    dx2, st = fb.fresnel_direct(t, dx, lam, z, amp=None if amp is None else to_gpu(amp, torch.float32),
+                                opd=None if opd is None else to_gpu(opd, torch.float32), lens_focal=f,
+                                adjoint=True)
+    assert st == 0 and dx2 == lam * z / (n * dx)
+    ref = oracle.direct_fresnel_adjoint(f32(field), dx, lam, z)
+    if optics:
+        ref = ref * np.conj(oracle.optic_phasor(n, dx, lam, amp=f32(amp), opd=f32(opd), lens_focal=f))
+    got = to_np(t)
+    assert rel_l2(got, ref) <= TOL
+
+
+def test_direct_round_trip_4096():
+    # forward, then the adjoint scaled by (dx2 / dx)^2: back to the input field
+    n, dx, lam = 4096, 2e-5, 550e-9
+    z = 1.5 * n * dx * dx / lam
+    field = synth.random_field(n, 17)
+    t = to_gpu(field)
+    dx2, _ = fb.fresnel_direct(t, dx, lam, z)
+    fb.fresnel_direct(t, dx, lam, z, adjoint=True)
+    assert rel_l2(to_np(t) * (dx2 / dx) ** 2, f32(field)) <= 2 * TOL

@@ -89,17 +89,18 @@ def test_fresnel_direct_argument_errors(L):
     null = ctypes.c_void_p()
     out = ctypes.c_double(-7.0)
     ref = ctypes.byref(out)
-    assert L.fresnel_direct(null, null, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, ref, null) == fb.FR_EINVAL
-    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, None, null) == fb.FR_EINVAL
-    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 0.0, null, null, 0.0, ref, null) == fb.FR_EINVAL
-    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, -1.0, null, null, 0.0, ref, null) == fb.FR_EINVAL
-    assert L.fresnel_direct(null, FAKE, 256, 0.0, 5e-7, 1.0, null, null, 0.0, ref, null) == fb.FR_EINVAL
-    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, float("inf"), ref, null) == fb.FR_EINVAL
+    assert L.fresnel_direct(null, null, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
+    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, None, null) == fb.FR_EINVAL
+    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 0.0, null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
+    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, -1.0, null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
+    assert L.fresnel_direct(null, FAKE, 256, 0.0, 5e-7, 1.0, null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
+    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, float("inf"), 0, ref, null) == fb.FR_EINVAL
+    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 2, ref, null) == fb.FR_EINVAL
     # power-of-two edges only (the mixed-radix sweeps have no direct variant)
-    assert L.fresnel_direct(null, FAKE, 3584, 1e-4, 5e-7, 1.0, null, null, 0.0, ref, null) == fb.FR_EUNSUPPORTED
-    assert L.fresnel_direct(null, FAKE, 32, 1e-4, 5e-7, 1.0, null, null, 0.0, ref, null) == fb.FR_EUNSUPPORTED
+    assert L.fresnel_direct(null, FAKE, 3584, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, ref, null) == fb.FR_EUNSUPPORTED
+    assert L.fresnel_direct(null, FAKE, 32, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, ref, null) == fb.FR_EUNSUPPORTED
     # valid arguments but no context; the output pitch is written only on success
-    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, ref, null) == fb.FR_EINVAL
+    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
     assert out.value == -7.0
 
 
