@@ -186,8 +186,8 @@ def mft_adjoint(eb, n_d, n_out, du):
 # --------------------------------------------------------------------------------------------
 
 def direct_pitch(n, dx, wavelength, z):
-    """Output pixel pitch of the direct step: lambda z / (n dx)."""
-    return float(wavelength) * float(z) / (n * float(dx))
+    """Output pixel pitch of the direct step: lambda |z| / (n dx)."""
+    return float(wavelength) * abs(float(z)) / (n * float(dx))
 
 
 def quadratic_phase(n, pitch, wavelength, z):
@@ -199,11 +199,12 @@ def quadratic_phase(n, pitch, wavelength, z):
     return np.exp(2j * np.pi * turns)
 
 
-def direct_kernel_matrix(n):
-    """F[k, i] = exp(-2 pi i c(k) c(i) / n): the Fresnel transform kernel between the centred
-    input grid x = c(i) dx and the centred output grid u = c(k) lambda z / (n dx)."""
+def direct_kernel_matrix(n, sign=1):
+    """F[k, i] = exp(-2 pi i sign c(k) c(i) / n): the Fresnel transform kernel exp(-2 pi i x u /
+    (lambda z)) between the centred input grid x = c(i) dx and the centred output grid
+    u = c(k) lambda |z| / (n dx); sign = the sign of z."""
     p = np.outer(centred(n), centred(n)) % n      # exact integer index reduction
-    return np.exp((-2j * np.pi / n) * p)
+    return np.exp((-2j * np.pi * (1 if sign > 0 else -1) / n) * p)
 
 
 def direct_fresnel(u, dx, wavelength, z):
@@ -212,11 +213,12 @@ def direct_fresnel(u, dx, wavelength, z):
         U2(u, v) = dx^2 / (i lambda z) q2(u) q2(v) sum_{x, y} U1(x, y) q1(x) q1(y)
                    exp(-2 pi i (x u + y v) / (lambda z)),
 
-    input pitch dx, output pitch dx2 = lambda z / (n dx), q1 / q2 the quadratic phase on the
-    input / output grid. No e^{ikz} piston (as for the angular-spectrum step).
+    input pitch dx, output pitch dx2 = lambda |z| / (n dx), q1 / q2 the quadratic phase on the
+    input / output grid, z of either sign (z < 0: towards the source; then the kernel's sign
+    flips with z). No e^{ikz} piston (as for the angular-spectrum step).
     Returns (U2, dx2)."""
-    if not float(z) > 0.0:
-        raise ValueError("the direct step takes z > 0")
+    if not float(z) != 0.0:
+        raise ValueError("the direct step takes z != 0")
     u = np.asarray(u, dtype=np.complex128)
     n = u.shape[0]
     if u.shape != (n, n):
@@ -224,7 +226,7 @@ def direct_fresnel(u, dx, wavelength, z):
     dx2 = direct_pitch(n, dx, wavelength, z)
     q1 = quadratic_phase(n, dx, wavelength, z)
     q2 = quadratic_phase(n, dx2, wavelength, z)
-    f = direct_kernel_matrix(n)
+    f = direct_kernel_matrix(n, np.sign(z))
     c = float(dx) ** 2 / (1j * float(wavelength) * float(z))
     inner = (q1[:, None] * u * q1[None, :])
     return c * (q2[:, None] * (f @ inner @ f.T) * q2[None, :]), dx2
@@ -240,8 +242,9 @@ def direct_fresnel_rows(u, dx, wavelength, z, rows):
     q1 = quadratic_phase(n, dx, wavelength, z)
     q2 = quadratic_phase(n, dx2, wavelength, z)
     c = float(dx) ** 2 / (1j * float(wavelength) * float(z))
-    fr = np.exp((-2j * np.pi / n) * (np.outer(centred(n)[rows], centred(n)) % n))   # len(rows) x n
-    f = direct_kernel_matrix(n)
+    sgn = 1 if float(z) > 0 else -1
+    fr = np.exp((-2j * np.pi * sgn / n) * (np.outer(centred(n)[rows], centred(n)) % n))   # len(rows) x n
+    f = direct_kernel_matrix(n, sgn)
     inner = (q1[:, None] * u * q1[None, :])
     return c * (q2[rows][:, None] * ((fr @ inner) @ f.T) * q2[None, :])
 
@@ -255,8 +258,8 @@ def direct_fresnel_adjoint(v, dx, wavelength, z):
 
     so that <direct_fresnel(u), v> = <u, direct_fresnel_adjoint(v)>. Scaled by (dx2 / dx)^2 it
     is the inverse step (the forward one is unitary up to the pitch change)."""
-    if not float(z) > 0.0:
-        raise ValueError("the direct step takes z > 0")
+    if not float(z) != 0.0:
+        raise ValueError("the direct step takes z != 0")
     v = np.asarray(v, dtype=np.complex128)
     n = v.shape[0]
     if v.shape != (n, n):
@@ -264,7 +267,7 @@ def direct_fresnel_adjoint(v, dx, wavelength, z):
     dx2 = direct_pitch(n, dx, wavelength, z)
     q1 = quadratic_phase(n, dx, wavelength, z)
     q2 = quadratic_phase(n, dx2, wavelength, z)
-    fh = direct_kernel_matrix(n).conj()          # the kernel matrix is symmetric: F^H = conj(F)
+    fh = direct_kernel_matrix(n, np.sign(z)).conj()   # the kernel matrix is symmetric: F^H = conj(F)
     c = float(dx) ** 2 / (1j * float(wavelength) * float(z))
     inner = q2.conj()[:, None] * v * q2.conj()[None, :]
     return np.conj(c) * (q1.conj()[:, None] * (fh @ inner @ fh.T) * q1.conj()[None, :])

@@ -22,10 +22,11 @@ def _gaussian_closed_form(n, pitch, lam, w0, z):
     return np.exp(-r2 / (w0 * w0 * q)) / q
 
 
+@pytest.mark.parametrize("sign", [1, -1])
 @pytest.mark.parametrize("n,dx", [(64, 1e-5), (96, 3e-6), (128, 2.5e-5)])
-def test_direct_equals_angular_spectrum_at_periodic_distance(n, dx):
+def test_direct_equals_angular_spectrum_at_periodic_distance(n, dx, sign):
     lam = 550e-9
-    z = n * dx * dx / lam
+    z = sign * n * dx * dx / lam
     rng = np.random.default_rng(n)
     u = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
     got, dx2 = oracle.direct_fresnel(u, dx, lam, z)
@@ -34,13 +35,13 @@ def test_direct_equals_angular_spectrum_at_periodic_distance(n, dx):
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("zr_mult", [0.5, 2.0, 4.0])
+@pytest.mark.parametrize("zr_mult", [0.5, 2.0, 4.0, -3.0])
 def test_direct_gaussian_beam_closed_form(zr_mult):
     n, dx, lam, w0px = 512, 1e-5, 550e-9, 12.0
     w0 = w0px * dx
     z = zr_mult * math.pi * w0 * w0 / lam
     got, dx2 = oracle.direct_fresnel(synth.gaussian_beam(n, w0px), dx, lam, z)
-    assert abs(dx2 - lam * z / (n * dx)) <= 1e-15 * dx2
+    assert abs(dx2 - lam * abs(z) / (n * dx)) <= 1e-15 * dx2
     ref = _gaussian_closed_form(n, dx2, lam, w0, z)
     assert np.max(np.abs(got - ref)) <= 1e-12
 
@@ -63,11 +64,12 @@ def test_direct_rows_and_argument_checks():
     full, _ = oracle.direct_fresnel(u, dx, lam, z)
     rows = [0, 1, 23, 24, 47]
     assert np.max(np.abs(oracle.direct_fresnel_rows(u, dx, lam, z, rows) - full[rows])) <= 1e-13
+    assert np.max(np.abs(oracle.direct_fresnel_rows(u, dx, lam, -z, rows) - oracle.direct_fresnel(u, dx, lam, -z)[0][rows])) <= 1e-13
     with pytest.raises(ValueError):
-        oracle.direct_fresnel(u, dx, lam, -z)
+        oracle.direct_fresnel(u, dx, lam, 0.0)
 
 
-@pytest.mark.parametrize("n,z", [(32, 0.02), (48, 0.7)])
+@pytest.mark.parametrize("n,z", [(32, 0.02), (48, 0.7), (40, -0.3)])
 def test_direct_adjoint_identity_and_inverse(n, z):
     # the adjoint by the dot-product identity against the (pinned) forward step, and the inverse
     # (adjoint times (dx2/dx)^2) undoing the forward step
@@ -81,3 +83,16 @@ def test_direct_adjoint_identity_and_inverse(n, z):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
     back = oracle.direct_fresnel_adjoint(du, dx, lam, z) * (dx2 / dx) ** 2
     assert np.max(np.abs(back - u)) <= 1e-12 * np.max(np.abs(u))
+
+
+def test_direct_negative_distance_is_the_conjugate_step():
+    # the Fresnel integral over -z is the complex conjugate of the one over z applied to the
+    # conjugate field (its kernel exp(i pi r^2 / (lambda z)) / (i lambda z) is conjugated by z -> -z)
+    n, dx, lam = 40, 1.1e-5, 633e-9
+    rng = np.random.default_rng(9)
+    u = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    for z in (0.05, 1.3):
+        neg, dxn = oracle.direct_fresnel(u, dx, lam, -z)
+        pos, dxp = oracle.direct_fresnel(np.conj(u), dx, lam, z)
+        assert dxn == dxp
+        assert np.max(np.abs(neg - np.conj(pos))) <= 1e-13 * np.max(np.abs(pos))
