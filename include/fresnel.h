@@ -95,18 +95,21 @@ int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wave
  *                            exp(-2 pi i ((x - n/2)(kx - n/2) + (y - n/2)(ky - n/2)) / n),
  *         q1(i) = exp(i pi ((i - n/2) dx)^2 / (lambda z)) on the input grid and
  *         q2(k) = exp(i pi ((k - n/2) dx2)^2 / (lambda z)) on the output grid of pitch
- *         dx2 = lambda z / (n dx): the Fresnel integral over z evaluated with one 2-D FFT (no
+ *         dx2 = lambda |z| / (n dx): the Fresnel integral over z evaluated with one 2-D FFT (no
  *         e^{ikz} piston, as for fresnel_step). The output plane is centred on pixel n/2 too.
+ *         Over z < 0 (towards the source) the same formula holds with the signed z (the
+ *         transform's kernel sign flips): the step over -z is the conjugate of the step over z
+ *         applied to the conjugate field.
  * flags : 0, or FR_ADJOINT: the exact adjoint of the call with the same arguments, from the
  *         output grid back to the input grid: field <- conj(optic) D^H(field), with D^H the
  *         conjugate transpose of the step above (conjugate phases and constant, exp(+2 pi i ...)).
  *         Scaled by (dx2 / dx)^2 it undoes the forward step (the step is unitary up to the
  *         pitch change), i.e. it propagates a far-field plane back over -z.
- * z_m   : > 0.   dx_out_m : receives dx2 (written only on success), for either direction.
+ * z_m   : nonzero.   dx_out_m : receives dx2 (written only on success), for either direction.
  * Implemented edges: powers of two from 64 to 8192. Errors: FR_EINVAL (null field or dx_out_m,
- * n <= 0, dx / lambda / z <= 0 or not finite, unknown flag), FR_EUNSUPPORTED (edge). Warning:
- * FR_W_DIRECT_UNDERSAMPLED (z < n dx^2 / lambda, where the angular-spectrum step is the sampled
- * one). Uses no workspace (in place, two sweeps). */
+ * n <= 0, dx / lambda <= 0, z = 0, a non-finite value, unknown flag), FR_EUNSUPPORTED (edge).
+ * Warning: FR_W_DIRECT_UNDERSAMPLED (|z| < n dx^2 / lambda, where the angular-spectrum step is
+ * the sampled one). Uses no workspace (in place, two sweeps). */
 int fresnel_direct(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wavelength_m, double z_m,
                    const float *amp, const float *opd_m, double lens_focal_m, int32_t flags,
                    double *dx_out_m, void *stream);

@@ -255,8 +255,9 @@ int Ctx::lens(int n, double dx, double lam, double f, hipStream_t s, const float
 // exp(+i pi r^2 / (lambda z))):
 //   pre[i]  = (-1)^i exp(i pi c(i)^2 dx^2 (1/z - 1/f) / lambda)  (a thin lens of focal f folded
 //             in; 1/f = 0 without one)
-//   post[k] = (-1)^k exp(i pi c(k)^2 dx2^2 / (lambda z)) (dx / sqrt(lambda z)) e^{-i pi/4},
-//             dx2 = lambda z / (n dx)
+//   post[k] = (-1)^k exp(i pi c(k)^2 dx2^2 / (lambda z)) (dx / sqrt(lambda |z|)) e^{-i pi sign(z)/4},
+//             dx2 = lambda |z| / (n dx)   (z of either sign; over z < 0 the transforms' kernel
+//             sign flips, kTowardSource)
 // so that post[ky] post[kx] DFT2(pre[y] pre[x] U)[ky][kx] is the step: the signs centre the
 // transform on pixel n/2 (exp(-2 pi i c(k) c(i) / n) = W^{ki} (-1)^{k + i} (-1)^{n/2}, the last
 // factor squaring to 1 over the two axes) and the two roots make the constant dx^2/(i lambda z).
@@ -270,13 +271,15 @@ int Ctx::direct_phases(int n, double dx, double lam, double z, double f, hipStre
       return FR_OK;
     }
     std::vector<float2> h(n);
-    const double dx2 = lam * z / (double(n) * dx);
+    const double dx2 = lam * std::fabs(z) / (double(n) * dx);
     const double coef = input ? dx * dx * (1.0 / z - (f != 0.0 ? 1.0 / f : 0.0)) / (2.0 * lam)
                               : dx2 * dx2 / (2.0 * lam * z);
-    const double scale = input ? 1.0 : dx / std::sqrt(lam * z);
+    const double scale = input ? 1.0 : dx / std::sqrt(lam * std::fabs(z));
+    // the root of dx^2 / (i lambda z) is (dx / sqrt(lambda |z|)) exp(-i pi sign(z) / 4)
+    const double root_turn = input ? 0.0 : (z > 0 ? -0.125 : 0.125);
     for (int i = 0; i < n; ++i) {
       const long long c = i - n / 2;
-      const double turns = double(c * c) * coef + 0.5 * double(i & 1) - (input ? 0.0 : 0.125);
+      const double turns = double(c * c) * coef + 0.5 * double(i & 1) + root_turn;
       h[i] = turn_to_c64(turns, scale);
     }
     void *d;
@@ -610,7 +613,7 @@ int fresnel_direct(fr_ctx *ctx_, fr_c64 *field, int32_t n, double dx_m, double w
                    const float *amp, const float *opd_m, double lens_focal_m, int32_t flags, double *dx_out_m,
                    void *stream) {
   if (!field || !dx_out_m || n <= 0 || (flags & ~FR_ADJOINT)) return FR_EINVAL;
-  if (!(dx_m > 0) || !(wavelength_m > 0) || !(z_m > 0) || !std::isfinite(dx_m) || !std::isfinite(wavelength_m) ||
+  if (!(dx_m > 0) || !(wavelength_m > 0) || z_m == 0.0 || !std::isfinite(dx_m) || !std::isfinite(wavelength_m) ||
       !std::isfinite(z_m) || !std::isfinite(lens_focal_m))
     return FR_EINVAL;
   if (!fr::fresnel_size_supported(n)) return FR_EUNSUPPORTED;
@@ -627,7 +630,7 @@ int fresnel_direct(fr_ctx *ctx_, fr_c64 *field, int32_t n, double dx_m, double w
   a.n = n;
   a.win = n;
   a.inv_lambda = float(1.0 / wavelength_m);
-  a.flags = flags;
+  a.flags = flags | (z_m < 0 ? fr::kTowardSource : 0);
   int st = ctx->direct_phases(n, dx_m, wavelength_m, z_m, lens_focal_m, s, &a.lens, &a.h);
   if (st != FR_OK) return st;
   const float2 *root;
@@ -635,8 +638,8 @@ int fresnel_direct(fr_ctx *ctx_, fr_c64 *field, int32_t n, double dx_m, double w
   if (st != FR_OK) return st;
   e = fr::launch_direct_batch(&a, 1, n, root, s, ctx->hook());
   if (e != hipSuccess) return fr::record_hip(e);
-  *dx_out_m = wavelength_m * z_m / (double(n) * dx_m);
-  return z_m < double(n) * dx_m * dx_m / wavelength_m ? FR_W_DIRECT_UNDERSAMPLED : FR_OK;
+  *dx_out_m = wavelength_m * std::fabs(z_m) / (double(n) * dx_m);
+  return std::fabs(z_m) < double(n) * dx_m * dx_m / wavelength_m ? FR_W_DIRECT_UNDERSAMPLED : FR_OK;
 }
 
 }  // extern "C"

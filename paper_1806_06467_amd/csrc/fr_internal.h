@@ -28,6 +28,7 @@ struct LaunchHook {
 // same kind of map stored in 4-column tiles (post_tiled_index) so that the column sweep, which
 // applies it, reads it contiguously.
 constexpr int kSourceOptic = 2;  // forward only: the input field is 1 (it is not read)
+constexpr int kTowardSource = 4;  // direct step over z < 0: the transforms' kernel sign flips
 struct PlaneArgs {
   float2 *field;             // n x n, in place
   const float *amp;          // win x win or null
@@ -39,7 +40,7 @@ struct PlaneArgs {
   float inv_lambda;          // 1 / lambda [1/m]
   int n;                     // plane edge
   int win;                   // window edge of amp / opd (n for full maps)
-  int flags;                 // FR_ADJOINT | kSourceOptic
+  int flags;                 // FR_ADJOINT | kSourceOptic | kTowardSource
 };
 
 // element (y, x) of an n x n map stored in 4-column tiles: tile x/4 holds rows 0..n-1 of its

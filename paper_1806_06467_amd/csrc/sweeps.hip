@@ -219,7 +219,8 @@ __global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const 
   if constexpr (DIRECT) {
     // the adjoint direct step runs this sweep second: inverse transform, then the conjugate
     // optic and input phase below
-    if (adj) PL::inverse(v, my, t, tw);
+    // the transform's kernel sign: + for the adjoint, flipped again over z < 0
+    if (adj != bool(pa.flags & kTowardSource)) PL::inverse(v, my, t, tw);
     else PL::forward(v, my, t, tw);
   } else {
     PL::forward(v, my, t, tw);
@@ -275,12 +276,14 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
     // the adjoint, which runs this sweep first, multiplies the conjugate phases before its
     // inverse transform)
     const c32 px = ld2(pa.h + x);
+    const bool inv = adj != bool(pa.flags & kTowardSource);  // kernel sign, as in the row sweep
     if (adj) {
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], cmul(ld2(pa.h + t + T * m), px));
-      PL::template inverse<HALF>(v, my, t, tw);
-    } else {
-      PL::template forward<HALF>(v, my, t, tw);
+    }
+    if (inv) PL::template inverse<HALF>(v, my, t, tw);
+    else PL::template forward<HALF>(v, my, t, tw);
+    if (!adj) {
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = cmul(v[m], cmul(ld2(pa.h + t + T * m), px));
     }

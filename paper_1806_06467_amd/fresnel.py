@@ -214,7 +214,7 @@ def fresnel_step(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, a
 
 def fresnel_direct(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, adjoint=False,
                    stream=None):
-    """In place: field <- the direct (single-transform) Fresnel step of field * optic over z > 0
+    """In place: field <- the direct (single-transform) Fresnel step of field * optic over z != 0
     (or its exact adjoint, from the output grid back). Returns (output pitch lambda z / (n dx),
     warning bits)."""
     _need(field, torch.complex64, None, "field")

@@ -92,7 +92,7 @@ def test_fresnel_direct_argument_errors(L):
     assert L.fresnel_direct(null, null, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
     assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, None, null) == fb.FR_EINVAL
     assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 0.0, null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
-    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, -1.0, null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
+    assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, float("nan"), null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
     assert L.fresnel_direct(null, FAKE, 256, 0.0, 5e-7, 1.0, null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
     assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, float("inf"), 0, ref, null) == fb.FR_EINVAL
     assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 2, ref, null) == fb.FR_EINVAL
