@@ -55,6 +55,7 @@ extern "C" {
 
 /* flags of fresnel_step and fresnel_direct */
 #define FR_ADJOINT 1 /* apply the adjoint: the step's adjoint first, then the conjugate optic */
+#define FR_INVERSE 2 /* fresnel_direct only: the inverse of the optic-free step             */
 
 typedef struct fr_ctx fr_ctx;
 typedef struct {
@@ -105,6 +106,8 @@ int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wave
  *         conjugate transpose of the step above (conjugate phases and constant, exp(+2 pi i ...)).
  *         Scaled by (dx2 / dx)^2 it undoes the forward step (the step is unitary up to the
  *         pitch change), i.e. it propagates a far-field plane back over -z.
+ *         FR_INVERSE: that scaled adjoint, the inverse of the step (no optic: amp, opd_m NULL and
+ *         lens_focal_m 0, else FR_EINVAL).
  * z_m   : nonzero.   dx_out_m : receives dx2 (written only on success), for either direction.
  * Implemented edges: powers of two from 64 to 8192. Errors: FR_EINVAL (null field or dx_out_m,
  * n <= 0, dx / lambda <= 0, z = 0, a non-finite value, unknown flag), FR_EUNSUPPORTED (edge).
@@ -113,6 +116,36 @@ int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wave
 int fresnel_direct(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wavelength_m, double z_m,
                    const float *amp, const float *opd_m, double lens_focal_m, int32_t flags,
                    double *dx_out_m, void *stream);
+
+/* ---- Gaussian pilot-beam planner (Sec. 1.1: both the direct and the angular-spectrum method
+ * propagate a wavefront; which one a step takes follows a Gaussian pilot beam, after Lawrence) --
+ * The beam has its waist (radius w0_m) at z_waist_m; its Rayleigh distance is
+ * z_R = pi w0^2 / lambda. A plane within z_R of the waist (|z - z_waist| <= z_R) is near: its
+ * field is held on the waist-plane pitch dx_w and moved by the angular-spectrum step. A farther
+ * plane is far: its field is held on the pitch lambda |d| / (n dx_w), d = z - z_waist, and is the
+ * direct step over d of the waist-plane field. fr_plan_route writes into steps[] (capacity >= 2)
+ * the steps that carry the field from z_from_m to z_to_m and returns their count (0, 1 or 2):
+ *   near -> near: one FR_ROUTE_AS step over z_to - z_from;
+ *   otherwise through the waist plane: leaving a far plane by FR_ROUTE_DIRECT_INVERSE, moving
+ *   between near planes and the waist by FR_ROUTE_AS, reaching a far plane by FR_ROUTE_DIRECT
+ *   (steps of zero length are left out).
+ * Each step gives the call to make: FR_ROUTE_AS: fresnel_step over z_m at pitch dx_in_m;
+ * FR_ROUTE_DIRECT: fresnel_direct over z_m from pitch dx_in_m (it returns dx_out_m);
+ * FR_ROUTE_DIRECT_INVERSE: fresnel_direct(..., FR_INVERSE) with dx = dx_out_m over z_m. dx_m is
+ * the pitch of the field at z_from_m (near or far as
+ * that plane is). Host-only arithmetic (no device call). Errors: FR_EINVAL (w0, lambda, dx <= 0,
+ * n <= 0, a non-finite value, steps NULL or capacity < 2). */
+#define FR_ROUTE_AS 1
+#define FR_ROUTE_DIRECT 2
+#define FR_ROUTE_DIRECT_INVERSE 3
+typedef struct {
+  int32_t kind;     /* FR_ROUTE_* */
+  double z_m;       /* signed distance of the call */
+  double dx_in_m;   /* pitch of the field before the step */
+  double dx_out_m;  /* pitch after it */
+} fr_route_step;
+int fr_plan_route(double w0_m, double z_waist_m, double wavelength_m, int32_t n, double dx_m,
+                  double z_from_m, double z_to_m, fr_route_step *steps, int32_t capacity);
 
 /* Many independent planes in one launch per sweep (e.g. the wavelengths of a broadband
  * model, Sec. 1.2). Each entry has the meaning of the fresnel_step arguments. `planes` is a

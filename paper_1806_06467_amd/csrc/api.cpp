@@ -261,10 +261,12 @@ int Ctx::lens(int n, double dx, double lam, double f, hipStream_t s, const float
 // so that post[ky] post[kx] DFT2(pre[y] pre[x] U)[ky][kx] is the step: the signs centre the
 // transform on pixel n/2 (exp(-2 pi i c(k) c(i) / n) = W^{ki} (-1)^{k + i} (-1)^{n/2}, the last
 // factor squaring to 1 over the two axes) and the two roots make the constant dx^2/(i lambda z).
+// With `inverse` the output phases of the two axes carry dx2 / dx each: the factor (dx2 / dx)^2
+// that turns the adjoint into the inverse step.
 int Ctx::direct_phases(int n, double dx, double lam, double z, double f, hipStream_t s, const float2 **pre,
-                       const float2 **post) {
+                       const float2 **post, bool inverse) {
   const TableKey kpre{kDirectPre, n, bits(dx), bits(lam), bits(z), bits(f)};
-  const TableKey kpost{kDirectPost, n, bits(dx), bits(lam), bits(z), 0};
+  const TableKey kpost{kDirectPost, n, bits(dx), bits(lam), bits(z), inverse ? 1u : 0u};
   auto build = [&](const TableKey &key, bool input, const float2 **out) -> int {
     if (auto it = tables.find(key); it != tables.end()) {
       *out = static_cast<const float2 *>(it->second);
@@ -274,7 +276,8 @@ int Ctx::direct_phases(int n, double dx, double lam, double z, double f, hipStre
     const double dx2 = lam * std::fabs(z) / (double(n) * dx);
     const double coef = input ? dx * dx * (1.0 / z - (f != 0.0 ? 1.0 / f : 0.0)) / (2.0 * lam)
                               : dx2 * dx2 / (2.0 * lam * z);
-    const double scale = input ? 1.0 : dx / std::sqrt(lam * std::fabs(z));
+    // (the inverse's (dx2 / dx)^2 is split over the two axes' tables)
+    const double scale = input ? 1.0 : dx / std::sqrt(lam * std::fabs(z)) * (inverse ? dx2 / dx : 1.0);
     // the root of dx^2 / (i lambda z) is (dx / sqrt(lambda |z|)) exp(-i pi sign(z) / 4)
     const double root_turn = input ? 0.0 : (z > 0 ? -0.125 : 0.125);
     for (int i = 0; i < n; ++i) {
@@ -609,10 +612,45 @@ int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wave
   return fresnel_step_batched(ctx, &p, 1, stream);
 }
 
+int fr_plan_route(double w0_m, double z_waist_m, double wavelength_m, int32_t n, double dx_m, double z_from_m,
+                  double z_to_m, fr_route_step *steps, int32_t capacity) {
+  if (!steps || capacity < 2 || n <= 0 || !(w0_m > 0) || !(wavelength_m > 0) || !(dx_m > 0)) return FR_EINVAL;
+  for (double v : {w0_m, z_waist_m, wavelength_m, dx_m, z_from_m, z_to_m})
+    if (!std::isfinite(v)) return FR_EINVAL;
+  const double z_r = M_PI * w0_m * w0_m / wavelength_m;
+  const double d_from = z_from_m - z_waist_m, d_to = z_to_m - z_waist_m;
+  const bool near_from = std::fabs(d_from) <= z_r, near_to = std::fabs(d_to) <= z_r;
+  // pitch of the waist plane (near planes share it; a far plane's pitch is lambda |d| / (n dx_w))
+  const double dx_w = near_from ? dx_m : wavelength_m * std::fabs(d_from) / (double(n) * dx_m);
+  auto far_pitch = [&](double d) { return wavelength_m * std::fabs(d) / (double(n) * dx_w); };
+  int k = 0;
+  auto add = [&](int kind, double z, double dx_in, double dx_out) {
+    steps[k].kind = kind;
+    steps[k].z_m = z;
+    steps[k].dx_in_m = dx_in;
+    steps[k].dx_out_m = dx_out;
+    ++k;
+  };
+  if (z_to_m == z_from_m) return 0;
+  if (near_from && near_to) {
+    add(FR_ROUTE_AS, z_to_m - z_from_m, dx_w, dx_w);
+    return k;
+  }
+  // through the waist plane
+  if (!near_from) add(FR_ROUTE_DIRECT_INVERSE, d_from, dx_m, dx_w);
+  if (near_from && d_from != 0.0) add(FR_ROUTE_AS, -d_from, dx_w, dx_w);
+  if (near_to && d_to != 0.0) add(FR_ROUTE_AS, d_to, dx_w, dx_w);
+  if (!near_to) add(FR_ROUTE_DIRECT, d_to, dx_w, far_pitch(d_to));
+  return k;
+}
+
 int fresnel_direct(fr_ctx *ctx_, fr_c64 *field, int32_t n, double dx_m, double wavelength_m, double z_m,
                    const float *amp, const float *opd_m, double lens_focal_m, int32_t flags, double *dx_out_m,
                    void *stream) {
-  if (!field || !dx_out_m || n <= 0 || (flags & ~FR_ADJOINT)) return FR_EINVAL;
+  if (!field || !dx_out_m || n <= 0 || (flags & ~(FR_ADJOINT | FR_INVERSE)) || flags == (FR_ADJOINT | FR_INVERSE))
+    return FR_EINVAL;
+  const bool inverse = flags & FR_INVERSE;
+  if (inverse && (amp || opd_m || lens_focal_m != 0.0)) return FR_EINVAL;
   if (!(dx_m > 0) || !(wavelength_m > 0) || z_m == 0.0 || !std::isfinite(dx_m) || !std::isfinite(wavelength_m) ||
       !std::isfinite(z_m) || !std::isfinite(lens_focal_m))
     return FR_EINVAL;
@@ -630,8 +668,8 @@ int fresnel_direct(fr_ctx *ctx_, fr_c64 *field, int32_t n, double dx_m, double w
   a.n = n;
   a.win = n;
   a.inv_lambda = float(1.0 / wavelength_m);
-  a.flags = flags | (z_m < 0 ? fr::kTowardSource : 0);
-  int st = ctx->direct_phases(n, dx_m, wavelength_m, z_m, lens_focal_m, s, &a.lens, &a.h);
+  a.flags = (inverse ? FR_ADJOINT : flags) | (z_m < 0 ? fr::kTowardSource : 0);
+  int st = ctx->direct_phases(n, dx_m, wavelength_m, z_m, lens_focal_m, s, &a.lens, &a.h, inverse);
   if (st != FR_OK) return st;
   const float2 *root;
   st = ctx->twiddles(n, s, &root);

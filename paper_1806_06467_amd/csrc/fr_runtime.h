@@ -70,7 +70,7 @@ struct Ctx {
   int transfer(int n, double dx, double lam, double z, hipStream_t s, const float2 **out);
   int lens(int n, double dx, double lam, double f, hipStream_t s, const float2 **out);
   int direct_phases(int n, double dx, double lam, double z, double f, hipStream_t s, const float2 **pre,
-                    const float2 **post);
+                    const float2 **post, bool inverse = false);
   int mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out,
                  bool transposed = false);
   int dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **out);

@@ -27,6 +27,8 @@ FR_W_AS_UNDERSAMPLED = 1
 FR_W_MFT_ALIASED = 2
 FR_W_DIRECT_UNDERSAMPLED = 4
 FR_ADJOINT = 1
+FR_INVERSE = 2
+FR_ROUTE_AS, FR_ROUTE_DIRECT, FR_ROUTE_DIRECT_INVERSE = 1, 2, 3
 FR_TRAIN_NO_OCCULTER = 1
 FR_TRAIN_GRAD = 2
 FR_TRAIN_BATCHED = 4
@@ -40,6 +42,10 @@ class FrError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
         super().__init__(f"{where}: {status_string(status)} (status {status})")
+
+
+class FrRouteStep(_c.Structure):
+    _fields_ = [("kind", _c.c_int32), ("z_m", _c.c_double), ("dx_in_m", _c.c_double), ("dx_out_m", _c.c_double)]
 
 
 class FrPlane(_c.Structure):
@@ -80,6 +86,7 @@ def lib():
             "fresnel_step": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
             "fresnel_step_batched": (_c.c_int, [_vp, _c.POINTER(FrPlane), i32, _vp]),
             "fresnel_direct": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _c.POINTER(f64), _vp]),
+            "fr_plan_route": (_c.c_int, [f64, f64, f64, i32, f64, f64, f64, _c.POINTER(FrRouteStep), i32]),
             "mft_workspace_bytes": (sz, [i32, i32]),
             "mft_forward": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, _vp, _vp, sz, _vp]),
             "mft_adjoint": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, f32, f32, _vp,
@@ -213,7 +220,7 @@ def fresnel_step(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, a
 
 
 def fresnel_direct(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, adjoint=False,
-                   stream=None):
+                   inverse=False, stream=None):
     """In place: field <- the direct (single-transform) Fresnel step of field * optic over z != 0
     (or its exact adjoint, from the output grid back). Returns (output pitch lambda z / (n dx),
     warning bits)."""
@@ -226,9 +233,36 @@ def fresnel_direct(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0,
     dev = field.device.index
     out = _c.c_double(0.0)
     st = lib().fresnel_direct(context(dev).handle, _ptr(field), n, float(dx), float(wavelength), float(z),
-                              _ptr(amp), _ptr(opd), float(lens_focal), FR_ADJOINT if adjoint else 0,
+                              _ptr(amp), _ptr(opd), float(lens_focal),
+                              (FR_ADJOINT if adjoint else 0) | (FR_INVERSE if inverse else 0),
                               _c.byref(out), _stream_handle(dev, stream))
     return out.value, _check(st, "fresnel_direct")
+
+
+def plan_route(w0, z_waist, wavelength, n, dx, z_from, z_to):
+    """fr_plan_route: the steps (kind, z, dx_in, dx_out) carrying a field from z_from to z_to
+    under a Gaussian pilot beam of waist w0 at z_waist."""
+    steps = (FrRouteStep * 2)()
+    k = _check(lib().fr_plan_route(float(w0), float(z_waist), float(wavelength), int(n), float(dx),
+                                   float(z_from), float(z_to), steps, 2), "fr_plan_route")
+    return [(steps[i].kind, steps[i].z_m, steps[i].dx_in_m, steps[i].dx_out_m) for i in range(k)]
+
+
+def follow_route(field, wavelength, steps, stream=None):
+    """Run planned steps on `field` in place (fresnel_step / fresnel_direct, one call each);
+    returns the final pitch."""
+    dx = None
+    for kind, z, dx_in, dx_out in steps:
+        if kind == FR_ROUTE_AS:
+            fresnel_step(field, dx_in, wavelength, z, stream=stream)
+        elif kind == FR_ROUTE_DIRECT:
+            fresnel_direct(field, dx_in, wavelength, z, stream=stream)
+        elif kind == FR_ROUTE_DIRECT_INVERSE:
+            fresnel_direct(field, dx_out, wavelength, z, inverse=True, stream=stream)
+        else:
+            raise ValueError("unknown route step")
+        dx = dx_out
+    return dx
 
 
 def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens_focals=None,

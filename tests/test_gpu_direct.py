@@ -136,3 +136,38 @@ def test_direct_round_trip_4096(sign):
     dx2, _ = fb.fresnel_direct(t, dx, lam, z)
     fb.fresnel_direct(t, dx, lam, z, adjoint=True)
     assert rel_l2(to_np(t) * (dx2 / dx) ** 2, f32(field)) <= 2 * TOL
+
+
+def test_gaussian_beam_along_planned_routes():
+    # the planner's routes run with the GPU steps: waist -> 5 z_R (far, direct step) -> 0.5 z_R
+    # (near: inverse direct step back to the waist, then the angular spectrum) -> -3 z_R (far on
+    # the other side of the waist), each plane against the Gaussian-beam closed form on its grid
+    n, dx, lam = 1024, 1e-5, 600e-9
+    w0 = (n / 40.0) * dx
+    zr = math.pi * w0 * w0 / lam
+    banner("Gaussian beam along planned routes, n=1024")
+    t = to_gpu(synth.gaussian_beam(n, n / 40.0))
+    z, pitch = 0.0, dx
+    for z_next, kinds in ((5.0 * zr, [fb.FR_ROUTE_DIRECT]),
+                          (0.5 * zr, [fb.FR_ROUTE_DIRECT_INVERSE, fb.FR_ROUTE_AS]),
+                          (-3.0 * zr, [fb.FR_ROUTE_AS, fb.FR_ROUTE_DIRECT])):
+        steps = fb.plan_route(w0, 0.0, lam, n, pitch, z, z_next)
+        assert [s[0] for s in steps] == kinds
+        pitch = fb.follow_route(t, lam, steps)
+        z = z_next
+        zeta = z / zr
+        r2 = (synth.radius_grid(n) * pitch) ** 2
+        ref = np.exp(-r2 / (w0 * w0 * (1 + 1j * zeta))) / (1 + 1j * zeta)
+        assert rel_l2(to_np(t), ref) <= 3 * TOL
+
+
+def test_direct_inverse_undoes_the_step():
+    n, dx, lam = 512, 2e-5, 550e-9
+    for z in (2.3 * n * dx * dx / lam, -1.4 * n * dx * dx / lam):
+        field = synth.random_field(n, 23)
+        t = to_gpu(field)
+        dx2, _ = fb.fresnel_direct(t, dx, lam, z)
+        fb.fresnel_direct(t, dx, lam, z, inverse=True)
+        assert rel_l2(to_np(t), f32(field)) <= 2 * TOL
+    with pytest.raises(fb.FrError):   # the inverse takes no optic
+        fb.fresnel_direct(t, dx, lam, z, inverse=True, lens_focal=1.0)
