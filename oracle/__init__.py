@@ -26,7 +26,7 @@ from .core import (  # noqa: F401
     centred, signed_index, dft_matrix, dft2, idft2, transfer_function,
     as_propagate, as_propagate_rows, optic_phasor, fresnel_step, mft_matrix, mft, mft_adjoint,
     direct_pitch, quadratic_phase, direct_kernel_matrix, direct_fresnel, direct_fresnel_rows,
-    direct_fresnel_adjoint,
+    direct_fresnel_adjoint, transfer_function_exact, as_propagate_exact,
 )
 from .train import (  # noqa: F401
     embed, extract, dm_influence, dm_surface, TrainGeometry, train_forward,

@@ -271,3 +271,36 @@ def direct_fresnel_adjoint(v, dx, wavelength, z):
     c = float(dx) ** 2 / (1j * float(wavelength) * float(z))
     inner = q2.conj()[:, None] * v * q2.conj()[None, :]
     return np.conj(c) * (q1.conj()[:, None] * (fh @ inner @ fh.T) * q1.conj()[None, :])
+
+
+# --------------------------------------------------------------------------------------------
+# O10. Angular-spectrum step with the exact (non-paraxial) transfer function (Sec. 1.1: the
+#      angular-spectrum method after Lawrence, here without the paraxial approximation).
+# --------------------------------------------------------------------------------------------
+
+def transfer_function_exact(n, dx, wavelength, z):
+    """H[ky, kx] = exp(2 pi i z (sqrt(1/lambda^2 - f^2) - 1/lambda)) for f^2 = fx^2 + fy^2 below
+    1/lambda^2 (the piston exp(2 pi i z / lambda) left out, as for the paraxial form, which is
+    this phase to second order in lambda f); evanescent components (f^2 > 1/lambda^2) decay as
+    exp(-2 pi |z| sqrt(f^2 - 1/lambda^2)) in either direction. The phase is taken in turns as
+    -z f^2 / (sqrt(1/lambda^2 - f^2) + 1/lambda) (no cancellation) and reduced before the
+    exponential."""
+    k = signed_index(n)
+    lam = float(wavelength)
+    f2 = (k[:, None] ** 2 + k[None, :] ** 2).astype(np.float64) / (n * float(dx)) ** 2
+    inv2 = 1.0 / (lam * lam)
+    prop = f2 < inv2
+    root = np.sqrt(np.where(prop, inv2 - f2, 0.0))
+    turns = np.where(prop, -float(z) * f2 / (root + 1.0 / lam), 0.0)
+    turns = turns - np.round(turns)
+    decay = np.where(prop, 1.0, np.exp(-2.0 * np.pi * abs(float(z)) * np.sqrt(np.where(prop, 0.0, f2 - inv2))))
+    # the piston is left out of the evanescent part too
+    piston = np.where(prop, 1.0, np.exp(-2j * np.pi * ((float(z) / lam) - np.round(float(z) / lam))))
+    return np.where(prop, np.exp(2j * np.pi * turns), decay * piston)
+
+
+def as_propagate_exact(u, dx, wavelength, z):
+    """U(z) = IDFT2( H_exact . DFT2(U) ): one angular-spectrum step with the exact transfer
+    function."""
+    n = u.shape[0]
+    return idft2(transfer_function_exact(n, dx, wavelength, z) * dft2(np.asarray(u, dtype=np.complex128)))
