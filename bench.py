@@ -352,6 +352,25 @@ def main():
                            "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": sweep_bytes(N, 0), "avg_launch_ms": ms}
     dr_planes = N_LAMBDA * dr_calls
     dr_frac = dr_planes * 2 * sweep_bytes(N, 0) / (ms_dr * 1e-3) / 1e9 / HBM_PEAK_GBS
+    # the angular-spectrum step with the exact transfer function over the train's distance, one
+    # plane per call: three sweeps, each reading and writing the whole field
+    ex_calls = 3
+
+    def exact_all():
+        for i in range(N_LAMBDA):
+            fb.fresnel_step_exact(fields[i], DX, lam_pl[i], Z)
+    ms_ex, prof_ex = timed(exact_all, ex_calls, 1, profile=True)
+    ex_rl = {}
+    for name in ("exact_rows_fwd", "exact_cols", "exact_rows_inv"):
+        tot = sum(v[0] for k, v in prof_ex.items() if k.partition("/")[0] == name)
+        cnt = sum(v[1] for k, v in prof_ex.items() if k.partition("/")[0] == name)
+        if cnt:
+            ms = tot / cnt
+            gbs = sweep_bytes(N, 0) / (ms * 1e-3) / 1e9
+            ex_rl[name] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": sweep_bytes(N, 0), "avg_launch_ms": ms}
+    ex_planes = N_LAMBDA * ex_calls
+    ex_frac = ex_planes * 3 * sweep_bytes(N, 0) / (ms_ex * 1e-3) / 1e9 / HBM_PEAK_GBS
     del fields
     if args.copy_calibration:
         src = torch.randn((N, N), dtype=torch.complex64, device=dev)
@@ -394,6 +413,10 @@ def main():
         "direct_fresnel": {
             "value": dr_planes / (ms_dr * 1e-3), "unit": "Fresnel planes/s", "z_m": z_dir,
             "planes_per_call": 1, "hbm_frac_whole_plane": dr_frac, "roofline": dr_rl,
+        },
+        "exact_fresnel": {
+            "value": ex_planes / (ms_ex * 1e-3), "unit": "Fresnel planes/s", "z_m": Z,
+            "planes_per_call": 1, "hbm_frac_whole_plane": ex_frac, "roofline": ex_rl,
         },
         "autotuned": {"choices": tuned, "seconds": t_tune, "loaded_from_file": bool(args.tune_file)},
         "checksum_psf_sum": psf_sum,

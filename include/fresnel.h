@@ -87,6 +87,21 @@ int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wave
                  double z_m, const float *amp, const float *opd_m, double lens_focal_m,
                  int32_t flags, void *stream);
 
+/* ---- angular-spectrum step with the exact transfer function (Sec. 1.1: the angular-spectrum
+ * method after Lawrence, without the paraxial approximation) ----------------------------------
+ * As fresnel_step (same optic, same conventions, same flags), with
+ *   H[ky][kx] = exp(2 pi i z (sqrt(1/lambda^2 - f^2) - 1/lambda)),  f^2 = (kx^2 + ky^2)/(n dx)^2,
+ * the piston exp(2 pi i z / lambda) left out as in the paraxial form (which is this phase to
+ * second order in lambda f); evanescent components (f > 1/lambda) decay as
+ * exp(-2 pi |z| sqrt(f^2 - 1/lambda^2)) in either direction. H is not separable, so a plane takes
+ * three sweeps (row FFT, column FFT * H * inverse FFT, inverse row FFT). Implemented edges:
+ * powers of two from 64 to 8192. Errors: FR_EINVAL (null field, n <= 0, dx / lambda <= 0, a
+ * non-finite value, unknown flag), FR_EUNSUPPORTED (edge). Warning: FR_W_AS_UNDERSAMPLED. Uses no
+ * workspace. */
+int fresnel_step_exact(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wavelength_m,
+                       double z_m, const float *amp, const float *opd_m, double lens_focal_m,
+                       int32_t flags, void *stream);
+
 /* ---- direct (single-transform) Fresnel step (Sec. 1.1: the direct Fresnel method beside the
  * angular spectrum; Sec. 2.3, Eq. 2: the quadratic phase factor, read as
  * exp(+i pi (x^2 + y^2) / (lambda z))) -----------------------------------------------------

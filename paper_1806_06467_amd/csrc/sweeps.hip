@@ -16,6 +16,7 @@
 // neighbouring columns at the same time.
 #include "fft_line.hpp"
 #include "fr_internal.h"
+#include "fr_exact.h"
 #include "../../include/fresnel.h"
 
 namespace fr {
@@ -272,6 +273,36 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   }
   c32 *my = lds + c * LINE;
   if constexpr (DIRECT) {
+    if (pa.flags & kExactTF) {
+      // exact transfer function of frequency (kx, ky) = (x, t + T m) (signed), with the 1/n^2
+      // of the two inverse transforms; conjugated for the adjoint
+      const double *prm = reinterpret_cast<const double *>(pa.h);
+      const double zl = prm[0], a2 = prm[1];
+      PL::template forward<HALF>(v, my, t, tw);
+      const int kx = x < N / 2 ? x : x - N;
+      constexpr float inv_n2 = 1.0f / (float(N) * float(N));
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int k = t + T * m;
+        const int ky = k < N / 2 ? k : k - N;
+        const double u = a2 * double(kx * kx + ky * ky);  // (lambda f)^2
+        float amp = inv_n2, turns;
+        if (u < 1.0) {
+          const double tr = -zl * u / (sqrt(1.0 - u) + 1.0);
+          turns = float(tr - rint(tr));
+        } else {
+          amp *= float(exp(-2.0 * kPi * fabs(zl) * sqrt(u - 1.0)));
+          turns = float(-(zl - rint(zl)));
+        }
+        float sn, cs;
+        sincos_turns(adj ? -turns : turns, &sn, &cs);
+        v[m] = cmul(v[m], c32{amp * cs, amp * sn});
+      }
+      PL::template inverse<HALF>(v, my, t, tw);
+#pragma unroll
+      for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
+      return;
+    }
     // slot m holds frequency row ky = t + T m of column kx = x (after the forward transform;
     // the adjoint, which runs this sweep first, multiplies the conjugate phases before its
     // inverse transform)
@@ -436,6 +467,59 @@ hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const
     default: return hipErrorInvalidValue;
   }
 #undef FR_SWEEPS
+}
+
+// the exact-transfer-function step: row FFT (optic prologue, or plain for the adjoint), column
+// FFT * H * IFFT, row IFFT (plain, or the conjugate optic epilogue for the adjoint), each sweep
+// the direct step's kernel with its own plane arguments
+template <class PL, int RL, int CL>
+hipError_t launch_exact_sweeps(const PlaneArgs *planes, int count, const float2 *tw, hipStream_t s,
+                               const LaunchHook &hook) {
+  constexpr int N = PL::N;
+  BatchArgs a, b, c;
+  for (int i = 0; i < count; ++i) {
+    const PlaneArgs &p = planes[i];
+    const bool adj = p.flags & FR_ADJOINT;
+    PlaneArgs plain = p;
+    plain.amp = plain.opd = plain.pre_surf = plain.post_surf = nullptr;
+    plain.lens = nullptr;
+    a.p[i] = adj ? plain : p;
+    a.p[i].flags = 0;                        // forward row transform (optic first when forward)
+    b.p[i] = p;
+    b.p[i].flags = (p.flags & FR_ADJOINT) | kExactTF;
+    c.p[i] = adj ? p : plain;
+    c.p[i].flags = FR_ADJOINT;               // inverse row transform (conjugate optic after when adjoint)
+  }
+  auto rows = [&](const BatchArgs &x, const char *name) {
+    hook(s, name, count, 0);
+    hipLaunchKernelGGL((row_sweep<PL, RL, true>), dim3(N / RL, count), dim3(PL::T * RL), 0, s, x, tw);
+    hipError_t e = hipGetLastError();
+    hook(s, name, count, 1);
+    return e;
+  };
+  hipError_t e = rows(a, "exact_rows_fwd");
+  if (e != hipSuccess) return e;
+  hook(s, "exact_cols", count, 0);
+  hipLaunchKernelGGL((col_sweep<PL, CL, false, true>), dim3(N / CL, count), dim3(PL::T * CL), 0, s, b, tw);
+  e = hipGetLastError();
+  hook(s, "exact_cols", count, 1);
+  if (e != hipSuccess) return e;
+  return rows(c, "exact_rows_inv");
+}
+
+hipError_t launch_exact_batch(const PlaneArgs *planes, int count, int n, const float2 *root, hipStream_t s,
+                              const LaunchHook &hook) {
+  switch (n) {
+    case 64: return launch_exact_sweeps<Plan<64, 8, 8, 8>, 8, 16>(planes, count, root, s, hook);
+    case 128: return launch_exact_sweeps<Plan<128, 16, 16, 8>, 16, 32>(planes, count, root, s, hook);
+    case 256: return launch_exact_sweeps<Plan<256, 16, 16, 16>, 16, 32>(planes, count, root, s, hook);
+    case 512: return launch_exact_sweeps<Plan<512, 8, 8, 8, 8>, 4, 16>(planes, count, root, s, hook);
+    case 1024: return launch_exact_sweeps<Plan<1024, 16, 16, 8, 8>, 4, 8>(planes, count, root, s, hook);
+    case 2048: return launch_exact_sweeps<Plan<2048, 16, 16, 16, 8>, 2, 8>(planes, count, root, s, hook);
+    case 4096: return launch_exact_sweeps<Plan<4096, 16, 16, 16, 16>, 1, 4>(planes, count, root, s, hook);
+    case 8192: return launch_exact_sweeps<Plan<8192, 16, 16, 16, 16, 2>, 1, 2>(planes, count, root, s, hook);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_direct_batch(const PlaneArgs *planes, int count, int n, const float2 *root, hipStream_t s,

@@ -85,6 +85,7 @@ def lib():
             "fr_fft_size_supported": (_c.c_int, [i32]),
             "fresnel_step": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
             "fresnel_step_batched": (_c.c_int, [_vp, _c.POINTER(FrPlane), i32, _vp]),
+            "fresnel_step_exact": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
             "fresnel_direct": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _c.POINTER(f64), _vp]),
             "fr_plan_route": (_c.c_int, [f64, f64, f64, i32, f64, f64, f64, _c.POINTER(FrRouteStep), i32]),
             "mft_workspace_bytes": (sz, [i32, i32]),
@@ -217,6 +218,23 @@ def fresnel_step(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, a
                             float(z), _ptr(amp), _ptr(opd), float(lens_focal),
                             FR_ADJOINT if adjoint else 0, _stream_handle(dev, stream))
     return _check(st, "fresnel_step")
+
+
+def fresnel_step_exact(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, adjoint=False,
+                       stream=None):
+    """In place: field <- the angular-spectrum step with the exact transfer function (as
+    fresnel_step otherwise). Returns the warning bits."""
+    _need(field, torch.complex64, None, "field")
+    n = field.shape[0]
+    _need(field, torch.complex64, (n, n), "field")
+    for t, nm in ((amp, "amp"), (opd, "opd")):
+        if t is not None:
+            _need(t, torch.float32, (n, n), nm)
+    dev = field.device.index
+    st = lib().fresnel_step_exact(context(dev).handle, _ptr(field), n, float(dx), float(wavelength), float(z),
+                                  _ptr(amp), _ptr(opd), float(lens_focal), FR_ADJOINT if adjoint else 0,
+                                  _stream_handle(dev, stream))
+    return _check(st, "fresnel_step_exact")
 
 
 def fresnel_direct(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, adjoint=False,

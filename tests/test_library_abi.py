@@ -11,7 +11,7 @@ from paper_1806_06467_amd import fresnel as fb
 
 EXPECTED = {
     "fr_create", "fr_destroy", "fr_status_string", "fr_fft_size_supported", "fresnel_step",
-    "fresnel_step_batched", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
+    "fresnel_step_batched", "fresnel_step_exact", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
     "propagate_train_workspace_bytes", "propagate_train", "fr_profile_enable", "fr_profile_read",
     "fr_autotune", "fr_autotune_save", "fr_autotune_load",
 }
@@ -102,6 +102,22 @@ def test_fresnel_direct_argument_errors(L):
     # valid arguments but no context; the output pitch is written only on success
     assert L.fresnel_direct(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, ref, null) == fb.FR_EINVAL
     assert out.value == -7.0
+
+
+def test_fresnel_step_exact_argument_errors(L):
+    null = ctypes.c_void_p()
+    assert L.fresnel_step_exact(null, null, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null) == fb.FR_EINVAL
+    assert L.fresnel_step_exact(null, FAKE, 0, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null) == fb.FR_EINVAL
+    assert L.fresnel_step_exact(null, FAKE, 256, 0.0, 5e-7, 1.0, null, null, 0.0, 0, null) == fb.FR_EINVAL
+    assert L.fresnel_step_exact(null, FAKE, 256, 1e-4, -5e-7, 1.0, null, null, 0.0, 0, null) == fb.FR_EINVAL
+    assert L.fresnel_step_exact(null, FAKE, 256, 1e-4, 5e-7, float("nan"), null, null, 0.0, 0, null) == fb.FR_EINVAL
+    assert L.fresnel_step_exact(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, float("inf"), 0, null) == fb.FR_EINVAL
+    assert L.fresnel_step_exact(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 2, null) == fb.FR_EINVAL
+    # power-of-two edges from 64 only
+    assert L.fresnel_step_exact(null, FAKE, 3584, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null) == fb.FR_EUNSUPPORTED
+    assert L.fresnel_step_exact(null, FAKE, 32, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null) == fb.FR_EUNSUPPORTED
+    # valid arguments but no context
+    assert L.fresnel_step_exact(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null) == fb.FR_EINVAL
 
 
 def test_batched_argument_errors(L):
