@@ -7,12 +7,9 @@
 
 namespace fr {
 
-// PlaneArgs flag of the column sweep's exact mode (the `h` slot then points at two float64
-// parameters: z / lambda and (lambda / (n dx))^2)
-constexpr int kExactTF = 8;
-
 // count planes of power-of-two edge n (count <= kMaxBatch), forward or (FR_ADJOINT) adjoint,
-// in place; `planes[i].h` holds the parameters above, `lens` the thin lens or null
+// in place; `planes[i].h` points at two float64 parameters, z / lambda and (lambda / (n dx))^2,
+// `lens` at the thin lens or null
 hipError_t launch_exact_batch(const PlaneArgs *planes, int count, int n, const float2 *tw, hipStream_t s,
                               const LaunchHook &hook);
 

@@ -244,8 +244,10 @@ __global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const 
 // HALF: the FFT exchanges go through half-size LDS lines in two rounds, so that two blocks fit
 // on a compute unit. DIRECT: the column half of the direct Fresnel step: the forward transform,
 // then the output quadratic phase of both axes (h holds it per index, with the constant's root).
-template <class PL, int LINES, bool HALF = false, bool DIRECT = false>
+// EXACT (with DIRECT): the column sweep of the exact-transfer-function step (fr_exact.h).
+template <class PL, int LINES, bool HALF = false, bool DIRECT = false, bool EXACT = false>
 __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const float2 *tw) {
+  static_assert(!EXACT || (DIRECT && !HALF), "the exact mode runs on full LDS lines");
   constexpr int N = PL::N, E = PL::E, T = PL::T;
   constexpr int G = N / LINES;  // column groups per plane
   // the lines of the LINES columns start 8 float2 apart in the bank pattern (measured: a
@@ -273,15 +275,20 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   }
   c32 *my = lds + c * LINE;
   if constexpr (DIRECT) {
-    if (pa.flags & kExactTF) {
+    if constexpr (EXACT) {
       // exact transfer function of frequency (kx, ky) = (x, t + T m) (signed), with the 1/n^2
-      // of the two inverse transforms; conjugated for the adjoint
+      // of the two inverse transforms; conjugated for the adjoint. The spectrum goes through the
+      // thread's own LDS slots so that the float64 phase of one element at a time is formed
+      // beside no more than the loop's registers (the LDS is free between the transforms: the
+      // forward one ends on a barrier after its last read).
       const double *prm = reinterpret_cast<const double *>(pa.h);
       const double zl = prm[0], a2 = prm[1];
       PL::template forward<HALF>(v, my, t, tw);
+#pragma unroll
+      for (int m = 0; m < E; ++m) my[t + T * m] = v[m];
       const int kx = x < N / 2 ? x : x - N;
       constexpr float inv_n2 = 1.0f / (float(N) * float(N));
-#pragma unroll
+#pragma unroll 1
       for (int m = 0; m < E; ++m) {
         const int k = t + T * m;
         const int ky = k < N / 2 ? k : k - N;
@@ -296,8 +303,11 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
         }
         float sn, cs;
         sincos_turns(adj ? -turns : turns, &sn, &cs);
-        v[m] = cmul(v[m], c32{amp * cs, amp * sn});
+        my[k] = cmul(my[k], c32{amp * cs, amp * sn});
       }
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = my[t + T * m];
+      __syncthreads();  // every slot read back before the inverse transform's first exchange
       PL::template inverse<HALF>(v, my, t, tw);
 #pragma unroll
       for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
@@ -486,7 +496,7 @@ hipError_t launch_exact_sweeps(const PlaneArgs *planes, int count, const float2 
     a.p[i] = adj ? plain : p;
     a.p[i].flags = 0;                        // forward row transform (optic first when forward)
     b.p[i] = p;
-    b.p[i].flags = (p.flags & FR_ADJOINT) | kExactTF;
+    b.p[i].flags = p.flags & FR_ADJOINT;
     c.p[i] = adj ? p : plain;
     c.p[i].flags = FR_ADJOINT;               // inverse row transform (conjugate optic after when adjoint)
   }
@@ -500,7 +510,7 @@ hipError_t launch_exact_sweeps(const PlaneArgs *planes, int count, const float2 
   hipError_t e = rows(a, "exact_rows_fwd");
   if (e != hipSuccess) return e;
   hook(s, "exact_cols", count, 0);
-  hipLaunchKernelGGL((col_sweep<PL, CL, false, true>), dim3(N / CL, count), dim3(PL::T * CL), 0, s, b, tw);
+  hipLaunchKernelGGL((col_sweep<PL, CL, false, true, true>), dim3(N / CL, count), dim3(PL::T * CL), 0, s, b, tw);
   e = hipGetLastError();
   hook(s, "exact_cols", count, 1);
   if (e != hipSuccess) return e;
