@@ -43,6 +43,7 @@ LAMBDA_C = 550e-9
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
+FP64_PEAK_TFLOPS = 78.6  # vector and matrix alike
 
 # HBM bytes per launch from two rocprofv3 --pmc runs of this bench (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch), scaled by what the counters read for a device copy of one 128 MiB plane in
@@ -370,6 +371,27 @@ def main():
             ex_rl[name] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": sweep_bytes(N, 0), "avg_launch_ms": ms}
     ex_planes = N_LAMBDA * ex_calls
+    # the float64 MFT of the occulter plane (4096^2 pupil -> 256^2 focal, n_d = 1024), forward
+    # and adjoint: two complex GEMMs each, 8 (m n^2 + m^2 n) flops per call
+    e64 = fields[0].to(torch.complex128)
+    f64_calls = 3
+    f64_out = {}
+
+    def mft64_fwd():
+        f64_out["b"] = fb.mft_f64(e64, N_D, OCC_M, OCC_DU)
+
+    def mft64_adj():
+        fb.mft_f64(f64_out["b"], N_D, N, OCC_DU, adjoint=True)
+    mft64_fwd()
+    ms_f64f, _ = timed(mft64_fwd, f64_calls, 1)
+    ms_f64a, _ = timed(mft64_adj, f64_calls, 1)
+    f64_flops = 8.0 * (OCC_M * N * N + OCC_M * OCC_M * N)
+    f64_res = {}
+    for name, ms in (("forward", ms_f64f), ("adjoint", ms_f64a)):
+        tf = f64_flops / (ms / f64_calls * 1e-3) / 1e12
+        f64_res[name] = {"ms_per_call": ms / f64_calls, "achieved": tf, "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS, "flops_per_call": f64_flops}
+    del e64, f64_out
     ex_frac = ex_planes * 3 * sweep_bytes(N, 0) / (ms_ex * 1e-3) / 1e9 / HBM_PEAK_GBS
     del fields
     if args.copy_calibration:
@@ -414,6 +436,7 @@ def main():
             "value": dr_planes / (ms_dr * 1e-3), "unit": "Fresnel planes/s", "z_m": z_dir,
             "planes_per_call": 1, "hbm_frac_whole_plane": dr_frac, "roofline": dr_rl,
         },
+        "mft_f64_occulter": {"shape": [N, OCC_M], "n_d": N_D, "du": OCC_DU, "bound": "fp64", **f64_res},
         "exact_fresnel": {
             "value": ex_planes / (ms_ex * 1e-3), "unit": "Fresnel planes/s", "z_m": Z,
             "planes_per_call": 1, "hbm_frac_whole_plane": ex_frac, "roofline": ex_rl,

@@ -61,6 +61,9 @@ typedef struct fr_ctx fr_ctx;
 typedef struct {
   float re, im;
 } fr_c64;
+typedef struct {
+  double re, im;
+} fr_c128;
 
 /* Create a context bound to HIP device `device`. *ctx receives the handle. */
 int fr_create(fr_ctx **ctx, int device);
@@ -189,6 +192,20 @@ int fresnel_step_batched(fr_ctx *ctx, const fr_plane *planes, int32_t count, voi
  * ws: device workspace of at least mft_workspace_bytes(n_in, m_out) bytes (forward) or
  * mft_workspace_bytes(n_out, m_in) bytes (adjoint); contents on entry are ignored.
  * Errors: FR_EINVAL, FR_EWORKSPACE. Warning: FR_W_MFT_ALIASED. */
+/* ---- the MFT in float64 (Sec. 1.1, after Soummer et al.; the paper benchmarks float64) -------
+ * Forward (flags 0): in is the n_pupil x n_pupil pupil field, out the m_focal x m_focal focal
+ *   field, out = (du/n_d) W in W^T with W as for mft_forward (phases from the exact integer
+ *   index product times du/n_d, reduced in float64 turns).
+ * Adjoint (FR_ADJOINT): in is m_focal x m_focal, out n_pupil x n_pupil,
+ *   out = (du/n_d) W^H in conj(W), the exact adjoint of the forward.
+ * in, out: dense row-major fr_c128 in DEVICE memory, not overlapping. ws: device workspace of
+ * 16 n_pupil m_focal bytes (the intermediate product), contents on entry ignored; the caller
+ * owns every buffer. The matrix W is built once per (shape, n_d, du) and cached in the
+ * context. Errors: FR_EINVAL (null buffer, a size <= 0, n_d or du not positive and finite,
+ * unknown flag). */
+int mft_f64(fr_ctx *ctx, const fr_c128 *in, fr_c128 *out, int32_t n_pupil, int32_t m_focal, double n_d,
+            double du, int32_t flags, fr_c128 *ws, void *stream);
+
 size_t mft_workspace_bytes(int32_t n_pupil, int32_t m_focal);
 int mft_forward(fr_ctx *ctx, const fr_c64 *in, int32_t n_in, int32_t ld_in, fr_c64 *out,
                 int32_t m_out, int32_t ld_out, double n_d, double du, const float *out_mask,

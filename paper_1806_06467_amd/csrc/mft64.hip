@@ -1,0 +1,165 @@
+// The matrix Fourier transform in float64 (Sec. 1.1, after Soummer et al.; Sec. 2.3 for the
+// precision the paper benchmarks): out = (du / n_d) W in W^T and its adjoint
+// (du / n_d) W^H in conj(W), as two complex GEMMs in float64. On gfx950 the float64 vector
+// units and the float64 matrix cores have the same dense peak (78.6 TFLOP/s), so the GEMM is an
+// LDS-tiled VALU kernel: each 256-thread block forms a 64 x 64 tile of C from 16-deep slices of
+// A and B staged in LDS, each thread a 4 x 4 sub-tile (rows ty + 16 r, columns tx + 16 c).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/fresnel.h"
+#include "fr_runtime.h"
+
+namespace fr {
+namespace {
+
+struct z64 {
+  double x, y;
+};
+
+constexpr int kTile = 64, kDepth = 16, kPad = kTile + 1;
+
+// C[i][j] = s sum_k A(i, k) B(k, j). A(i, k) = a[i lda + k] (or a[k lda + i] when TA), conjugated
+// when CA; B(k, j) = b[k ldb + j] (or b[j ldb + k] when TB), conjugated when CB.
+template <bool TA, bool CA, bool TB, bool CB>
+__global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, int lda, const z64 *__restrict__ b,
+                                                    int ldb, z64 *__restrict__ c, int ldc, int M, int N, int K,
+                                                    double s) {
+  __shared__ z64 As[kDepth][kPad];
+  __shared__ z64 Bs[kDepth][kPad];
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+  z64 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[r][q] = {0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += kDepth) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      // A slice: 64 rows x 16 k; B slice: 16 k x 64 columns; zero outside the matrices
+      int i, k;
+      if constexpr (TA) { i = e % kTile; k = e / kTile; } else { k = e % kDepth; i = e / kDepth; }
+      z64 va = {0.0, 0.0};
+      if (i0 + i < M && k0 + k < K)
+        va = TA ? a[size_t(k0 + k) * lda + (i0 + i)] : a[size_t(i0 + i) * lda + (k0 + k)];
+      if constexpr (CA) va.y = -va.y;
+      As[k][i] = va;
+      int j, kb;
+      if constexpr (TB) { kb = e % kDepth; j = e / kDepth; } else { j = e % kTile; kb = e / kTile; }
+      z64 vb = {0.0, 0.0};
+      if (j0 + j < N && k0 + kb < K)
+        vb = TB ? b[size_t(j0 + j) * ldb + (k0 + kb)] : b[size_t(k0 + kb) * ldb + (j0 + j)];
+      if constexpr (CB) vb.y = -vb.y;
+      Bs[kb][j] = vb;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kDepth; ++kk) {
+      z64 av[4], bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[r] = As[kk][ty + 16 * r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = Bs[kk][tx + 16 * q];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[r][q].x = fma(av[r].x, bv[q].x, fma(-av[r].y, bv[q].y, acc[r][q].x));
+          acc[r][q].y = fma(av[r].x, bv[q].y, fma(av[r].y, bv[q].x, acc[r][q].y));
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + ty + 16 * r;
+    if (i >= M) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + tx + 16 * q;
+      if (j < N) c[size_t(i) * ldc + j] = {s * acc[r][q].x, s * acc[r][q].y};
+    }
+  }
+}
+
+template <bool TA, bool CA, bool TB, bool CB>
+hipError_t zgemm(const z64 *a, int lda, const z64 *b, int ldb, z64 *c, int ldc, int M, int N, int K, double s,
+                 hipStream_t st, const LaunchHook &hook, const char *name) {
+  hook(st, name, 1, 0);
+  hipLaunchKernelGGL((zgemm_kernel<TA, CA, TB, CB>), dim3((N + kTile - 1) / kTile, (M + kTile - 1) / kTile),
+                     dim3(256), 0, st, a, lda, b, ldb, c, ldc, M, N, K, s);
+  hipError_t e = hipGetLastError();
+  hook(st, name, 1, 1);
+  return e;
+}
+
+uint64_t dbits(double v) {
+  uint64_t u;
+  std::memcpy(&u, &v, sizeof u);
+  return u;
+}
+
+// W[k][x] = exp(-2 pi i (k - m/2)(x - n/2) du / n_d), m x n float64 pairs; the index product is
+// an exact integer, its turns reduced to [-1/2, 1/2] before the exponential
+int mft64_matrix(Ctx *ctx, int m, int n, double n_d, double du, hipStream_t s, const z64 **out) {
+  const TableKey key{kMft64, m, uint64_t(n), dbits(n_d), dbits(du), 0};
+  if (auto it = ctx->tables.find(key); it != ctx->tables.end()) {
+    *out = static_cast<const z64 *>(it->second);
+    return FR_OK;
+  }
+  std::vector<double> w(size_t(2) * m * n);
+  const double r = du / n_d;
+  for (int k = 0; k < m; ++k)
+    for (int x = 0; x < n; ++x) {
+      const double p = double(int64_t(k - m / 2) * int64_t(x - n / 2));
+      double t = p * r;
+      t -= std::rint(t);
+      w[2 * (size_t(k) * n + x)] = std::cos(2.0 * M_PI * t);
+      w[2 * (size_t(k) * n + x) + 1] = -std::sin(2.0 * M_PI * t);
+    }
+  void *d = nullptr;
+  const int st = ctx->upload(key, w.data(), w.size() * sizeof(double), s, &d);
+  *out = static_cast<const z64 *>(d);
+  return st;
+}
+
+}  // namespace
+}  // namespace fr
+
+extern "C" int mft_f64(fr_ctx *ctx_, const fr_c128 *in, fr_c128 *out, int32_t n_pupil, int32_t m_focal,
+                       double n_d, double du, int32_t flags, fr_c128 *ws, void *stream) {
+  if (!in || !out || !ws || n_pupil <= 0 || m_focal <= 0 || (flags & ~FR_ADJOINT)) return FR_EINVAL;
+  if (!(n_d > 0) || !std::isfinite(n_d) || !(du > 0) || !std::isfinite(du)) return FR_EINVAL;
+  fr::Ctx *ctx = reinterpret_cast<fr::Ctx *>(ctx_);
+  if (!ctx) return FR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fr::record_hip(e);
+  const int n = n_pupil, m = m_focal;
+  const fr::z64 *w;
+  int st = fr::mft64_matrix(ctx, m, n, n_d, du, s, &w);
+  if (st != FR_OK) return st;
+  const auto *src = reinterpret_cast<const fr::z64 *>(in);
+  auto *dst = reinterpret_cast<fr::z64 *>(out);
+  auto *t = reinterpret_cast<fr::z64 *>(ws);
+  const double scale = du / n_d;
+  const fr::LaunchHook hook = ctx->hook();
+  if (!(flags & FR_ADJOINT)) {
+    // T = W in (m x n); out = scale T W^T (m x m)
+    e = fr::zgemm<false, false, false, false>(w, n, src, n, t, n, m, n, n, 1.0, s, hook, "zgemm_mft64_1");
+    if (e == hipSuccess)
+      e = fr::zgemm<false, false, true, false>(t, n, w, n, dst, m, m, m, n, scale, s, hook, "zgemm_mft64_2");
+  } else {
+    // T = W^H in (n x m); out = scale T conj(W) (n x n)
+    e = fr::zgemm<true, true, false, false>(w, n, src, m, t, m, n, m, m, 1.0, s, hook, "zgemm_mft64_adj_1");
+    if (e == hipSuccess)
+      e = fr::zgemm<false, false, false, true>(t, m, w, n, dst, n, n, n, m, scale, s, hook, "zgemm_mft64_adj_2");
+  }
+  if (e != hipSuccess) return fr::record_hip(e);
+  return FR_OK;
+}

@@ -89,6 +89,7 @@ def lib():
             "fresnel_direct": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _c.POINTER(f64), _vp]),
             "fr_plan_route": (_c.c_int, [f64, f64, f64, i32, f64, f64, f64, _c.POINTER(FrRouteStep), i32]),
             "mft_workspace_bytes": (sz, [i32, i32]),
+            "mft_f64": (_c.c_int, [_vp, _vp, _vp, i32, i32, f64, f64, i32, _vp, _vp]),
             "mft_forward": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, _vp, _vp, sz, _vp]),
             "mft_adjoint": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, f32, f32, _vp,
                                        _vp, sz, _vp]),
@@ -342,6 +343,25 @@ def mft_forward(inp, n_d, m_out, du, mask=None, out=None, stream=None):
                        float(n_d), float(du), _ptr(mask), _ptr(ws), ws.numel(),
                        _stream_handle(dev, stream))
     _check(st, "mft_forward")
+    return out
+
+
+def mft_f64(inp, n_d, size_out, du, adjoint=False, stream=None):
+    """The MFT in float64: (du/n_d) W inp W^T (n x n -> size_out x size_out), or with adjoint its
+    exact adjoint (du/n_d) W^H inp conj(W) (m x m -> size_out x size_out). inp: dense complex128
+    GPU tensor."""
+    if inp.dtype != torch.complex128 or not inp.is_cuda or not inp.is_contiguous():
+        raise TypeError("inp must be a contiguous complex128 GPU tensor")
+    k = inp.shape[0]
+    if inp.shape != (k, k):
+        raise ValueError("inp must be square")
+    n, m = (size_out, k) if adjoint else (k, size_out)
+    dev = inp.device.index
+    out = torch.empty((size_out, size_out), dtype=torch.complex128, device=inp.device)
+    ws = torch.empty((n * m,), dtype=torch.complex128, device=inp.device)
+    st = lib().mft_f64(context(dev).handle, _ptr(inp), _ptr(out), n, m, float(n_d), float(du),
+                       FR_ADJOINT if adjoint else 0, _ptr(ws), _stream_handle(dev, stream))
+    _check(st, "mft_f64")
     return out
 
 

@@ -11,7 +11,7 @@ from paper_1806_06467_amd import fresnel as fb
 
 EXPECTED = {
     "fr_create", "fr_destroy", "fr_status_string", "fr_fft_size_supported", "fresnel_step",
-    "fresnel_step_batched", "fresnel_step_exact", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
+    "fresnel_step_batched", "fresnel_step_exact", "mft_f64", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
     "propagate_train_workspace_bytes", "propagate_train", "fr_profile_enable", "fr_profile_read",
     "fr_autotune", "fr_autotune_save", "fr_autotune_load",
 }
@@ -118,6 +118,20 @@ def test_fresnel_step_exact_argument_errors(L):
     assert L.fresnel_step_exact(null, FAKE, 32, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null) == fb.FR_EUNSUPPORTED
     # valid arguments but no context
     assert L.fresnel_step_exact(null, FAKE, 256, 1e-4, 5e-7, 1.0, null, null, 0.0, 0, null) == fb.FR_EINVAL
+
+
+def test_mft_f64_argument_errors(L):
+    null = ctypes.c_void_p()
+    assert L.mft_f64(null, null, FAKE, 64, 16, 32.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, null, 64, 16, 32.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 0, null, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 0, 16, 32.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, -1, 32.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 0.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, float("inf"), 0, FAKE, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 2, FAKE, null) == fb.FR_EINVAL
+    # valid arguments but no context
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
 
 
 def test_batched_argument_errors(L):
