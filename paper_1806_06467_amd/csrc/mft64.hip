@@ -2,8 +2,9 @@
 // precision the paper benchmarks): out = (du / n_d) W in W^T and its adjoint
 // (du / n_d) W^H in conj(W), as two complex GEMMs in float64. On gfx950 the float64 vector
 // units and the float64 matrix cores have the same dense peak (78.6 TFLOP/s), so the GEMM is an
-// LDS-tiled VALU kernel: each 256-thread block forms a 64 x 64 tile of C from 16-deep slices of
-// A and B staged in LDS, each thread a 4 x 4 sub-tile (rows ty + 16 r, columns tx + 16 c).
+// LDS-tiled VALU kernel: each 256-thread block forms a 16 R x 16 Q tile of C from 16-deep slices
+// of A and B staged in LDS, each thread an R x Q sub-tile (rows ty + 16 r, columns tx + 16 q):
+// 64 x 64 tiles where they give the launch at least 4 blocks per compute unit, 32 x 32 otherwise.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -20,37 +21,43 @@ struct z64 {
   double x, y;
 };
 
-constexpr int kTile = 64, kDepth = 16, kPad = kTile + 1;
+constexpr int kDepth = 16;
 
 // C[i][j] = s sum_k A(i, k) B(k, j). A(i, k) = a[i lda + k] (or a[k lda + i] when TA), conjugated
 // when CA; B(k, j) = b[k ldb + j] (or b[j ldb + k] when TB), conjugated when CB.
-template <bool TA, bool CA, bool TB, bool CB>
+template <int R, int Q, bool TA, bool CA, bool TB, bool CB>
 __global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, int lda, const z64 *__restrict__ b,
                                                     int ldb, z64 *__restrict__ c, int ldc, int M, int N, int K,
                                                     double s) {
-  __shared__ z64 As[kDepth][kPad];
-  __shared__ z64 Bs[kDepth][kPad];
+  constexpr int TM = 16 * R, TN = 16 * Q;
+  __shared__ z64 As[kDepth][TM + 1];
+  __shared__ z64 Bs[kDepth][TN + 1];
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
-  z64 acc[4][4];
+  const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TN;
+  z64 acc[R][Q];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[r][q] = {0.0, 0.0};
+    for (int q = 0; q < Q; ++q) acc[r][q] = {0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += kDepth) {
+    // A slice: TM rows x 16 k (R elements per thread); zero outside the matrix
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      // A slice: 64 rows x 16 k; B slice: 16 k x 64 columns; zero outside the matrices
+    for (int r = 0; r < R; ++r) {
+      const int e = tid + 256 * r;
       int i, k;
-      if constexpr (TA) { i = e % kTile; k = e / kTile; } else { k = e % kDepth; i = e / kDepth; }
+      if constexpr (TA) { i = e % TM; k = e / TM; } else { k = e % kDepth; i = e / kDepth; }
       z64 va = {0.0, 0.0};
       if (i0 + i < M && k0 + k < K)
         va = TA ? a[size_t(k0 + k) * lda + (i0 + i)] : a[size_t(i0 + i) * lda + (k0 + k)];
       if constexpr (CA) va.y = -va.y;
       As[k][i] = va;
+    }
+    // B slice: 16 k x TN columns (Q elements per thread)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + 256 * q;
       int j, kb;
-      if constexpr (TB) { kb = e % kDepth; j = e / kDepth; } else { j = e % kTile; kb = e / kTile; }
+      if constexpr (TB) { kb = e % kDepth; j = e / kDepth; } else { j = e % TN; kb = e / TN; }
       z64 vb = {0.0, 0.0};
       if (j0 + j < N && k0 + kb < K)
         vb = TB ? b[size_t(j0 + j) * ldb + (k0 + kb)] : b[size_t(k0 + kb) * ldb + (j0 + j)];
@@ -60,15 +67,15 @@ __global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, i
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < kDepth; ++kk) {
-      z64 av[4], bv[4];
+      z64 av[R], bv[Q];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) av[r] = As[kk][ty + 16 * r];
+      for (int r = 0; r < R; ++r) av[r] = As[kk][ty + 16 * r];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) bv[q] = Bs[kk][tx + 16 * q];
+      for (int q = 0; q < Q; ++q) bv[q] = Bs[kk][tx + 16 * q];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < Q; ++q) {
           acc[r][q].x = fma(av[r].x, bv[q].x, fma(-av[r].y, bv[q].y, acc[r][q].x));
           acc[r][q].y = fma(av[r].x, bv[q].y, fma(av[r].y, bv[q].x, acc[r][q].y));
         }
@@ -76,11 +83,11 @@ __global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, i
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < R; ++r) {
     const int i = i0 + ty + 16 * r;
     if (i >= M) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const int j = j0 + tx + 16 * q;
       if (j < N) c[size_t(i) * ldc + j] = {s * acc[r][q].x, s * acc[r][q].y};
     }
@@ -91,8 +98,13 @@ template <bool TA, bool CA, bool TB, bool CB>
 hipError_t zgemm(const z64 *a, int lda, const z64 *b, int ldb, z64 *c, int ldc, int M, int N, int K, double s,
                  hipStream_t st, const LaunchHook &hook, const char *name) {
   hook(st, name, 1, 0);
-  hipLaunchKernelGGL((zgemm_kernel<TA, CA, TB, CB>), dim3((N + kTile - 1) / kTile, (M + kTile - 1) / kTile),
-                     dim3(256), 0, st, a, lda, b, ldb, c, ldc, M, N, K, s);
+  const long big = long((N + 63) / 64) * long((M + 63) / 64);
+  if (big >= 1024)
+    hipLaunchKernelGGL((zgemm_kernel<4, 4, TA, CA, TB, CB>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, st,
+                       a, lda, b, ldb, c, ldc, M, N, K, s);
+  else
+    hipLaunchKernelGGL((zgemm_kernel<2, 2, TA, CA, TB, CB>), dim3((N + 31) / 32, (M + 31) / 32), dim3(256), 0, st,
+                       a, lda, b, ldb, c, ldc, M, N, K, s);
   hipError_t e = hipGetLastError();
   hook(st, name, 1, 1);
   return e;

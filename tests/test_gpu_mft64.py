@@ -18,9 +18,9 @@ TOL = 1e-12
 
 # (pupil edge, focal edge, pupil diameter in pixels, focal pitch in lambda/D): tile multiples,
 # ragged edges below and above one 64-wide tile, and the occulter and detector shapes of the
-# 4096^2 train
+# 4096^2 train, and a ragged product of 33 x 33 tiles of 64 (the large-tile kernel)
 CASES = [(64, 16, 32.0, 0.5), (300, 77, 150.0, 0.37), (33, 130, 20.0, 0.11), (1024, 256, 512.0, 0.125),
-         (4096, 256, 1024.0, 0.03125), (1024, 512, 1024.0, 0.25)]
+         (4096, 256, 1024.0, 0.03125), (1024, 512, 1024.0, 0.25), (2100, 40, 700.0, 0.3)]
 
 
 def _dev(a):
