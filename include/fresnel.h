@@ -199,12 +199,14 @@ int fresnel_step_batched(fr_ctx *ctx, const fr_plane *planes, int32_t count, voi
  * Adjoint (FR_ADJOINT): in is m_focal x m_focal, out n_pupil x n_pupil,
  *   out = (du/n_d) W^H in conj(W), the exact adjoint of the forward.
  * in, out: dense row-major fr_c128 in DEVICE memory, not overlapping. ws: device workspace of
- * 16 n_pupil m_focal bytes (the intermediate product), contents on entry ignored; the caller
- * owns every buffer. The matrix W is built once per (shape, n_d, du) and cached in the
- * context. Errors: FR_EINVAL (null buffer, a size <= 0, n_d or du not positive and finite,
- * unknown flag). */
+ * ws_bytes >= mft_f64_workspace_bytes(n_pupil, m_focal) bytes (the intermediate product, in
+ * split-K partial sums where the first product's K is long), for either direction; contents
+ * on entry ignored; the caller owns every buffer. The matrix W is built once per (shape, n_d,
+ * du) and cached in the context. Errors: FR_EINVAL (null buffer, a size <= 0, n_d or du not
+ * positive and finite, unknown flag), FR_EWORKSPACE (ws_bytes too small). */
+size_t mft_f64_workspace_bytes(int32_t n_pupil, int32_t m_focal);
 int mft_f64(fr_ctx *ctx, const fr_c128 *in, fr_c128 *out, int32_t n_pupil, int32_t m_focal, double n_d,
-            double du, int32_t flags, fr_c128 *ws, void *stream);
+            double du, int32_t flags, fr_c128 *ws, size_t ws_bytes, void *stream);
 
 size_t mft_workspace_bytes(int32_t n_pupil, int32_t m_focal);
 int mft_forward(fr_ctx *ctx, const fr_c64 *in, int32_t n_in, int32_t ld_in, fr_c64 *out,

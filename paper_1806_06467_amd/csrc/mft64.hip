@@ -24,11 +24,13 @@ struct z64 {
 constexpr int kDepth = 16;
 
 // C[i][j] = s sum_k A(i, k) B(k, j). A(i, k) = a[i lda + k] (or a[k lda + i] when TA), conjugated
-// when CA; B(k, j) = b[k ldb + j] (or b[j ldb + k] when TB), conjugated when CB.
+// when CA; B(k, j) = b[k ldb + j] (or b[j ldb + k] when TB), conjugated when CB. Split K:
+// blockIdx.z takes k in [z kc, (z + 1) kc) and writes its partial C at c + z c_split. A may be
+// the ordered sum of sa partial matrices a_split apart (the previous product's split-K slices).
 template <int R, int Q, bool TA, bool CA, bool TB, bool CB>
 __global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, int lda, const z64 *__restrict__ b,
                                                     int ldb, z64 *__restrict__ c, int ldc, int M, int N, int K,
-                                                    double s) {
+                                                    double s, int kc, size_t c_split, int sa, size_t a_split) {
   constexpr int TM = 16 * R, TN = 16 * Q;
   __shared__ z64 As[kDepth][TM + 1];
   __shared__ z64 Bs[kDepth][TN + 1];
@@ -39,7 +41,9 @@ __global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, i
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc[r][q] = {0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += kDepth) {
+  const int kbeg = blockIdx.z * kc, kend = min(K, kbeg + kc);
+  c += blockIdx.z * c_split;
+  for (int k0 = kbeg; k0 < kend; k0 += kDepth) {
     // A slice: TM rows x 16 k (R elements per thread); zero outside the matrix
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -47,8 +51,15 @@ __global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, i
       int i, k;
       if constexpr (TA) { i = e % TM; k = e / TM; } else { k = e % kDepth; i = e / kDepth; }
       z64 va = {0.0, 0.0};
-      if (i0 + i < M && k0 + k < K)
-        va = TA ? a[size_t(k0 + k) * lda + (i0 + i)] : a[size_t(i0 + i) * lda + (k0 + k)];
+      if (i0 + i < M && k0 + k < kend) {
+        const size_t at = TA ? size_t(k0 + k) * lda + (i0 + i) : size_t(i0 + i) * lda + (k0 + k);
+        va = a[at];
+        for (int p = 1; p < sa; ++p) {
+          const z64 w = a[p * a_split + at];
+          va.x += w.x;
+          va.y += w.y;
+        }
+      }
       if constexpr (CA) va.y = -va.y;
       As[k][i] = va;
     }
@@ -59,7 +70,7 @@ __global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, i
       int j, kb;
       if constexpr (TB) { kb = e % kDepth; j = e / kDepth; } else { j = e % TN; kb = e / TN; }
       z64 vb = {0.0, 0.0};
-      if (j0 + j < N && k0 + kb < K)
+      if (j0 + j < N && k0 + kb < kend)
         vb = TB ? b[size_t(j0 + j) * ldb + (k0 + kb)] : b[size_t(k0 + kb) * ldb + (j0 + j)];
       if constexpr (CB) vb.y = -vb.y;
       Bs[kb][j] = vb;
@@ -94,17 +105,27 @@ __global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, i
   }
 }
 
+// split-K factor of the first GEMM of the forward transform (m x n x n): 4 where its 64 x 64
+// tiles alone would give the launch fewer than 4 blocks per compute unit and K is long
+int f64_split(int n, int m) {
+  const long tiles = long((n + 63) / 64) * long((m + 63) / 64);
+  return tiles < 1024 && n >= 1024 ? 4 : 1;
+}
+
 template <bool TA, bool CA, bool TB, bool CB>
 hipError_t zgemm(const z64 *a, int lda, const z64 *b, int ldb, z64 *c, int ldc, int M, int N, int K, double s,
-                 hipStream_t st, const LaunchHook &hook, const char *name) {
+                 hipStream_t st, const LaunchHook &hook, const char *name, int split = 1, int sa = 1,
+                 size_t a_split = 0) {
   hook(st, name, 1, 0);
-  const long big = long((N + 63) / 64) * long((M + 63) / 64);
+  const int kc = ((K + split - 1) / split + kDepth - 1) / kDepth * kDepth;
+  const size_t c_split = size_t(M) * size_t(ldc);
+  const long big = long((N + 63) / 64) * long((M + 63) / 64) * split;
   if (big >= 1024)
-    hipLaunchKernelGGL((zgemm_kernel<4, 4, TA, CA, TB, CB>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, st,
-                       a, lda, b, ldb, c, ldc, M, N, K, s);
+    hipLaunchKernelGGL((zgemm_kernel<4, 4, TA, CA, TB, CB>), dim3((N + 63) / 64, (M + 63) / 64, split), dim3(256), 0,
+                       st, a, lda, b, ldb, c, ldc, M, N, K, s, kc, c_split, sa, a_split);
   else
-    hipLaunchKernelGGL((zgemm_kernel<2, 2, TA, CA, TB, CB>), dim3((N + 31) / 32, (M + 31) / 32), dim3(256), 0, st,
-                       a, lda, b, ldb, c, ldc, M, N, K, s);
+    hipLaunchKernelGGL((zgemm_kernel<2, 2, TA, CA, TB, CB>), dim3((N + 31) / 32, (M + 31) / 32, split), dim3(256), 0,
+                       st, a, lda, b, ldb, c, ldc, M, N, K, s, kc, c_split, sa, a_split);
   hipError_t e = hipGetLastError();
   hook(st, name, 1, 1);
   return e;
@@ -143,10 +164,16 @@ int mft64_matrix(Ctx *ctx, int m, int n, double n_d, double du, hipStream_t s, c
 }  // namespace
 }  // namespace fr
 
+extern "C" size_t mft_f64_workspace_bytes(int32_t n_pupil, int32_t m_focal) {
+  if (n_pupil <= 0 || m_focal <= 0) return 0;
+  return sizeof(fr_c128) * size_t(n_pupil) * size_t(m_focal) * size_t(fr::f64_split(n_pupil, m_focal));
+}
+
 extern "C" int mft_f64(fr_ctx *ctx_, const fr_c128 *in, fr_c128 *out, int32_t n_pupil, int32_t m_focal,
-                       double n_d, double du, int32_t flags, fr_c128 *ws, void *stream) {
+                       double n_d, double du, int32_t flags, fr_c128 *ws, size_t ws_bytes, void *stream) {
   if (!in || !out || !ws || n_pupil <= 0 || m_focal <= 0 || (flags & ~FR_ADJOINT)) return FR_EINVAL;
   if (!(n_d > 0) || !std::isfinite(n_d) || !(du > 0) || !std::isfinite(du)) return FR_EINVAL;
+  if (ws_bytes < mft_f64_workspace_bytes(n_pupil, m_focal)) return FR_EWORKSPACE;
   fr::Ctx *ctx = reinterpret_cast<fr::Ctx *>(ctx_);
   if (!ctx) return FR_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -162,10 +189,14 @@ extern "C" int mft_f64(fr_ctx *ctx_, const fr_c128 *in, fr_c128 *out, int32_t n_
   const double scale = du / n_d;
   const fr::LaunchHook hook = ctx->hook();
   if (!(flags & FR_ADJOINT)) {
-    // T = W in (m x n); out = scale T W^T (m x m)
-    e = fr::zgemm<false, false, false, false>(w, n, src, n, t, n, m, n, n, 1.0, s, hook, "zgemm_mft64_1");
+    // T = W in (m x n, in `split` partial sums over k); out = scale T W^T (m x m), the partials
+    // added in order as the second product reads them
+    const int split = fr::f64_split(n, m);
+    const size_t part = size_t(m) * size_t(n);
+    e = fr::zgemm<false, false, false, false>(w, n, src, n, t, n, m, n, n, 1.0, s, hook, "zgemm_mft64_1", split);
     if (e == hipSuccess)
-      e = fr::zgemm<false, false, true, false>(t, n, w, n, dst, m, m, m, n, scale, s, hook, "zgemm_mft64_2");
+      e = fr::zgemm<false, false, true, false>(t, n, w, n, dst, m, m, m, n, scale, s, hook, "zgemm_mft64_2", 1,
+                                               split, part);
   } else {
     // T = W^H in (n x m); out = scale T conj(W) (n x n)
     e = fr::zgemm<true, true, false, false>(w, n, src, m, t, m, n, m, m, 1.0, s, hook, "zgemm_mft64_adj_1");

@@ -89,7 +89,8 @@ def lib():
             "fresnel_direct": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _c.POINTER(f64), _vp]),
             "fr_plan_route": (_c.c_int, [f64, f64, f64, i32, f64, f64, f64, _c.POINTER(FrRouteStep), i32]),
             "mft_workspace_bytes": (sz, [i32, i32]),
-            "mft_f64": (_c.c_int, [_vp, _vp, _vp, i32, i32, f64, f64, i32, _vp, _vp]),
+            "mft_f64_workspace_bytes": (sz, [i32, i32]),
+            "mft_f64": (_c.c_int, [_vp, _vp, _vp, i32, i32, f64, f64, i32, _vp, sz, _vp]),
             "mft_forward": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, _vp, _vp, sz, _vp]),
             "mft_adjoint": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, f32, f32, _vp,
                                        _vp, sz, _vp]),
@@ -358,9 +359,11 @@ def mft_f64(inp, n_d, size_out, du, adjoint=False, stream=None):
     n, m = (size_out, k) if adjoint else (k, size_out)
     dev = inp.device.index
     out = torch.empty((size_out, size_out), dtype=torch.complex128, device=inp.device)
-    ws = torch.empty((n * m,), dtype=torch.complex128, device=inp.device)
-    st = lib().mft_f64(context(dev).handle, _ptr(inp), _ptr(out), n, m, float(n_d), float(du),
-                       FR_ADJOINT if adjoint else 0, _ptr(ws), _stream_handle(dev, stream))
+    L = lib()
+    nbytes = L.mft_f64_workspace_bytes(n, m)
+    ws = torch.empty((nbytes,), dtype=torch.uint8, device=inp.device)
+    st = L.mft_f64(context(dev).handle, _ptr(inp), _ptr(out), n, m, float(n_d), float(du),
+                   FR_ADJOINT if adjoint else 0, _ptr(ws), nbytes, _stream_handle(dev, stream))
     _check(st, "mft_f64")
     return out
 

@@ -11,7 +11,7 @@ from paper_1806_06467_amd import fresnel as fb
 
 EXPECTED = {
     "fr_create", "fr_destroy", "fr_status_string", "fr_fft_size_supported", "fresnel_step",
-    "fresnel_step_batched", "fresnel_step_exact", "mft_f64", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
+    "fresnel_step_batched", "fresnel_step_exact", "mft_f64", "mft_f64_workspace_bytes", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
     "propagate_train_workspace_bytes", "propagate_train", "fr_profile_enable", "fr_profile_read",
     "fr_autotune", "fr_autotune_save", "fr_autotune_load",
 }
@@ -122,16 +122,22 @@ def test_fresnel_step_exact_argument_errors(L):
 
 def test_mft_f64_argument_errors(L):
     null = ctypes.c_void_p()
-    assert L.mft_f64(null, null, FAKE, 64, 16, 32.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
-    assert L.mft_f64(null, FAKE, null, 64, 16, 32.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
-    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 0, null, null) == fb.FR_EINVAL
-    assert L.mft_f64(null, FAKE, FAKE, 0, 16, 32.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
-    assert L.mft_f64(null, FAKE, FAKE, 64, -1, 32.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
-    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 0.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
-    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, float("inf"), 0, FAKE, null) == fb.FR_EINVAL
-    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 2, FAKE, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, null, FAKE, 64, 16, 32.0, 0.5, 0, FAKE, 1 << 30, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, null, 64, 16, 32.0, 0.5, 0, FAKE, 1 << 30, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 0, null, 1 << 30, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 0, 16, 32.0, 0.5, 0, FAKE, 1 << 30, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, -1, 32.0, 0.5, 0, FAKE, 1 << 30, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 0.0, 0.5, 0, FAKE, 1 << 30, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, float("inf"), 0, FAKE, 1 << 30, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 2, FAKE, 1 << 30, null) == fb.FR_EINVAL
+    # workspace below mft_f64_workspace_bytes: 16 n m, four times that where the first product
+    # is split over k
+    assert L.mft_f64_workspace_bytes(64, 16) == 16 * 64 * 16
+    assert L.mft_f64_workspace_bytes(4096, 256) == 4 * 16 * 4096 * 256
+    assert L.mft_f64_workspace_bytes(0, 16) == 0
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 0, FAKE, 16 * 64 * 16 - 1, null) == fb.FR_EWORKSPACE
     # valid arguments but no context
-    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 0, FAKE, null) == fb.FR_EINVAL
+    assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 0, FAKE, 1 << 30, null) == fb.FR_EINVAL
 
 
 def test_batched_argument_errors(L):
