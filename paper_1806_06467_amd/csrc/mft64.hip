@@ -105,11 +105,30 @@ __global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, i
   }
 }
 
-// split-K factor of the first GEMM of the forward transform (m x n x n): 4 where its 64 x 64
-// tiles alone would give the launch fewer than 4 blocks per compute unit and K is long
+// split-K factors of the forward transform's two GEMMs (m x n x n, then m x m x n): 4 and 16
+// where their 64 x 64 tiles alone would give a launch fewer than 4 blocks per compute unit and
+// K is long
 int f64_split(int n, int m) {
   const long tiles = long((n + 63) / 64) * long((m + 63) / 64);
   return tiles < 1024 && n >= 1024 ? 4 : 1;
+}
+int f64_split2(int n, int m) {
+  const long tiles = long((m + 63) / 64) * long((m + 63) / 64);
+  return tiles < 1024 && n >= 1024 ? 16 : 1;
+}
+
+// out[i] = s sum_p part[p stride + i], the partials added in order
+__global__ void __launch_bounds__(256) zsum_kernel(const z64 *__restrict__ part, size_t stride, int np,
+                                                   z64 *__restrict__ out, size_t count, double s) {
+  const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= count) return;
+  z64 acc = part[i];
+  for (int p = 1; p < np; ++p) {
+    const z64 v = part[p * stride + i];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  out[i] = {s * acc.x, s * acc.y};
 }
 
 template <bool TA, bool CA, bool TB, bool CB>
@@ -166,7 +185,9 @@ int mft64_matrix(Ctx *ctx, int m, int n, double n_d, double du, hipStream_t s, c
 
 extern "C" size_t mft_f64_workspace_bytes(int32_t n_pupil, int32_t m_focal) {
   if (n_pupil <= 0 || m_focal <= 0) return 0;
-  return sizeof(fr_c128) * size_t(n_pupil) * size_t(m_focal) * size_t(fr::f64_split(n_pupil, m_focal));
+  const int s2 = fr::f64_split2(n_pupil, m_focal);
+  return sizeof(fr_c128) * (size_t(n_pupil) * size_t(m_focal) * size_t(fr::f64_split(n_pupil, m_focal)) +
+                            (s2 > 1 ? size_t(m_focal) * size_t(m_focal) * size_t(s2) : 0));
 }
 
 extern "C" int mft_f64(fr_ctx *ctx_, const fr_c128 *in, fr_c128 *out, int32_t n_pupil, int32_t m_focal,
@@ -190,13 +211,26 @@ extern "C" int mft_f64(fr_ctx *ctx_, const fr_c128 *in, fr_c128 *out, int32_t n_
   const fr::LaunchHook hook = ctx->hook();
   if (!(flags & FR_ADJOINT)) {
     // T = W in (m x n, in `split` partial sums over k); out = scale T W^T (m x m), the partials
-    // added in order as the second product reads them
-    const int split = fr::f64_split(n, m);
-    const size_t part = size_t(m) * size_t(n);
+    // of T added in order as the second product reads them; that product in turn split over k
+    // into `split2` partials after T in the workspace, added in order by zsum_kernel
+    const int split = fr::f64_split(n, m), split2 = fr::f64_split2(n, m);
+    const size_t part = size_t(m) * size_t(n), part2 = size_t(m) * size_t(m);
     e = fr::zgemm<false, false, false, false>(w, n, src, n, t, n, m, n, n, 1.0, s, hook, "zgemm_mft64_1", split);
-    if (e == hipSuccess)
+    if (e == hipSuccess && split2 == 1)
       e = fr::zgemm<false, false, true, false>(t, n, w, n, dst, m, m, m, n, scale, s, hook, "zgemm_mft64_2", 1,
                                                split, part);
+    if (e == hipSuccess && split2 > 1) {
+      fr::z64 *t2 = t + part * split;
+      e = fr::zgemm<false, false, true, false>(t, n, w, n, t2, m, m, m, n, 1.0, s, hook, "zgemm_mft64_2", split2,
+                                               split, part);
+      if (e == hipSuccess) {
+        hook(s, "zsum_mft64", 1, 0);
+        hipLaunchKernelGGL(fr::zsum_kernel, dim3(unsigned((part2 + 255) / 256)), dim3(256), 0, s, t2, part2, split2,
+                           dst, part2, scale);
+        e = hipGetLastError();
+        hook(s, "zsum_mft64", 1, 1);
+      }
+    }
   } else {
     // T = W^H in (n x m); out = scale T conj(W) (n x n)
     e = fr::zgemm<true, true, false, false>(w, n, src, m, t, m, n, m, m, 1.0, s, hook, "zgemm_mft64_adj_1");
