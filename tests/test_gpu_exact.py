@@ -118,3 +118,21 @@ def test_exact_4096():
     rows = np.random.default_rng(3).choice(n, 64, replace=False)
     assert rel_l2(got[rows], ref[rows]) <= TOL
     assert rel_l2(got, ref) <= TOL
+
+
+def test_exact_round_trip_8192():
+    """The largest edge: a step over z then -z returns the field (all frequencies propagating),
+    checked on the device."""
+    banner("fresnel_step_exact round trip n=8192")
+    n, lam = 8192, 633e-9
+    dx, z = 1.2 * lam, 150.0 * lam
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(8192)
+    field = torch.randn((n, n), dtype=torch.complex64, device="cuda:0", generator=g)
+    t = field.clone()
+    assert fb.fresnel_step_exact(t, dx, lam, z) == 0
+    moved = float(torch.linalg.vector_norm(t - field) / torch.linalg.vector_norm(field))
+    fb.fresnel_step_exact(t, dx, lam, -z)
+    err = float(torch.linalg.vector_norm(t - field) / torch.linalg.vector_norm(field))
+    assert moved > 0.1
+    assert err <= 2 * TOL
