@@ -17,9 +17,13 @@ the angular-spectrum step where its kernel is periodic, the exact DFT special ca
 the MFT, dot-product (adjoint) identities, the AS/MFT lattice invariance,
 finite differences and a Taylor test of the gradient.
 
-parity unpinned: the composed Lyot-train intensity (O5) beyond its component
-pins, its no-occulter reduction and its adjoint identity — there is no printed
-value in the paper for that system to compare against.
+The composed Lyot-train intensity (O5) is pinned through its parts and by three
+whole-train cases: a full-band occulter rejects everything, no occulter leaves the
+Lyot-stopped pupil MFT, and a one-pixel spot on the axis removes exactly the field's
+mean term (plus the dot-product identity of the whole linear map). The exact transfer
+function's evanescent branch (O10) is pinned by continuity at grazing incidence (its
+piston phase) and by the adjoint identity between the steps over z and -z (its decay
+for z < 0). No oracle function is parity unpinned.
 """
 
 from .core import (  # noqa: F401

@@ -66,3 +66,60 @@ def test_unitary_and_group_law_on_propagating_fields(rng=np.random.default_rng(4
     assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(a))
     back = oracle.as_propagate_exact(a, dx, lam, -3e-4)
     assert np.max(np.abs(back - u)) <= 1e-11 * np.max(np.abs(u))
+
+
+def _grazing_plane_wave(kx, n, wavelength, eps):
+    """A grid plane wave of x-frequency (1 + eps) / lambda (just past grazing incidence for
+    eps > 0, just before it for eps < 0), with the pitch that puts it there."""
+    dx = kx * wavelength / (n * (1.0 + eps))
+    x = np.arange(n)[None, :] * np.ones((n, 1))
+    return dx, np.exp(2j * np.pi * kx * x / n)
+
+
+@pytest.mark.parametrize("z_over_lambda", [10.3, -7.7, 3.45])
+def test_transfer_is_continuous_across_the_cutoff(z_over_lambda):
+    # At grazing incidence the propagation angle reaches 90 degrees: cos(theta) -> 0, so the
+    # exact (piston-free) eigenvalue exp(2 pi i z (cos(theta) - 1) / lambda) tends to
+    # exp(-2 pi i z / lambda) from the propagating side. The evanescent side must reach the
+    # same value (its decay -> 1 and its phase is the piston's), for either sign of z: a dropped
+    # or sign-flipped piston factor fails here (z / lambda is not an integer).
+    n, kx, lam = 64, 20, 633e-9
+    z = z_over_lambda * lam
+    limit = np.exp(-2j * np.pi * z_over_lambda)
+    eps = 1e-10
+    # distance of either side from the limit: 2 pi |z| / lambda * sqrt(2 eps) to first order
+    tol = 1.1 * 2.0 * math.pi * abs(z_over_lambda) * math.sqrt(2.0 * eps)
+    vals = []
+    for e in (-eps, eps):
+        dx, u = _grazing_plane_wave(kx, n, lam, e)
+        got = oracle.as_propagate_exact(u, dx, lam, z)
+        h = got / u
+        assert np.max(np.abs(h - h[0, 0])) <= 1e-9        # still an eigenfunction
+        assert abs(h[0, 0] - limit) <= tol
+        vals.append(h[0, 0])
+    assert abs(vals[0] - vals[1]) <= 2 * tol
+    # and the two sides really straddle the cutoff: the propagating side keeps |H| = 1
+    assert abs(abs(vals[0]) - 1.0) <= 1e-12
+    assert abs(vals[1]) < 1.0 - 1e-5
+
+
+def test_backward_step_is_the_adjoint_on_every_frequency(rng=np.random.default_rng(11)):
+    # Reading for z < 0: evanescent components decay in either direction, so that the step over
+    # -z is the exact adjoint of the step over z on the whole grid (the inverse on the
+    # propagating frequencies, where |H| = 1). The z > 0 decay is physics (pinned above); this
+    # fixes the z < 0 branch relative to it: <AS(z) u, v> = <u, AS(-z) v> with a pitch below
+    # lambda / 2, where most grid frequencies are evanescent.
+    n, dx, lam, z = 32, 0.3e-6, 633e-9, 0.4e-6
+    u = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    v = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    lhs = np.vdot(v, oracle.as_propagate_exact(u, dx, lam, z))
+    rhs = np.vdot(oracle.as_propagate_exact(v, dx, lam, -z), u)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # evanescent waves lose the same fraction of amplitude over -z as over +z
+    y, x = np.mgrid[0:n, 0:n]
+    w = np.exp(2j * np.pi * (13 * x - 9 * y) / n)
+    f = math.hypot(13, 9) / (n * dx)
+    assert f > 1.0 / lam
+    decay = math.exp(-2.0 * math.pi * abs(z) * math.sqrt(f * f - 1.0 / lam ** 2))
+    for zz in (z, -z):
+        assert np.max(np.abs(np.abs(oracle.as_propagate_exact(w, dx, lam, zz)) - decay)) <= 1e-12

@@ -136,3 +136,22 @@ def test_step_cache_is_pure_memoisation():
     b = oracle.train_loss(g, lams, ns, w, heights, dh, mref, step_cache=cache)
     c = oracle.train_loss(g, lams, ns, w, heights, dh, mref, step_cache=cache)
     assert a == b == c and len(cache) == 2
+
+
+def test_one_pixel_axial_spot_removes_the_mean_term():
+    # A spot of one focal pixel on the optical axis (u = 0) blocks only the zero-frequency MFT
+    # sample, (du/n_d) sum(E) over the whole padded plane (the DC term, pinned in the MFT
+    # tests); its adjoint spreads that value evenly over the pupil window with the same factor.
+    # So the Babinet step must leave lyot * (window(E) - (du/n_d)^2 sum(E)) at the Lyot plane:
+    # a sign, mask, window-offset or normalisation mistake in the train fails this.
+    n_d, n, lam = 32, 64, 550e-9
+    g = _geom(n_d)
+    g.occ_mask = np.zeros((g.occ_m, g.occ_m))
+    g.occ_mask[g.occ_m // 2, g.occ_m // 2] = 1.0
+    fwd = oracle.train_forward(g, lam, n, [synth.dm_heights(8, 1)], occulter=True)
+    e_dm = fwd.e_dm[-1]
+    du = g.occ_du_c * g.lambda_c / lam
+    off = (n - n_d) // 2
+    e_lyot = g.lyot * (e_dm[off:off + n_d, off:off + n_d] - (du / n_d) ** 2 * e_dm.sum())
+    ref = oracle.mft(e_lyot, n_d, g.det_m, g.det_du_c * g.lambda_c / lam)
+    assert np.max(np.abs(fwd.e_det - ref)) <= 1e-12 * np.max(np.abs(ref))
