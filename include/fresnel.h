@@ -28,7 +28,8 @@
  *   - an fr_ctx caches per-geometry tables (FFT roots, transfer functions, lens chirps, MFT
  *     matrices, DM influence matrices). The first call with new parameters builds them
  *     (allocating device memory and waiting on `stream` for the upload); later calls with the
- *     same parameters allocate nothing. One fr_ctx may be used by one host thread at a time.
+ *     same parameters allocate nothing (the cache bound: fr_set_cache_limit). One fr_ctx may be
+ *     used by one host thread at a time.
  */
 #ifndef FRESNEL_H
 #define FRESNEL_H
@@ -69,6 +70,12 @@ typedef struct {
 int fr_create(fr_ctx **ctx, int device);
 /* Free every cached table and the context (synchronises the device). NULL is accepted. */
 int fr_destroy(fr_ctx *ctx);
+/* Bound of the context's table cache (default 4096 tables; max_tables >= 1, else FR_EINVAL).
+ * The bound is applied when an entry point starts: a call that finds max_tables or more tables
+ * cached first waits for the device (hipDeviceSynchronize) and frees every table and recorded
+ * graph, then builds what it needs; tables are never freed in the middle of a call. So a long
+ * scan over distances or wavelengths holds at most max_tables plus one call's tables. */
+int fr_set_cache_limit(fr_ctx *ctx, int32_t max_tables);
 /* Static text for a status code (never NULL). For FR_EHIP the last HIP error is appended. */
 const char *fr_status_string(int status);
 /* 1 if n is a plane edge fresnel_step implements, else 0. */
@@ -192,6 +199,14 @@ int fresnel_step_batched(fr_ctx *ctx, const fr_plane *planes, int32_t count, voi
  * ws: device workspace of at least mft_workspace_bytes(n_in, m_out) bytes (forward) or
  * mft_workspace_bytes(n_out, m_in) bytes (adjoint); contents on entry are ignored.
  * Errors: FR_EINVAL, FR_EWORKSPACE. Warning: FR_W_MFT_ALIASED. */
+size_t mft_workspace_bytes(int32_t n_pupil, int32_t m_focal);
+int mft_forward(fr_ctx *ctx, const fr_c64 *in, int32_t n_in, int32_t ld_in, fr_c64 *out,
+                int32_t m_out, int32_t ld_out, double n_d, double du, const float *out_mask,
+                void *ws, size_t ws_bytes, void *stream);
+int mft_adjoint(fr_ctx *ctx, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_c64 *out,
+                int32_t n_out, int32_t ld_out, double n_d, double du, float alpha, float beta,
+                const float *out_mask, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- the MFT in float64 (Sec. 1.1, after Soummer et al.; the paper benchmarks float64) -------
  * Forward (flags 0): in is the n_pupil x n_pupil pupil field, out the m_focal x m_focal focal
  *   field, out = (du/n_d) W in W^T with W as for mft_forward (phases from the exact integer
@@ -207,14 +222,6 @@ int fresnel_step_batched(fr_ctx *ctx, const fr_plane *planes, int32_t count, voi
 size_t mft_f64_workspace_bytes(int32_t n_pupil, int32_t m_focal);
 int mft_f64(fr_ctx *ctx, const fr_c128 *in, fr_c128 *out, int32_t n_pupil, int32_t m_focal, double n_d,
             double du, int32_t flags, fr_c128 *ws, size_t ws_bytes, void *stream);
-
-size_t mft_workspace_bytes(int32_t n_pupil, int32_t m_focal);
-int mft_forward(fr_ctx *ctx, const fr_c64 *in, int32_t n_in, int32_t ld_in, fr_c64 *out,
-                int32_t m_out, int32_t ld_out, double n_d, double du, const float *out_mask,
-                void *ws, size_t ws_bytes, void *stream);
-int mft_adjoint(fr_ctx *ctx, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_c64 *out,
-                int32_t n_out, int32_t ld_out, double n_d, double du, float alpha, float beta,
-                const float *out_mask, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- Lyot coronagraph train over wavelengths (Sec. 1.1 and 1.2) ------------------------
  * Per wavelength lambda_j on an n_pad[j]-wide grid (dx = d_m / n_d):

@@ -88,14 +88,9 @@ static void timing_hook(void *user, hipStream_t s, const char *name, int tag, in
 }
 
 int Ctx::sweep_variant(int n) const {
-  // FR_SWEEP_VARIANT overrides the tile configuration of the plane sweeps (manual tuning runs);
-  // else the autotuner's choice, else variant 0
+  // the autotuner's choice, else variant 0
   int k = 0;
-  if (const char *v = std::getenv("FR_SWEEP_VARIANT")) {
-    k = std::atoi(v);
-  } else if (auto it = tuned_variant.find(n); it != tuned_variant.end()) {
-    k = it->second;
-  }
+  if (auto it = tuned_variant.find(n); it != tuned_variant.end()) k = it->second;
   if (k < 0 || k >= fr::fresnel_variants(n)) k = 0;
   return k;
 }
@@ -140,15 +135,6 @@ int Ctx::upload(const TableKey &key, const void *host, size_t bytes, hipStream_t
     return FR_OK;
   }
   if (capturing) return FR_ESTATE;
-  if (tables.size() >= kMaxTables) {
-    // bounded cache: drop everything once it is full (tables are cheap to rebuild), and the
-    // graphs that reference them
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return record_hip(e);
-    drop_graphs();
-    for (auto &kv : tables) (void)hipFree(kv.second);
-    tables.clear();
-  }
   void *d = nullptr;
   if (hipMalloc(&d, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -162,6 +148,20 @@ int Ctx::upload(const TableKey &key, const void *host, size_t bytes, hipStream_t
   }
   tables.emplace(key, d);
   *out = d;
+  return FR_OK;
+}
+
+// The cache is bounded at call boundaries only: a call that starts with max_tables or more
+// cached waits for the device and drops every table (and the graphs that reference them)
+// before it fetches anything, so every table pointer a call holds stays valid to its end
+// (upload never frees). The cache thus holds at most max_tables plus what one call adds.
+int Ctx::begin_call() {
+  if (tables.size() < max_tables) return FR_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return record_hip(e);
+  drop_graphs();
+  for (auto &kv : tables) (void)hipFree(kv.second);
+  tables.clear();
   return FR_OK;
 }
 
@@ -439,14 +439,8 @@ bool plane_size_supported(int n) {
 // reads what the first one has just written from that cache instead of from HBM.
 constexpr size_t kCacheGroupBytes = size_t(160) << 20;
 
-// end of the group that starts at plane i (at most `cap` planes); FR_PLANE_GROUPS=0 turns the
-// grouping off (one group of up to `cap` planes) for tuning runs
+// end of the group that starts at plane i (at most `cap` planes)
 static int group_end(const PlaneArgs *args, int count, int i, int cap) {
-  static const bool grouping = [] {
-    const char *v = std::getenv("FR_PLANE_GROUPS");
-    return !(v && v[0] == '0');
-  }();
-  if (!grouping) return std::min(count, i + cap);
   size_t bytes = 0;
   int j = i;
   while (j < count && j - i < cap) {
@@ -525,6 +519,13 @@ int fr_destroy(fr_ctx *ctx) {
   return FR_OK;
 }
 
+int fr_set_cache_limit(fr_ctx *ctx_, int32_t max_tables) {
+  Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
+  if (!ctx || max_tables < 1) return FR_EINVAL;
+  ctx->max_tables = size_t(max_tables);
+  return FR_OK;
+}
+
 const char *fr_status_string(int status) {
   switch (status) {
     case FR_OK: return "ok";
@@ -573,6 +574,7 @@ int fresnel_step_batched(fr_ctx *ctx_, const fr_plane *planes, int32_t count, vo
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
+  if (int st = ctx->begin_call(); st != FR_OK) return st;
   std::vector<PlaneArgs> args(count);
   for (int i = 0; i < count; ++i) {
     const fr_plane &p = planes[i];
@@ -660,6 +662,7 @@ int fresnel_direct(fr_ctx *ctx_, fr_c64 *field, int32_t n, double dx_m, double w
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
+  if (int st = ctx->begin_call(); st != FR_OK) return st;
   PlaneArgs a;
   std::memset(&a, 0, sizeof a);
   a.field = reinterpret_cast<float2 *>(field);
@@ -716,6 +719,7 @@ int mft_forward(fr_ctx *ctx_, const fr_c64 *in, int32_t n_in, int32_t ld_in, fr_
   if (!ctx) return FR_EINVAL;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
+  if (int c = ctx->begin_call(); c != FR_OK) return c;
   fr::MftOut o;
   o.out = reinterpret_cast<float2 *>(out);
   o.ld_out = ld_out;
@@ -737,6 +741,7 @@ int mft_adjoint(fr_ctx *ctx_, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_
   if (!ctx) return FR_EINVAL;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
+  if (int c = ctx->begin_call(); c != FR_OK) return c;
   st = fr::mft_adjoint_impl(ctx, reinterpret_cast<const float2 *>(in), m_in, ld_in,
                             reinterpret_cast<float2 *>(out), n_out, ld_out, n_d, du, alpha, beta,
                             nullptr, 0, out_mask, ws, static_cast<hipStream_t>(stream));

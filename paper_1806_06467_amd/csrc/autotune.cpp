@@ -203,6 +203,7 @@ int fr_autotune(fr_ctx *ctx_, int32_t kind, int32_t a, int32_t b, void *stream) 
   if (a <= 0 || (kind == FR_TUNE_MFT && b <= 0)) return FR_EINVAL;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
+  if (int st = ctx->begin_call(); st != FR_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool prof = ctx->profiling;
   ctx->profiling = false;

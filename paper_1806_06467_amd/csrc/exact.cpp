@@ -33,6 +33,7 @@ extern "C" int fresnel_step_exact(fr_ctx *ctx_, fr_c64 *field, int32_t n, double
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
+  if (int st = ctx->begin_call(); st != FR_OK) return st;
   fr::PlaneArgs a;
   std::memset(&a, 0, sizeof a);
   a.field = reinterpret_cast<float2 *>(field);

@@ -20,7 +20,9 @@ struct Ctx {
   int device = 0;
   int cus = 256;  // compute units of the device
   std::map<TableKey, void *> tables;
-  static constexpr size_t kMaxTables = 4096;
+  size_t max_tables = 4096;  // fr_set_cache_limit
+  // start of an entry point that may fetch tables (before the first fetch): trims the cache
+  int begin_call();
 
   // kernel timing: while enabled, every launch is bracketed by HIP events on its stream
   struct Timed {

@@ -619,17 +619,10 @@ bool use_large(int M, int N, int K) {
 }
 
 // tile configuration: 0 small, 1 large, 2 extra large, 3 small with deeper prefetch, 4 small and
-// 5 large with three products per complex step, 6 small on bfloat16 pieces;
-// `cfg` >= 0 is a choice made by the autotuner, else FR_GEMM_TILE (s, l, x, p, t, u, b)
-// overrides the default for manual tuning runs
+// 5 large with three products per complex step, 6 small on bfloat16 pieces; `cfg` >= 0 is a
+// choice made by the autotuner (or a tuning file), else the default by shape
 int tile_choice(int M, int N, int K, int cfg) {
   if (cfg >= 0 && cfg < kGemmTiles) return cfg;
-  static const int forced = [] {
-    const char *v = std::getenv("FR_GEMM_TILE");
-    if (!v) return -1;
-    return v[0] == 's' ? 0 : v[0] == 'l' ? 1 : v[0] == 'x' ? 2 : v[0] == 'p' ? 3 : v[0] == 't' ? 4 : v[0] == 'u' ? 5 : v[0] == 'b' ? 6 : -1;
-  }();
-  if (forced >= 0) return forced;
   return use_large(M, N, K) ? 1 : 0;
 }
 

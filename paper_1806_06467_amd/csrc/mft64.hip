@@ -200,6 +200,7 @@ extern "C" int mft_f64(fr_ctx *ctx_, const fr_c128 *in, fr_c128 *out, int32_t n_
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
+  if (int st = ctx->begin_call(); st != FR_OK) return st;
   const int n = n_pupil, m = m_focal;
   const fr::z64 *w;
   int st = fr::mft64_matrix(ctx, m, n, n_d, du, s, &w);

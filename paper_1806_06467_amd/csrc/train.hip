@@ -470,16 +470,24 @@ size_t train_workspace_bytes(const fr_train_desc *d, int32_t n_lambda, const int
   return layout(d, n_lambda, n_pad, mode).total;
 }
 
+// every argument check of propagate_train (nothing touched, nothing launched)
+int check_call(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *lam, const int32_t *n_pad,
+               const float *weight, int32_t mode, const float *psf, const float *grad_psf,
+               const float *grad_heights, const void *ws, size_t ws_bytes) {
+  int st = check_desc(d, n_lambda, lam, n_pad, weight, mode);
+  if (st != FR_OK) return st;
+  if (!psf || ((mode & FR_TRAIN_GRAD) && (!grad_psf || !grad_heights))) return FR_EINVAL;
+  if (!ws || ws_bytes < train_workspace_bytes(d, n_lambda, n_pad, mode)) return FR_EWORKSPACE;
+  return ctx ? FR_OK : FR_EINVAL;
+}
+
 int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *lam,
               const int32_t *n_pad, const float *weight, int32_t mode, float *psf,
               const float *grad_psf, float *grad_heights, void *ws, size_t ws_bytes, hipStream_t s) {
-  int st = check_desc(d, n_lambda, lam, n_pad, weight, mode);
+  int st = check_call(ctx, d, n_lambda, lam, n_pad, weight, mode, psf, grad_psf, grad_heights, ws, ws_bytes);
   if (st != FR_OK) return st;
   const bool grad = (mode & FR_TRAIN_GRAD) != 0;
   const bool occ = !(mode & FR_TRAIN_NO_OCCULTER);
-  if (!psf || (grad && (!grad_psf || !grad_heights))) return FR_EINVAL;
-  if (!ws || ws_bytes < train_workspace_bytes(d, n_lambda, n_pad, mode)) return FR_EWORKSPACE;
-  if (!ctx) return FR_EINVAL;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return record_hip(e);
 
@@ -768,12 +776,14 @@ std::string graph_key(const fr_train_desc *d, int32_t n_lambda, const double *la
 int train_call(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *lam,
                const int32_t *n_pad, const float *w, int32_t mode, float *psf, const float *gpsf,
                float *gh, void *ws, size_t ws_bytes, hipStream_t s) {
-  if (!(mode & FR_TRAIN_GRAPH) || !ctx)
-    return train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
-  int st = check_desc(d, n_lambda, lam, n_pad, w, mode);
+  int st = check_call(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes);
   if (st != FR_OK) return st;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return record_hip(e);
+  // the cache is trimmed here, once per call (the recording run below must not trim it)
+  if ((st = ctx->begin_call()) != FR_OK) return st;
+  if (!(mode & FR_TRAIN_GRAPH))
+    return train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
   const std::string key = graph_key(d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
   if (hipGraphExec_t g = ctx->find_graph(key)) {
     const LaunchHook hook = ctx->hook();

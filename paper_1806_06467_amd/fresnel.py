@@ -81,6 +81,7 @@ def lib():
         sig = {
             "fr_create": (_c.c_int, [_c.POINTER(_vp), _c.c_int]),
             "fr_destroy": (_c.c_int, [_vp]),
+            "fr_set_cache_limit": (_c.c_int, [_vp, i32]),
             "fr_status_string": (_c.c_char_p, [_c.c_int]),
             "fr_fft_size_supported": (_c.c_int, [i32]),
             "fresnel_step": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
@@ -165,22 +166,36 @@ def context(device=None):
     return ctx
 
 
+def _stream(device, stream):
+    """The torch stream a call runs on: the given one, else the device's current stream."""
+    return torch.cuda.current_stream(device) if stream is None else stream
+
+
 def _stream_handle(device, stream):
-    if stream is None:
-        stream = torch.cuda.current_stream(device)
-    return _vp(stream.cuda_stream)
+    return _vp(_stream(device, stream).cuda_stream)
 
 
 _workspaces = {}
 
 
-def workspace(nbytes, device):
-    """A cached device byte buffer of at least nbytes (one per device; grows on demand)."""
-    buf = _workspaces.get(device)
+def workspace(nbytes, device, stream=None):
+    """A cached device byte buffer of at least nbytes, one per (device, stream) and allocated on
+    that stream, so that the caching allocator never hands it (or a buffer it outgrew) to other
+    work while the library's kernels on that stream may still use it."""
+    s = _stream(device, stream)
+    key = (int(device), s.cuda_stream)
+    buf = _workspaces.get(key)
     if buf is None or buf.numel() < nbytes:
-        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{device}")
-        _workspaces[device] = buf
+        with torch.cuda.stream(s):
+            buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{device}")
+        _workspaces[key] = buf
     return buf
+
+
+def _empty(shape, dtype, device, stream):
+    """An output allocated on the stream the library writes it from."""
+    with torch.cuda.stream(_stream(device.index, stream)):
+        return torch.empty(shape, dtype=dtype, device=device)
 
 
 def _ptr(t):
@@ -333,13 +348,13 @@ def mft_forward(inp, n_d, m_out, du, mask=None, out=None, stream=None):
     ld_in = _row_stride(inp, "inp")
     dev = inp.device.index
     if out is None:
-        out = torch.empty((m_out, m_out), dtype=torch.complex64, device=inp.device)
+        out = _empty((m_out, m_out), torch.complex64, inp.device, stream)
     ld_out = _row_stride(out, "out")
     if mask is not None:
         _need(mask, torch.float32, (m_out, m_out), "mask")
     L = lib()
     nbytes = L.mft_workspace_bytes(n_in, m_out)
-    ws = workspace(nbytes, dev)
+    ws = workspace(nbytes, dev, stream)
     st = L.mft_forward(context(dev).handle, _ptr(inp), n_in, ld_in, _ptr(out), m_out, ld_out,
                        float(n_d), float(du), _ptr(mask), _ptr(ws), ws.numel(),
                        _stream_handle(dev, stream))
@@ -358,12 +373,12 @@ def mft_f64(inp, n_d, size_out, du, adjoint=False, stream=None):
         raise ValueError("inp must be square")
     n, m = (size_out, k) if adjoint else (k, size_out)
     dev = inp.device.index
-    out = torch.empty((size_out, size_out), dtype=torch.complex128, device=inp.device)
+    out = _empty((size_out, size_out), torch.complex128, inp.device, stream)
     L = lib()
     nbytes = L.mft_f64_workspace_bytes(n, m)
-    ws = torch.empty((nbytes,), dtype=torch.uint8, device=inp.device)
+    ws = workspace(nbytes, dev, stream)
     st = L.mft_f64(context(dev).handle, _ptr(inp), _ptr(out), n, m, float(n_d), float(du),
-                   FR_ADJOINT if adjoint else 0, _ptr(ws), nbytes, _stream_handle(dev, stream))
+                   FR_ADJOINT if adjoint else 0, _ptr(ws), ws.numel(), _stream_handle(dev, stream))
     _check(st, "mft_f64")
     return out
 
@@ -378,7 +393,7 @@ def mft_adjoint(inp, n_d, n_out, du, alpha=1.0, beta=0.0, mask=None, out=None, s
     if out is None:
         if beta != 0.0:
             raise ValueError("beta != 0 needs an out tensor")
-        out = torch.empty((n_out, n_out), dtype=torch.complex64, device=inp.device)
+        out = _empty((n_out, n_out), torch.complex64, inp.device, stream)
     if tuple(out.shape) != (n_out, n_out):
         raise ValueError("out shape mismatch")
     ld_out = _row_stride(out, "out")
@@ -386,12 +401,17 @@ def mft_adjoint(inp, n_d, n_out, du, alpha=1.0, beta=0.0, mask=None, out=None, s
         _need(mask, torch.float32, (n_out, n_out), "mask")
     L = lib()
     nbytes = L.mft_workspace_bytes(n_out, m_in)
-    ws = workspace(nbytes, dev)
+    ws = workspace(nbytes, dev, stream)
     st = L.mft_adjoint(context(dev).handle, _ptr(inp), m_in, ld_in, _ptr(out), n_out, ld_out,
                        float(n_d), float(du), float(alpha), float(beta), _ptr(mask), _ptr(ws),
                        ws.numel(), _stream_handle(dev, stream))
     _check(st, "mft_adjoint")
     return out
+
+
+def set_cache_limit(max_tables, device=None):
+    """fr_set_cache_limit: bound of the device context's table cache (applied at call starts)."""
+    _check(lib().fr_set_cache_limit(context(device).handle, int(max_tables)), "fr_set_cache_limit")
 
 
 # ---- autotuner -------------------------------------------------------------------------------
@@ -511,8 +531,8 @@ def propagate_train(train, wavelengths, n_pad, weights, heights=None, occulter=T
             _need(grad_out, torch.float32, (train.n_dm, train.n_act, train.n_act), "grad_out")
             gh = grad_out
         else:
-            gh = torch.empty((train.n_dm, train.n_act, train.n_act), dtype=torch.float32,
-                             device=train.pupil_amp.device)
+            gh = _empty((train.n_dm, train.n_act, train.n_act), torch.float32, train.pupil_amp.device,
+                        stream)
     lam = (_c.c_double * nl)(*[float(x) for x in wavelengths])
     npd = (_c.c_int32 * nl)(*[int(x) for x in n_pad])
     w = (_c.c_float * nl)(*[float(x) for x in weights])
@@ -521,12 +541,12 @@ def propagate_train(train, wavelengths, n_pad, weights, heights=None, occulter=T
     nbytes = L.propagate_train_workspace_bytes(_c.byref(d), nl, npd, mode)
     if nbytes == 0:
         raise ValueError("invalid train geometry")
-    ws = workspace(nbytes, dev)
+    ws = workspace(nbytes, dev, stream)
     if out is not None:
         _need(out, torch.float32, (train.det_m, train.det_m), "out")
         psf = out
     else:
-        psf = torch.empty((train.det_m, train.det_m), dtype=torch.float32, device=train.pupil_amp.device)
+        psf = _empty((train.det_m, train.det_m), torch.float32, train.pupil_amp.device, stream)
     st = L.propagate_train(context(dev).handle, _c.byref(d), nl, lam, npd, w, mode, _ptr(psf),
                            _ptr(grad_psf), _ptr(gh), _ptr(ws), ws.numel(), _stream_handle(dev, stream))
     _check(st, "propagate_train")

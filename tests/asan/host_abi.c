@@ -47,6 +47,8 @@ int main(void) {
   EXPECT(mft_adjoint(NULL, NULL, 64, 64, NULL, 256, 256, 128.0, 0.5, 1.0f, 0.0f, NULL, NULL, 0, NULL) == FR_EINVAL);
   EXPECT(fr_autotune(NULL, 1, 4096, 0, NULL) == FR_EINVAL);
   EXPECT(fr_profile_enable(NULL, 1) == FR_EINVAL);
+  EXPECT(fr_set_cache_limit(NULL, 8) == FR_EINVAL);
+  EXPECT(fr_set_cache_limit((fr_ctx *)0x1000, 0) == FR_EINVAL);
   fr_route_step steps[2];
   memset(steps, 0, sizeof steps);
   const double lam = 6e-7, w0 = 2e-3, zr = M_PI * w0 * w0 / lam;

@@ -259,3 +259,31 @@ def test_autotuner_choices_keep_parity(tmp_path):
     bad.write_text("plan 3840 17\n")  # not an order of 3840's radices
     with pytest.raises(fb.FrError):
         fb.autotune_load(str(bad))
+
+
+def test_table_cache_bound_is_applied_between_calls_only():
+    # With the cache bound at 2 tables, a batch of five planes over five distances needs six
+    # tables (five transfer functions and the FFT roots): the bound must not free any of them
+    # while the call runs, and the next call (which starts over the bound) rebuilds what it
+    # needs. Every plane of both calls matches the oracle.
+    n, dx, lam = 256, 2e-5, 550e-9
+    banner("table cache bound 2 across batched calls")
+    fb.set_cache_limit(2)
+    try:
+        for call in range(2):
+            zs = [(0.1 + 0.05 * i + 0.013 * call) * n * dx * dx / lam for i in range(5)]
+            fields = [synth.random_field(n, 40 + 5 * call + i) for i in range(5)]
+            ts = [to_gpu(f) for f in fields]
+            fb.fresnel_step_batched(ts, dx, lam, zs)
+            for i in range(5):
+                ref = oracle.as_propagate(f32(fields[i]), dx, lam, zs[i])
+                assert rel_l2(to_np(ts[i]), ref) <= TOL
+        # single exact steps over a scan of distances (one parameter table each)
+        field = synth.random_field(n, 60)
+        for k in range(4):
+            z = (0.2 + 0.1 * k) * n * dx * dx / lam
+            t = to_gpu(field)
+            fb.fresnel_step_exact(t, dx, lam, z)
+            assert rel_l2(to_np(t), oracle.as_propagate_exact(f32(field), dx, lam, z)) <= TOL
+    finally:
+        fb.set_cache_limit(4096)

@@ -10,7 +10,7 @@ import pytest
 from paper_1806_06467_amd import fresnel as fb
 
 EXPECTED = {
-    "fr_create", "fr_destroy", "fr_status_string", "fr_fft_size_supported", "fresnel_step",
+    "fr_create", "fr_destroy", "fr_set_cache_limit", "fr_status_string", "fr_fft_size_supported", "fresnel_step",
     "fresnel_step_batched", "fresnel_step_exact", "mft_f64", "mft_f64_workspace_bytes", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
     "propagate_train_workspace_bytes", "propagate_train", "fr_profile_enable", "fr_profile_read",
     "fr_autotune", "fr_autotune_save", "fr_autotune_load",
@@ -169,3 +169,10 @@ def test_profile_argument_errors(L):
     assert L.fr_profile_enable(null, 1) == fb.FR_EINVAL
     n = ctypes.c_int32()
     assert L.fr_profile_read(null, 0, None, 0, None, None, ctypes.byref(n)) == fb.FR_EINVAL
+
+
+def test_cache_limit_argument_errors(L):
+    null = ctypes.c_void_p()
+    assert L.fr_set_cache_limit(null, 16) == fb.FR_EINVAL
+    assert L.fr_set_cache_limit(FAKE, 0) == fb.FR_EINVAL
+    assert L.fr_set_cache_limit(FAKE, -3) == fb.FR_EINVAL
