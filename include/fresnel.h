@@ -184,6 +184,15 @@ typedef struct {
   int32_t n, flags;
 } fr_plane;
 int fresnel_step_batched(fr_ctx *ctx, const fr_plane *planes, int32_t count, void *stream);
+/* The same batched step (Sec. 1.2: the planes of the wavelengths of one broadband model), with
+ * the whole call's launch sequence held as one instantiated HIP graph: the first call with a given
+ * set of entry values (every field of every fr_plane, count and stream) runs as
+ * fresnel_step_batched and then records that sequence; a later call with the same values replays
+ * the recording (no table lookups, no host work per plane). Field contents, amp and opd_m may
+ * change between calls, their addresses may not. The context keeps at most 8 recordings (the
+ * oldest is dropped); fr_set_cache_limit's trim drops them all. Same errors and warnings as
+ * fresnel_step_batched; FR_EHIP if recording fails. */
+int fresnel_step_batched_graph(fr_ctx *ctx, const fr_plane *planes, int32_t count, void *stream);
 
 /* ---- matrix Fourier transform (Sec. 1.1, Soummer et al.; Sec. 2.3) ---------------------
  * Pupil sample m of an n_in-wide window sits at x_m = (m - n_in/2)/n_d  [D];

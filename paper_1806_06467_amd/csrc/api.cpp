@@ -128,6 +128,44 @@ void Ctx::drop_graphs() {
   graphs.clear();
 }
 
+int Ctx::graph_call(const std::string &key, hipStream_t s, const char *name, int tag,
+                    const std::function<int(hipStream_t)> &body) {
+  if (hipGraphExec_t g = find_graph(key)) {
+    const LaunchHook h = hook();
+    h(s, name, tag, 0);
+    hipError_t e = hipGraphLaunch(g, s);
+    h(s, name, tag, 1);
+    return record_hip(e);
+  }
+  int st = body(s);
+  if (st < 0) return st;
+  if (!capture_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return record_hip(e);
+  }
+  hipError_t e = hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return record_hip(e);
+  const bool prof = profiling;
+  profiling = false;
+  capturing = true;
+  const int cap = body(capture_stream);
+  capturing = false;
+  profiling = prof;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(capture_stream, &graph);
+  if (cap < 0 || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return cap < 0 ? cap : record_hip(e);
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return record_hip(e);
+  keep_graph(key, exec);
+  return FR_OK;
+}
+
 int Ctx::upload(const TableKey &key, const void *host, size_t bytes, hipStream_t s, void **out) {
   auto it = tables.find(key);
   if (it != tables.end()) {
@@ -464,7 +502,7 @@ int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s) {
     if (st != FR_OK) return st;
     for (int i = 0; i < count;) {
       const int j = group_end(args, count, i, kMaxBatch);
-      hipError_t e = launch_fresnel_batch(args + i, j - i, n, root, s, ctx->hook(), ctx->sweep_variant(n));
+      hipError_t e = launch_fresnel_batch(args + i, j - i, n, root, s, ctx->hook(), ctx->sweep_variant(n), ctx->cus);
       if (e != hipSuccess) return record_hip(e);
       i = j;
     }
@@ -559,22 +597,21 @@ static int plane_warnings(const fr_plane &p) {
                                                                              : 0;
 }
 
-int fresnel_step_batched(fr_ctx *ctx_, const fr_plane *planes, int32_t count, void *stream) {
-  // arguments are validated before the context is touched
+// arguments of one batched call, checked before the context is touched: FR_EINVAL /
+// FR_EUNSUPPORTED, else the OR of the per-plane warnings
+static int check_batch(const fr_plane *planes, int32_t count) {
   if (!planes || count <= 0) return FR_EINVAL;
-  const int n = planes[0].n;
   int warn = 0;
   for (int i = 0; i < count; ++i) {
     int st = check_plane(planes[i]);
     if (st != FR_OK) return st;
     warn |= plane_warnings(planes[i]);
   }
-  Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
-  if (!ctx) return FR_EINVAL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = hipSetDevice(ctx->device);
-  if (e != hipSuccess) return fr::record_hip(e);
-  if (int st = ctx->begin_call(); st != FR_OK) return st;
+  return warn;
+}
+
+// the tables and launches of one batched call on stream s
+static int batch_body(Ctx *ctx, const fr_plane *planes, int32_t count, hipStream_t s) {
   std::vector<PlaneArgs> args(count);
   for (int i = 0; i < count; ++i) {
     const fr_plane &p = planes[i];
@@ -594,7 +631,46 @@ int fresnel_step_batched(fr_ctx *ctx_, const fr_plane *planes, int32_t count, vo
       if (st != FR_OK) return st;
     }
   }
-  int st = fr::run_planes(ctx, args.data(), count, n, s);
+  return fr::run_planes(ctx, args.data(), count, planes[0].n, s);
+}
+
+int fresnel_step_batched(fr_ctx *ctx_, const fr_plane *planes, int32_t count, void *stream) {
+  const int warn = check_batch(planes, count);
+  if (warn < 0) return warn;
+  Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
+  if (!ctx) return FR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fr::record_hip(e);
+  if (int st = ctx->begin_call(); st != FR_OK) return st;
+  int st = batch_body(ctx, planes, count, s);
+  return st != FR_OK ? st : warn;
+}
+
+int fresnel_step_batched_graph(fr_ctx *ctx_, const fr_plane *planes, int32_t count, void *stream) {
+  const int warn = check_batch(planes, count);
+  if (warn < 0) return warn;
+  Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
+  if (!ctx) return FR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fr::record_hip(e);
+  if (int st = ctx->begin_call(); st != FR_OK) return st;
+  // every value the launches bake in: the plane entries field by field, and the stream
+  std::string key("fresnel_batch");
+  auto put = [&](const void *p, size_t b) { key.append(static_cast<const char *>(p), b); };
+  for (int i = 0; i < count; ++i) {
+    const fr_plane &p = planes[i];
+    const void *ptrs[3] = {p.field, p.amp, p.opd_m};
+    const double vals[4] = {p.dx_m, p.wavelength_m, p.z_m, p.lens_focal_m};
+    const int32_t ints[2] = {p.n, p.flags};
+    put(ptrs, sizeof ptrs);
+    put(vals, sizeof vals);
+    put(ints, sizeof ints);
+  }
+  put(&s, sizeof s);
+  int st = ctx->graph_call(key, s, "fresnel_graph", count,
+                           [&](hipStream_t cs) { return batch_body(ctx, planes, count, cs); });
   return st != FR_OK ? st : warn;
 }
 

@@ -92,7 +92,7 @@ int tune_fresnel(Ctx *ctx, int n, hipStream_t s) {
     int best = 0;
     float best_ms = -1.f;
     for (int v = 0; v < fresnel_variants(n); ++v) {
-      const float ms = time_min(s, [&] { return launch_fresnel_batch(&pa, 1, n, tw, s, none, v); });
+      const float ms = time_min(s, [&] { return launch_fresnel_batch(&pa, 1, n, tw, s, none, v, ctx->cus); });
       if (ms < 0.f) return record_hip(hipGetLastError());
       if (best_ms < 0.f || ms < best_ms) {
         best_ms = ms;

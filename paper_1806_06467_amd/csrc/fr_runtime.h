@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <string>
 #include <tuple>
@@ -50,6 +51,12 @@ struct Ctx {
   hipGraphExec_t find_graph(const std::string &key);
   void keep_graph(const std::string &key, hipGraphExec_t exec);
   void drop_graphs();
+  // Record-or-replay of a whole call: if a graph was recorded under `key`, launch it on `s`;
+  // otherwise run `body(s)` eagerly (which builds every table it reads), then record the same
+  // launch sequence on the context's own stream (no table may be missing then: FR_ESTATE) and
+  // keep the instantiated graph under `key`. `name` / `tag` label the replay for the timing hook.
+  int graph_call(const std::string &key, hipStream_t s, const char *name, int tag,
+                 const std::function<int(hipStream_t)> &body);
 
   ~Ctx();
   // copy `bytes` of host data to a new cached device buffer (waits on `s` for the copy)

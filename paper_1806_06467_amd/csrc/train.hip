@@ -759,7 +759,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
 std::string graph_key(const fr_train_desc *d, int32_t n_lambda, const double *lam, const int32_t *n_pad,
                       const float *w, int32_t mode, const void *psf, const void *gpsf, const void *gh,
                       const void *ws, size_t ws_bytes, hipStream_t s) {
-  std::string k;
+  std::string k("train");
   auto put = [&](const void *p, size_t b) { k.append(static_cast<const char *>(p), b); };
   put(d, sizeof *d);
   put(&n_lambda, sizeof n_lambda);
@@ -785,41 +785,9 @@ int train_call(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double 
   if (!(mode & FR_TRAIN_GRAPH))
     return train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
   const std::string key = graph_key(d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
-  if (hipGraphExec_t g = ctx->find_graph(key)) {
-    const LaunchHook hook = ctx->hook();
-    hook(s, "train_graph", n_lambda, 0);
-    e = hipGraphLaunch(g, s);
-    hook(s, "train_graph", n_lambda, 1);
-    return record_hip(e);
-  }
-  st = train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
-  if (st != FR_OK) return st;
-  if (!ctx->capture_stream) {
-    e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return record_hip(e);
-  }
-  hipStream_t cs = ctx->capture_stream;
-  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return record_hip(e);
-  const bool prof = ctx->profiling;
-  ctx->profiling = false;
-  ctx->capturing = true;
-  const int cap = train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, cs);
-  ctx->capturing = false;
-  ctx->profiling = prof;
-  hipGraph_t graph = nullptr;
-  e = hipStreamEndCapture(cs, &graph);
-  if (cap != FR_OK || e != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipGetLastError();
-    return cap != FR_OK ? cap : record_hip(e);
-  }
-  hipGraphExec_t exec = nullptr;
-  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return record_hip(e);
-  ctx->keep_graph(key, exec);
-  return FR_OK;
+  return ctx->graph_call(key, s, "train_graph", n_lambda, [&](hipStream_t cs) {
+    return train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, cs);
+  });
 }
 
 }  // namespace fr

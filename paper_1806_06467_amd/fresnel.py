@@ -86,6 +86,7 @@ def lib():
             "fr_fft_size_supported": (_c.c_int, [i32]),
             "fresnel_step": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
             "fresnel_step_batched": (_c.c_int, [_vp, _c.POINTER(FrPlane), i32, _vp]),
+            "fresnel_step_batched_graph": (_c.c_int, [_vp, _c.POINTER(FrPlane), i32, _vp]),
             "fresnel_step_exact": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
             "fresnel_direct": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _c.POINTER(f64), _vp]),
             "fr_plan_route": (_c.c_int, [f64, f64, f64, i32, f64, f64, f64, _c.POINTER(FrRouteStep), i32]),
@@ -301,9 +302,11 @@ def follow_route(field, wavelength, steps, stream=None):
 
 
 def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens_focals=None,
-                         adjoints=None, stream=None):
+                         adjoints=None, stream=None, graph=False):
     """Many planes in one launch per sweep; per-plane sequences (or scalars). Planes may have
-    different edges (then every plane goes through the mixed-radix sweeps)."""
+    different edges (then every plane goes through the mixed-radix sweeps).
+    graph: the library records the call's launches as one graph the first time these plane
+    entries (field / map addresses, parameters) and stream are seen, and replays it later."""
     count = len(fields)
     if count == 0:
         raise ValueError("empty batch")
@@ -332,8 +335,9 @@ def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens
                          float(lams[i]), float(zz[i]), float(lf[i]), n,
                          FR_ADJOINT if adj[i] else 0)
     dev = fields[0].device.index
-    st = lib().fresnel_step_batched(context(dev).handle, arr, count, _stream_handle(dev, stream))
-    return _check(st, "fresnel_step_batched")
+    fn = lib().fresnel_step_batched_graph if graph else lib().fresnel_step_batched
+    st = fn(context(dev).handle, arr, count, _stream_handle(dev, stream))
+    return _check(st, "fresnel_step_batched_graph" if graph else "fresnel_step_batched")
 
 
 # ---- MFT ----------------------------------------------------------------------------------

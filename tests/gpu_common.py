@@ -55,3 +55,16 @@ def forced_gemm_tile(tile, tmp_path):
         forced.write_text("gemm_default -1 0\n")
         fb.autotune_load(str(forced))
         fb.autotune_load(str(saved))
+
+
+def grid_plane_wave_sum(n, waves, dtype=np.complex128):
+    """sum_j a_j exp(2 pi i (kx_j x + ky_j y) / n) on the n x n grid, for integer frequencies
+    (kx_j, ky_j, a_j): each term is an exact eigenvector of every shift-invariant step on the
+    grid. The index products are reduced modulo n in integers before the float64 exponential."""
+    x = np.arange(n, dtype=np.int64)
+    out = np.zeros((n, n), dtype=dtype)
+    for kx, ky, a in waves:
+        ex = np.exp(2j * np.pi * ((kx * x) % n) / n)
+        ey = np.exp(2j * np.pi * ((ky * x) % n) / n)
+        out += (complex(a) * ey)[:, None].astype(dtype) * ex[None, :].astype(dtype)
+    return out

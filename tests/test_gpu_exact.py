@@ -3,6 +3,8 @@ transfer function) against the FP64 oracle (O10), its adjoint and its round trip
 relative L2 <= 1e-5 (the float32 FFT error budget of fresnel_step); the adjoint identity
 <A x, y> = <x, A^H y> to 1e-5 of |A x| |y|."""
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -10,7 +12,7 @@ import torch
 import oracle
 from paper_1806_06467_amd import fresnel as fb
 from paper_1806_06467_amd import synth
-from tests.gpu_common import banner, f32, rel_l2, to_gpu, to_np
+from tests.gpu_common import banner, f32, grid_plane_wave_sum, rel_l2, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -136,3 +138,38 @@ def test_exact_round_trip_8192():
     err = float(torch.linalg.vector_norm(t - field) / torch.linalg.vector_norm(field))
     assert moved > 0.1
     assert err <= 2 * TOL
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+@pytest.mark.parametrize("zl", [0.4, -0.4])
+def test_exact_8192_plane_waves_closed_form(zl, adjoint):
+    """The largest edge on the whole plane against a closed form: a sum of grid plane waves is
+    carried term by term, each wave multiplied by the exact transfer function of its own
+    frequency, formed here in float64 from the propagation angle (propagating: the phase
+    2 pi z (cos(theta) - 1) / lambda, sin(theta) = lambda f; evanescent: the decay
+    exp(-2 pi |z| sqrt(f^2 - 1/lambda^2)) times the left-out piston's conjugate). At a pitch of
+    0.6 wavelengths two of the five waves are evanescent (one of them the Nyquist corner);
+    the adjoint takes the conjugate factors."""
+    n, lam = 8192, 500e-9
+    dx, z = 0.6 * lam, zl * lam
+    banner(f"fresnel_step_exact n=8192 plane waves z={zl} lambda adjoint={adjoint}")
+    waves = [(100, -300, 1.0), (2000, 1500, 0.7j), (-4000, 500, 0.5), (3600, 3600, 0.8), (-4096, -4096, 0.3)]
+    field = grid_plane_wave_sum(n, waves, np.complex64)
+    t = torch.from_numpy(field).to("cuda:0")
+    del field
+    fb.fresnel_step_exact(t, dx, lam, z, adjoint=adjoint)
+    expected = []
+    evanescent = 0
+    for kx, ky, a in waves:
+        f = math.hypot(kx, ky) / (n * dx)
+        if lam * f < 1.0:
+            hk = np.exp(2j * np.pi * z * (math.sqrt(1.0 - (lam * f) ** 2) - 1.0) / lam)
+        else:
+            evanescent += 1
+            hk = math.exp(-2.0 * math.pi * abs(z) * math.sqrt(f * f - 1.0 / lam ** 2)) * np.exp(-2j * np.pi * z / lam)
+        expected.append((kx, ky, a * (np.conj(hk) if adjoint else hk)))
+    assert evanescent == 2
+    ref = grid_plane_wave_sum(n, expected)
+    got = to_np(t)
+    del t
+    assert rel_l2(got, ref) <= TOL

@@ -12,7 +12,7 @@ import torch
 import oracle
 from paper_1806_06467_amd import fresnel as fb
 from paper_1806_06467_amd import synth
-from tests.gpu_common import banner, f32, rel_l2, to_gpu, to_np
+from tests.gpu_common import banner, f32, grid_plane_wave_sum, rel_l2, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -122,6 +122,34 @@ def test_batched_equals_single_and_is_deterministic():
     fb.fresnel_step_batched(ts, 3e-5, lams, 0.5, opds=opd, adjoints=[False, True, False])
     for i in range(3):
         assert np.array_equal(to_np(ts[i]), singles[i])
+
+
+@pytest.mark.parametrize("n,count", [(256, 6), (4096, 4), (3840, 3)])
+def test_batched_graph_replays_equal_eager(n, count):
+    """The recorded batched call (fresnel_step_batched_graph), replayed three times with new field
+    contents written in place and unrelated eager work in between, equals the eager batched call
+    bit for bit on every replay (forward and adjoint planes, amplitude and OPD maps); 3840 takes
+    the mixed-radix sweeps."""
+    banner(f"batched graph replays n={n} count={count}")
+    rng = np.random.default_rng(n + count)
+    amp = to_gpu(rng.uniform(0.5, 1.0, (n, n)), torch.float32)
+    opd = to_gpu(rng.normal(0, 30e-9, (n, n)), torch.float32)
+    lams = [500e-9 + 20e-9 * i for i in range(count)]
+    adj = [i % 2 == 1 for i in range(count)]
+    dx = 2.0 * math.sqrt(600e-9 * 0.5 / n)
+    ts = [torch.empty((n, n), dtype=torch.complex64, device="cuda:0") for _ in range(count)]
+    for rep in range(4):
+        inputs = [to_gpu(synth.random_field(n, 100 * rep + i)) for i in range(count)]
+        refs = [x.clone() for x in inputs]
+        fb.fresnel_step_batched(refs, dx, lams, 0.5, amps=amp, opds=opd, adjoints=adj)
+        for t, x in zip(ts, inputs):
+            t.copy_(x)
+        fb.fresnel_step_batched(ts, dx, lams, 0.5, amps=amp, opds=opd, adjoints=adj, graph=True)
+        junk = torch.randn(1 << 20, device="cuda:0").sum()
+        torch.cuda.synchronize()
+        for i in range(count):
+            assert torch.equal(ts[i], refs[i]), (rep, i)
+        assert torch.isfinite(junk)
 
 
 def test_warning_bit_for_undersampled_distance():
@@ -287,3 +315,23 @@ def test_table_cache_bound_is_applied_between_calls_only():
             assert rel_l2(to_np(t), oracle.as_propagate_exact(f32(field), dx, lam, z)) <= TOL
     finally:
         fb.set_cache_limit(4096)
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_fresnel_step_8192_plane_waves_closed_form(adjoint):
+    """The whole 8192^2 plane against a closed form: each grid plane wave of a sum is multiplied
+    by the paraxial transfer function of its frequency, exp(-i pi lambda z f^2), formed here in
+    float64 (conjugated for the adjoint); frequencies up to the Nyquist corner."""
+    n, dx, lam, z = 8192, 1.25e-5, 550e-9, 1.0
+    banner(f"fresnel_step n=8192 plane waves adjoint={adjoint}")
+    waves = [(1, 0, 1.0), (-37, 1500, 0.6j), (4000, -2500, 0.5), (-4096, -4096, 0.25), (2048, 7, -0.4)]
+    t = torch.from_numpy(grid_plane_wave_sum(n, waves, np.complex64)).to("cuda:0")
+    fb.fresnel_step(t, dx, lam, z, adjoint=adjoint)
+    expected = []
+    for kx, ky, a in waves:
+        hk = np.exp(-1j * np.pi * lam * z * (kx * kx + ky * ky) / (n * dx) ** 2)
+        expected.append((kx, ky, a * (np.conj(hk) if adjoint else hk)))
+    ref = grid_plane_wave_sum(n, expected)
+    got = to_np(t)
+    del t
+    assert rel_l2(got, ref) <= TOL

@@ -319,3 +319,53 @@ def test_large_train_8192_two_dms():
     gerr = rel_l2(gj, gref)
     banner(f"large train gradient rel L2 vs FP64 adjoint: {gerr:.3e}")
     assert gerr <= 1e-4
+
+
+def test_bench_train_4096_two_dms_graph_replays():
+    """The train the benchmark times: a 1024 px pupil padded 4x to 4096, two 48 x 48 DMs (pupil
+    and after the 1 m step), 21 wavelengths over 500-600 nm, occulter 256^2 at 8/256 lambda_c/D,
+    detector 512^2 at 0.25 lambda_c/D, PSF and gradient, batched and recorded as a graph. With
+    the benchmark's equal weights every replay (eager work and synchronisations in between)
+    equals the eager batched call bit for bit; with one-hot weights on the first and the last
+    wavelength the replays match the oracle (PSF, normalised contrast, gradient)."""
+    banner("bench train: 4096 grid, two 48x48 DMs, 21 wavelengths, graph replays")
+    geom, tr, heights, hg = make(1024, 256, 8 / 256, 512, 0.25, 1.0, 48, 2)
+    nl = 21
+    lams = list(synth.wavelengths(nl))
+    ns = [4096] * nl
+    dhn = synth.dark_hole(512, 0.25, 3.0, 10.0)
+    dh = to_gpu(dhn / dhn.sum(), torch.float32)
+    out = torch.empty((512, 512), dtype=torch.float32, device="cuda:0")
+    gout = torch.empty((2, 48, 48), dtype=torch.float32, device="cuda:0")
+    w = [1.0 / nl] * nl
+    p_ref, g_ref = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh, batched=True)
+    for rep in range(3):
+        fb.propagate_train(tr, lams, ns, w, hg, grad_psf=dh, batched=True, graph=True, out=out, grad_out=gout)
+        junk = torch.randn(1 << 20, device="cuda:0").sum()
+        torch.cuda.synchronize()
+        assert torch.equal(out, p_ref), rep
+        assert torch.equal(gout, g_ref), rep
+        assert torch.isfinite(junk)
+    cache = {}
+    for j in (0, nl - 1):
+        one_hot = [1.0 if k == j else 0.0 for k in range(nl)]
+        for rep in range(2):
+            fb.propagate_train(tr, lams, ns, one_hot, hg, grad_psf=dh, batched=True, graph=True, out=out,
+                               grad_out=gout)
+            torch.cuda.synchronize()
+        pj, gj = _np(out), _np(gout)
+        pj0 = _np(fb.propagate_train(tr, lams, ns, one_hot, hg, batched=True, occulter=False))
+        banner(f"bench train: oracle for {lams[j] * 1e9:.0f} nm at 4096")
+        fwd = oracle.train_forward(geom, lams[j], 4096, heights, True, cache)
+        ref = fwd.e_det.real ** 2 + fwd.e_det.imag ** 2
+        e0 = oracle.train_forward(geom, lams[j], 4096, heights, False, cache).e_det
+        ref0 = e0.real ** 2 + e0.imag ** 2
+        assert rel_l2(pj, ref) <= 1e-5, j
+        assert rel_l2(pj0, ref0) <= 1e-5, j
+        err = np.max(np.abs(pj / pj0.max() - ref / ref0.max()))
+        banner(f"bench train {lams[j] * 1e9:.0f} nm: max |dC| = {err:.3e}")
+        assert err <= 1e-9, j
+        gref = np.stack(oracle.train_backward(geom, lams[j], 4096, heights, fwd, dhn / dhn.sum()))
+        gerr = rel_l2(gj, gref)
+        banner(f"bench train {lams[j] * 1e9:.0f} nm: gradient rel L2 vs FP64 adjoint {gerr:.3e}")
+        assert gerr <= 1e-4, j

@@ -11,7 +11,7 @@ from paper_1806_06467_amd import fresnel as fb
 
 EXPECTED = {
     "fr_create", "fr_destroy", "fr_set_cache_limit", "fr_status_string", "fr_fft_size_supported", "fresnel_step",
-    "fresnel_step_batched", "fresnel_step_exact", "mft_f64", "mft_f64_workspace_bytes", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
+    "fresnel_step_batched", "fresnel_step_batched_graph", "fresnel_step_exact", "mft_f64", "mft_f64_workspace_bytes", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
     "propagate_train_workspace_bytes", "propagate_train", "fr_profile_enable", "fr_profile_read",
     "fr_autotune", "fr_autotune_save", "fr_autotune_load",
 }
@@ -145,8 +145,12 @@ def test_batched_argument_errors(L):
     arr = (fb.FrPlane * 2)()
     arr[0] = fb.FrPlane(0x1000, None, None, 1e-4, 5e-7, 1.0, 0.0, 256, 0)
     arr[1] = fb.FrPlane(0x2000, None, None, 1e-4, 5e-7, 1.0, 0.0, 512, 0)
-    assert L.fresnel_step_batched(null, arr, 2, null) == fb.FR_EINVAL   # mixed edges
-    assert L.fresnel_step_batched(null, arr, 0, null) == fb.FR_EINVAL
+    for fn in (L.fresnel_step_batched, L.fresnel_step_batched_graph):
+        assert fn(null, arr, 2, null) == fb.FR_EINVAL   # valid planes, no context
+        assert fn(null, arr, 0, null) == fb.FR_EINVAL
+        bad = (fb.FrPlane * 1)()
+        bad[0] = fb.FrPlane(0x1000, None, None, 1e-4, 5e-7, 1.0, 0.0, 4097, 0)
+        assert fn(null, bad, 1, null) == fb.FR_EUNSUPPORTED
 
 
 def test_mft_argument_errors(L):
