@@ -297,11 +297,15 @@ int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda,
  *     three sums are combined in float64 at every 32-deep group), tile 6 from four real products
  *     each summed from six products of exact bfloat16 pieces of the float32 operands on the
  *     bf16 matrix cores.
- * Every candidate computes the same result up to the order of float32 roundings. The call
+ * Every candidate computes the same result up to the order of float32 roundings. fr_autotune and
+ * fr_autotune_load drop every recorded graph (fresnel_step_batched_graph, FR_TRAIN_GRAPH), after
+ * waiting for the device, since a recording holds the kernel choices of its time. The call
  * allocates scratch device memory for its duration, synchronises `stream`, and is not meant for
  * a hot loop or a graph capture. Errors: FR_EINVAL, FR_EUNSUPPORTED, FR_ENOMEM, FR_EHIP.
  * fr_autotune_save / fr_autotune_load write / read the tuned choices as a text file (one
- * "sweep n variant", "plan n packed_order", "gemm M N K transA transB tile [split]" or
+ * "sweep n variant [planes]" (planes: the power-of-two sweeps' planes per launch in batched calls,
+ * 1..64, or 0 = as many as fit the last-level cache together), "plan n packed_order",
+ * "gemm M N K transA transB tile [split]" or
  * "gemm_default tile split" per line; the default applies to GEMM shapes without their own line,
  * tile -1 restoring the choice by shape); a malformed or inconsistent line makes load return
  * FR_EINVAL (valid lines are still taken). */

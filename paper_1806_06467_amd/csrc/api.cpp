@@ -7,6 +7,7 @@
 // float. Separability keeps them O(n) per plane instead of O(n^2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -477,8 +478,10 @@ bool plane_size_supported(int n) {
 // reads what the first one has just written from that cache instead of from HBM.
 constexpr size_t kCacheGroupBytes = size_t(160) << 20;
 
-// end of the group that starts at plane i (at most `cap` planes)
-static int group_end(const PlaneArgs *args, int count, int i, int cap) {
+// end of the group that starts at plane i: at most `cap` planes, and either `planes` planes
+// (a tuned group size) or, with planes = 0, as many as fit the last-level cache together
+static int group_end(const PlaneArgs *args, int count, int i, int cap, int planes = 0) {
+  if (planes > 0) return std::min(count, i + std::min(planes, cap));
   size_t bytes = 0;
   int j = i;
   while (j < count && j - i < cap) {
@@ -500,9 +503,11 @@ int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s) {
     const float2 *root;
     int st = ctx->twiddles(n, s, &root);
     if (st != FR_OK) return st;
+    int planes = 0;
+    if (auto it = ctx->tuned_group.find(n); it != ctx->tuned_group.end()) planes = it->second;
     for (int i = 0; i < count;) {
-      const int j = group_end(args, count, i, kMaxBatch);
-      hipError_t e = launch_fresnel_batch(args + i, j - i, n, root, s, ctx->hook(), ctx->sweep_variant(n), ctx->cus);
+      const int j = group_end(args, count, i, kMaxBatch, planes);
+      hipError_t e = launch_fresnel_batch(args + i, j - i, n, root, s, ctx->hook(), ctx->sweep_variant(n));
       if (e != hipSuccess) return record_hip(e);
       i = j;
     }

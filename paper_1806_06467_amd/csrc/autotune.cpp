@@ -92,7 +92,7 @@ int tune_fresnel(Ctx *ctx, int n, hipStream_t s) {
     int best = 0;
     float best_ms = -1.f;
     for (int v = 0; v < fresnel_variants(n); ++v) {
-      const float ms = time_min(s, [&] { return launch_fresnel_batch(&pa, 1, n, tw, s, none, v, ctx->cus); });
+      const float ms = time_min(s, [&] { return launch_fresnel_batch(&pa, 1, n, tw, s, none, v); });
       if (ms < 0.f) return record_hip(hipGetLastError());
       if (best_ms < 0.f || ms < best_ms) {
         best_ms = ms;
@@ -209,6 +209,9 @@ int fr_autotune(fr_ctx *ctx_, int32_t kind, int32_t a, int32_t b, void *stream) 
   ctx->profiling = false;
   const int st = kind == FR_TUNE_FRESNEL ? fr::tune_fresnel(ctx, a, s) : fr::tune_mft(ctx, a, b, s);
   ctx->profiling = prof;
+  // recorded graphs bake in the kernel choices of their time
+  (void)hipDeviceSynchronize();
+  ctx->drop_graphs();
   return st;
 }
 
@@ -218,7 +221,10 @@ int fr_autotune_save(fr_ctx *ctx_, const char *path) {
   FILE *f = std::fopen(path, "w");
   if (!f) return FR_EINVAL;
   std::fprintf(f, "# fresnel autotune v1\n");
-  for (auto &kv : ctx->tuned_variant) std::fprintf(f, "sweep %d %d\n", kv.first, kv.second);
+  for (auto &kv : ctx->tuned_variant) {
+    auto g = ctx->tuned_group.find(kv.first);
+    std::fprintf(f, "sweep %d %d %d\n", kv.first, kv.second, g == ctx->tuned_group.end() ? 0 : g->second);
+  }
   for (auto &kv : ctx->tuned_plan) std::fprintf(f, "plan %d %u\n", kv.first, kv.second);
   if (ctx->default_gemm.tile >= 0)
     std::fprintf(f, "gemm_default %d %d\n", ctx->default_gemm.tile, ctx->default_gemm.split);
@@ -236,6 +242,9 @@ int fr_autotune_load(fr_ctx *ctx_, const char *path) {
   if (!ctx || !path) return FR_EINVAL;
   FILE *f = std::fopen(path, "r");
   if (!f) return FR_EINVAL;
+  // recorded graphs bake in the kernel choices of their time
+  if (hipSetDevice(ctx->device) == hipSuccess) (void)hipDeviceSynchronize();
+  ctx->drop_graphs();
   char line[256];
   int st = FR_OK;
   while (std::fgets(line, sizeof line, f)) {
@@ -246,9 +255,12 @@ int fr_autotune_load(fr_ctx *ctx_, const char *path) {
     if (std::sscanf(line, "gemm_default %d %d", &v, &sp) == 2) {
       if (v < -1 || v >= fr::kGemmTiles || sp < 0 || sp > fr::kMaxSplit) st = FR_EINVAL;
       else ctx->default_gemm = {v, sp};
-    } else if (std::sscanf(line, "sweep %d %d", &n, &v) == 2) {
-      if (!fr::fresnel_size_supported(n) || v < 0 || v >= fr::fresnel_variants(n)) st = FR_EINVAL;
-      else ctx->tuned_variant[n] = v;
+    } else if ((fields = std::sscanf(line, "sweep %d %d %d", &n, &v, &sp)) >= 2) {
+      if (fields == 2) sp = 0;
+      if (!fr::fresnel_size_supported(n) || v < 0 || v >= fr::fresnel_variants(n) || sp < 0 || sp > fr::kMaxBatch)
+        st = FR_EINVAL;
+      else
+        ctx->tuned_variant[n] = v, ctx->tuned_group[n] = sp;
     } else if (std::sscanf(line, "plan %d %u", &n, &plan) == 2) {
       if (!fr::valid_plan(n, plan)) st = FR_EINVAL;
       else ctx->tuned_plan[n] = plan;

@@ -59,9 +59,8 @@ struct BatchArgs {
 // tw: the plan's twiddle table (fresnel_twiddle_build). Returns a hipError_t.
 // `variant` selects a tile configuration (row lines per block, column tile width); every
 // variant computes the same result. fresnel_variants(n) = number of variants for edge n.
-// cus: compute units of the device (sizes the persistent variants' grids).
 hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const float2 *tw,
-                                hipStream_t stream, const LaunchHook &hook, int variant, int cus);
+                                hipStream_t stream, const LaunchHook &hook, int variant);
 // The direct (single-transform) Fresnel step of `count` planes of power-of-two edge n
 // (count <= kMaxBatch): the row sweep applies the optic times the input quadratic phase (lens
 // slot) and the forward transform, the column sweep the forward transform and the output

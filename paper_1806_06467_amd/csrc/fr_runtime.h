@@ -68,6 +68,7 @@ struct Ctx {
 
   // choices made by the autotuner (fr_autotune), consulted by every later call
   std::map<int, int> tuned_variant;                 // power-of-two sweep tile variant per edge
+  std::map<int, int> tuned_group;                   // planes per launch group per edge (0: cache-sized)
   std::map<int, unsigned> tuned_plan;               // mixed-radix pass order per edge
   struct GemmChoice {
     int tile;   // tile configuration

@@ -345,157 +345,6 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
 }
 
-// Persistent, software-pipelined column sweep of 4096^2 planes without a column-side optic.
-// One 512-thread block per compute unit walks 2-column tiles (16 elements per thread, up to 256
-// VGPRs); while it transforms tile i in registers (forward FFT, h, inverse FFT, exchanges
-// through LDS) the loads of tile i + 1 are in flight into a second register set, and the stores
-// of tile i drain behind the next tile's arithmetic, so HBM traffic and the FFT overlap instead
-// of alternating. Nothing else is read from global memory inside the loop, because vector loads
-// complete in order: the transfer function sits in LDS as its non-negative half (h[k] =
-// h[n - k], the signed index enters squared), the second pass's twiddles (span 16) in LDS, the
-// last pass's (span 256: leg r of butterfly t, w_4096^{r t}) in registers for the whole kernel.
-// The FFT, its exchange layout, the arithmetic and every table value are those of
-// col_sweep<Plan<4096, 16, 16, 16, 16>, ...>, so the results are bitwise the same. Tiles are
-// dealt plane-major in waves of gridDim.x (a power of two dividing 2048, the tiles of one
-// plane), each XCD taking a contiguous run of a wave, so the blocks of one XCD share the L2
-// lines of neighbouring columns at the same time; when the next wave starts a new plane, that
-// plane's h is fetched after this tile's frequency product and written to LDS once every
-// thread has passed it.
-namespace pipe4096 {
-constexpr int N = 4096, E = 16, T = N / E, LINES = 2, THREADS = T * LINES, G = N / LINES;
-constexpr int LINE = LdsLine<N>::size + 8;
-constexpr int HALF_H = N / 2 + 1;
-
-// radix-16 pass after span P on the thread's butterfly (b = t); P = 1 and 16 exchange the
-// outputs through the line's LDS, P = 256 (the last) leaves them in the registers (slot m =
-// position t + T m throughout)
-template <bool INV, int P>
-__device__ __forceinline__ void pass(c32 (&v)[E], c32 *__restrict__ lds, int t, const c32 (&w)[15]) {
-  c32 u[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) u[r] = v[r];
-  if constexpr (P > 1) {
-#pragma unroll
-    for (int r = 1; r < 16; ++r) u[r] = INV ? cmulc(u[r], w[r - 1]) : cmul(u[r], w[r - 1]);
-  }
-  DftDir<16, INV>::run(u);
-  if constexpr (P == 256) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = u[r];
-  } else {
-    const PassOut<P, 16> o(t);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) lds[o.base + PassOut<P, 16>::off(r)] = u[r];
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = lds[lds_pad(t) + m * (T + T / 16)];
-    __syncthreads();
-  }
-}
-
-template <bool INV>
-__device__ __forceinline__ void fft(c32 (&v)[E], c32 *lds, int t, const c32 *tw2s, const c32 (&w3)[15]) {
-  c32 w2[15];
-  pass<INV, 1>(v, lds, t, w2);
-#pragma unroll
-  for (int r = 1; r < 16; ++r) w2[r - 1] = tw2s[(r - 1) * 16 + (t & 15)];
-  pass<INV, 16>(v, lds, t, w2);
-  pass<INV, 256>(v, lds, t, w3);
-}
-}  // namespace pipe4096
-
-template <bool ADJ>
-__global__ void __launch_bounds__(pipe4096::THREADS) col_sweep_pipe(BatchArgs args, int count, const float2 *tw) {
-  using namespace pipe4096;
-  __shared__ c32 xch[LINES * LINE];
-  __shared__ c32 hs[HALF_H];
-  __shared__ c32 tw2s[15 * 16];
-  const int c = threadIdx.x & (LINES - 1);
-  const int t = threadIdx.x / LINES;
-  // twiddle tables of Plan<4096, 16, 16, 16, 16>: [r - 1][k] per pass with span > 1
-  if (threadIdx.x < 15 * 16) tw2s[threadIdx.x] = ld2(tw + threadIdx.x);
-  c32 w3[15];
-#pragma unroll
-  for (int r = 1; r < 16; ++r) w3[r - 1] = ld2(tw + 15 * 16 + (r - 1) * 256 + t);
-  constexpr int HV = (HALF_H + THREADS - 1) / THREADS;
-  auto load_h = [&](const float2 *h, c32 (&hv)[HV]) {
-#pragma unroll
-    for (int j = 0; j < HV; ++j) {
-      const int k = threadIdx.x + THREADS * j;
-      hv[j] = k < HALF_H ? ld2(h + k) : c32{0.0f, 0.0f};
-    }
-  };
-  auto store_h = [&](const c32 (&hv)[HV]) {
-#pragma unroll
-    for (int j = 0; j < HV; ++j) {
-      const int k = threadIdx.x + THREADS * j;
-      if (k < HALF_H) hs[k] = hv[j];
-    }
-  };
-  const int B = gridDim.x;
-  const int slot = (blockIdx.x & 7) * (B >> 3) + (blockIdx.x >> 3);
-  const int iters = G / B * count;
-  c32 *my = xch + c * LINE;
-  auto tile_of = [&](int k, int &plane, int &x) {
-    const int id = k * B + slot;
-    plane = id / G;
-    x = (id - plane * G) * LINES + c;
-  };
-  int plane, x;
-  tile_of(0, plane, x);
-  {
-    c32 hv[HV];
-    load_h(args.p[plane].h, hv);
-    store_h(hv);
-  }
-  c32 cur[E], nxt[E];
-  {
-    const PlaneBuf buf(args.p[plane].field, unsigned(N) * N * 8u);
-#pragma unroll
-    for (int m = 0; m < E; ++m) cur[m] = buf.load(unsigned(t * N + x) * 8u, unsigned(T * m) * unsigned(N) * 8u);
-  }
-  for (int k = 0; k < iters; ++k) {
-    int nplane = plane, nx = x;
-    if (k + 1 < iters) {
-      tile_of(k + 1, nplane, nx);
-      const PlaneBuf nb(args.p[nplane].field, unsigned(N) * N * 8u);
-#pragma unroll
-      for (int m = 0; m < E; ++m) nxt[m] = nb.load(unsigned(t * N + nx) * 8u, unsigned(T * m) * unsigned(N) * 8u);
-    }
-    __syncthreads();  // h (first tile or a new plane) written by every thread
-    fft<false>(cur, my, t, tw2s, w3);
-    // frequency product: slot m holds frequency row t + T m of the column
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int kf = t + T * m;
-      const c32 hk = hs[kf <= N / 2 ? kf : N - kf];
-      cur[m] = ADJ ? cmulc(cur[m], hk) : cmul(cur[m], hk);
-    }
-    const bool new_plane = nplane != plane;
-    c32 hv[HV];
-    if (new_plane) load_h(args.p[nplane].h, hv);
-    fft<true>(cur, my, t, tw2s, w3);  // its exchanges' barriers follow every thread's product
-    {
-      const PlaneBuf buf(args.p[plane].field, unsigned(N) * N * 8u);
-#pragma unroll
-      for (int m = 0; m < E; ++m) buf.store(unsigned(t * N + x) * 8u, unsigned(T * m) * unsigned(N) * 8u, cur[m]);
-    }
-    if (new_plane) store_h(hv);
-#pragma unroll
-    for (int m = 0; m < E; ++m) cur[m] = nxt[m];
-    plane = nplane;
-    x = nx;
-  }
-}
-
-// blocks of the pipelined column sweep: the largest power of two <= the compute units (at
-// least 8, at most the tiles of a plane)
-static int pipe_blocks(int cus) {
-  int b = 8;
-  while (2 * b <= cus && 2 * b <= pipe4096::G) b *= 2;
-  return b;
-}
-
 // Forward planes run the row sweep first (optic prologue on contiguous rows) and the column
 // sweep second (mirror epilogue); adjoint planes run the column sweep first (conjugate mirror
 // prologue) and the row sweep second (conjugate optic epilogue). The two halves of the
@@ -573,43 +422,8 @@ void fresnel_twiddle_build(int n, float2 *out) {
 
 int fresnel_variants(int n) { return n == 4096 ? 4 : n == 2048 || n == 8192 ? 3 : 1; }
 
-// variant 4 of the 4096 edge: the row sweep of variant 0 and the pipelined column sweep (planes
-// with a column-side optic, the DM after the step, take col_sweep)
-static hipError_t launch_pipe4096(const BatchArgs &fwd, int nf, const BatchArgs &adj, int na,
-                                  const float2 *tw, hipStream_t s, const LaunchHook &hook, int cus) {
-  using P4 = Plan<4096, 16, 16, 16, 16>;
-  bool post = false;
-  for (int i = 0; i < nf; ++i) post = post || fwd.p[i].post_surf;
-  for (int i = 0; i < na; ++i) post = post || adj.p[i].post_surf;
-  if (post) return launch_sweeps<P4, 1, 4>(fwd, nf, adj, na, tw, s, hook);
-  const int blocks = pipe_blocks(cus);
-  auto rows = [&](const BatchArgs &a, int count, const char *name) {
-    hook(s, name, count, 0);
-    hipLaunchKernelGGL((row_sweep<P4, 1, false>), dim3(4096, count), dim3(P4::T), 0, s, a, tw);
-    hipError_t e = hipGetLastError();
-    hook(s, name, count, 1);
-    return e;
-  };
-  auto cols = [&](const BatchArgs &a, int count, bool adjoint, const char *name) {
-    hook(s, name, count, 0);
-    if (adjoint)
-      hipLaunchKernelGGL((col_sweep_pipe<true>), dim3(blocks), dim3(pipe4096::THREADS), 0, s, a, count, tw);
-    else
-      hipLaunchKernelGGL((col_sweep_pipe<false>), dim3(blocks), dim3(pipe4096::THREADS), 0, s, a, count, tw);
-    hipError_t e = hipGetLastError();
-    hook(s, name, count, 1);
-    return e;
-  };
-  hipError_t e = hipSuccess;
-  if (nf && (e = rows(fwd, nf, "row_sweep")) != hipSuccess) return e;
-  if (nf && (e = cols(fwd, nf, false, "col_sweep")) != hipSuccess) return e;
-  if (na && (e = cols(adj, na, true, "col_sweep_adj")) != hipSuccess) return e;
-  if (na && (e = rows(adj, na, "row_sweep_adj")) != hipSuccess) return e;
-  return e;
-}
-
 hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const float2 *root,
-                                hipStream_t s, const LaunchHook &hook, int variant, int cus) {
+                                hipStream_t s, const LaunchHook &hook, int variant) {
   BatchArgs fwd, adj;
   int nf = 0, na = 0;
   for (int i = 0; i < count; ++i) {
@@ -652,7 +466,6 @@ hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const
       if (variant == 2) FR_SWEEPS(P4, 2, 2);
       // column exchanges through half-size LDS lines
       if (variant == 3) return launch_sweeps<P4, 1, 4, P4, true>(fwd, nf, adj, na, root, s, hook);
-      if (variant == 4) return launch_pipe4096(fwd, nf, adj, na, root, s, hook, cus);
       FR_SWEEPS(P4, 1, 4);
     }
     case 8192: {

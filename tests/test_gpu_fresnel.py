@@ -289,6 +289,73 @@ def test_autotuner_choices_keep_parity(tmp_path):
         fb.autotune_load(str(bad))
 
 
+def test_sweep_variants_4096_agree_bitwise(tmp_path):
+    """The tile variants of the 4096 sweeps (rows per block, columns per tile, half-size LDS
+    exchanges: instances of one kernel template) compute the same planes bit for bit, on batches
+    of one to three planes of different wavelengths launched together (a tuned group of three
+    planes per launch) and one plane per launch, forward and adjoint with a dense optic; variant
+    0 against the oracle."""
+    n = 4096
+    saved = tmp_path / "saved.txt"
+    fb.autotune_save(str(saved))
+    rng = np.random.default_rng(4096)
+    amp = rng.uniform(0.5, 1.0, (n, n))
+    opd = rng.normal(0, 40e-9, (n, n))
+    amp_g, opd_g = to_gpu(amp, torch.float32), to_gpu(opd, torch.float32)
+    lams = [500e-9, 550e-9, 600e-9]
+    dx, z = 2.5e-5, 1.0
+    fields = [synth.random_field(n, 900 + i) for i in range(3)]
+    results = {}
+    try:
+        for v in range(4):
+            for group in (1, 3):
+                (tmp_path / "v.txt").write_text("sweep 4096 %d %d\n" % (v, group))
+                fb.autotune_load(str(tmp_path / "v.txt"))
+                for adjoint in (False, True):
+                    banner(f"sweep variant {v}: {group} plane(s) per launch adjoint={adjoint}")
+                    ts = [to_gpu(f) for f in fields]
+                    fb.fresnel_step_batched(ts, dx, lams, z, amps=amp_g, opds=opd_g, adjoints=adjoint)
+                    torch.cuda.synchronize()
+                    results[(v, group, adjoint)] = [t.cpu() for t in ts]
+                    del ts
+    finally:
+        fb.autotune_load(str(saved))
+    for key, planes in results.items():
+        ref = results[(0, 1, key[2])]
+        for i in range(3):
+            assert torch.equal(planes[i], ref[i]), key
+    for adjoint in (False, True):
+        want = oracle.fresnel_step(f32(fields[2]), dx, lams[2], z, amp=f32(amp), opd=f32(opd), adjoint=adjoint)
+        got = results[(0, 3, adjoint)][2].numpy().astype(np.complex128)
+        assert rel_l2(got, want) <= TOL, adjoint
+
+
+def test_tuning_change_drops_recorded_graphs(tmp_path):
+    """A recorded batched call replays its recording (one graph launch) until the kernel choices
+    change: loading tuned choices drops every recording, so the next call runs the sweeps eagerly
+    (and records again)."""
+    n = 256
+    saved = tmp_path / "saved.txt"
+    fb.autotune_save(str(saved))
+    ts = [to_gpu(synth.random_field(n, 70 + i)) for i in range(2)]
+
+    def launches():
+        fb.profile_read()
+        fb.profile_enable(True)
+        fb.fresnel_step_batched(ts, 2e-5, [500e-9, 600e-9], 0.05, graph=True)
+        torch.cuda.synchronize()
+        fb.profile_enable(False)
+        return {k.partition("/")[0] for k in fb.profile_read()}
+    try:
+        launches()
+        assert launches() == {"fresnel_graph"}
+        fb.autotune_load(str(saved))
+        assert "row_sweep" in launches()
+        assert launches() == {"fresnel_graph"}
+    finally:
+        fb.autotune_load(str(saved))
+
+
 def test_table_cache_bound_is_applied_between_calls_only():
     # With the cache bound at 2 tables, a batch of five planes over five distances needs six
     # tables (five transfer functions and the FFT roots): the bound must not free any of them
