@@ -216,6 +216,26 @@ int mft_adjoint(fr_ctx *ctx, const fr_c64 *in, int32_t m_in, int32_t ld_in, fr_c
                 int32_t n_out, int32_t ld_out, double n_d, double du, float alpha, float beta,
                 const float *out_mask, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- mft_forward for callers that cannot allocate device memory -----------------------------
+ * For code under HIP graph capture, tight serving loops and harnesses that forbid allocation: the
+ * same transform, arguments and kernels as mft_forward without the workspace arguments. The
+ * working memory (the n_in x m_out product T, then split-K partial sums in what is left) is a
+ * library-owned array of 64 MiB per device (2^26 bytes, a static device array held until the
+ * process ends; its address is taken once per device by fr_create). The call allocates and frees
+ * nothing: it neither trims the table cache nor builds tables, so the MFT matrix of the geometry
+ * (m_out, n_in, n_d, du) must already be cached in the context by an earlier mft_forward (or
+ * propagate_train) call with that geometry; if it is not, FR_ESTATE and nothing is launched.
+ * Sizes whose product T exceeds the array (8 n_in m_out bytes, 256-aligned, above 2^26) give
+ * FR_EWORKSPACE. Calls on one device share the array: calls that overlap on one device (several
+ * streams or host threads) race and must be ordered by the caller; the array needs no clearing
+ * (every byte read is written by the same call first). Results equal mft_forward's up to the
+ * split-K factor, which the smaller array may reduce (float32 rounding order). Errors: FR_EINVAL
+ * (as mft_forward), FR_EWORKSPACE, FR_ESTATE, FR_EHIP (the array's address could not be taken).
+ * Warning: FR_W_MFT_ALIASED. */
+int mft_forward_noalloc(fr_ctx *ctx, const fr_c64 *in, int32_t n_in, int32_t ld_in, fr_c64 *out,
+                        int32_t m_out, int32_t ld_out, double n_d, double du, const float *out_mask,
+                        void *stream);
+
 /* ---- the MFT in float64 (Sec. 1.1, after Soummer et al.; the paper benchmarks float64) -------
  * Forward (flags 0): in is the n_pupil x n_pupil pupil field, out the m_focal x m_focal focal
  *   field, out = (du/n_d) W in W^T with W as for mft_forward (phases from the exact integer

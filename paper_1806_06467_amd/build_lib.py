@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfresnel.so")
-SOURCES = ["api.cpp", "autotune.cpp", "exact.cpp", "train.hip", "sweeps.hip", "sweeps_mr.hip", "mft.hip", "mft64.hip"]
+SOURCES = ["api.cpp", "autotune.cpp", "exact.cpp", "train.hip", "sweeps.hip", "sweeps_mr.hip", "mft.hip", "mft64.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -173,7 +173,7 @@ int Ctx::upload(const TableKey &key, const void *host, size_t bytes, hipStream_t
     *out = it->second;
     return FR_OK;
   }
-  if (capturing) return FR_ESTATE;
+  if (capturing || no_alloc) return FR_ESTATE;
   void *d = nullptr;
   if (hipMalloc(&d, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -382,7 +382,7 @@ int Ctx::dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **ou
 
 // workspace of one MFT: the n x m c64 intermediate, then (256-byte aligned) the float64
 // split-K partials
-static size_t mft_t_bytes(int n, int m) { return (size_t(n) * size_t(m) * sizeof(float2) + 255) & ~size_t(255); }
+size_t mft_t_bytes(int n, int m) { return (size_t(n) * size_t(m) * sizeof(float2) + 255) & ~size_t(255); }
 size_t mft_ws_bytes(int n, int m) {
   return mft_t_bytes(n, m) + size_t(kMaxSplit) * size_t(n) * size_t(m) * 2 * sizeof(double);
 }
@@ -408,13 +408,13 @@ hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, void *partial, size_t partial_elems,
 }
 
 int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out, double n_d,
-                     double du, const MftOut &o, void *ws, hipStream_t s) {
+                     double du, const MftOut &o, void *ws, hipStream_t s, size_t partial_cap) {
   const float2 *w;
   int st = ctx->mft_matrix(m_out, n_in, n_d, du, s, &w);
   if (st != FR_OK) return st;
   float2 *t = static_cast<float2 *>(ws);
   void *partial = static_cast<char *>(ws) + mft_t_bytes(n_in, m_out);
-  const size_t pcap = size_t(kMaxSplit) * n_in * m_out;
+  const size_t pcap = std::min(size_t(kMaxSplit) * n_in * m_out, partial_cap);
   // T = E W^T  (n_in x m_out)
   CGemmArgs g1 = gemm_args();
   g1.M = n_in; g1.N = m_out; g1.K = n_in;
@@ -548,6 +548,9 @@ int fr_create(fr_ctx **ctx, int device) {
   if (device < 0 || device >= ndev) return FR_EINVAL;
   e = hipSetDevice(device);
   if (e != hipSuccess) return fr::record_hip(e);
+  // the allocation-free entry point's scratch array: its address on this device (once per device;
+  // a failure is kept and reported by that entry point, the other entry points do not need it)
+  (void)fr::noalloc_setup(device);
   Ctx *c = new Ctx();
   c->device = device;
   int cus = 0;
@@ -576,7 +579,7 @@ const char *fr_status_string(int status) {
     case FR_EUNSUPPORTED: return "unsupported size or combination";
     case FR_EWORKSPACE: return "workspace missing or too small";
     case FR_ENOMEM: return "device allocation for a cached table failed";
-    case FR_ESTATE: return "a table was missing while a graph was being recorded";
+    case FR_ESTATE: return "a table was not cached (a graph recording or an allocation-free call cannot build it)";
     case FR_EHIP:
       g_status_text = std::string("HIP error: ") + hipGetErrorString(g_last_hip);
       return g_status_text.c_str();

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <functional>
 #include <map>
@@ -48,6 +49,7 @@ struct Ctx {
   static constexpr size_t kMaxGraphs = 8;
   hipStream_t capture_stream = nullptr;
   bool capturing = false;  // table uploads are refused while a capture is open
+  bool no_alloc = false;   // ... and during an allocation-free call
   hipGraphExec_t find_graph(const std::string &key);
   void keep_graph(const std::string &key, hipGraphExec_t exec);
   void drop_graphs();
@@ -104,8 +106,14 @@ struct MftOut {
 // split > 0 forces that many K slices (at most kMaxSplit, reduced to fit partial_elems)
 hipError_t run_gemm(Ctx *ctx, CGemmArgs &g, void *partial, size_t partial_elems, hipStream_t s, int cfg = -1,
                     int split = 0);
+// partial_cap: float64 complex split-K partial sums that fit ws after the n_in x m_out product
+// (the split factor is reduced to fit; 0 runs every GEMM unsplit)
 int mft_forward_impl(Ctx *ctx, const float2 *in, int n_in, int ld_in, int m_out, double n_d,
-                     double du, const MftOut &o, void *ws, hipStream_t s);
+                     double du, const MftOut &o, void *ws, hipStream_t s, size_t partial_cap = SIZE_MAX);
+size_t mft_t_bytes(int n, int m);  // the product T of an MFT pair, 256-byte aligned
+// address of the allocation-free entry point's scratch array on `device` (hipGetSymbolAddress once
+// per device, then cached); FR_EHIP if the runtime refuses
+int noalloc_setup(int device);
 // out = alpha (du/n_d) W^H in conj(W) + beta cin, * mask  (cin may alias out)
 int mft_adjoint_impl(Ctx *ctx, const float2 *in, int m_in, int ld_in, float2 *out, int n_out,
                      int ld_out, double n_d, double du, float alpha, float beta,

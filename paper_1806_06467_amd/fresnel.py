@@ -94,6 +94,7 @@ def lib():
             "mft_f64_workspace_bytes": (sz, [i32, i32]),
             "mft_f64": (_c.c_int, [_vp, _vp, _vp, i32, i32, f64, f64, i32, _vp, sz, _vp]),
             "mft_forward": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, _vp, _vp, sz, _vp]),
+            "mft_forward_noalloc": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, _vp, _vp]),
             "mft_adjoint": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, f32, f32, _vp,
                                        _vp, sz, _vp]),
             "fr_profile_enable": (_c.c_int, [_vp, _c.c_int]),
@@ -385,6 +386,25 @@ def mft_f64(inp, n_d, size_out, du, adjoint=False, stream=None):
                    FR_ADJOINT if adjoint else 0, _ptr(ws), ws.numel(), _stream_handle(dev, stream))
     _check(st, "mft_f64")
     return out
+
+
+def mft_forward_noalloc(inp, n_d, m_out, du, out, mask=None, stream=None):
+    """mft_forward through the allocation-free entry point (the library's own device scratch
+    array, no workspace): the caller passes the output; the MFT matrix of the geometry must have
+    been built by an earlier mft_forward call. Returns the status (warning bits) or raises."""
+    if inp.dtype != torch.complex64 or not inp.is_cuda:
+        raise TypeError("inp must be a complex64 GPU tensor")
+    n_in = inp.shape[0]
+    if inp.shape != (n_in, n_in):
+        raise ValueError("inp must be square")
+    _need(out, torch.complex64, (m_out, m_out), "out")
+    if mask is not None:
+        _need(mask, torch.float32, (m_out, m_out), "mask")
+    dev = inp.device.index
+    st = lib().mft_forward_noalloc(context(dev).handle, _ptr(inp), n_in, _row_stride(inp, "inp"), _ptr(out),
+                                   m_out, _row_stride(out, "out"), float(n_d), float(du), _ptr(mask),
+                                   _stream_handle(dev, stream))
+    return _check(st, "mft_forward_noalloc")
 
 
 def mft_adjoint(inp, n_d, n_out, du, alpha=1.0, beta=0.0, mask=None, out=None, stream=None):

@@ -44,6 +44,13 @@ int main(void) {
   EXPECT(dx_out == -7.0);
   EXPECT(mft_workspace_bytes(4096, 256) > 0);
   EXPECT(mft_forward(NULL, NULL, 256, 256, NULL, 64, 64, 128.0, 0.5, NULL, NULL, 0, NULL) == FR_EINVAL);
+  EXPECT(mft_forward_noalloc(NULL, NULL, 256, 256, NULL, 64, 64, 128.0, 0.5, NULL, NULL) == FR_EINVAL);
+  EXPECT(mft_forward_noalloc(NULL, (const fr_c64 *)16, 256, 255, (fr_c64 *)16, 64, 64, 128.0, 0.5, NULL, NULL) ==
+         FR_EINVAL);
+  EXPECT(mft_forward_noalloc(NULL, (const fr_c64 *)16, 8192, 8192, (fr_c64 *)16, 1025, 1025, 128.0, 0.5, NULL, NULL) ==
+         FR_EWORKSPACE);
+  EXPECT(mft_forward_noalloc(NULL, (const fr_c64 *)16, 256, 256, (fr_c64 *)16, 64, 64, 128.0, 0.5, NULL, NULL) ==
+         FR_EINVAL);
   EXPECT(mft_adjoint(NULL, NULL, 64, 64, NULL, 256, 256, 128.0, 0.5, 1.0f, 0.0f, NULL, NULL, 0, NULL) == FR_EINVAL);
   EXPECT(fr_autotune(NULL, 1, 4096, 0, NULL) == FR_EINVAL);
   EXPECT(fr_profile_enable(NULL, 1) == FR_EINVAL);

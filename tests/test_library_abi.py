@@ -12,7 +12,7 @@ from paper_1806_06467_amd import fresnel as fb
 EXPECTED = {
     "fr_create", "fr_destroy", "fr_set_cache_limit", "fr_status_string", "fr_fft_size_supported", "fresnel_step",
     "fresnel_step_batched", "fresnel_step_batched_graph", "fresnel_step_exact", "mft_f64", "mft_f64_workspace_bytes", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
-    "propagate_train_workspace_bytes", "propagate_train", "fr_profile_enable", "fr_profile_read",
+    "propagate_train_workspace_bytes", "propagate_train", "mft_forward_noalloc", "fr_profile_enable", "fr_profile_read",
     "fr_autotune", "fr_autotune_save", "fr_autotune_load",
 }
 
