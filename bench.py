@@ -375,6 +375,25 @@ def main():
             "hbm_frac_whole_plane": frac_of(ms_ex / (3 * N_LAMBDA), 3 * sweep_bytes(N, 0)),
             "sweeps": {k: hbm_entry(k, sweep_bytes(N, 0), v[0] / v[1]) for k, v in aex.items()
                        if k.startswith("exact_") and v[1]}}
+        # ---- the Fresnel plane in float64 (the paper's precision): 8 forward + 8 adjoint planes at
+        # 4096^2 complex128 with float64 amplitude and OPD maps, one call each ------------------
+        n64 = 8
+        amp64, opd64 = amp.double(), opd.double()
+        f64f = [fields[i].to(torch.complex128) for i in range(2 * n64)]
+
+        def f64_planes():
+            for i in range(2 * n64):
+                fb.fresnel_step_f64(f64f[i], DX, lam_pl[i], Z, amp=amp64, opd=opd64, adjoint=i >= n64)
+        ms_64 = timed(f64_planes, 2, 1) / 2
+        a64 = profiled(f64_planes, 1)
+        b64 = 2 * (2 * N * N * 16) + 2 * N * N * 8   # two sweeps of the c128 field, two float64 maps
+        result_extra["fresnel_f64"] = {
+            "value": 2 * n64 / (ms_64 * 1e-3), "unit": "Fresnel planes/s", "dtype": "c128",
+            "planes_per_step": 2 * n64, "hbm_frac_whole_plane": frac_of(ms_64 / (2 * n64), b64),
+            "bytes_per_plane": b64,
+            "sweeps": {k: hbm_entry(k, 2 * N * N * 16 + (2 * N * N * 8 if k.startswith("row") else 0), v[0] / v[1])
+                       for k, v in a64.items() if "sweep64" in k and v[1]}}
+        del f64f, amp64, opd64
         # ---- the float64 MFT of the occulter plane (4096^2 -> 256^2), forward and adjoint -------
         e64 = fields[0].to(torch.complex128)
         out64 = {}
@@ -465,6 +484,24 @@ def train_step(args, fb, synth, np, torch, dev, timed, profiled, lams):
     k = max(2, args.steps // 2)
     ms_b = timed(batched, k, 2) / k
     ms_p = timed(plain, max(1, k // 2), 1) / max(1, k // 2)
+    # the gradient in two calls (an autograd forward / backward pair): the forward keeps the
+    # checkpoint, the backward runs only the adjoint chain; against one forward + gradient call
+    ck = torch.empty(fb.train_ckpt_bytes(tr, ns), dtype=torch.uint8, device=dev)
+
+    def save_then_backward():
+        fb.propagate_train(tr, lams, ns, w, hg, batched=True, out=psf, ckpt=ck, phase="save")
+        fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g_psf, batched=True, grad_out=gh, ckpt=ck,
+                           phase="backward")
+
+    def one_call():
+        fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g_psf, batched=True, out=psf, grad_out=gh)
+
+    def forward_only():
+        fb.propagate_train(tr, lams, ns, w, hg, batched=True, out=psf)
+    ms_two = timed(save_then_backward, k, 1) / k
+    ms_one = timed(one_call, k, 1) / k
+    ms_fwd = timed(forward_only, k, 1) / k
+    del ck
     agg = profiled(lambda: fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g_psf, batched=True, out=psf,
                                               grad_out=gh), 2)
     per_step = {name: v[0] / 2 for name, v in sorted(agg.items(), key=lambda kv: -kv[1][0])}
@@ -491,6 +528,10 @@ def train_step(args, fb, synth, np, torch, dev, timed, profiled, lams):
     return {"workload": "lyot_train_4096_21lambda_2dm_psf_and_gradient", "fresnel_planes_per_step": 2 * N_LAMBDA,
             "batched_graph": {"ms_per_step": ms_b, "fresnel_planes_per_s": 2 * N_LAMBDA / (ms_b * 1e-3)},
             "plain": {"ms_per_step": ms_p, "fresnel_planes_per_s": 2 * N_LAMBDA / (ms_p * 1e-3)},
+            "gradient_two_calls": {"forward_save_plus_backward_ms": ms_two, "one_call_ms": ms_one,
+                                   "forward_only_ms": ms_fwd,
+                                   "note": "batched eager calls; the backward reads the forward's checkpoint "
+                                           "(per wavelength the last-DM plane and the detector field)"},
             "kernels_ms_per_step": top, "gemm_rooflines": gemms,
             "checksum_psf_sum": float(psf.sum())}
 

@@ -97,6 +97,15 @@ int fresnel_step(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wave
                  double z_m, const float *amp, const float *opd_m, double lens_focal_m,
                  int32_t flags, void *stream);
 
+/* ---- one Fresnel plane in float64 (Sec. 2.2: the paper's benchmarks are double precision) ----
+ * fresnel_step with complex float64 fields (fr_c128, interleaved, row-major, n x n, in place)
+ * and float64 maps (amp, opd_m: n x n or NULL): the same optic, transfer function, lens, flags,
+ * conventions, errors and warning. Tables (transfer function, lens chirp, twiddles) are built
+ * and kept in float64. Implemented edges: powers of two from 64 to 8192. Uses no workspace. */
+int fresnel_step_f64(fr_ctx *ctx, fr_c128 *field, int32_t n, double dx_m, double wavelength_m,
+                     double z_m, const double *amp, const double *opd_m, double lens_focal_m,
+                     int32_t flags, void *stream);
+
 /* ---- angular-spectrum step with the exact transfer function (Sec. 1.1: the angular-spectrum
  * method after Lawrence, without the paraxial approximation) ----------------------------------
  * As fresnel_step (same optic, same conventions, same flags), with
@@ -277,11 +286,24 @@ int mft_f64(fr_ctx *ctx, const fr_c128 *in, fr_c128 *out, int32_t n_pupil, int32
  * values (descriptor bytes, host arrays, device pointers, stream) is seen, after running it
  * normally, and replays that graph on later identical calls; the device inputs may change
  * between calls, their addresses may not. At most 8 graphs are kept per context.
+ * The gradient in two calls (for an autograd forward / backward pair): FR_TRAIN_FWD_SAVE runs
+ * the forward (psf written, as without it) and keeps in the caller's checkpoint `ckpt` what the
+ * adjoint needs: per wavelength the field at the last DM plane (n_pad[j]^2 c64) and the detector
+ * field (det_m^2 c64), ckpt_bytes >= propagate_train_ckpt_bytes(desc, n_lambda, n_pad). A later
+ * FR_TRAIN_BWD call with the same descriptor, heights, wavelengths, grids, weights and occulter
+ * bit takes grad_psf, reads that checkpoint and writes grad_heights without running the forward
+ * again (psf is not touched and may be NULL); its grad_heights are bit-identical to those of one
+ * FR_TRAIN_GRAD call. The checkpoint is owned by the caller and only read by FR_TRAIN_BWD; the
+ * caller keeps its contents between the two calls. At most one of FR_TRAIN_GRAD,
+ * FR_TRAIN_FWD_SAVE, FR_TRAIN_BWD per call (else FR_EINVAL); ckpt / ckpt_bytes are ignored (may
+ * be NULL / 0) without the last two, FR_EWORKSPACE when they are too small.
  * ws: device workspace of propagate_train_workspace_bytes(...) bytes (same mode bits). */
 #define FR_TRAIN_NO_OCCULTER 1
 #define FR_TRAIN_GRAD 2
 #define FR_TRAIN_BATCHED 4
 #define FR_TRAIN_GRAPH 8
+#define FR_TRAIN_FWD_SAVE 16
+#define FR_TRAIN_BWD 32
 typedef struct {
   int32_t n_d;               /* pupil pixels across D                                   */
   double d_m;                /* pupil diameter [m]                                      */
@@ -301,10 +323,11 @@ typedef struct {
 } fr_train_desc;
 size_t propagate_train_workspace_bytes(const fr_train_desc *desc, int32_t n_lambda,
                                        const int32_t *n_pad, int32_t mode);
+size_t propagate_train_ckpt_bytes(const fr_train_desc *desc, int32_t n_lambda, const int32_t *n_pad);
 int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda,
                     const double *lambda_m, const int32_t *n_pad, const float *weight,
                     int32_t mode, float *psf, const float *grad_psf, float *grad_heights,
-                    void *ws, size_t ws_bytes, void *stream);
+                    void *ckpt, size_t ckpt_bytes, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- autotuner (Sec. 2.1: measurement decides among equivalent implementations) ---------
  * fr_autotune times the candidate kernel configurations of one workload shape on `stream` and

@@ -14,19 +14,32 @@ struct c32 {
   float x, y;
 };
 
-__device__ __forceinline__ c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
-__device__ __forceinline__ c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
-__device__ __forceinline__ c32 cmul(c32 a, c32 b) {
+// float64 complex (the float64 sweeps; float64 twiddle powers)
+struct c64d {
+  double x, y;
+};
+
+// complex arithmetic for either element type (c32 or c64d)
+template <class C>
+__device__ __forceinline__ C cadd(C a, C b) { return {a.x + b.x, a.y + b.y}; }
+template <class C>
+__device__ __forceinline__ C csub(C a, C b) { return {a.x - b.x, a.y - b.y}; }
+template <class C>
+__device__ __forceinline__ C cmul(C a, C b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
-__device__ __forceinline__ c32 cmulc(c32 a, c32 b) {  // a * conj(b)
+template <class C>
+__device__ __forceinline__ C cmulc(C a, C b) {  // a * conj(b)
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
-__device__ __forceinline__ c32 cconj(c32 a) { return {a.x, -a.y}; }
+template <class C>
+__device__ __forceinline__ C cconj(C a) { return {a.x, -a.y}; }
 __device__ __forceinline__ c32 csq(c32 a) { return {a.x * a.x - a.y * a.y, 2.0f * a.x * a.y}; }
 __device__ __forceinline__ c32 cscale(c32 a, float s) { return {a.x * s, a.y * s}; }
-__device__ __forceinline__ c32 mul_mi(c32 a) { return {a.y, -a.x}; }  // a * (-i)
-__device__ __forceinline__ c32 mul_pi(c32 a) { return {-a.y, a.x}; }  // a * (+i)
+template <class C>
+__device__ __forceinline__ C mul_mi(C a) { return {a.y, -a.x}; }  // a * (-i)
+template <class C>
+__device__ __forceinline__ C mul_pi(C a) { return {-a.y, a.x}; }  // a * (+i)
 
 // ---- compile-time trig ------------------------------------------------------------------
 constexpr double kPi = 3.14159265358979323846264338327950288;
@@ -86,11 +99,13 @@ constexpr double ct_sin_turn(long k, long m) {
   }
 }
 
-// v * exp(-2 pi i K / M), with the multiples of pi/4 done without multiplications
-template <int K, int M>
-__device__ __forceinline__ c32 twmul(c32 v) {
+// v * exp(-2 pi i K / M), with the multiples of pi/4 done without multiplications; the
+// constants in the element type's precision
+template <int K, int M, class C>
+__device__ __forceinline__ C twmul(C v) {
+  using S = decltype(v.x);
   constexpr int k = ((K % M) + M) % M;
-  constexpr float h = 0.70710678118654752440f;
+  constexpr S h = S(0.70710678118654752440);
   if constexpr (k == 0) {
     return v;
   } else if constexpr (2 * k == M) {
@@ -108,8 +123,8 @@ __device__ __forceinline__ c32 twmul(c32 v) {
   } else if constexpr (8 * k == 7 * M) {  // (1 + i)/sqrt2
     return {(v.x - v.y) * h, (v.x + v.y) * h};
   } else {
-    constexpr float c = float(ct_cos_turn(k, M));
-    constexpr float s = float(-ct_sin_turn(k, M));
+    constexpr S c = S(ct_cos_turn(k, M));
+    constexpr S s = S(-ct_sin_turn(k, M));
     return {v.x * c - v.y * s, v.x * s + v.y * c};
   }
 }
@@ -120,13 +135,15 @@ struct Dft;
 
 template <>
 struct Dft<1> {
-  __device__ __forceinline__ static void run(c32*) {}
+  template <class C>
+  __device__ __forceinline__ static void run(C*) {}
 };
 
 template <>
 struct Dft<2> {
-  __device__ __forceinline__ static void run(c32* u) {
-    c32 a = u[0], b = u[1];
+  template <class C>
+  __device__ __forceinline__ static void run(C* u) {
+    C a = u[0], b = u[1];
     u[0] = cadd(a, b);
     u[1] = csub(a, b);
   }
@@ -134,9 +151,10 @@ struct Dft<2> {
 
 template <>
 struct Dft<4> {
-  __device__ __forceinline__ static void run(c32* u) {
-    c32 t0 = cadd(u[0], u[2]), t1 = csub(u[0], u[2]);
-    c32 t2 = cadd(u[1], u[3]), t3 = csub(u[1], u[3]);
+  template <class C>
+  __device__ __forceinline__ static void run(C* u) {
+    C t0 = cadd(u[0], u[2]), t1 = csub(u[0], u[2]);
+    C t2 = cadd(u[1], u[3]), t3 = csub(u[1], u[3]);
     u[0] = cadd(t0, t2);
     u[2] = csub(t0, t2);
     u[1] = cadd(t1, mul_mi(t3));
@@ -146,12 +164,14 @@ struct Dft<4> {
 
 template <>
 struct Dft<3> {
-  __device__ __forceinline__ static void run(c32* u) {
-    constexpr float s3 = 0.86602540378443864676f;  // sqrt(3)/2
-    c32 t = cadd(u[1], u[2]), d = csub(u[1], u[2]);
-    c32 a = u[0];
-    c32 m = {a.x - 0.5f * t.x, a.y - 0.5f * t.y};
-    c32 r = {d.x * s3, d.y * s3};
+  template <class C>
+  __device__ __forceinline__ static void run(C* u) {
+    using S = decltype(u->x);
+    constexpr S s3 = S(0.86602540378443864676);  // sqrt(3)/2
+    C t = cadd(u[1], u[2]), d = csub(u[1], u[2]);
+    C a = u[0];
+    C m = {a.x - S(0.5) * t.x, a.y - S(0.5) * t.y};
+    C r = {d.x * s3, d.y * s3};
     u[0] = cadd(a, t);
     u[1] = cadd(m, mul_mi(r));
     u[2] = csub(m, mul_mi(r));
@@ -161,41 +181,43 @@ struct Dft<3> {
 // odd prime R: pair n with R - n; X_k = x0 + sum s_n cos - i sum d_n sin, X_{R-k} with +i
 template <int R>
 struct DftOdd {
-  __device__ __forceinline__ static void run(c32* u) {
+  template <class C>
+  __device__ __forceinline__ static void run(C* u) {
     constexpr int H = (R - 1) / 2;
-    c32 s[H], d[H];
+    C s[H], d[H];
 #pragma unroll
     for (int n = 1; n <= H; ++n) {
       s[n - 1] = cadd(u[n], u[R - n]);
       d[n - 1] = csub(u[n], u[R - n]);
     }
-    c32 x0 = u[0];
-    c32 sum = x0;
+    C x0 = u[0];
+    C sum = x0;
 #pragma unroll
     for (int n = 0; n < H; ++n) sum = cadd(sum, s[n]);
-    c32 out[R];
+    C out[R];
     out[0] = sum;
     run_k<1>(x0, s, d, out);
 #pragma unroll
     for (int k = 0; k < R; ++k) u[k] = out[k];
   }
-  template <int K>
-  __device__ __forceinline__ static void run_k(c32 x0, const c32* s, const c32* d, c32* out) {
+  template <int K, class C>
+  __device__ __forceinline__ static void run_k(C x0, const C* s, const C* d, C* out) {
     constexpr int H = (R - 1) / 2;
     if constexpr (K <= H) {
-      c32 a = x0, b = {0.f, 0.f};
+      C a = x0, b = {0, 0};
       acc<K, 1>(a, b, s, d);
       out[K] = cadd(a, mul_mi(b));
       out[R - K] = csub(a, mul_mi(b));
       run_k<K + 1>(x0, s, d, out);
     }
   }
-  template <int K, int N1>
-  __device__ __forceinline__ static void acc(c32& a, c32& b, const c32* s, const c32* d) {
+  template <int K, int N1, class C>
+  __device__ __forceinline__ static void acc(C& a, C& b, const C* s, const C* d) {
+    using S = decltype(a.x);
     constexpr int H = (R - 1) / 2;
     if constexpr (N1 <= H) {
-      constexpr float c = float(ct_cos_turn(long(K) * N1, R));
-      constexpr float sn = float(ct_sin_turn(long(K) * N1, R));
+      constexpr S c = S(ct_cos_turn(long(K) * N1, R));
+      constexpr S sn = S(ct_sin_turn(long(K) * N1, R));
       a.x += s[N1 - 1].x * c;
       a.y += s[N1 - 1].y * c;
       b.x += d[N1 - 1].x * sn;
@@ -214,12 +236,13 @@ struct Dft<7> : DftOdd<7> {};
 //   step 1: for each n2, DFT_A over n1; twiddle by w_R^(n2 k1); step 2: for each k1, DFT_B over n2
 template <int A, int B>
 struct DftComposite {
-  __device__ __forceinline__ static void run(c32* u) {
+  template <class C>
+  __device__ __forceinline__ static void run(C* u) {
     constexpr int R = A * B;
-    c32 t[R];
+    C t[R];
 #pragma unroll
     for (int n2 = 0; n2 < B; ++n2) {
-      c32 a[A];
+      C a[A];
 #pragma unroll
       for (int n1 = 0; n1 < A; ++n1) a[n1] = u[B * n1 + n2];
       Dft<A>::run(a);
@@ -229,7 +252,7 @@ struct DftComposite {
     }
 #pragma unroll
     for (int k1 = 0; k1 < A; ++k1) {
-      c32 b[B];
+      C b[B];
 #pragma unroll
       for (int n2 = 0; n2 < B; ++n2) b[n2] = t[k1 * B + n2];
       Dft<B>::run(b);
@@ -238,15 +261,15 @@ struct DftComposite {
     }
   }
   // a[k1] *= w_R^(n2 k1); n2 is a loop index that unrolls to a constant
-  template <int K1>
-  __device__ __forceinline__ static void tw_row(c32* a, int n2) {
+  template <int K1, class C>
+  __device__ __forceinline__ static void tw_row(C* a, int n2) {
     if constexpr (K1 < A) {
       a[K1] = tw_dispatch<K1, 0>(a[K1], n2);
       tw_row<K1 + 1>(a, n2);
     }
   }
-  template <int K1, int N2>
-  __device__ __forceinline__ static c32 tw_dispatch(c32 v, int n2) {
+  template <int K1, int N2, class C>
+  __device__ __forceinline__ static C tw_dispatch(C v, int n2) {
     if constexpr (N2 < B) {
       if (n2 == N2) return twmul<K1 * N2, A * B>(v);
       return tw_dispatch<K1, N2 + 1>(v, n2);
@@ -279,12 +302,13 @@ struct Dft<32> : DftComposite<4, 8> {};
 // forward butterfly is reused and its outputs are renamed (no arithmetic).
 template <int R, bool INV>
 struct DftDir {
-  __device__ __forceinline__ static void run(c32 *u) {
+  template <class C>
+  __device__ __forceinline__ static void run(C *u) {
     Dft<R>::run(u);
     if constexpr (INV) {
 #pragma unroll
       for (int k = 1; k < (R + 1) / 2; ++k) {
-        const c32 t = u[k];
+        const C t = u[k];
         u[k] = u[R - k];
         u[R - k] = t;
       }
@@ -296,9 +320,6 @@ struct DftDir {
 // float64 (full rate on CDNA, like non-packed float32), p_r = p_{r-1} w1, whose rounding
 // (~r 1e-16) stays far below float resolution, then rounded once to float: every twiddle is
 // within half an ulp from one table value per butterfly, with two float64 values live.
-struct c64d {
-  double x, y;
-};
 __device__ __forceinline__ c64d dmul(c64d a, c64d b) {
   return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
 }

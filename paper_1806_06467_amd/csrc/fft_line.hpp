@@ -42,23 +42,23 @@ struct PassOut {
 };
 
 // Twiddles of one pass for the NB butterflies a thread owns: leg r of butterfly b is
-// multiplied by w_{PR}^{r (b mod P)}, read from the pass's float32 table laid out
+// multiplied by w_{PR}^{r (b mod P)}, read from the pass's float32 (or float64) table laid out
 // [r - 1][k], k = b mod P, so that for each leg the lanes of a wavefront read consecutive
 // entries (the table is built in float64 on the host; each entry is within half an ulp).
-template <int P, int R, int NB, int T>
+template <int P, int R, int NB, int T, class C = c32, class TW = float2>
 struct PassTw {
   // with several butterflies per thread and long lines (32 elements per thread) the twiddles
   // are read per butterfly inside the pass instead (register budget)
   static constexpr bool lazy = NB > 1 && NB * R >= 32;
-  c32 w[lazy ? 1 : NB][R > 1 ? R - 1 : 1];
-  __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) {
+  C w[lazy ? 1 : NB][R > 1 ? R - 1 : 1];
+  __device__ __forceinline__ void load(const TW* __restrict__ tw, int t) {
     if constexpr (P > 1 && !lazy) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         const int k = (t + j * T) % P;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const float2 q = tw[(r - 1) * P + k];
+          const TW q = tw[(r - 1) * P + k];
           w[j][r - 1] = {q.x, q.y};
         }
       }
@@ -79,10 +79,11 @@ struct FirstOf {
 // one butterfly, else the first half of each thread's butterflies), then the upper half. Every
 // non-last pass has P R <= N/2, so the N/2 boundary never splits a butterfly's outputs, and the
 // reading slots split the same way (slot m < E/2 is position t + T m < N/2).
-template <bool INV, bool HALF, int N, int E, int P, int R, int... Rest>
-__device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, int t,
-                                           const float2* __restrict__ tw,
-                                           const PassTw<P, R, E / R, N / E>& cur) {
+// C: the element type (c32 or c64d); TW: the twiddle table's (float2 or double2)
+template <class C, class TW, bool INV, bool HALF, int N, int E, int P, int R, int... Rest>
+__device__ __forceinline__ void fft_passes(C (&v)[E], C* __restrict__ lds, int t,
+                                           const TW* __restrict__ tw,
+                                           const PassTw<P, R, E / R, N / E, C, TW>& cur) {
   constexpr int T = N / E;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide the elements per thread");
@@ -92,9 +93,9 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
   constexpr bool lazy = PassTw<P, R, NB, T>::lazy;
   // outputs of the second half-round, held until the first half has been exchanged
   constexpr int HOLD = !HALF || last ? 1 : (NB == 1 ? 1 : NB / 2);
-  c32 hold[HOLD][R];
+  C hold[HOLD][R];
   // write output r of butterfly b (positions shifted down by `shift`)
-  auto put = [&](int b, int shift, const c32 (&u)[R]) {
+  auto put = [&](int b, int shift, const C (&u)[R]) {
     if constexpr (PassOut<P, R>::exact) {
       const PassOut<P, R> o(b - shift / R);
 #pragma unroll
@@ -107,7 +108,7 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
   };
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    c32 u[R];
+    C u[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[j + r * NB];
     const int b = t + j * T;
@@ -116,8 +117,8 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
         const int k = b % P;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const float2 q = tw[(r - 1) * P + k];
-          u[r] = INV ? cmulc(u[r], c32{q.x, q.y}) : cmul(u[r], c32{q.x, q.y});
+          const TW q = tw[(r - 1) * P + k];
+          u[r] = INV ? cmulc(u[r], C{q.x, q.y}) : cmul(u[r], C{q.x, q.y});
         }
       } else {
 #pragma unroll
@@ -148,8 +149,8 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
   }
   if constexpr (!last) {
     constexpr int R2 = FirstOf<Rest...>::value;
-    const float2* tw_next = tw + (P > 1 ? (R - 1) * P : 0);
-    PassTw<P * R, R2, E / R2, T> nxt;
+    const TW* tw_next = tw + (P > 1 ? (R - 1) * P : 0);
+    PassTw<P * R, R2, E / R2, T, C, TW> nxt;
     nxt.load(tw_next, t);
     // read slots [m0, m1), whose positions start at T m0
     auto get = [&](int m0, int m1) {
@@ -180,22 +181,25 @@ __device__ __forceinline__ void fft_passes(c32 (&v)[E], c32* __restrict__ lds, i
       get(E / 2, E);
       __syncthreads();
     }
-    fft_passes<INV, HALF, N, E, P * R, Rest...>(v, lds, t, tw_next, nxt);
+    fft_passes<C, TW, INV, HALF, N, E, P * R, Rest...>(v, lds, t, tw_next, nxt);
   }
 }
 
 // float64-built twiddle table of a plan: for each pass with span P > 1 and radix R, the block
-// [r - 1][k] = exp(-2 pi i r k / (P R)), r = 1..R-1, k = 0..P-1 (rounded once to float)
+// [r - 1][k] = exp(-2 pi i r k / (P R)), r = 1..R-1, k = 0..P-1 (rounded once to float for a
+// float2 table, kept in float64 for a double2 table)
+inline void tw_store(float2* p, double c, double s) { *p = make_float2(float(c), float(s)); }
+inline void tw_store(double2* p, double c, double s) { *p = make_double2(c, s); }
 template <int N, int P, int R, int... Rest>
 struct TwiddleTable {
-  static void build(float2* out) {
+  template <class TW>
+  static void build(TW* out) {
     if (P > 1) {
       for (int r = 1; r < R; ++r)
         for (int k = 0; k < P; ++k) {
           const long long num = (long long)r * k % (P * R);
           const double turn = -double(num) / double(P * R);
-          out[(r - 1) * P + k] = make_float2(float(__builtin_cos(2.0 * kPi * turn)),
-                                             float(__builtin_sin(2.0 * kPi * turn)));
+          tw_store(out + (r - 1) * P + k, __builtin_cos(2.0 * kPi * turn), __builtin_sin(2.0 * kPi * turn));
         }
     }
     if constexpr (sizeof...(Rest) > 0) TwiddleTable<N, P * R, Rest...>::build(out + (P > 1 ? (R - 1) * P : 0));
@@ -215,19 +219,21 @@ struct Plan {
   static constexpr int T = N_ / E_;
   static constexpr int twiddles = TwiddleTable<N_, 1, Rs...>::size();
   static constexpr int R0 = FirstOf<Rs...>::value;
-  static void build_twiddles(float2* out) { TwiddleTable<N_, 1, Rs...>::build(out); }
-  // unnormalised DFT of the line, kernel exp(-2 pi i nk/N); tw = the plan's twiddle table.
-  // HALF: exchanges through an LDS line of N/2 (LdsLine<N/2>), in two rounds each.
-  template <bool HALF = false>
-  __device__ __forceinline__ static void forward(c32 (&v)[E_], c32* lds, int t, const float2* tw) {
-    PassTw<1, R0, E_ / R0, N_ / E_> none;
-    fft_passes<false, HALF, N_, E_, 1, Rs...>(v, lds, t, tw, none);
+  template <class TW>
+  static void build_twiddles(TW* out) { TwiddleTable<N_, 1, Rs...>::build(out); }
+  // unnormalised DFT of the line, kernel exp(-2 pi i nk/N); tw = the plan's twiddle table (float2
+  // for c32 elements, double2 for c64d). HALF: exchanges through an LDS line of N/2
+  // (LdsLine<N/2>), in two rounds each.
+  template <bool HALF = false, class C, class TW>
+  __device__ __forceinline__ static void forward(C (&v)[E_], C* lds, int t, const TW* tw) {
+    PassTw<1, R0, E_ / R0, N_ / E_, C, TW> none;
+    fft_passes<C, TW, false, HALF, N_, E_, 1, Rs...>(v, lds, t, tw, none);
   }
   // unnormalised inverse DFT, kernel exp(+2 pi i nk/N)
-  template <bool HALF = false>
-  __device__ __forceinline__ static void inverse(c32 (&v)[E_], c32* lds, int t, const float2* tw) {
-    PassTw<1, R0, E_ / R0, N_ / E_> none;
-    fft_passes<true, HALF, N_, E_, 1, Rs...>(v, lds, t, tw, none);
+  template <bool HALF = false, class C, class TW>
+  __device__ __forceinline__ static void inverse(C (&v)[E_], C* lds, int t, const TW* tw) {
+    PassTw<1, R0, E_ / R0, N_ / E_, C, TW> none;
+    fft_passes<C, TW, true, HALF, N_, E_, 1, Rs...>(v, lds, t, tw, none);
   }
 };
 

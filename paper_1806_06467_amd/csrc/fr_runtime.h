@@ -14,7 +14,10 @@
 
 namespace fr {
 
-enum TableKind : int { kRoots = 1, kTransfer, kLens, kMft, kDm, kMrTw, kDirectPre, kDirectPost, kExactPrm, kMft64 };
+enum TableKind : int {
+  kRoots = 1, kTransfer, kLens, kMft, kDm, kMrTw, kDirectPre, kDirectPost, kExactPrm, kMft64,
+  kRoots64, kTransfer64, kLens64
+};
 // (kind, size, then up to four parameter words: sizes or the bits of float64 parameters)
 using TableKey = std::tuple<int, int, uint64_t, uint64_t, uint64_t, uint64_t>;
 

@@ -378,9 +378,36 @@ struct Layout {
   size_t tpart, tsum, gpart, tdm, el, y1, eocc, edet, ydet, psf64, mft, total;
 };
 
+// Checkpoint layout (FR_TRAIN_FWD_SAVE writes it, FR_TRAIN_BWD reads it): per wavelength the
+// field at the last DM plane (n^2 c64), then per wavelength the detector field (det^2 c64).
+struct CkptLayout {
+  std::vector<size_t> e, det;
+  size_t total;
+};
+
+CkptLayout ckpt_layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad) {
+  CkptLayout C;
+  size_t off = 0;
+  C.e.resize(n_lambda);
+  C.det.resize(n_lambda);
+  for (int j = 0; j < n_lambda; ++j) {
+    C.e[j] = off;
+    off += align256(size_t(n_pad[j]) * n_pad[j] * 8);
+  }
+  for (int j = 0; j < n_lambda; ++j) {
+    C.det[j] = off;
+    off += align256(size_t(d->det_m) * d->det_m * 8);
+  }
+  C.total = off;
+  return C;
+}
+
 Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_t mode) {
   Layout L;
-  const bool grad = (mode & FR_TRAIN_GRAD) != 0;
+  // the gradient is computed by FR_TRAIN_GRAD (with the forward) and FR_TRAIN_BWD (from the
+  // checkpoint); with a checkpoint (FWD_SAVE or BWD) the E planes live in it, not here
+  const bool grad = (mode & (FR_TRAIN_GRAD | FR_TRAIN_BWD)) != 0;
+  const bool in_ckpt = (mode & (FR_TRAIN_FWD_SAVE | FR_TRAIN_BWD)) != 0;
   const bool batched = (mode & FR_TRAIN_BATCHED) != 0;
   int nmax = 0;
   for (int j = 0; j < n_lambda; ++j) nmax = std::max(nmax, int(n_pad[j]));
@@ -393,9 +420,11 @@ Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_
   const size_t n2max = size_t(nmax) * nmax;
   const size_t nd2 = size_t(d->n_d) * d->n_d;
   const bool b_per_lambda = batched && grad && d->n_dm == 2;
-  L.e.resize(n_lambda);
+  L.e.assign(n_lambda, 0);
   L.b.assign(n_lambda, 0);
-  if (batched) {
+  if (in_ckpt) {
+    // E planes and detector fields are in the checkpoint
+  } else if (batched) {
     for (int j = 0; j < n_lambda; ++j) L.e[j] = take(size_t(n_pad[j]) * n_pad[j] * 8);
   } else {
     const size_t e0 = take(n2max * 8);
@@ -440,7 +469,12 @@ Layout layout(const fr_train_desc *d, int n_lambda, const int32_t *n_pad, int32_
 int check_desc(const fr_train_desc *d, int32_t n_lambda, const double *lam, const int32_t *n_pad,
                const float *w, int32_t mode) {
   if (!d || n_lambda <= 0 || !lam || !n_pad || !w) return FR_EINVAL;
-  if (mode & ~(FR_TRAIN_NO_OCCULTER | FR_TRAIN_GRAD | FR_TRAIN_BATCHED | FR_TRAIN_GRAPH)) return FR_EINVAL;
+  if (mode & ~(FR_TRAIN_NO_OCCULTER | FR_TRAIN_GRAD | FR_TRAIN_BATCHED | FR_TRAIN_GRAPH | FR_TRAIN_FWD_SAVE |
+               FR_TRAIN_BWD))
+    return FR_EINVAL;
+  // one of: forward, forward + gradient, forward saving the checkpoint, gradient from it
+  const int phase = mode & (FR_TRAIN_GRAD | FR_TRAIN_FWD_SAVE | FR_TRAIN_BWD);
+  if (phase & (phase - 1)) return FR_EINVAL;
   if (d->n_d <= 0 || !(d->d_m > 0) || !d->pupil_amp) return FR_EINVAL;
   if (d->n_dm < 0 || d->n_dm > 2) return FR_EINVAL;
   if (d->n_dm > 0 && (d->n_act <= 0 || !d->dm_heights_m)) return FR_EINVAL;
@@ -451,7 +485,7 @@ int check_desc(const fr_train_desc *d, int32_t n_lambda, const double *lam, cons
   if (d->occ_m <= 0 || !(d->occ_du_c > 0) || d->det_m <= 0 || !(d->det_du_c > 0)) return FR_EINVAL;
   if (!(mode & FR_TRAIN_NO_OCCULTER) && !d->occ_mask) return FR_EINVAL;
   if (!d->lyot || !(d->lambda_c_m > 0)) return FR_EINVAL;
-  if ((mode & FR_TRAIN_GRAD) && d->n_dm == 0) return FR_EINVAL;
+  if ((mode & (FR_TRAIN_GRAD | FR_TRAIN_FWD_SAVE | FR_TRAIN_BWD)) && d->n_dm == 0) return FR_EINVAL;
   for (int j = 0; j < n_lambda; ++j) {
     if (!(lam[j] > 0) || !std::isfinite(w[j])) return FR_EINVAL;
     if (n_pad[j] < d->n_d || ((n_pad[j] - d->n_d) & 1)) return FR_EINVAL;
@@ -471,22 +505,38 @@ size_t train_workspace_bytes(const fr_train_desc *d, int32_t n_lambda, const int
 }
 
 // every argument check of propagate_train (nothing touched, nothing launched)
+size_t train_ckpt_bytes(const fr_train_desc *d, int32_t n_lambda, const int32_t *n_pad) {
+  if (!d || n_lambda <= 0 || !n_pad || d->det_m <= 0) return 0;
+  for (int j = 0; j < n_lambda; ++j)
+    if (n_pad[j] <= 0) return 0;
+  return ckpt_layout(d, n_lambda, n_pad).total;
+}
+
 int check_call(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *lam, const int32_t *n_pad,
                const float *weight, int32_t mode, const float *psf, const float *grad_psf,
-               const float *grad_heights, const void *ws, size_t ws_bytes) {
+               const float *grad_heights, const void *ckpt, size_t ckpt_bytes, const void *ws, size_t ws_bytes) {
   int st = check_desc(d, n_lambda, lam, n_pad, weight, mode);
   if (st != FR_OK) return st;
-  if (!psf || ((mode & FR_TRAIN_GRAD) && (!grad_psf || !grad_heights))) return FR_EINVAL;
+  const bool bwd = (mode & FR_TRAIN_BWD) != 0;
+  if ((!bwd && !psf) || ((mode & (FR_TRAIN_GRAD | FR_TRAIN_BWD)) && (!grad_psf || !grad_heights)))
+    return FR_EINVAL;
+  if ((mode & (FR_TRAIN_FWD_SAVE | FR_TRAIN_BWD)) && (!ckpt || ckpt_bytes < train_ckpt_bytes(d, n_lambda, n_pad)))
+    return FR_EWORKSPACE;
   if (!ws || ws_bytes < train_workspace_bytes(d, n_lambda, n_pad, mode)) return FR_EWORKSPACE;
   return ctx ? FR_OK : FR_EINVAL;
 }
 
 int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *lam,
               const int32_t *n_pad, const float *weight, int32_t mode, float *psf,
-              const float *grad_psf, float *grad_heights, void *ws, size_t ws_bytes, hipStream_t s) {
-  int st = check_call(ctx, d, n_lambda, lam, n_pad, weight, mode, psf, grad_psf, grad_heights, ws, ws_bytes);
+              const float *grad_psf, float *grad_heights, void *ckpt, size_t ckpt_bytes, void *ws,
+              size_t ws_bytes, hipStream_t s) {
+  int st = check_call(ctx, d, n_lambda, lam, n_pad, weight, mode, psf, grad_psf, grad_heights, ckpt, ckpt_bytes,
+                      ws, ws_bytes);
   if (st != FR_OK) return st;
-  const bool grad = (mode & FR_TRAIN_GRAD) != 0;
+  // fwd: this call runs the forward (every mode but FR_TRAIN_BWD); grad: it computes the gradient
+  const bool fwd = !(mode & FR_TRAIN_BWD);
+  const bool grad = (mode & (FR_TRAIN_GRAD | FR_TRAIN_BWD)) != 0;
+  const bool in_ckpt = (mode & (FR_TRAIN_FWD_SAVE | FR_TRAIN_BWD)) != 0;
   const bool occ = !(mode & FR_TRAIN_NO_OCCULTER);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return record_hip(e);
@@ -495,6 +545,12 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   const Layout L = layout(d, n_lambda, n_pad, mode);
   char *base = static_cast<char *>(ws);
   auto c64at = [&](size_t o) { return reinterpret_cast<float2 *>(base + o); };
+  const CkptLayout CK = ckpt_layout(d, n_lambda, n_pad);
+  char *cbase = static_cast<char *>(ckpt);
+  // the field at the last DM plane and the detector field of wavelength j: in the checkpoint
+  // (FWD_SAVE, BWD) or in the workspace (one detector field reused wavelength after wavelength)
+  auto e_of = [&](int j) { return in_ckpt ? reinterpret_cast<float2 *>(cbase + CK.e[j]) : c64at(L.e[j]); };
+  auto det_of = [&](int j) { return in_ckpt ? reinterpret_cast<float2 *>(cbase + CK.det[j]) : c64at(L.edet); };
   float *GPART = grad ? reinterpret_cast<float *>(base + L.gpart) : nullptr;
   float *TPART = grad ? reinterpret_cast<float *>(base + L.tpart) : nullptr;
   float *TSUM = grad ? reinterpret_cast<float *>(base + L.tsum) : nullptr;
@@ -502,7 +558,6 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   float2 *EL = c64at(L.el);
   float2 *Y1 = grad ? c64at(L.y1) : nullptr;
   float2 *EOCC = c64at(L.eocc);
-  float2 *EDET = c64at(L.edet);
   float2 *YDET = grad ? c64at(L.ydet) : nullptr;
   void *MWS = base + L.mft;
   double *PSF64 = reinterpret_cast<double *>(base + L.psf64);
@@ -548,7 +603,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     const int n = n_pad[j];
     const float *surf = surf_of(j);
     std::memset(pa, 0, sizeof *pa);
-    pa->field = c64at(L.e[j]);
+    pa->field = e_of(j);
     pa->n = n;
     pa->amp = d->pupil_amp;
     pa->opd = d->pupil_opd_m;
@@ -575,7 +630,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   // occulter, Babinet subtraction, Lyot stop, detector; psf += w_j |Ed|^2 (a3, a4, a5)
   auto focal_chain = [&](int j) -> int {
     const int n = n_pad[j];
-    const float2 *E = c64at(L.e[j]);
+    const float2 *E = e_of(j);
     const double du_occ = d->occ_du_c * d->lambda_c_m / lam[j];
     const double du_det = d->det_du_c * d->lambda_c_m / lam[j];
     const int off = (n - nd) / 2;
@@ -592,7 +647,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       FR_TRY_HIP(launch1d(window_mask, size_t(nd) * nd, s, hook, "window_mask", E, n, nd, d->lyot, EL));
     }
     MftOut o;
-    o.out = EDET;
+    o.out = det_of(j);
     o.ld_out = d->det_m;
     o.intensity = PSF64;
     o.weight = weight[j];
@@ -656,12 +711,12 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   auto back_to_last_dm = [&](int j) -> int {
     const int n = n_pad[j];
     const size_t n2 = size_t(n) * n;
-    const float2 *E = c64at(L.e[j]);
+    const float2 *E = e_of(j);
     float2 *B = c64at(L.b[j]);
     const double du_occ = d->occ_du_c * d->lambda_c_m / lam[j];
     const double du_det = d->det_du_c * d->lambda_c_m / lam[j];
     FR_TRY_HIP(launch1d(scale_by_grad, det2, s, hook, "scale_by_grad", grad_psf, weight[j],
-                        (const float2 *)EDET, YDET, det2));
+                        (const float2 *)det_of(j), YDET, det2));
     FR_TRY(mft_adjoint_impl(ctx, YDET, d->det_m, d->det_m, Y1, nd, nd, double(nd), du_det, 1.f, 0.f,
                             nullptr, 0, d->lyot, MWS, s));
     if (occ) {
@@ -684,7 +739,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     return dm_grad(j, 0, nullptr, c64at(L.b[j]), surf_of(j));
   };
 
-  FR_TRY_HIP(launch1d(fill_f64, det2, s, hook, "fill", PSF64, det2));
+  if (fwd) FR_TRY_HIP(launch1d(fill_f64, det2, s, hook, "fill", PSF64, det2));
   if (grad) {
     const size_t ng = size_t(ndm) * na * na;
     FR_TRY_HIP(launch1d(fill_f32, ng, s, hook, "fill", grad_heights, ng, 0.f));
@@ -698,10 +753,12 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
         FR_TRY(surfaces(n_pad[j], surf_of(j)));
         surf_n = n_pad[j];
       }
-      PlaneArgs pa;
-      FR_TRY(fwd_plane(j, &pa));
-      FR_TRY(run_planes(ctx, &pa, 1, n_pad[j], s));
-      FR_TRY(focal_chain(j));
+      if (fwd) {
+        PlaneArgs pa;
+        FR_TRY(fwd_plane(j, &pa));
+        FR_TRY(run_planes(ctx, &pa, 1, n_pad[j], s));
+        FR_TRY(focal_chain(j));
+      }
       if (!grad) continue;
       FR_TRY(back_to_last_dm(j));
       if (ndm == 2) {
@@ -729,10 +786,12 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
         bytes += b;
         ++g1;
       }
-      for (int j = g0; j < g1; ++j) FR_TRY(fwd_plane(j, &planes[j]));
-      FR_TRY(run_planes(ctx, planes.data() + g0, g1 - g0, n_pad[g0], s));
+      if (fwd) {
+        for (int j = g0; j < g1; ++j) FR_TRY(fwd_plane(j, &planes[j]));
+        FR_TRY(run_planes(ctx, planes.data() + g0, g1 - g0, n_pad[g0], s));
+      }
       for (int j = g0; j < g1; ++j) {
-        FR_TRY(focal_chain(j));
+        if (fwd) FR_TRY(focal_chain(j));
         if (grad) FR_TRY(back_to_last_dm(j));
       }
       if (grad && ndm == 2) {
@@ -745,7 +804,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
   }
   if (grad)
     for (int k = 0; k < ndm; ++k) FR_TRY(flush(k));
-  FR_TRY_HIP(launch1d(to_f32, det2, s, hook, "psf_to_f32", (const double *)PSF64, psf, det2));
+  if (fwd) FR_TRY_HIP(launch1d(to_f32, det2, s, hook, "psf_to_f32", (const double *)PSF64, psf, det2));
 #undef FR_TRY
 #undef FR_TRY_HIP
   return FR_OK;
@@ -758,7 +817,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
 // same launch sequence on the context's own stream.
 std::string graph_key(const fr_train_desc *d, int32_t n_lambda, const double *lam, const int32_t *n_pad,
                       const float *w, int32_t mode, const void *psf, const void *gpsf, const void *gh,
-                      const void *ws, size_t ws_bytes, hipStream_t s) {
+                      const void *ckpt, size_t ckpt_bytes, const void *ws, size_t ws_bytes, hipStream_t s) {
   std::string k("train");
   auto put = [&](const void *p, size_t b) { k.append(static_cast<const char *>(p), b); };
   put(d, sizeof *d);
@@ -767,26 +826,28 @@ std::string graph_key(const fr_train_desc *d, int32_t n_lambda, const double *la
   put(n_pad, sizeof(int32_t) * n_lambda);
   put(w, sizeof(float) * n_lambda);
   put(&mode, sizeof mode);
-  const void *ptrs[5] = {psf, gpsf, gh, ws, s};
+  const void *ptrs[6] = {psf, gpsf, gh, ckpt, ws, s};
   put(ptrs, sizeof ptrs);
+  put(&ckpt_bytes, sizeof ckpt_bytes);
   put(&ws_bytes, sizeof ws_bytes);
   return k;
 }
 
 int train_call(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *lam,
                const int32_t *n_pad, const float *w, int32_t mode, float *psf, const float *gpsf,
-               float *gh, void *ws, size_t ws_bytes, hipStream_t s) {
-  int st = check_call(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes);
+               float *gh, void *ckpt, size_t ckpt_bytes, void *ws, size_t ws_bytes, hipStream_t s) {
+  int st = check_call(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ckpt, ckpt_bytes, ws, ws_bytes);
   if (st != FR_OK) return st;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return record_hip(e);
   // the cache is trimmed here, once per call (the recording run below must not trim it)
   if ((st = ctx->begin_call()) != FR_OK) return st;
   if (!(mode & FR_TRAIN_GRAPH))
-    return train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
-  const std::string key = graph_key(d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, s);
+    return train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ckpt, ckpt_bytes, ws, ws_bytes, s);
+  const std::string key = graph_key(d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ckpt, ckpt_bytes, ws,
+                                    ws_bytes, s);
   return ctx->graph_call(key, s, "train_graph", n_lambda, [&](hipStream_t cs) {
-    return train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ws, ws_bytes, cs);
+    return train_run(ctx, d, n_lambda, lam, n_pad, w, mode, psf, gpsf, gh, ckpt, ckpt_bytes, ws, ws_bytes, cs);
   });
 }
 
@@ -799,11 +860,16 @@ size_t propagate_train_workspace_bytes(const fr_train_desc *desc, int32_t n_lamb
   return fr::train_workspace_bytes(desc, n_lambda, n_pad, mode);
 }
 
+size_t propagate_train_ckpt_bytes(const fr_train_desc *desc, int32_t n_lambda, const int32_t *n_pad) {
+  return fr::train_ckpt_bytes(desc, n_lambda, n_pad);
+}
+
 int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda, const double *lambda_m,
                     const int32_t *n_pad, const float *weight, int32_t mode, float *psf,
-                    const float *grad_psf, float *grad_heights, void *ws, size_t ws_bytes,
-                    void *stream) {
+                    const float *grad_psf, float *grad_heights, void *ckpt, size_t ckpt_bytes, void *ws,
+                    size_t ws_bytes, void *stream) {
   return fr::train_call(reinterpret_cast<fr::Ctx *>(ctx), desc, n_lambda, lambda_m, n_pad, weight, mode,
-                        psf, grad_psf, grad_heights, ws, ws_bytes, static_cast<hipStream_t>(stream));
+                        psf, grad_psf, grad_heights, ckpt, ckpt_bytes, ws, ws_bytes,
+                        static_cast<hipStream_t>(stream));
 }
 }

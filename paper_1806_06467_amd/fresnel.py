@@ -33,6 +33,8 @@ FR_TRAIN_NO_OCCULTER = 1
 FR_TRAIN_GRAD = 2
 FR_TRAIN_BATCHED = 4
 FR_TRAIN_GRAPH = 8
+FR_TRAIN_FWD_SAVE = 16
+FR_TRAIN_BWD = 32
 
 _c = ctypes
 _vp = _c.c_void_p
@@ -95,6 +97,7 @@ def lib():
             "mft_f64": (_c.c_int, [_vp, _vp, _vp, i32, i32, f64, f64, i32, _vp, sz, _vp]),
             "mft_forward": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, _vp, _vp, sz, _vp]),
             "mft_forward_noalloc": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, _vp, _vp]),
+            "fresnel_step_f64": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
             "mft_adjoint": (_c.c_int, [_vp, _vp, i32, i32, _vp, i32, i32, f64, f64, f32, f32, _vp,
                                        _vp, sz, _vp]),
             "fr_profile_enable": (_c.c_int, [_vp, _c.c_int]),
@@ -104,9 +107,10 @@ def lib():
             "fr_autotune_save": (_c.c_int, [_vp, _c.c_char_p]),
             "fr_autotune_load": (_c.c_int, [_vp, _c.c_char_p]),
             "propagate_train_workspace_bytes": (sz, [_c.POINTER(FrTrainDesc), i32, _c.POINTER(i32), i32]),
+            "propagate_train_ckpt_bytes": (sz, [_c.POINTER(FrTrainDesc), i32, _c.POINTER(i32)]),
             "propagate_train": (_c.c_int, [_vp, _c.POINTER(FrTrainDesc), i32, _c.POINTER(f64),
                                            _c.POINTER(i32), _c.POINTER(f32), i32, _vp, _vp, _vp, _vp,
-                                           sz, _vp]),
+                                           sz, _vp, sz, _vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -300,6 +304,22 @@ def follow_route(field, wavelength, steps, stream=None):
             raise ValueError("unknown route step")
         dx = dx_out
     return dx
+
+
+def fresnel_step_f64(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, adjoint=False,
+                     stream=None):
+    """In place on an n x n complex128 GPU tensor: the Fresnel step of fresnel_step in float64
+    (float64 amp / opd maps). Returns the status (warning bits) or raises."""
+    n = field.shape[0] if field.dim() == 2 else -1
+    _need(field, torch.complex128, (n, n), "field")
+    for t, name in ((amp, "amp"), (opd, "opd")):
+        if t is not None:
+            _need(t, torch.float64, (n, n), name)
+    dev = field.device.index
+    st = lib().fresnel_step_f64(context(dev).handle, _ptr(field), n, float(dx), float(wavelength), float(z),
+                                _ptr(amp), _ptr(opd), float(lens_focal), FR_ADJOINT if adjoint else 0,
+                                _stream_handle(dev, stream))
+    return _check(st, "fresnel_step_f64")
 
 
 def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens_focals=None,
@@ -530,7 +550,7 @@ class Train:
 
 def propagate_train(train, wavelengths, n_pad, weights, heights=None, occulter=True,
                     grad_psf=None, batched=False, graph=False, out=None, grad_out=None,
-                    stream=None):
+                    stream=None, ckpt=None, phase=None):
     """Broadband PSF (det_m x det_m float32) of the train; with grad_psf = dL/dPSF also returns
     dL/dheights (n_dm x n_act x n_act float32).
 
@@ -538,25 +558,39 @@ def propagate_train(train, wavelengths, n_pad, weights, heights=None, occulter=T
     wavelength held in the workspace; same results).
     graph: the library records the whole call as one graph and replays it on later calls with
     the same arguments, which includes the addresses of heights, grad_psf, the outputs and the
-    workspace; pass out= / grad_out= (and keep heights in place) so that they stay fixed."""
+    workspace; pass out= / grad_out= (and keep heights in place) so that they stay fixed.
+    phase="save": forward only, keeping what the adjoint needs in `ckpt` (a uint8 GPU tensor of
+    at least train_ckpt_bytes(...) bytes; returns the PSF); phase="backward": the gradient from
+    that checkpoint (grad_psf required; returns dL/dheights only)."""
     dev = train.pupil_amp.device.index
     nl = len(wavelengths)
     if len(n_pad) != nl or len(weights) != nl:
         raise ValueError("wavelengths, n_pad and weights must have one entry per wavelength")
     if train.n_dm:
         _need(heights, torch.float32, (train.n_dm, train.n_act, train.n_act), "heights")
+    if phase not in (None, "save", "backward"):
+        raise ValueError("phase must be None, 'save' or 'backward'")
     mode = ((0 if occulter else FR_TRAIN_NO_OCCULTER) | (FR_TRAIN_BATCHED if batched else 0)
             | (FR_TRAIN_GRAPH if graph else 0))
+    if phase is not None:
+        if ckpt is None or ckpt.dtype != torch.uint8 or not ckpt.is_cuda:
+            raise TypeError("ckpt must be a uint8 GPU tensor")
+        mode |= FR_TRAIN_FWD_SAVE if phase == "save" else FR_TRAIN_BWD
     gh = None
     if grad_psf is not None:
+        if phase == "save":
+            raise ValueError("phase='save' takes no grad_psf")
         _need(grad_psf, torch.float32, (train.det_m, train.det_m), "grad_psf")
-        mode |= FR_TRAIN_GRAD
+        if phase is None:
+            mode |= FR_TRAIN_GRAD
         if grad_out is not None:
             _need(grad_out, torch.float32, (train.n_dm, train.n_act, train.n_act), "grad_out")
             gh = grad_out
         else:
             gh = _empty((train.n_dm, train.n_act, train.n_act), torch.float32, train.pupil_amp.device,
                         stream)
+    elif phase == "backward":
+        raise ValueError("phase='backward' needs grad_psf")
     lam = (_c.c_double * nl)(*[float(x) for x in wavelengths])
     npd = (_c.c_int32 * nl)(*[int(x) for x in n_pad])
     w = (_c.c_float * nl)(*[float(x) for x in weights])
@@ -566,35 +600,49 @@ def propagate_train(train, wavelengths, n_pad, weights, heights=None, occulter=T
     if nbytes == 0:
         raise ValueError("invalid train geometry")
     ws = workspace(nbytes, dev, stream)
-    if out is not None:
-        _need(out, torch.float32, (train.det_m, train.det_m), "out")
-        psf = out
-    else:
-        psf = _empty((train.det_m, train.det_m), torch.float32, train.pupil_amp.device, stream)
+    psf = None
+    if phase != "backward":
+        if out is not None:
+            _need(out, torch.float32, (train.det_m, train.det_m), "out")
+            psf = out
+        else:
+            psf = _empty((train.det_m, train.det_m), torch.float32, train.pupil_amp.device, stream)
     st = L.propagate_train(context(dev).handle, _c.byref(d), nl, lam, npd, w, mode, _ptr(psf),
-                           _ptr(grad_psf), _ptr(gh), _ptr(ws), ws.numel(), _stream_handle(dev, stream))
+                           _ptr(grad_psf), _ptr(gh), _ptr(ckpt), ckpt.numel() if ckpt is not None else 0,
+                           _ptr(ws), ws.numel(), _stream_handle(dev, stream))
     _check(st, "propagate_train")
+    if phase == "backward":
+        return gh
     return (psf, gh) if grad_psf is not None else psf
+
+
+def train_ckpt_bytes(train, n_pad):
+    """Bytes of the checkpoint that propagate_train(phase='save') fills for these grids."""
+    nl = len(n_pad)
+    npd = (_c.c_int32 * nl)(*[int(x) for x in n_pad])
+    d = train.desc(None)
+    return int(lib().propagate_train_ckpt_bytes(_c.byref(d), nl, npd))
 
 
 class DMHeightsToPSF(torch.autograd.Function):
     """heights (n_dm x n_act x n_act) -> broadband PSF, with the library's adjoint as backward.
 
-    apply(heights, train, wavelengths, n_pad, weights[, batched]). The backward pass reruns the
-    forward of each wavelength inside the library (keeping that wavelength's planes in the
-    workspace) and then its adjoint."""
+    apply(heights, train, wavelengths, n_pad, weights[, batched]). The forward keeps the
+    library's checkpoint (per wavelength the field at the last DM plane and the detector field)
+    and the backward runs only the adjoint chain from it."""
 
     @staticmethod
     def forward(ctx, heights, train, wavelengths, n_pad, weights, batched=False):
         h = heights.detach().contiguous()
         ctx.train, ctx.args = train, (list(wavelengths), list(n_pad), list(weights), bool(batched))
-        ctx.save_for_backward(h)
-        return propagate_train(train, wavelengths, n_pad, weights, h, batched=batched)
+        ck = torch.empty(train_ckpt_bytes(train, n_pad), dtype=torch.uint8, device=h.device)
+        ctx.save_for_backward(h, ck)
+        return propagate_train(train, wavelengths, n_pad, weights, h, batched=batched, ckpt=ck, phase="save")
 
     @staticmethod
     def backward(ctx, grad_out):
-        (h,) = ctx.saved_tensors
+        h, ck = ctx.saved_tensors
         wl, npd, w, batched = ctx.args
-        _, gh = propagate_train(ctx.train, wl, npd, w, h, grad_psf=grad_out.contiguous().float(),
-                                batched=batched)
+        gh = propagate_train(ctx.train, wl, npd, w, h, grad_psf=grad_out.contiguous().float(), batched=batched,
+                             ckpt=ck, phase="backward")
         return gh, None, None, None, None, None

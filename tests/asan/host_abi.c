@@ -45,6 +45,9 @@ int main(void) {
   EXPECT(mft_workspace_bytes(4096, 256) > 0);
   EXPECT(mft_forward(NULL, NULL, 256, 256, NULL, 64, 64, 128.0, 0.5, NULL, NULL, 0, NULL) == FR_EINVAL);
   EXPECT(mft_forward_noalloc(NULL, NULL, 256, 256, NULL, 64, 64, 128.0, 0.5, NULL, NULL) == FR_EINVAL);
+  EXPECT(fresnel_step_f64(NULL, NULL, 256, 1e-5, 5e-7, 1.0, NULL, NULL, 0.0, 0, NULL) == FR_EINVAL);
+  EXPECT(fresnel_step_f64(NULL, (fr_c128 *)16, 96, 1e-5, 5e-7, 1.0, NULL, NULL, 0.0, 0, NULL) == FR_EUNSUPPORTED);
+  EXPECT(fresnel_step_f64(NULL, (fr_c128 *)16, 256, 1e-5, 5e-7, 1.0, NULL, NULL, 0.0, 0, NULL) == FR_EINVAL);
   EXPECT(mft_forward_noalloc(NULL, (const fr_c64 *)16, 256, 255, (fr_c64 *)16, 64, 64, 128.0, 0.5, NULL, NULL) ==
          FR_EINVAL);
   EXPECT(mft_forward_noalloc(NULL, (const fr_c64 *)16, 8192, 8192, (fr_c64 *)16, 1025, 1025, 128.0, 0.5, NULL, NULL) ==

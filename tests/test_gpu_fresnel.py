@@ -93,6 +93,38 @@ def test_talbot_closed_form(n):
     assert np.max(np.abs(got.imag)) <= 1e-5
 
 
+@pytest.mark.parametrize("fraction", [0.05, 0.25])
+def test_talbot_appendix_a_with_aperture(fraction):
+    """The Talbot example of Sec. 1.1 / Fig. 1 as Appendix A prescribes it: a 2 cm radius circular
+    aperture sampled by 256 px, oversampled 8x to a 2048^2 grid, a 5 nm sine OPD of 500
+    cycles per metre, 0.5 um, propagated 0.05 and 0.25 Talbot lengths (Z_T = 2 p^2 / lambda =
+    16 m; tests/golden/talbot_appendix_a.json), against the FP64 oracle on the whole plane. The
+    conversion of phase into amplitude error: inside half the radius (away from the edge's
+    ringing) the intensity's component along sin(2 pi x / p) is, as for the unbounded grating
+    whose harmonic n advances by exp(-2 pi i n^2 z / Z_T), 4 J0(a) J1(a) sin(2 pi z / Z_T) to
+    first order in a = 2 pi 5 nm / lambda: complete at 0.25 Z_T, 31 % of it at 0.05 Z_T."""
+    n, dx, lam, period, amp_m = 2048, 0.04 / 256, 0.5e-6, 2e-3, 5e-9
+    z_t = 2 * period ** 2 / lam
+    z = fraction * z_t
+    banner(f"talbot with aperture: 2048^2, z = {fraction} Z_T = {z} m")
+    aperture = synth.circular_aperture(n, 128.0)
+    opd = synth.sine_opd(n, dx, period, amp_m)
+    t = torch.ones((n, n), dtype=torch.complex64, device="cuda:0")
+    st = fb.fresnel_step(t, dx, lam, z, amp=to_gpu(aperture, torch.float32), opd=to_gpu(opd, torch.float32))
+    assert st == 0
+    got = to_np(t)
+    ref = oracle.fresnel_step(np.ones((n, n), dtype=np.complex128), dx, lam, z, amp=f32(aperture), opd=f32(opd))
+    assert rel_l2(got, ref) <= TOL
+    from scipy.special import j0, j1
+    inner = synth.radius_grid(n) < 64.0
+    sin_x = np.broadcast_to(np.sin(2 * math.pi * (np.arange(n) - n // 2) * dx / period), (n, n))[inner]
+    inten = np.abs(got[inner]) ** 2
+    c = np.sum((inten - inten.mean()) * sin_x) / np.sum(sin_x ** 2)
+    a = 2 * math.pi * amp_m / lam
+    want = 4 * j0(a) * j1(a) * math.sin(2 * math.pi * fraction)
+    assert abs(c - want) <= 0.01 * want
+
+
 def test_round_trip_and_zero_distance_4096():
     n = 4096
     banner("round trip n=4096")

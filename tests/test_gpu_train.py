@@ -163,6 +163,29 @@ def test_autograd_function_matches_direct_call():
     assert torch.allclose(h.grad, gh, rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("batched", [False, True])
+@pytest.mark.parametrize("n_dm", [1, 2])
+def test_checkpointed_backward_equals_one_call_gradient(n_dm, batched):
+    """FR_TRAIN_FWD_SAVE then FR_TRAIN_BWD (forward once, adjoint from the checkpoint) give the PSF
+    and the gradient of one FR_TRAIN_GRAD call bit for bit, on grids of two edges (power-of-two
+    and mixed-radix), with and without the occulter; the backward leaves psf untouched."""
+    banner(f"checkpointed backward n_dm={n_dm} batched={batched}")
+    geom, tr, heights, hg, lams, ns, w, dh, mref = _grad_setup(64, 128, 64, 64, 0.5, 8, n_dm, 3, 0.05)
+    ns = [128, 120, 128]
+    g = to_gpu(dh / (dh.sum() * mref), torch.float32)
+    for occulter in (True, False):
+        p_ref, g_ref = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g, batched=batched, occulter=occulter)
+        ck = torch.full((fb.train_ckpt_bytes(tr, ns),), 0xA5, dtype=torch.uint8, device="cuda:0")
+        psf = fb.propagate_train(tr, lams, ns, w, hg, batched=batched, occulter=occulter, ckpt=ck, phase="save")
+        junk = torch.randn(1 << 18, device="cuda:0")   # other work between the two halves
+        gh = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g, batched=batched, occulter=occulter, ckpt=ck,
+                                phase="backward")
+        torch.cuda.synchronize()
+        assert torch.equal(psf, p_ref), occulter
+        assert torch.equal(gh, g_ref), occulter
+        assert torch.isfinite(junk).all()
+
+
 def test_batched_matches_plain_mixed_grids():
     # a batch of mixed edges runs every plane through the mixed-radix sweeps, so it agrees with
     # the plain mode to float32 rounding; a batch of one power-of-two edge is bit-identical
