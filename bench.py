@@ -375,6 +375,35 @@ def main():
             "hbm_frac_whole_plane": frac_of(ms_ex / (3 * N_LAMBDA), 3 * sweep_bytes(N, 0)),
             "sweeps": {k: hbm_entry(k, sweep_bytes(N, 0), v[0] / v[1]) for k, v in aex.items()
                        if k.startswith("exact_") and v[1]}}
+        # ---- the App. B relay at 4096^2 (the system the paper's Fig. 2 times per wavelength):
+        # aperture + primary, relay lenses, a shaped pupil, a bow-tie focal-plane mask, the focus
+        d_prim, d_relay = 2.37, 0.02
+        f1 = d_prim * 7.8
+        f2, f3 = f1 * d_relay / d_prim, 20.0 * d_relay
+        zf = [(0.0, f1), (f1 + f2, f2), (f2 + f3, f3), (2 * f3, f3), (f3, 0.0), (f3, f3), (f3, 0.0),
+              (2 * f3, f3), (f3 + 0.39999923, 0.0)]
+        dx_r = d_prim / (N // 4)
+        pitches, transforms = fb.plan_system(N, dx_r, LAMBDA_C, d_prim / 2, [(z, f, None, None) for z, f in zf])
+
+        def g32(a):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+        masks = {0: g32(synth.embed_centred(synth.pupil_amplitude(N // 4, 0.1, 0.01), N)),
+                 4: g32(synth.embed_centred(synth.shaped_pupil(int(round(d_relay / pitches[4]))), N)),
+                 6: g32(synth.bowtie_mask(N, LAMBDA_C * f3 / d_relay / pitches[6]))}
+        r_optics = [(z, f, masks.get(i), None) for i, (z, f) in enumerate(zf)]
+        r_field = torch.ones((N, N), dtype=torch.complex64, device=dev)
+
+        def relay():
+            r_field.fill_(1.0)
+            fb.propagate_system(r_field, dx_r, LAMBDA_C, d_prim / 2, r_optics)
+        ms_relay = timed(relay, 5, 1) / 5
+        result_extra["relay_appendix_b"] = {
+            "n": N, "optics": len(zf), "transforms_per_wavelength": transforms, "ms_per_wavelength": ms_relay,
+            "systems_per_s": 1e3 / ms_relay,
+            "context": "Fig. 2 of the paper: 90.16 s per wavelength for its App. B system at N = 4096 "
+                       "(NumPy, float64, 8-core 2 GHz Xeon); this run is float32 on one MI355X "
+                       "(the whole system including the field reset)"}
+        del masks, r_optics, r_field
         # ---- the Fresnel plane in float64 (the paper's precision): 8 forward + 8 adjoint planes at
         # 4096^2 complex128 with float64 amplitude and OPD maps, one call each ------------------
         n64 = 8

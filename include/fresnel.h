@@ -181,6 +181,37 @@ typedef struct {
 int fr_plan_route(double w0_m, double z_waist_m, double wavelength_m, int32_t n, double dx_m,
                   double z_from_m, double z_to_m, fr_route_step *steps, int32_t capacity);
 
+/* ---- a multi-optic system (App. B: the paper's benchmark relay of optics -- aperture, primary,
+ * relay mirrors as thin lenses, a shaped pupil, a focal-plane mask, a final focus -- with Fresnel
+ * propagation between them, about 19 FFTs per wavelength; Sec. 1.2) ----------------------------
+ * optics[0] sits on the input plane; optics[i] (i > 0) sits z_m >= 0 after optics[i - 1]. At each
+ * plane the field is multiplied by its optic: amp (transmission) and opd_m (OPD, phasor
+ * exp(2 pi i opd / lambda), Eq. 3), n x n float maps sampled on the pitch fr_plan_system gives
+ * that plane (NULL = none), and a thin lens exp(-i pi r^2 / (lambda f)) (lens_focal_m, 0 =
+ * none). Between planes the field travels by the steps of fr_plan_route under a Gaussian pilot
+ * beam that starts collimated with waist radius beam_radius_m on the input plane and changes at
+ * every lens by the q-law 1/q' = 1/q - 1/f (q = z - z_waist - i z_R): the angular spectrum
+ * between near planes, the direct step (or its inverse) to (or from) far planes, so the pitch
+ * changes where the field crosses a focus. fr_plan_system (host arithmetic, no device call)
+ * writes each plane's pitch into plane_dx_m[count] (where masks must be sampled; the first is
+ * dx_m) and the number of 2-D transforms the system takes into *transforms (two per
+ * angular-spectrum step, one per direct step); either output may be NULL. propagate_system runs
+ * it on field (n x n c64, in place, pitch dx_m on the input plane) and leaves the field at the
+ * last plane, after its optic, with its pitch in *dx_out_m. Power-of-two edges 64..8192.
+ * Errors: FR_EINVAL (a NULL or non-finite argument, count <= 0, a negative distance, a lens
+ * that leaves no beam), FR_EUNSUPPORTED (edge); warnings of the steps are ORed. */
+typedef struct {
+  double z_m;           /* distance from the previous optic's plane (ignored for optics[0]) */
+  double lens_focal_m;  /* thin lens at this plane, 0 = none                                  */
+  const float *amp;     /* n x n transmission on this plane's pitch, or NULL                   */
+  const float *opd_m;   /* n x n OPD [m] on this plane's pitch, or NULL                        */
+} fr_optic;
+int fr_plan_system(int32_t n, double dx_m, double wavelength_m, double beam_radius_m, const fr_optic *optics,
+                   int32_t count, double *plane_dx_m, int32_t *transforms);
+int propagate_system(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double wavelength_m,
+                     double beam_radius_m, const fr_optic *optics, int32_t count, double *dx_out_m,
+                     void *stream);
+
 /* Many independent planes in one launch per sweep (e.g. the wavelengths of a broadband
  * model, Sec. 1.2). Each entry has the meaning of the fresnel_step arguments. `planes` is a
  * HOST array read during the call. All planes must share one edge n. Returns the OR of

@@ -15,7 +15,9 @@ the complex Gaussian-beam closed form, the Talbot self-imaging closed form,
 the thin-lens q-parameter law, the Airy pattern, the direct Fresnel step's agreement with
 the angular-spectrum step where its kernel is periodic, the exact DFT special case of
 the MFT, dot-product (adjoint) identities, the AS/MFT lattice invariance,
-finite differences and a Taylor test of the gradient.
+finite differences and a Taylor test of the gradient; the multi-optic system (O11) by the
+complex Gaussian beam carried through lenses and a focus by the q-law, exact energy
+conservation across near and far planes, and the relay's pitch ratios.
 
 The composed Lyot-train intensity (O5) is pinned through its parts and by three
 whole-train cases: a full-band occulter rejects everything, no occulter leaves the
@@ -31,6 +33,9 @@ from .core import (  # noqa: F401
     as_propagate, as_propagate_rows, optic_phasor, fresnel_step, mft_matrix, mft, mft_adjoint,
     direct_pitch, quadratic_phase, direct_kernel_matrix, direct_fresnel, direct_fresnel_rows,
     direct_fresnel_adjoint, transfer_function_exact, as_propagate_exact,
+)
+from .relay import (  # noqa: F401
+    pilot_through_lens, route, system_plan, propagate_system, gaussian_through_system,
 )
 from .train import (  # noqa: F401
     embed, extract, dm_influence, dm_surface, TrainGeometry, train_forward,

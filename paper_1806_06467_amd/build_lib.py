@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfresnel.so")
 SOURCES = ["api.cpp", "autotune.cpp", "exact.cpp", "train.hip", "sweeps.hip", "sweeps_mr.hip", "mft.hip", "mft64.hip",
-           "noalloc.hip", "sweeps64.hip"]
+           "noalloc.hip", "sweeps64.hip", "relay.hip"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

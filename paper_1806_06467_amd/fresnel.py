@@ -50,6 +50,10 @@ class FrRouteStep(_c.Structure):
     _fields_ = [("kind", _c.c_int32), ("z_m", _c.c_double), ("dx_in_m", _c.c_double), ("dx_out_m", _c.c_double)]
 
 
+class FrOptic(_c.Structure):
+    _fields_ = [("z_m", _c.c_double), ("lens_focal_m", _c.c_double), ("amp", _vp), ("opd_m", _vp)]
+
+
 class FrPlane(_c.Structure):
     _fields_ = [("field", _vp), ("amp", _vp), ("opd_m", _vp), ("dx_m", _c.c_double),
                 ("wavelength_m", _c.c_double), ("z_m", _c.c_double), ("lens_focal_m", _c.c_double),
@@ -92,6 +96,10 @@ def lib():
             "fresnel_step_exact": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
             "fresnel_direct": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _c.POINTER(f64), _vp]),
             "fr_plan_route": (_c.c_int, [f64, f64, f64, i32, f64, f64, f64, _c.POINTER(FrRouteStep), i32]),
+            "fr_plan_system": (_c.c_int, [i32, f64, f64, f64, _c.POINTER(FrOptic), i32, _c.POINTER(f64),
+                                          _c.POINTER(i32)]),
+            "propagate_system": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _c.POINTER(FrOptic), i32,
+                                            _c.POINTER(f64), _vp]),
             "mft_workspace_bytes": (sz, [i32, i32]),
             "mft_f64_workspace_bytes": (sz, [i32, i32]),
             "mft_f64": (_c.c_int, [_vp, _vp, _vp, i32, i32, f64, f64, i32, _vp, sz, _vp]),
@@ -304,6 +312,44 @@ def follow_route(field, wavelength, steps, stream=None):
             raise ValueError("unknown route step")
         dx = dx_out
     return dx
+
+
+def _optics(optics, n=None):
+    """optics: sequence of (z_m, lens_focal_m, amp or None, opd or None) -> FrOptic array."""
+    arr = (FrOptic * len(optics))()
+    for i, (z, f, amp, opd) in enumerate(optics):
+        for t, name in ((amp, "amp"), (opd, "opd")):
+            if t is not None and n is not None:
+                _need(t, torch.float32, (n, n), f"optics[{i}].{name}")
+        arr[i] = FrOptic(float(z), float(f), amp.data_ptr() if amp is not None else None,
+                         opd.data_ptr() if opd is not None else None)
+    return arr
+
+
+def plan_system(n, dx, wavelength, beam_radius, optics):
+    """fr_plan_system: ([pitch of each plane], 2-D transforms of the system). optics as for
+    propagate_system (masks may be None: only distances and lenses matter)."""
+    arr = _optics(optics)
+    pitches = (_c.c_double * len(optics))()
+    tr = _c.c_int32()
+    _check(lib().fr_plan_system(int(n), float(dx), float(wavelength), float(beam_radius), arr, len(optics),
+                                pitches, _c.byref(tr)), "fr_plan_system")
+    return list(pitches), tr.value
+
+
+def propagate_system(field, dx, wavelength, beam_radius, optics, stream=None):
+    """In place on an n x n complex64 GPU tensor: the system of optics (z_m from the previous
+    plane, lens focal length, amp, opd: maps on each plane's pitch from plan_system); returns the
+    pitch of the last plane."""
+    n = field.shape[0] if field.dim() == 2 else -1
+    _need(field, torch.complex64, (n, n), "field")
+    arr = _optics(optics, n)
+    dx_out = _c.c_double()
+    dev = field.device.index
+    _check(lib().propagate_system(context(dev).handle, _ptr(field), n, float(dx), float(wavelength),
+                                  float(beam_radius), arr, len(optics), _c.byref(dx_out),
+                                  _stream_handle(dev, stream)), "propagate_system")
+    return dx_out.value
 
 
 def fresnel_step_f64(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.0, adjoint=False,

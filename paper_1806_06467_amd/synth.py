@@ -135,3 +135,36 @@ def sine_opd(n, dx, period_m, amplitude_m):
     """1-D sinusoidal OPD along x: amplitude sin(2 pi x / period), x = (i - n//2) dx."""
     x = _coords(n) * dx
     return np.broadcast_to(amplitude_m * np.sin(2 * np.pi * x / period_m), (n, n)).copy()
+
+
+def embed_centred(a, n):
+    """An n_d x n_d map placed in an n x n zero map with its centre pixel on (n//2, n//2)."""
+    a = np.asarray(a)
+    m = a.shape[0]
+    out = np.zeros((n, n), dtype=a.dtype)
+    o = n // 2 - m // 2
+    out[o:o + m, o:o + m] = a
+    return out
+
+
+def shaped_pupil(n_d, bars=3, bar_width=0.06):
+    """A binary pupil standing in for a shaped-pupil mask: a clear circle of diameter n_d px
+    crossed by `bars` opaque horizontal bars of width bar_width D, evenly spaced."""
+    c = _coords(n_d) / n_d  # in units of D
+    r = np.hypot(c[:, None], c[None, :])
+    clear = r < 0.5
+    for k in range(bars):
+        y0 = -0.5 + (k + 1) / (bars + 1)
+        clear &= ~(np.abs(c[:, None] - y0) < bar_width / 2)
+    return clear.astype(np.float64)
+
+
+def bowtie_mask(n, px_per_lamd, r_in=2.5, r_out=9.0, opening_deg=65.0):
+    """A focal-plane mask: clear between r_in and r_out lambda/D inside two opposite wedges of
+    full angle opening_deg about the x axis, opaque elsewhere; px_per_lamd pixels per lambda/D."""
+    c = _coords(n) / float(px_per_lamd)
+    x, y = c[None, :], c[:, None]
+    r = np.hypot(x, y)
+    ang = np.degrees(np.arctan2(np.abs(y), np.abs(x)))
+    return ((r >= r_in) & (r < r_out) & (ang <= opening_deg / 2)).astype(np.float64)
+

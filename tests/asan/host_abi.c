@@ -46,6 +46,15 @@ int main(void) {
   EXPECT(mft_forward(NULL, NULL, 256, 256, NULL, 64, 64, 128.0, 0.5, NULL, NULL, 0, NULL) == FR_EINVAL);
   EXPECT(mft_forward_noalloc(NULL, NULL, 256, 256, NULL, 64, 64, 128.0, 0.5, NULL, NULL) == FR_EINVAL);
   EXPECT(fresnel_step_f64(NULL, NULL, 256, 1e-5, 5e-7, 1.0, NULL, NULL, 0.0, 0, NULL) == FR_EINVAL);
+  {
+    fr_optic ops[3] = {{0.0, 2.0, NULL, NULL}, {3.0, 1.0, NULL, NULL}, {1.0, 0.0, NULL, NULL}};
+    double pitches[3];
+    int32_t tr = 0;
+    EXPECT(fr_plan_system(256, 1e-4, 5e-7, 2e-3, ops, 3, pitches, &tr) == FR_OK && tr > 0);
+    EXPECT(fr_plan_system(256, 1e-4, 5e-7, 2e-3, ops, 0, pitches, &tr) == FR_EINVAL);
+    double dx_out = 0.0;
+    EXPECT(propagate_system(NULL, (fr_c64 *)16, 256, 1e-4, 5e-7, 2e-3, ops, 3, &dx_out, NULL) == FR_EINVAL);
+  }
   EXPECT(fresnel_step_f64(NULL, (fr_c128 *)16, 96, 1e-5, 5e-7, 1.0, NULL, NULL, 0.0, 0, NULL) == FR_EUNSUPPORTED);
   EXPECT(fresnel_step_f64(NULL, (fr_c128 *)16, 256, 1e-5, 5e-7, 1.0, NULL, NULL, 0.0, 0, NULL) == FR_EINVAL);
   EXPECT(mft_forward_noalloc(NULL, (const fr_c64 *)16, 256, 255, (fr_c64 *)16, 64, 64, 128.0, 0.5, NULL, NULL) ==

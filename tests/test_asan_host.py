@@ -1,5 +1,5 @@
 """The host-side C-ABI layer (api.cpp, autotune.cpp, exact.cpp, the host parts of mft64.hip,
-noalloc.hip and sweeps64.hip) built
+noalloc.hip, sweeps64.hip and relay.hip) built
 with AddressSanitizer, linked with the ordinary device objects, and driven by a C harness through every entry point's argument checks
 and the pilot-beam planner (no GPU needed). Sanitizers apply to host code only here."""
 
@@ -23,7 +23,7 @@ def test_host_abi_under_address_sanitizer(tmp_path):
         pytest.skip("library not built (run __graft_entry__.build())")
     flags = ["-O1", "-g", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=address"]
     objs = []
-    for src in ("api.cpp", "autotune.cpp", "exact.cpp", "mft64.hip", "noalloc.hip", "sweeps64.hip"):
+    for src in ("api.cpp", "autotune.cpp", "exact.cpp", "mft64.hip", "noalloc.hip", "sweeps64.hip", "relay.hip"):
         obj = str(tmp_path / (src + ".o"))
         subprocess.run([HIPCC] + flags + ["-c", os.path.join(PKG, "csrc", src), "-o", obj], check=True,
                        capture_output=True)

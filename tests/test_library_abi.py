@@ -11,7 +11,7 @@ from paper_1806_06467_amd import fresnel as fb
 
 EXPECTED = {
     "fr_create", "fr_destroy", "fr_set_cache_limit", "fr_status_string", "fr_fft_size_supported", "fresnel_step",
-    "fresnel_step_batched", "fresnel_step_batched_graph", "fresnel_step_exact", "fresnel_step_f64", "mft_f64", "mft_f64_workspace_bytes", "fresnel_direct", "fr_plan_route", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
+    "fresnel_step_batched", "fresnel_step_batched_graph", "fresnel_step_exact", "fresnel_step_f64", "mft_f64", "mft_f64_workspace_bytes", "fresnel_direct", "fr_plan_route", "fr_plan_system", "propagate_system", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
     "propagate_train_workspace_bytes", "propagate_train_ckpt_bytes", "propagate_train", "mft_forward_noalloc", "fr_profile_enable", "fr_profile_read",
     "fr_autotune", "fr_autotune_save", "fr_autotune_load",
 }
@@ -230,3 +230,26 @@ def test_fresnel_step_f64_argument_errors(L):
     for n in (3, 96, 3840, 16384):
         assert f(null, FAKE, n, 1e-5, 5e-7, 1.0, None, None, 0.0, 0, null) == fb.FR_EUNSUPPORTED
     assert f(null, FAKE, 4096, 1e-5, 5e-7, 1.0, None, None, 0.0, 0, null) == fb.FR_EINVAL   # no context
+
+
+def test_system_argument_errors(L):
+    null = ctypes.c_void_p()
+    ops = (fb.FrOptic * 2)()
+    ops[0] = fb.FrOptic(0.0, 2.0, None, None)
+    ops[1] = fb.FrOptic(1.0, 0.0, None, None)
+    out = ctypes.c_double()
+    tr = ctypes.c_int32()
+    pitches = (ctypes.c_double * 2)()
+    assert L.fr_plan_system(256, 1e-4, 5e-7, 2e-3, ops, 2, pitches, ctypes.byref(tr)) == 0
+    assert tr.value > 0 and pitches[0] == 1e-4
+    assert L.fr_plan_system(256, 1e-4, 5e-7, 2e-3, None, 2, pitches, None) == fb.FR_EINVAL
+    assert L.fr_plan_system(256, 1e-4, 5e-7, 2e-3, ops, 0, pitches, None) == fb.FR_EINVAL
+    assert L.fr_plan_system(256, -1e-4, 5e-7, 2e-3, ops, 2, pitches, None) == fb.FR_EINVAL
+    assert L.fr_plan_system(256, 1e-4, 5e-7, 0.0, ops, 2, pitches, None) == fb.FR_EINVAL
+    assert L.fr_plan_system(96, 1e-4, 5e-7, 2e-3, ops, 2, pitches, None) == fb.FR_EUNSUPPORTED
+    ops[1] = fb.FrOptic(-1.0, 0.0, None, None)   # a negative distance
+    assert L.fr_plan_system(256, 1e-4, 5e-7, 2e-3, ops, 2, pitches, None) == fb.FR_EINVAL
+    ops[1] = fb.FrOptic(1.0, 0.0, None, None)
+    assert L.propagate_system(null, FAKE, 256, 1e-4, 5e-7, 2e-3, ops, 2, None, null) == fb.FR_EINVAL
+    assert L.propagate_system(null, None, 256, 1e-4, 5e-7, 2e-3, ops, 2, ctypes.byref(out), null) == fb.FR_EINVAL
+    assert L.propagate_system(null, FAKE, 256, 1e-4, 5e-7, 2e-3, ops, 2, ctypes.byref(out), null) == fb.FR_EINVAL
