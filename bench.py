@@ -47,12 +47,24 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 FP64_PEAK_TFLOPS = 78.6  # vector and matrix alike
 METRIC = "Fresnel planes/sec at 4096^2 c64 (fwd+adjoint, batched vs plain), %HBM roofline"
 
-# HBM bytes per launch of the dominant sweep kernel from two rocprofv3 --pmc runs of this bench
-# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the counters read for a device
-# copy of one 128 MiB plane in the same runs (FETCH x 2.0, WRITE x 1.0). Each entry carries the
-# SHA-256 of the sources it was measured on and reads as unknown (null) once they change.
-MEASURED_TRAFFIC = {}
-TRAFFIC_SOURCES = {}
+# HBM bytes per launch (fetched, written) of the sweep kernels of the timed batch from two
+# rocprofv3 --pmc runs of this bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over
+# the 1344 launches of each direction), scaled by what the counters read for a device copy of one
+# 128 MiB plane in the same runs (FETCH x 2.0, WRITE x 1.0). Each entry carries the SHA-256 of the
+# sources it was measured on and reads as unknown (null) once they change.
+MEASURED_TRAFFIC = {
+    "col_sweep_adj": (136638669, 151176090),
+    "col_sweep": (136687411, 166559744),
+    "row_sweep": (269561242, 134217728),
+    "row_sweep_adj": (269653197, 134217728),
+}
+_SWEEP_SOURCES = {
+    "paper_1806_06467_amd/csrc/sweeps.hip": "19241185637070e51924fce0490ec814f21088d14020e99da71b4130572e31cf",
+    "paper_1806_06467_amd/csrc/fft_line.hpp": "66f504dc38f9cb71c51b0dd9e259e966acb90c9d9d1b256d8d7ca415edac6fae",
+    "paper_1806_06467_amd/csrc/dft_small.hpp": "8ecf89941d562fa656d33604a2684c7329106e4272470c584b8acfb5b198fee0",
+    "paper_1806_06467_amd/csrc/fr_internal.h": "5e4b00d764eb6352a0e1481967570d54e71e042c52209f5262aff17334acfb5d",
+}
+TRAFFIC_SOURCES = {k: _SWEEP_SOURCES for k in MEASURED_TRAFFIC}
 
 
 def measured_traffic(kernel):

@@ -59,17 +59,16 @@ def test_appendix_b_relay_matches_oracle(n):
     ref, pitch_ref = oracle.propagate_system(np.ones((n, n)), dx, lam, 2.37 / 2, or_optics)
     assert pitch == pytest.approx(pitch_ref, rel=1e-12)
     assert pitch == pytest.approx(pitches[-1], rel=1e-12)
-    got = to_np(t)
-    assert rel_l2(got, ref) <= TOL
-    # the field reaches the final focus: a compact image (most energy within 20 lambda/D)
-    assert np.isfinite(got).all()
+    assert rel_l2(to_np(t), ref) <= TOL
 
 
-def test_gaussian_through_appendix_b_lenses():
+@pytest.mark.parametrize("n", [512, 4096])
+def test_gaussian_through_appendix_b_lenses(n):
     """A Gaussian beam of waist 0.4 m on the 2.37 m relay's first plane through all its lenses
-    (no masks), against the q-law closed form on the last plane's grid."""
-    n, lam = 512, 0.55e-6
-    banner("relay lenses: Gaussian beam, n=512")
+    (no masks), against the q-law closed form on the last plane's grid; 4096 is the benchmark's
+    edge, on the benchmark's plan (same pitches, routes and 19 transforms)."""
+    lam = 0.55e-6
+    banner(f"relay lenses: Gaussian beam, n={n}")
     zf, dx, _, _, _ = appendix_b(n, lam, with_masks=False)
     w0 = 0.4
     t = to_gpu(synth.gaussian_beam(n, w0 / dx))
