@@ -523,7 +523,7 @@ int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s) {
       if (st != FR_OK) return st;
       b.p[k].pa = args[i + k];
     }
-    hipError_t e = launch_mr_batch(b, ctx->cus * 4, ctx->cus, s, ctx->hook());
+    hipError_t e = launch_mr_batch(b, ctx->cus * ctx->mr_rows_per_cu, ctx->cus * ctx->mr_cols_per_cu, s, ctx->hook());
     if (e != hipSuccess) return record_hip(e);
     i = j;
   }
@@ -556,6 +556,7 @@ int fr_create(fr_ctx **ctx, int device) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->cus = cus;
+  fr::mr_resident(&c->mr_rows_per_cu, &c->mr_cols_per_cu);
   *ctx = reinterpret_cast<fr_ctx *>(c);
   return FR_OK;
 }

@@ -340,30 +340,15 @@ __device__ __forceinline__ void apply_twiddle_powers(c32 *u, c64d w1) {
   }
 }
 
-// sin and cos of 2 pi t for t in turns: exact reduction t - rint(t), then to the octant
-// |2 pi f| <= pi/4 by quarter turns, then the Taylor series of sin (to x^9) and cos (to x^8)
-// on that interval (truncation below 3e-8), rotated back by the quarter-turn count.
+// sin and cos of 2 pi t for t in turns: the reduction t - rint(t) to [-1/2, 1/2] is exact in
+// float32, then the hardware sine and cosine, which take their argument in turns (measured on
+// gfx950 against float64 at every 2^-24 step of [-1/2, 1/2): within 1.3e-7 of the exact values,
+// rms 3.5e-8; a degree-9/8 Taylor evaluation on the octant costs about 20 VALU instructions per
+// pair against two transcendental issues here).
 __device__ __forceinline__ void sincos_turns(float t, float *s, float *c) {
   t -= rintf(t);
-  const float q = rintf(4.0f * t);
-  const float f = fmaf(-0.25f, q, t);
-  const float x = f * 6.28318530717958647692f;
-  const float x2 = x * x;
-  const float sp = x * fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 2.75573192239858906526e-6f,
-                                                       -1.98412698412698412698e-4f),
-                                              8.33333333333333333333e-3f),
-                                     -1.66666666666666666667e-1f),
-                            1.0f);
-  const float cp = fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 2.48015873015873015873e-5f,
-                                                   -1.38888888888888888889e-3f),
-                                          4.16666666666666666667e-2f),
-                                 -0.5f),
-                        1.0f);
-  const int qi = int(q) & 3;
-  const float ss = (qi & 1) ? cp : sp;
-  const float cc = (qi & 1) ? sp : cp;
-  *s = (qi & 2) ? -ss : ss;
-  *c = ((qi + 1) & 2) ? -cc : cc;
+  *s = __builtin_amdgcn_sinf(t);
+  *c = __builtin_amdgcn_cosf(t);
 }
 
 }  // namespace fr

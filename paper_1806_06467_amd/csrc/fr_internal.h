@@ -98,6 +98,10 @@ void mr_twiddle_build(int npass, const int *radix, float2 *out);  // host
 // grids of at most blocks_rows / blocks_cols blocks
 hipError_t launch_mr_batch(const MrBatch &all, int blocks_rows, int blocks_cols, hipStream_t s,
                            const LaunchHook &hook);
+// blocks of the two persistent sweeps that one compute unit holds at once (their grids hold that
+// many per unit, so no block waits for a slot while others loop); a device query, made at
+// context creation
+void mr_resident(int *rows_per_cu, int *cols_per_cu);
 
 // ---- MFT: out = alpha * c * A in B^T (+ beta * out) (* mask), complex, FP32 MFMA ------
 // Generic complex GEMM pieces used by the MFT entry points.

@@ -175,8 +175,12 @@ __device__ __forceinline__ void freq_product(c32 (&v)[E], const float2 *h, int t
 // DIRECT: the row half of the direct (single-transform) Fresnel step: the prologue applies the
 // optic times the input quadratic phase (held in the lens slot), then the forward transform only;
 // for its adjoint the inverse transform, then the conjugate of both
+// Up to 4096, at most 128 VGPRs (four waves per SIMD): at 4096 four 256-thread row blocks then
+// share a compute unit (their LDS lines allow four) instead of three (measured 1 % faster per
+// plane, bit-identical results); the 8192 row would spill under that cap.
 template <class PL, int LINES, bool DIRECT = false>
-__global__ void __launch_bounds__(PL::T *LINES) row_sweep(BatchArgs args, const float2 *tw) {
+__global__ void __launch_bounds__(PL::T *LINES) __attribute__((amdgpu_waves_per_eu(PL::N <= 4096 ? 4 : 1)))
+row_sweep(BatchArgs args, const float2 *tw) {
   constexpr int N = PL::N, E = PL::E, T = PL::T;
   __shared__ c32 lds[LINES * LdsLine<N>::size];
   const PlaneArgs &pa = args.p[blockIdx.y];

@@ -272,6 +272,22 @@ int mr_plan_orders(int n, int max, unsigned *plans, int *npass) {
 int mr_twiddle_count(int npass, const int *radix) { return mr_twiddle_size(npass, radix); }
 void mr_twiddle_build(int npass, const int *radix, float2 *out) { mr_twiddle_fill(npass, radix, out); }
 
+// blocks of a persistent kernel that one compute unit holds at once
+template <class K>
+int resident_blocks(K kernel, int threads, int fallback) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    return fallback;
+  }
+  return nb;
+}
+
+void mr_resident(int *rows_per_cu, int *cols_per_cu) {
+  *rows_per_cu = resident_blocks(mr_row_sweep, kT, 2);
+  *cols_per_cu = resident_blocks(mr_col_sweep, 4 * kT, 1);
+}
+
 hipError_t launch_mr_batch(const MrBatch &all, int blocks_rows, int blocks_cols, hipStream_t s,
                            const LaunchHook &hook) {
   // forward planes: rows then columns; adjoint planes: columns then rows (see the power-of-two
