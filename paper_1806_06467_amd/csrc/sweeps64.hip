@@ -1,7 +1,7 @@
 // fresnel_step_f64: one Fresnel plane in float64, the paper's precision (Sec. 2.2: the
 // benchmarks run in double precision). The same plane as fresnel_step (Sec. 1.1: the optic of
-// Eq. 3 and a thin lens, then angular-spectrum propagation), the same two sweeps on the same
-// Stockham plans (fft_line.hpp with complex float64 elements and float64 twiddle tables):
+// Eq. 3 and a thin lens, then angular-spectrum propagation), the same two sweeps on the
+// Stockham passes of fft_line.hpp (complex float64 elements, float64 twiddle tables):
 //
 //   row_sweep64 : load rows, optic prologue (forward) -- amplitude, exp(2 pi i opd / lambda) by a
 //                 float64 sincospi, lens chirp --, FFT, * h (carrying 1/n), inverse FFT, conjugate
@@ -15,7 +15,10 @@
 // times a float64 constant and reduced to a fraction of a turn before the float64 cos / sin.
 // A complex float64 line of n elements takes 16 n bytes of LDS (plus the padding of
 // fft_line.hpp), so the tiles hold half the lines of the float32 sweeps' (2048 and 4096: one row
-// per row block, two columns per column tile, 32-byte row pieces; 8192: one of each).
+// per row block, two columns per column tile, 32-byte row pieces; 8192: one of each). From 1024
+// to 4096 the plans hold 8 elements per thread (radix-8 passes) where the float32 sweeps hold 16:
+// twice the threads per line, under 128 VGPRs, so a compute unit runs 16 waves of the column
+// sweep instead of 8 (measured at 4096: 200 us against 247 us per row sweep).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -117,7 +120,12 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep64(Batch64 args, const 
   const Plane64 &pa = args.p[blockIdx.y];
   const int c = threadIdx.x % LINES;
   const int t = threadIdx.x / LINES;
-  const int x = blockIdx.x * LINES + c;
+  // blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous run of tiles, so that
+  // the tiles sharing a 128-byte line of a row are read through one L2
+  constexpr int G = N / LINES;
+  int g = blockIdx.x;
+  if constexpr (G % 8 == 0) g = (blockIdx.x & 7) * (G / 8) + (blockIdx.x >> 3);
+  const int x = g * LINES + c;
   double2 *col = pa.field + x;
   c64d v[E];
 #pragma unroll
@@ -155,7 +163,8 @@ hipError_t launch64(const Batch64 &b, int count, bool adjoint, const double2 *tw
   return adjoint ? rows() : cols();
 }
 
-// the plans of the float32 sweeps, with the tiles halved for 16-byte elements
+// the float32 sweeps' edges and tiles, halved for 16-byte elements (8 elements per thread from
+// 1024 to 4096)
 template <class F>
 auto with_plan64(int n, F &&f) {
   switch (n) {
@@ -163,9 +172,9 @@ auto with_plan64(int n, F &&f) {
     case 128: return f(Plan<128, 16, 16, 8>{}, std::integral_constant<int, 8>{}, std::integral_constant<int, 16>{});
     case 256: return f(Plan<256, 16, 16, 16>{}, std::integral_constant<int, 8>{}, std::integral_constant<int, 16>{});
     case 512: return f(Plan<512, 8, 8, 8, 8>{}, std::integral_constant<int, 2>{}, std::integral_constant<int, 8>{});
-    case 1024: return f(Plan<1024, 16, 16, 8, 8>{}, std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{});
-    case 2048: return f(Plan<2048, 16, 16, 16, 8>{}, std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{});
-    case 4096: return f(Plan<4096, 16, 16, 16, 16>{}, std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{});
+    case 1024: return f(Plan<1024, 8, 8, 8, 8, 2>{}, std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{});
+    case 2048: return f(Plan<2048, 8, 8, 8, 8, 4>{}, std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{});
+    case 4096: return f(Plan<4096, 8, 8, 8, 8, 8>{}, std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{});
     default: return f(Plan<8192, 16, 16, 16, 16, 2>{}, std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{});
   }
 }
