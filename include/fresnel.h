@@ -234,6 +234,15 @@ int fresnel_step_batched(fr_ctx *ctx, const fr_plane *planes, int32_t count, voi
  * fresnel_step_batched; FR_EHIP if recording fails. */
 int fresnel_step_batched_graph(fr_ctx *ctx, const fr_plane *planes, int32_t count, void *stream);
 
+/* Many planes of the exact-transfer-function step (fresnel_step_exact; e.g. the wavelengths of
+ * a broadband model, Sec. 1.2) in one call. Each fr_plane entry has the meaning of the
+ * fresnel_step_exact arguments; all planes share one power-of-two edge n (64..8192). Planes go
+ * in groups that fit the last-level cache together, each of the three sweeps over a group in one
+ * launch. `planes` is a HOST array read during the call. Returns the OR of the per-plane
+ * warnings, or an error; argument errors (FR_EINVAL: count <= 0, mixed edges, any plane's
+ * fresnel_step_exact error; FR_EUNSUPPORTED: edge) are found before anything is launched. */
+int fresnel_step_exact_batched(fr_ctx *ctx, const fr_plane *planes, int32_t count, void *stream);
+
 /* ---- matrix Fourier transform (Sec. 1.1, Soummer et al.; Sec. 2.3) ---------------------
  * Pupil sample m of an n_in-wide window sits at x_m = (m - n_in/2)/n_d  [D];
  * focal sample k of an m_out grid sits at u_k = (k - m_out/2) du      [lambda/D].

@@ -473,11 +473,6 @@ bool plane_size_supported(int n) {
   return fresnel_size_supported(n) || mr_plan(n, &np, rad);
 }
 
-// Planes are swept in groups whose fields fit the last-level cache together (at least one plane
-// per group), both sweeps of a group before the next group: the second sweep of a plane then
-// reads what the first one has just written from that cache instead of from HBM.
-constexpr size_t kCacheGroupBytes = size_t(160) << 20;
-
 // end of the group that starts at plane i: at most `cap` planes, and either `planes` planes
 // (a tuned group size) or, with planes = 0, as many as fit the last-level cache together
 static int group_end(const PlaneArgs *args, int count, int i, int cap, int planes = 0) {

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "../../include/fresnel.h"
 #include "fr_exact.h"
@@ -18,15 +20,65 @@ uint64_t dbits(double v) {
   return u;
 }
 
+// one checked plane's arguments with its tables fetched (z / lambda and (lambda / (n dx))^2 in
+// float64, the lens chirp, the twiddles); returns the plane's warning bits or an error
+int exact_plane(fr::Ctx *ctx, const fr_plane &p, hipStream_t s, fr::PlaneArgs *a, const float2 **root) {
+  const int n = p.n;
+  std::memset(a, 0, sizeof *a);
+  a->field = reinterpret_cast<float2 *>(p.field);
+  a->amp = p.amp;
+  a->opd = p.opd_m;
+  a->n = n;
+  a->win = n;
+  a->inv_lambda = float(1.0 / p.wavelength_m);
+  a->flags = p.flags;
+  const fr::TableKey key{fr::kExactPrm, n, dbits(p.dx_m), dbits(p.wavelength_m), dbits(p.z_m), 0};
+  void *d = nullptr;
+  if (auto it = ctx->tables.find(key); it != ctx->tables.end()) {
+    d = it->second;
+  } else {
+    const double q = p.wavelength_m / (double(n) * p.dx_m);
+    const double prm[2] = {p.z_m / p.wavelength_m, q * q};
+    const int st = ctx->upload(key, prm, sizeof prm, s, &d);
+    if (st != FR_OK) return st;
+  }
+  a->h = static_cast<const float2 *>(d);
+  if (p.lens_focal_m != 0.0) {
+    const int st = ctx->lens(n, p.dx_m, p.wavelength_m, p.lens_focal_m, s, &a->lens);
+    if (st != FR_OK) return st;
+  }
+  if (const int st = ctx->twiddles(n, s, root); st != FR_OK) return st;
+  return std::fabs(p.z_m) > double(n) * p.dx_m * p.dx_m / p.wavelength_m ? FR_W_AS_UNDERSAMPLED : FR_OK;
+}
+
 }  // namespace
 
 extern "C" int fresnel_step_exact(fr_ctx *ctx_, fr_c64 *field, int32_t n, double dx_m, double wavelength_m,
                                   double z_m, const float *amp, const float *opd_m, double lens_focal_m,
                                   int32_t flags, void *stream) {
-  if (!field || n <= 0 || (flags & ~FR_ADJOINT)) return FR_EINVAL;
-  if (!(dx_m > 0) || !(wavelength_m > 0) || !std::isfinite(dx_m) || !std::isfinite(wavelength_m) ||
-      !std::isfinite(z_m) || !std::isfinite(lens_focal_m))
-    return FR_EINVAL;
+  fr_plane p;
+  p.field = field;
+  p.amp = amp;
+  p.opd_m = opd_m;
+  p.dx_m = dx_m;
+  p.wavelength_m = wavelength_m;
+  p.z_m = z_m;
+  p.lens_focal_m = lens_focal_m;
+  p.n = n;
+  p.flags = flags;
+  return fresnel_step_exact_batched(ctx_, &p, 1, stream);
+}
+
+extern "C" int fresnel_step_exact_batched(fr_ctx *ctx_, const fr_plane *planes, int32_t count, void *stream) {
+  if (!planes || count <= 0) return FR_EINVAL;
+  const int n = planes[0].n;
+  for (int i = 0; i < count; ++i) {
+    const fr_plane &p = planes[i];
+    if (!p.field || p.n != n || n <= 0 || (p.flags & ~FR_ADJOINT)) return FR_EINVAL;
+    if (!(p.dx_m > 0) || !(p.wavelength_m > 0) || !std::isfinite(p.dx_m) || !std::isfinite(p.wavelength_m) ||
+        !std::isfinite(p.z_m) || !std::isfinite(p.lens_focal_m))
+      return FR_EINVAL;
+  }
   if (!fr::fresnel_size_supported(n)) return FR_EUNSUPPORTED;
   fr::Ctx *ctx = reinterpret_cast<fr::Ctx *>(ctx_);
   if (!ctx) return FR_EINVAL;
@@ -34,35 +86,21 @@ extern "C" int fresnel_step_exact(fr_ctx *ctx_, fr_c64 *field, int32_t n, double
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fr::record_hip(e);
   if (int st = ctx->begin_call(); st != FR_OK) return st;
-  fr::PlaneArgs a;
-  std::memset(&a, 0, sizeof a);
-  a.field = reinterpret_cast<float2 *>(field);
-  a.amp = amp;
-  a.opd = opd_m;
-  a.n = n;
-  a.win = n;
-  a.inv_lambda = float(1.0 / wavelength_m);
-  a.flags = flags;
-  // z / lambda and (lambda / (n dx))^2, in float64 on the device
-  const fr::TableKey key{fr::kExactPrm, n, dbits(dx_m), dbits(wavelength_m), dbits(z_m), 0};
-  void *d = nullptr;
-  if (auto it = ctx->tables.find(key); it != ctx->tables.end()) {
-    d = it->second;
-  } else {
-    const double q = wavelength_m / (double(n) * dx_m);
-    const double prm[2] = {z_m / wavelength_m, q * q};
-    const int st = ctx->upload(key, prm, sizeof prm, s, &d);
-    if (st != FR_OK) return st;
+  // planes per launch: as many as the last-level cache holds between a plane's three sweeps
+  const size_t plane_bytes = size_t(n) * size_t(n) * 8u;
+  const int group = int(std::max<size_t>(1, std::min<size_t>(fr::kMaxBatch, fr::kCacheGroupBytes / plane_bytes)));
+  int warn = 0;
+  std::vector<fr::PlaneArgs> args(group);
+  for (int i0 = 0; i0 < count; i0 += group) {
+    const int g = std::min(group, count - i0);
+    const float2 *root = nullptr;
+    for (int j = 0; j < g; ++j) {
+      const int st = exact_plane(ctx, planes[i0 + j], s, &args[j], &root);
+      if (st < 0) return st;
+      warn |= st;
+    }
+    e = fr::launch_exact_batch(args.data(), g, n, root, s, ctx->hook());
+    if (e != hipSuccess) return fr::record_hip(e);
   }
-  a.h = static_cast<const float2 *>(d);
-  if (lens_focal_m != 0.0) {
-    const int st = ctx->lens(n, dx_m, wavelength_m, lens_focal_m, s, &a.lens);
-    if (st != FR_OK) return st;
-  }
-  const float2 *root;
-  int st = ctx->twiddles(n, s, &root);
-  if (st != FR_OK) return st;
-  e = fr::launch_exact_batch(&a, 1, n, root, s, ctx->hook());
-  if (e != hipSuccess) return fr::record_hip(e);
-  return std::fabs(z_m) > double(n) * dx_m * dx_m / wavelength_m ? FR_W_AS_UNDERSAMPLED : FR_OK;
+  return warn;
 }

@@ -14,6 +14,11 @@
 
 namespace fr {
 
+// Planes are swept in groups whose fields fit the last-level cache together (at least one plane
+// per group), every sweep of a group before the next group: the later sweeps of a plane then
+// read what the previous one has just written from that cache instead of from HBM.
+constexpr size_t kCacheGroupBytes = size_t(160) << 20;
+
 enum TableKind : int {
   kRoots = 1, kTransfer, kLens, kMft, kDm, kMrTw, kDirectPre, kDirectPost, kExactPrm, kMft64,
   kRoots64, kTransfer64, kLens64

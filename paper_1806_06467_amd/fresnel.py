@@ -94,6 +94,7 @@ def lib():
             "fresnel_step_batched": (_c.c_int, [_vp, _c.POINTER(FrPlane), i32, _vp]),
             "fresnel_step_batched_graph": (_c.c_int, [_vp, _c.POINTER(FrPlane), i32, _vp]),
             "fresnel_step_exact": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _vp]),
+            "fresnel_step_exact_batched": (_c.c_int, [_vp, _c.POINTER(FrPlane), i32, _vp]),
             "fresnel_direct": (_c.c_int, [_vp, _vp, i32, f64, f64, f64, _vp, _vp, f64, i32, _c.POINTER(f64), _vp]),
             "fr_plan_route": (_c.c_int, [f64, f64, f64, i32, f64, f64, f64, _c.POINTER(FrRouteStep), i32]),
             "fr_plan_system": (_c.c_int, [i32, f64, f64, f64, _c.POINTER(FrOptic), i32, _c.POINTER(f64),
@@ -368,12 +369,8 @@ def fresnel_step_f64(field, dx, wavelength, z, amp=None, opd=None, lens_focal=0.
     return _check(st, "fresnel_step_f64")
 
 
-def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens_focals=None,
-                         adjoints=None, stream=None, graph=False):
-    """Many planes in one launch per sweep; per-plane sequences (or scalars). Planes may have
-    different edges (then every plane goes through the mixed-radix sweeps).
-    graph: the library records the call's launches as one graph the first time these plane
-    entries (field / map addresses, parameters) and stream are seen, and replays it later."""
+def _planes(fields, dx, wavelengths, zs, amps, opds, lens_focals, adjoints):
+    """FrPlane array of a batch: per-plane sequences (or scalars)."""
     count = len(fields)
     if count == 0:
         raise ValueError("empty batch")
@@ -401,10 +398,31 @@ def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens
                          opds[i].data_ptr() if opds[i] is not None else None, float(dxs[i]),
                          float(lams[i]), float(zz[i]), float(lf[i]), n,
                          FR_ADJOINT if adj[i] else 0)
+    return arr
+
+
+def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens_focals=None,
+                         adjoints=None, stream=None, graph=False):
+    """Many planes in one launch per sweep; per-plane sequences (or scalars). Planes may have
+    different edges (then every plane goes through the mixed-radix sweeps).
+    graph: the library records the call's launches as one graph the first time these plane
+    entries (field / map addresses, parameters) and stream are seen, and replays it later."""
+    arr = _planes(fields, dx, wavelengths, zs, amps, opds, lens_focals, adjoints)
+    count = len(fields)
     dev = fields[0].device.index
     fn = lib().fresnel_step_batched_graph if graph else lib().fresnel_step_batched
     st = fn(context(dev).handle, arr, count, _stream_handle(dev, stream))
     return _check(st, "fresnel_step_batched_graph" if graph else "fresnel_step_batched")
+
+
+def fresnel_step_exact_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens_focals=None,
+                               adjoints=None, stream=None):
+    """Many planes of the exact-transfer-function step in one call (one power-of-two edge);
+    per-plane sequences (or scalars). Returns the warning bits."""
+    arr = _planes(fields, dx, wavelengths, zs, amps, opds, lens_focals, adjoints)
+    dev = fields[0].device.index
+    st = lib().fresnel_step_exact_batched(context(dev).handle, arr, len(fields), _stream_handle(dev, stream))
+    return _check(st, "fresnel_step_exact_batched")
 
 
 # ---- MFT ----------------------------------------------------------------------------------

@@ -30,6 +30,23 @@ int main(void) {
   EXPECT(fresnel_step_exact(NULL, fake, 256, 1e-4, 5e-7, 1.0, NULL, NULL, 0.0, 2, NULL) == FR_EINVAL);
   EXPECT(fresnel_step_exact(NULL, fake, 4099, 1e-4, 5e-7, 1.0, NULL, NULL, 0.0, 0, NULL) == FR_EUNSUPPORTED);
   EXPECT(fresnel_step_exact(NULL, fake, 256, 1e-4, 5e-7, 1.0, NULL, NULL, 0.0, 0, NULL) == FR_EINVAL);
+  {
+    fr_plane ex[2];
+    memset(ex, 0, sizeof ex);
+    for (int i = 0; i < 2; ++i) {
+      ex[i].field = fake;
+      ex[i].dx_m = 1e-4;
+      ex[i].wavelength_m = 5e-7;
+      ex[i].z_m = 1.0;
+      ex[i].n = 256;
+    }
+    EXPECT(fresnel_step_exact_batched(NULL, ex, 2, NULL) == FR_EINVAL); /* no context */
+    EXPECT(fresnel_step_exact_batched(NULL, ex, 0, NULL) == FR_EINVAL);
+    ex[1].n = 512;
+    EXPECT(fresnel_step_exact_batched(NULL, ex, 2, NULL) == FR_EINVAL); /* mixed edges */
+    ex[0].n = ex[1].n = 3584;
+    EXPECT(fresnel_step_exact_batched(NULL, ex, 2, NULL) == FR_EUNSUPPORTED);
+  }
   fr_c128 *fake64 = (fr_c128 *)0x1000;
   EXPECT(mft_f64(NULL, NULL, fake64, 64, 16, 32.0, 0.5, 0, fake64, 1u << 30, NULL) == FR_EINVAL);
   EXPECT(mft_f64(NULL, fake64, fake64, 64, 16, 32.0, NAN, 0, fake64, 1u << 30, NULL) == FR_EINVAL);

@@ -11,7 +11,7 @@ from paper_1806_06467_amd import fresnel as fb
 
 EXPECTED = {
     "fr_create", "fr_destroy", "fr_set_cache_limit", "fr_status_string", "fr_fft_size_supported", "fresnel_step",
-    "fresnel_step_batched", "fresnel_step_batched_graph", "fresnel_step_exact", "fresnel_step_f64", "mft_f64", "mft_f64_workspace_bytes", "fresnel_direct", "fr_plan_route", "fr_plan_system", "propagate_system", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
+    "fresnel_step_batched", "fresnel_step_batched_graph", "fresnel_step_exact", "fresnel_step_exact_batched", "fresnel_step_f64", "mft_f64", "mft_f64_workspace_bytes", "fresnel_direct", "fr_plan_route", "fr_plan_system", "propagate_system", "mft_workspace_bytes", "mft_forward", "mft_adjoint",
     "propagate_train_workspace_bytes", "propagate_train_ckpt_bytes", "propagate_train", "mft_forward_noalloc", "fr_profile_enable", "fr_profile_read",
     "fr_autotune", "fr_autotune_save", "fr_autotune_load",
 }
@@ -151,6 +151,32 @@ def test_batched_argument_errors(L):
         bad = (fb.FrPlane * 1)()
         bad[0] = fb.FrPlane(0x1000, None, None, 1e-4, 5e-7, 1.0, 0.0, 4097, 0)
         assert fn(null, bad, 1, null) == fb.FR_EUNSUPPORTED
+
+
+def test_exact_batched_argument_errors(L):
+    null = ctypes.c_void_p()
+    fn = L.fresnel_step_exact_batched
+    good = (fb.FrPlane * 2)()
+    good[0] = fb.FrPlane(0x1000, None, None, 1e-4, 5e-7, 1.0, 0.0, 256, 0)
+    good[1] = fb.FrPlane(0x2000, None, None, 2e-4, 6e-7, -1.0, 0.0, 256, fb.FR_ADJOINT)
+    assert fn(null, good, 2, null) == fb.FR_EINVAL     # valid planes, no context
+    assert fn(null, good, 0, null) == fb.FR_EINVAL
+    assert fn(null, None, 1, null) == fb.FR_EINVAL
+    mixed = (fb.FrPlane * 2)()
+    mixed[0] = fb.FrPlane(0x1000, None, None, 1e-4, 5e-7, 1.0, 0.0, 256, 0)
+    mixed[1] = fb.FrPlane(0x2000, None, None, 1e-4, 5e-7, 1.0, 0.0, 512, 0)
+    assert fn(null, mixed, 2, null) == fb.FR_EINVAL    # one edge per call
+    odd = (fb.FrPlane * 1)()
+    odd[0] = fb.FrPlane(0x1000, None, None, 1e-4, 5e-7, 1.0, 0.0, 3584, 0)
+    assert fn(null, odd, 1, null) == fb.FR_EUNSUPPORTED   # power-of-two edges only
+    for plane, want in ((fb.FrPlane(0x1000, None, None, 1e-4, 5e-7, 1.0, 0.0, 256, 2), fb.FR_EINVAL),
+                        (fb.FrPlane(None, None, None, 1e-4, 5e-7, 1.0, 0.0, 256, 0), fb.FR_EINVAL),
+                        (fb.FrPlane(0x1000, None, None, 1e-4, 5e-7, float("nan"), 0.0, 256, 0), fb.FR_EINVAL),
+                        (fb.FrPlane(0x1000, None, None, 1e-4, 0.0, 1.0, 0.0, 256, 0), fb.FR_EINVAL)):
+        one = (fb.FrPlane * 2)()
+        one[0] = good[0]
+        one[1] = plane
+        assert fn(null, one, 2, null) == want
 
 
 def test_mft_argument_errors(L):
