@@ -53,16 +53,16 @@ METRIC = "Fresnel planes/sec at 4096^2 c64 (fwd+adjoint, batched vs plain), %HBM
 # 128 MiB plane in the same runs (FETCH x 2.0, WRITE x 1.0). Each entry carries the SHA-256 of the
 # sources it was measured on and reads as unknown (null) once they change.
 MEASURED_TRAFFIC = {
-    "col_sweep_adj": (136638669, 151176090),
-    "col_sweep": (136687411, 166559744),
-    "row_sweep": (269561242, 134217728),
-    "row_sweep_adj": (269653197, 134217728),
+    "row_sweep": (269226249, 134217728),
+    "col_sweep": (136670558, 162994189),
+    "col_sweep_adj": (136681753, 150908683),
+    "row_sweep_adj": (269251713, 134217728),
 }
 _SWEEP_SOURCES = {
-    "paper_1806_06467_amd/csrc/sweeps.hip": "19241185637070e51924fce0490ec814f21088d14020e99da71b4130572e31cf",
+    "paper_1806_06467_amd/csrc/sweeps.hip": "f440ccc9622d739c8ab4f89a7f0bf1947ef47dc43a759800ee6075639881e8bb",
     "paper_1806_06467_amd/csrc/fft_line.hpp": "66f504dc38f9cb71c51b0dd9e259e966acb90c9d9d1b256d8d7ca415edac6fae",
-    "paper_1806_06467_amd/csrc/dft_small.hpp": "8ecf89941d562fa656d33604a2684c7329106e4272470c584b8acfb5b198fee0",
-    "paper_1806_06467_amd/csrc/fr_internal.h": "5e4b00d764eb6352a0e1481967570d54e71e042c52209f5262aff17334acfb5d",
+    "paper_1806_06467_amd/csrc/dft_small.hpp": "f079518edd36aa105b5a40ce60935e1cdb8f3c06c3c59d0fa46a65eea89b7209",
+    "paper_1806_06467_amd/csrc/fr_internal.h": "82b876eca30f282551467af7da66a055c94d466ca7982c57b9856e331faadb45",
 }
 TRAFFIC_SOURCES = {k: _SWEEP_SOURCES for k in MEASURED_TRAFFIC}
 
