@@ -1,10 +1,9 @@
 // The matrix Fourier transform in float64 (Sec. 1.1, after Soummer et al.; Sec. 2.3 for the
 // precision the paper benchmarks): out = (du / n_d) W in W^T and its adjoint
-// (du / n_d) W^H in conj(W), as two complex GEMMs in float64. On gfx950 the float64 vector
-// units and the float64 matrix cores have the same dense peak (78.6 TFLOP/s), so the GEMM is an
-// LDS-tiled VALU kernel: each 256-thread block forms a 16 R x 16 Q tile of C from 16-deep slices
-// of A and B staged in LDS, each thread an R x Q sub-tile (rows ty + 16 r, columns tx + 16 q):
-// 64 x 64 tiles where they give the launch at least 4 blocks per compute unit, 32 x 32 otherwise.
+// (du / n_d) W^H in conj(W), as two complex GEMMs in float64 on the matrix cores (on gfx950 their
+// dense float64 peak, 78.6 TFLOP/s, equals the vector units'; the matrix-core tile reads each
+// operand from LDS once per 16 x 16 x 4 product instead of once per multiply-add, and leaves the
+// vector units free for the loads).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -27,94 +26,149 @@ constexpr int kDepth = 16;
 // when CA; B(k, j) = b[k ldb + j] (or b[j ldb + k] when TB), conjugated when CB. Split K:
 // blockIdx.z takes k in [z kc, (z + 1) kc) and writes its partial C at c + z c_split. A may be
 // the ordered sum of sa partial matrices a_split apart (the previous product's split-K slices).
-template <int R, int Q, bool TA, bool CA, bool TB, bool CB>
-__global__ void __launch_bounds__(256) zgemm_kernel(const z64 *__restrict__ a, int lda, const z64 *__restrict__ b,
-                                                    int ldb, z64 *__restrict__ c, int ldc, int M, int N, int K,
-                                                    double s, int kc, size_t c_split, int sa, size_t a_split) {
-  constexpr int TM = 16 * R, TN = 16 * Q;
+// On the float64 matrix cores: a 256-thread block forms a 64 x 64 tile of C from 16-deep slices of
+// A and B staged in LDS (the next slice read into registers while the current one is
+// multiplied), each wave a 32 x 32 piece as 2 x 2 blocks of 16 x 16, every complex k-step of 4 as
+// four real v_mfma_f64_16x16x4 per block (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br). Fragment
+// layouts (checked on gfx950 with one-hot operands): lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16] of the 16 x 4 and 4 x 16 operands, and item r of the result
+// D[4 r + l / 16][l % 16].
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <bool TA, bool CA, bool TB, bool CB>
+__global__ void __launch_bounds__(256) zgemm_mfma_kernel(const z64 *__restrict__ a, int lda,
+                                                         const z64 *__restrict__ b, int ldb, z64 *__restrict__ c,
+                                                         int ldc, int M, int N, int K, double s, int kc,
+                                                         size_t c_split, int sa, size_t a_split) {
+  constexpr int TM = 64, TN = 64, R = TM * kDepth / 256, Q = TN * kDepth / 256;
   __shared__ z64 As[kDepth][TM + 1];
   __shared__ z64 Bs[kDepth][TN + 1];
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
   const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TN;
-  z64 acc[R][Q];
+  d4 cr[2][2], ci[2][2];
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+  for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-    for (int q = 0; q < Q; ++q) acc[r][q] = {0.0, 0.0};
+    for (int jb = 0; jb < 2; ++jb) cr[ib][jb] = ci[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
   const int kbeg = blockIdx.z * kc, kend = min(K, kbeg + kc);
   c += blockIdx.z * c_split;
-  for (int k0 = kbeg; k0 < kend; k0 += kDepth) {
-    // A slice: TM rows x 16 k (R elements per thread); zero outside the matrix
+  const int fr = lane & 15, fk = lane >> 4;  // fragment row (column) and k within a 4-deep step
+  // the next slice's operands are read into registers while the current one is multiplied
+  z64 va[R], vb[Q];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int e = tid + 256 * r;
       int i, k;
       if constexpr (TA) { i = e % TM; k = e / TM; } else { k = e % kDepth; i = e / kDepth; }
-      z64 va = {0.0, 0.0};
+      va[r] = {0.0, 0.0};
       if (i0 + i < M && k0 + k < kend) {
         const size_t at = TA ? size_t(k0 + k) * lda + (i0 + i) : size_t(i0 + i) * lda + (k0 + k);
-        va = a[at];
+        va[r] = a[at];
         for (int p = 1; p < sa; ++p) {
           const z64 w = a[p * a_split + at];
-          va.x += w.x;
-          va.y += w.y;
+          va[r].x += w.x;
+          va[r].y += w.y;
         }
       }
-      if constexpr (CA) va.y = -va.y;
-      As[k][i] = va;
     }
-    // B slice: 16 k x TN columns (Q elements per thread)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
       int j, kb;
       if constexpr (TB) { kb = e % kDepth; j = e / kDepth; } else { j = e % TN; kb = e / TN; }
-      z64 vb = {0.0, 0.0};
+      vb[q] = {0.0, 0.0};
       if (j0 + j < N && k0 + kb < kend)
-        vb = TB ? b[size_t(j0 + j) * ldb + (k0 + kb)] : b[size_t(k0 + kb) * ldb + (j0 + j)];
-      if constexpr (CB) vb.y = -vb.y;
-      Bs[kb][j] = vb;
+        vb[q] = TB ? b[size_t(j0 + j) * ldb + (k0 + kb)] : b[size_t(k0 + kb) * ldb + (j0 + j)];
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < kDepth; ++kk) {
-      z64 av[R], bv[Q];
+  };
+  auto put = [&] {
 #pragma unroll
-      for (int r = 0; r < R; ++r) av[r] = As[kk][ty + 16 * r];
+    for (int r = 0; r < R; ++r) {
+      const int e = tid + 256 * r;
+      int i, k;
+      if constexpr (TA) { i = e % TM; k = e / TM; } else { k = e % kDepth; i = e / kDepth; }
+      z64 v = va[r];
+      if constexpr (CA) v.y = -v.y;
+      As[k][i] = v;
+    }
 #pragma unroll
-      for (int q = 0; q < Q; ++q) bv[q] = Bs[kk][tx + 16 * q];
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + 256 * q;
+      int j, kb;
+      if constexpr (TB) { kb = e % kDepth; j = e / kDepth; } else { j = e % TN; kb = e / TN; }
+      z64 v = vb[q];
+      if constexpr (CB) v.y = -v.y;
+      Bs[kb][j] = v;
+    }
+  };
+  if (kbeg < kend) {
+    fetch(kbeg);
+    put();
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += kDepth) {
+    const bool more = k0 + kDepth < kend;
+    if (more) fetch(k0 + kDepth);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
+    for (int k4 = 0; k4 < kDepth; k4 += 4) {
+      double ar[2], ai[2], nai[2], br[2], bi[2];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          acc[r][q].x = fma(av[r].x, bv[q].x, fma(-av[r].y, bv[q].y, acc[r][q].x));
-          acc[r][q].y = fma(av[r].x, bv[q].y, fma(av[r].y, bv[q].x, acc[r][q].y));
+      for (int ib = 0; ib < 2; ++ib) {
+        const z64 v = As[k4 + fk][wm * 32 + ib * 16 + fr];
+        ar[ib] = v.x;
+        ai[ib] = v.y;
+        nai[ib] = -v.y;
+      }
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) {
+        const z64 v = Bs[k4 + fk][wn * 32 + jb * 16 + fr];
+        br[jb] = v.x;
+        bi[jb] = v.y;
+      }
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+          cr[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ib], br[jb], cr[ib][jb], 0, 0, 0);
+          ci[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ib], bi[jb], ci[ib][jb], 0, 0, 0);
+        }
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+          cr[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[ib], bi[jb], cr[ib][jb], 0, 0, 0);
+          ci[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[ib], br[jb], ci[ib][jb], 0, 0, 0);
         }
     }
     __syncthreads();
+    if (more) put();
+    __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int i = i0 + ty + 16 * r;
-    if (i >= M) continue;
+  for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int j = j0 + tx + 16 * q;
-      if (j < N) c[size_t(i) * ldc + j] = {s * acc[r][q].x, s * acc[r][q].y};
+    for (int jb = 0; jb < 2; ++jb) {
+      const int j = j0 + wn * 32 + jb * 16 + fr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wm * 32 + ib * 16 + 4 * r + fk;
+        if (i < M && j < N) c[size_t(i) * ldc + j] = {s * cr[ib][jb][r], s * ci[ib][jb][r]};
+      }
     }
-  }
 }
 
-// split-K factors of the forward transform's two GEMMs (m x n x n, then m x m x n): 4 and 16
+// split-K factors of the forward transform's two products (m x n x n, then m x m x n): 4 and 32
 // where their 64 x 64 tiles alone would give a launch fewer than 4 blocks per compute unit and
-// K is long
+// the pupil is large
 int f64_split(int n, int m) {
   const long tiles = long((n + 63) / 64) * long((m + 63) / 64);
   return tiles < 1024 && n >= 1024 ? 4 : 1;
 }
 int f64_split2(int n, int m) {
   const long tiles = long((m + 63) / 64) * long((m + 63) / 64);
-  return tiles < 1024 && n >= 1024 ? 16 : 1;
+  return tiles < 1024 && n >= 1024 ? 32 : 1;
 }
 
 // out[i] = s sum_p part[p stride + i], the partials added in order
@@ -138,13 +192,8 @@ hipError_t zgemm(const z64 *a, int lda, const z64 *b, int ldb, z64 *c, int ldc, 
   hook(st, name, 1, 0);
   const int kc = ((K + split - 1) / split + kDepth - 1) / kDepth * kDepth;
   const size_t c_split = size_t(M) * size_t(ldc);
-  const long big = long((N + 63) / 64) * long((M + 63) / 64) * split;
-  if (big >= 1024)
-    hipLaunchKernelGGL((zgemm_kernel<4, 4, TA, CA, TB, CB>), dim3((N + 63) / 64, (M + 63) / 64, split), dim3(256), 0,
-                       st, a, lda, b, ldb, c, ldc, M, N, K, s, kc, c_split, sa, a_split);
-  else
-    hipLaunchKernelGGL((zgemm_kernel<2, 2, TA, CA, TB, CB>), dim3((N + 31) / 32, (M + 31) / 32, split), dim3(256), 0,
-                       st, a, lda, b, ldb, c, ldc, M, N, K, s, kc, c_split, sa, a_split);
+  hipLaunchKernelGGL((zgemm_mfma_kernel<TA, CA, TB, CB>), dim3((N + 63) / 64, (M + 63) / 64, split), dim3(256), 0,
+                     st, a, lda, b, ldb, c, ldc, M, N, K, s, kc, c_split, sa, a_split);
   hipError_t e = hipGetLastError();
   hook(st, name, 1, 1);
   return e;
@@ -233,7 +282,9 @@ extern "C" int mft_f64(fr_ctx *ctx_, const fr_c128 *in, fr_c128 *out, int32_t n_
       }
     }
   } else {
-    // T = W^H in (n x m); out = scale T conj(W) (n x n)
+    // T = W^H in (n x m); out = scale T conj(W) (n x n). (T in split-K partials would be summed
+    // by every column tile of the second product: 0.99 ms against 0.62 ms for it at the occulter
+    // shape.)
     e = fr::zgemm<true, true, false, false>(w, n, src, m, t, m, n, m, m, 1.0, s, hook, "zgemm_mft64_adj_1");
     if (e == hipSuccess)
       e = fr::zgemm<false, false, false, true>(t, m, w, n, dst, n, n, n, m, scale, s, hook, "zgemm_mft64_adj_2");

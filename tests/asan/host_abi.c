@@ -53,7 +53,7 @@ int main(void) {
   EXPECT(mft_f64(NULL, fake64, fake64, 64, 16, 32.0, 0.5, 4, fake64, 1u << 30, NULL) == FR_EINVAL);
   EXPECT(mft_f64(NULL, fake64, fake64, 64, 16, 32.0, 0.5, FR_ADJOINT, fake64, 1u << 30, NULL) == FR_EINVAL);
   EXPECT(mft_f64(NULL, fake64, fake64, 64, 16, 32.0, 0.5, 0, fake64, 100, NULL) == FR_EWORKSPACE);
-  EXPECT(mft_f64_workspace_bytes(4096, 256) == 4u * 16u * 4096u * 256u + 16u * 16u * 256u * 256u);
+  EXPECT(mft_f64_workspace_bytes(4096, 256) == 4u * 16u * 4096u * 256u + 32u * 16u * 256u * 256u);
   EXPECT(fresnel_direct(NULL, fake, 256, 1e-4, 5e-7, 0.0, NULL, NULL, 0.0, 0, &dx_out, NULL) == FR_EINVAL);
   EXPECT(fresnel_direct(NULL, fake, 256, 1e-4, 5e-7, 1.0, NULL, NULL, 0.0, 3, &dx_out, NULL) == FR_EINVAL);
   EXPECT(fresnel_direct(NULL, fake, 3584, 1e-4, 5e-7, 1.0, NULL, NULL, 0.0, 0, &dx_out, NULL) == FR_EUNSUPPORTED);

@@ -133,7 +133,7 @@ def test_mft_f64_argument_errors(L):
     # workspace below mft_f64_workspace_bytes: 16 n m, four times that where the first product
     # is split over k, plus 16 partial m x m products where the second is
     assert L.mft_f64_workspace_bytes(64, 16) == 16 * 64 * 16
-    assert L.mft_f64_workspace_bytes(4096, 256) == 4 * 16 * 4096 * 256 + 16 * 16 * 256 * 256
+    assert L.mft_f64_workspace_bytes(4096, 256) == 4 * 16 * 4096 * 256 + 32 * 16 * 256 * 256
     assert L.mft_f64_workspace_bytes(0, 16) == 0
     assert L.mft_f64(null, FAKE, FAKE, 64, 16, 32.0, 0.5, 0, FAKE, 16 * 64 * 16 - 1, null) == fb.FR_EWORKSPACE
     # valid arguments but no context
