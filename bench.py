@@ -342,8 +342,8 @@ def main():
                         "hbm_frac_bytes_weighted": frac_of(ms_u, ubytes)},
             "plain": {"value": n_pl / (ms_up * 1e-3), "unit": "Fresnel planes/s", "ms_per_step": ms_up,
                       "hbm_frac_bytes_weighted": frac_of(ms_up, ubytes)},
-            "note": "every plane of a mixed-edge batch takes the persistent mixed-radix sweeps; the "
-                    "plain form runs the power-of-two sweeps for its 4096^2 planes"}
+            "note": "the 4096^2 planes take the power-of-two sweeps, the others the persistent "
+                    "mixed-radix sweeps (in the batched form one launch per sweep for each group)"}
         del ufields, ua, uo, maps
 
     # ---- device-copy ceiling: 1 GiB copied (2 GiB moved), beyond the last-level cache ----------

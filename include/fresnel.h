@@ -214,8 +214,12 @@ int propagate_system(fr_ctx *ctx, fr_c64 *field, int32_t n, double dx_m, double 
 
 /* Many independent planes in one launch per sweep (e.g. the wavelengths of a broadband
  * model, Sec. 1.2). Each entry has the meaning of the fresnel_step arguments. `planes` is a
- * HOST array read during the call. All planes must share one edge n. Returns the OR of
- * the per-plane warnings, or the first error (then nothing was launched). */
+ * HOST array read during the call. Planes may have different edges (e.g. one grid per
+ * wavelength): the planes of each power-of-two edge take the two-sweep kernels together, the
+ * planes of other edges the persistent mixed-radix sweeps together; each plane's result is the
+ * one fresnel_step gives. The fields must not overlap. Planes go in groups that fit the
+ * last-level cache (both sweeps of a group before the next). Returns the OR of the per-plane
+ * warnings, or the first error (then nothing was launched). */
 typedef struct {
   fr_c64 *field;
   const float *amp;
@@ -318,10 +322,10 @@ int mft_f64(fr_ctx *ctx, const fr_c128 *in, fr_c128 *out, int32_t n_pupil, int32
  * steps of a group of wavelengths (grids of different edges allowed) in one launch per sweep;
  * groups are as many wavelengths as fit the last-level cache together (one 4096^2 plane,
  * several smaller ones), each followed by its focal-plane chains; all sums still go in
- * wavelength order. With one power-of-two edge
- * for all wavelengths, psf and grad_heights are bit-identical to the plain (wavelength after
- * wavelength) mode; with mixed edges every plane takes the mixed-radix sweeps and the results
- * agree with the plain mode to float32 rounding. Its workspace grows with sum_j n_pad[j]^2.
+ * wavelength order. Each plane takes the same kernels as in the plain (wavelength after
+ * wavelength) mode (power-of-two edges the two-sweep kernels, other edges the mixed-radix
+ * sweeps), so psf and grad_heights are bit-identical to that mode. Its workspace grows with
+ * sum_j n_pad[j]^2.
  * FR_TRAIN_GRAPH records the whole call as one graph the first time a given set of argument
  * values (descriptor bytes, host arrays, device pointers, stream) is seen, after running it
  * normally, and replays that graph on later identical calls; the device inputs may change

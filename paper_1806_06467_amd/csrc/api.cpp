@@ -488,35 +488,43 @@ static int group_end(const PlaneArgs *args, int count, int i, int cap, int plane
   return j;
 }
 
-// All planes share edge n (a power of two with a tuned register-resident plan): the two-sweep
-// kernels. Otherwise (mixed edges or a mixed-radix edge): the persistent mixed-radix kernels,
-// one launch per sweep for each group of planes.
-int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s) {
-  bool uniform = fresnel_size_supported(n);
-  for (int i = 0; i < count && uniform; ++i) uniform = (args[i].n == n);
-  if (uniform) {
+// Planes whose edge has a register-resident power-of-two plan go through the two-sweep kernels,
+// those of one edge together; the others (mixed-radix edges) through the persistent mixed-radix
+// kernels, one launch per sweep for each group of planes of any edges. The planes of a batch are
+// independent, so their order across the two paths does not matter.
+int run_planes(Ctx *ctx, PlaneArgs *args, int count, hipStream_t s) {
+  std::vector<PlaneArgs> rest;
+  std::map<int, std::vector<PlaneArgs>> pow2;
+  for (int i = 0; i < count; ++i) {
+    if (fresnel_size_supported(args[i].n))
+      pow2[args[i].n].push_back(args[i]);
+    else
+      rest.push_back(args[i]);
+  }
+  for (auto &[n, v] : pow2) {
     const float2 *root;
     int st = ctx->twiddles(n, s, &root);
     if (st != FR_OK) return st;
     int planes = 0;
     if (auto it = ctx->tuned_group.find(n); it != ctx->tuned_group.end()) planes = it->second;
-    for (int i = 0; i < count;) {
-      const int j = group_end(args, count, i, kMaxBatch, planes);
-      hipError_t e = launch_fresnel_batch(args + i, j - i, n, root, s, ctx->hook(), ctx->sweep_variant(n));
+    const int nv = int(v.size());
+    for (int i = 0; i < nv;) {
+      const int j = group_end(v.data(), nv, i, kMaxBatch, planes);
+      hipError_t e = launch_fresnel_batch(v.data() + i, j - i, n, root, s, ctx->hook(), ctx->sweep_variant(n));
       if (e != hipSuccess) return record_hip(e);
       i = j;
     }
-    return FR_OK;
   }
-  for (int i = 0; i < count;) {
-    const int j = group_end(args, count, i, kMrMaxBatch);
+  const int nr = int(rest.size());
+  for (int i = 0; i < nr;) {
+    const int j = group_end(rest.data(), nr, i, kMrMaxBatch);
     MrBatch b;
     b.count = j - i;
     b.total = 0;
     for (int k = 0; k < b.count; ++k) {
-      int st = ctx->mr(args[i + k].n, s, &b.p[k]);
+      int st = ctx->mr(rest[i + k].n, s, &b.p[k]);
       if (st != FR_OK) return st;
-      b.p[k].pa = args[i + k];
+      b.p[k].pa = rest[i + k];
     }
     hipError_t e = launch_mr_batch(b, ctx->cus * ctx->mr_rows_per_cu, ctx->cus * ctx->mr_cols_per_cu, s, ctx->hook());
     if (e != hipSuccess) return record_hip(e);
@@ -635,7 +643,7 @@ static int batch_body(Ctx *ctx, const fr_plane *planes, int32_t count, hipStream
       if (st != FR_OK) return st;
     }
   }
-  return fr::run_planes(ctx, args.data(), count, planes[0].n, s);
+  return fr::run_planes(ctx, args.data(), count, s);
 }
 
 int fresnel_step_batched(fr_ctx *ctx_, const fr_plane *planes, int32_t count, void *stream) {

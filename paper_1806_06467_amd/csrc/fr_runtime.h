@@ -101,7 +101,7 @@ int record_hip(hipError_t e);
 
 // Internal entry points shared by the C ABI and the train orchestration (arguments already
 // validated; tables are fetched from / added to the context cache).
-int run_planes(Ctx *ctx, PlaneArgs *args, int count, int n, hipStream_t s);
+int run_planes(Ctx *ctx, PlaneArgs *args, int count, hipStream_t s);
 struct MftOut {
   float2 *out = nullptr;
   int ld_out = 0;

@@ -756,7 +756,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       if (fwd) {
         PlaneArgs pa;
         FR_TRY(fwd_plane(j, &pa));
-        FR_TRY(run_planes(ctx, &pa, 1, n_pad[j], s));
+        FR_TRY(run_planes(ctx, &pa, 1, s));
         FR_TRY(focal_chain(j));
       }
       if (!grad) continue;
@@ -764,7 +764,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       if (ndm == 2) {
         PlaneArgs pb;
         FR_TRY(adj_plane(j, &pb));
-        FR_TRY(run_planes(ctx, &pb, 1, n_pad[j], s));
+        FR_TRY(run_planes(ctx, &pb, 1, s));
         FR_TRY(back_to_pupil_dm(j));
       }
     }
@@ -788,7 +788,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       }
       if (fwd) {
         for (int j = g0; j < g1; ++j) FR_TRY(fwd_plane(j, &planes[j]));
-        FR_TRY(run_planes(ctx, planes.data() + g0, g1 - g0, n_pad[g0], s));
+        FR_TRY(run_planes(ctx, planes.data() + g0, g1 - g0, s));
       }
       for (int j = g0; j < g1; ++j) {
         if (fwd) FR_TRY(focal_chain(j));
@@ -796,7 +796,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
       }
       if (grad && ndm == 2) {
         for (int j = g0; j < g1; ++j) FR_TRY(adj_plane(j, &planes[j]));
-        FR_TRY(run_planes(ctx, planes.data() + g0, g1 - g0, n_pad[g0], s));
+        FR_TRY(run_planes(ctx, planes.data() + g0, g1 - g0, s));
         for (int j = g0; j < g1; ++j) FR_TRY(back_to_pupil_dm(j));
       }
       g0 = g1;

@@ -404,7 +404,8 @@ def _planes(fields, dx, wavelengths, zs, amps, opds, lens_focals, adjoints):
 def fresnel_step_batched(fields, dx, wavelengths, zs, amps=None, opds=None, lens_focals=None,
                          adjoints=None, stream=None, graph=False):
     """Many planes in one launch per sweep; per-plane sequences (or scalars). Planes may have
-    different edges (then every plane goes through the mixed-radix sweeps).
+    different edges (power-of-two edges take the two-sweep kernels, one launch per sweep for
+    the planes of each edge; the others the mixed-radix sweeps).
     graph: the library records the call's launches as one graph the first time these plane
     entries (field / map addresses, parameters) and stream are seen, and replays it later."""
     arr = _planes(fields, dx, wavelengths, zs, amps, opds, lens_focals, adjoints)
