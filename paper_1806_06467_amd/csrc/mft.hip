@@ -557,18 +557,22 @@ cgemm_bf_kernel(GemmParams gp) {
   }
 }
 
+// output rows over blockIdx.y, columns over blockIdx.x and the threads (no index division),
+// the partials added in slice order
 __global__ void __launch_bounds__(256) split_reduce(GemmParams gp) {
   const CGemmArgs &a = gp.a;
   const size_t total = size_t(a.M) * a.N;
-  for (size_t e = size_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += size_t(gridDim.x) * 256) {
-    double sr = 0.0, si = 0.0;
-    for (int s = 0; s < gp.split; ++s) {
-      const double2 v = gp.partial[size_t(s) * total + e];
-      sr += v.x;
-      si += v.y;
+  for (int i = blockIdx.y; i < a.M; i += gridDim.y) {
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < a.N; j += gridDim.x * 256) {
+      const size_t e = size_t(i) * a.N + j;
+      double sr = 0.0, si = 0.0;
+      for (int s = 0; s < gp.split; ++s) {
+        const double2 v = gp.partial[size_t(s) * total + e];
+        sr += v.x;
+        si += v.y;
+      }
+      epilogue(a, i, j, sr, si);
     }
-    const int i = int(e / a.N), j = int(e % a.N);
-    epilogue(a, i, j, sr, si);
   }
 }
 
@@ -672,10 +676,8 @@ hipError_t launch_cgemm_split(const CGemmArgs &a, int split, int cfg_choice, voi
                             : launch_cfg<CfgS>(gp, stream);
   hook(stream, name, a.K, 1);
   if (e != hipSuccess || split == 1) return e;
-  const size_t total = size_t(a.M) * a.N;
-  int blocks = int(std::min<size_t>((total + 255) / 256, 4096));
   hook(stream, "split_reduce", a.K, 0);
-  hipLaunchKernelGGL(split_reduce, dim3(blocks), dim3(256), 0, stream, gp);
+  hipLaunchKernelGGL(split_reduce, dim3(std::min((a.N + 255) / 256, 16), std::min(a.M, 65535)), dim3(256), 0, stream, gp);
   e = hipGetLastError();
   hook(stream, "split_reduce", a.K, 1);
   return e;
