@@ -62,11 +62,11 @@ def test_appendix_b_relay_matches_oracle(n):
     assert rel_l2(to_np(t), ref) <= TOL
 
 
-@pytest.mark.parametrize("n", [512, 4096])
+@pytest.mark.parametrize("n", [512, 4096, 8192])
 def test_gaussian_through_appendix_b_lenses(n):
     """A Gaussian beam of waist 0.4 m on the 2.37 m relay's first plane through all its lenses
     (no masks), against the q-law closed form on the last plane's grid; 4096 is the benchmark's
-    edge, on the benchmark's plan (same pitches, routes and 19 transforms)."""
+    edge, on the benchmark's plan (same pitches, routes and 19 transforms), 8192 the largest."""
     lam = 0.55e-6
     banner(f"relay lenses: Gaussian beam, n={n}")
     zf, dx, _, _, _ = appendix_b(n, lam, with_masks=False)
@@ -75,4 +75,45 @@ def test_gaussian_through_appendix_b_lenses(n):
     optics = [(z, f, None, None) for z, f in zf]
     pitch = fb.propagate_system(t, dx, lam, 2.37 / 2, optics)
     ref = oracle.gaussian_through_system(n, pitch, lam, w0, optics)
+    assert rel_l2(to_np(t), ref) <= TOL
+
+
+def test_single_plane_system_is_its_optic():
+    """A system of one plane applies that plane's optic (transmission, OPD phasor, thin lens) and
+    nothing else; its pitch is the input pitch."""
+    n, lam, dx = 128, 0.6e-6, 1e-4
+    banner("relay: one plane")
+    rng = np.random.default_rng(3)
+    field = synth.random_field(n, 4)
+    amp = rng.uniform(0.2, 1.0, (n, n))
+    opd = rng.normal(0.0, 80e-9, (n, n))
+    t = to_gpu(field)
+    pitch = fb.propagate_system(t, dx, lam, 40 * dx, [(0.0, 3.0, to_gpu(amp, torch.float32),
+                                                       to_gpu(opd, torch.float32))])
+    assert pitch == dx
+    ref = f32(field) * oracle.optic_phasor(n, dx, lam, amp=f32(amp), opd=f32(opd), lens_focal=3.0)
+    assert rel_l2(to_np(t), ref) <= 1e-6
+
+
+def test_planes_at_zero_distance_and_negative_lens_match_oracle():
+    """Two optics on one plane (a zero distance between them), a diverging lens and a plane
+    beyond the pilot beam's Rayleigh range, against the oracle."""
+    n, lam, dx = 256, 0.55e-6, 2e-4
+    banner("relay: zero distances, diverging lens")
+    rng = np.random.default_rng(9)
+    mask = synth.embed_centred(synth.pupil_amplitude(n // 2, 0.2, 0.02), n)
+    opd = rng.normal(0.0, 30e-9, (n, n))
+    zf = [(0.0, 5.0), (0.0, -2.5), (0.7, 0.0), (0.0, 1.5), (2.0, 0.0), (0.5, 0.0)]
+    gpu_optics, or_optics = [], []
+    for i, (z, f) in enumerate(zf):
+        amp = mask if i == 0 else None
+        op = opd if i == 3 else None
+        gpu_optics.append((z, f, None if amp is None else to_gpu(amp, torch.float32),
+                           None if op is None else to_gpu(op, torch.float32)))
+        or_optics.append((z, f, None if amp is None else f32(amp), None if op is None else f32(op)))
+    field = synth.random_field(n, 10)
+    t = to_gpu(field)
+    pitch = fb.propagate_system(t, dx, lam, n * dx / 4, gpu_optics)
+    ref, pitch_ref = oracle.propagate_system(f32(field), dx, lam, n * dx / 4, or_optics)
+    assert pitch == pytest.approx(pitch_ref, rel=1e-12)
     assert rel_l2(to_np(t), ref) <= TOL
