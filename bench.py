@@ -13,9 +13,11 @@ Beside it: per-iteration spread (median / IQR over 50 steps) and the paper's own
 (mean +- sigma over 7 runs); the same 42 planes on the uneven per-wavelength grids 3584..4096
 (bytes-weighted); the whole Lyot coronagraph train with two DMs, PSF and gradient (the rest of
 the hot path: MFTs, PSF accumulation, DM synthesis and adjoint) as a secondary figure; the
-direct and exact-transfer-function steps; the float64 MFT; a device-copy ceiling.
+direct and exact-transfer-function steps (the exact one also batched); the App. B relay analogue
+at 4096^2; the float64 Fresnel plane and MFT; a device-copy ceiling.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
+                [--save-tune FILE | --tune-file FILE] [--copy-calibration]
 Prints one JSON line.
 """
 
