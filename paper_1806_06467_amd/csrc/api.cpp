@@ -490,8 +490,9 @@ static int group_end(const PlaneArgs *args, int count, int i, int cap, int plane
 
 // Planes whose edge has a register-resident power-of-two plan go through the two-sweep kernels,
 // those of one edge together; the others (mixed-radix edges) through the persistent mixed-radix
-// kernels, one launch per sweep for each group of planes of any edges. The planes of a batch are
-// independent, so their order across the two paths does not matter.
+// kernels, one launch per sweep for each group of planes, the planes ordered by edge so that a
+// group of one edge can take that edge's compile-time plan. The planes of a batch are
+// independent, so their order across the paths does not matter.
 int run_planes(Ctx *ctx, PlaneArgs *args, int count, hipStream_t s) {
   std::vector<PlaneArgs> rest;
   std::map<int, std::vector<PlaneArgs>> pow2;
@@ -501,6 +502,7 @@ int run_planes(Ctx *ctx, PlaneArgs *args, int count, hipStream_t s) {
     else
       rest.push_back(args[i]);
   }
+  std::stable_sort(rest.begin(), rest.end(), [](const PlaneArgs &a, const PlaneArgs &b) { return a.n < b.n; });
   for (auto &[n, v] : pow2) {
     const float2 *root;
     int st = ctx->twiddles(n, s, &root);
@@ -526,7 +528,7 @@ int run_planes(Ctx *ctx, PlaneArgs *args, int count, hipStream_t s) {
       if (st != FR_OK) return st;
       b.p[k].pa = rest[i + k];
     }
-    hipError_t e = launch_mr_batch(b, ctx->cus * ctx->mr_rows_per_cu, ctx->cus * ctx->mr_cols_per_cu, s, ctx->hook());
+    hipError_t e = launch_mr_batch(b, ctx->mr_rows_per_cu, ctx->mr_cols_per_cu, ctx->cus, s, ctx->hook());
     if (e != hipSuccess) return record_hip(e);
     i = j;
   }
@@ -559,7 +561,7 @@ int fr_create(fr_ctx **ctx, int device) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->cus = cus;
-  fr::mr_resident(&c->mr_rows_per_cu, &c->mr_cols_per_cu);
+  fr::mr_resident(c->mr_rows_per_cu, c->mr_cols_per_cu);
   *ctx = reinterpret_cast<fr_ctx *>(c);
   return FR_OK;
 }

@@ -114,7 +114,7 @@ int tune_fresnel(Ctx *ctx, int n, hipStream_t s) {
     st = ctx->mr(n, s, &b.p[0], plans[c]);
     if (st != FR_OK) return st;
     b.p[0].pa = pa;
-    const float ms = time_min(s, [&] { return launch_mr_batch(b, ctx->cus * ctx->mr_rows_per_cu, ctx->cus * ctx->mr_cols_per_cu, s, none); });
+    const float ms = time_min(s, [&] { return launch_mr_batch(b, ctx->mr_rows_per_cu, ctx->mr_cols_per_cu, ctx->cus, s, none); });
     if (ms < 0.f) return record_hip(hipGetLastError());
     if (best_ms < 0.f || ms < best_ms) {
       best_ms = ms;

@@ -100,6 +100,74 @@ __device__ __forceinline__ void mr_fft(c32 *lds, int n, int npass, unsigned plan
   }
 }
 
+// The same passes with the line length, the radices and the spans known at compile time (the
+// plans of the broadband grids): no runtime radix switch, divisions by constants, no bounds
+// checks where the butterflies fill the threads. Same twiddle table layout as mr_fft's for the
+// same radix order, same arithmetic per butterfly.
+template <int N, int R, int P, bool INV, int T>
+__device__ __forceinline__ void mr_pass_ct(c32 *lds, const float2 *__restrict__ tw, int t,
+                                           const float2 *__restrict__ h, bool hconj) {
+  constexpr int NR = N / R;
+  constexpr int NB = (NR + T - 1) / T;
+  c32 u[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = t + i * T;
+    if (NR % T == 0 || b < NR) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = b + r * NR;
+        c32 x = lds[lds_pad(e)];
+        if (h) x = hconj ? cmulc(x, c32{h[e].x, h[e].y}) : cmul(x, c32{h[e].x, h[e].y});
+        u[i][r] = x;
+      }
+      if constexpr (P > 1) {
+        const int k = b % P;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float2 q = tw[(r - 1) * P + k];
+          u[i][r] = INV ? cmulc(u[i][r], c32{q.x, q.y}) : cmul(u[i][r], c32{q.x, q.y});
+        }
+      }
+      DftDir<R, INV>::run(u[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = t + i * T;
+    if (NR % T == 0 || b < NR) {
+      const int base = (b / P) * (P * R) + (b % P);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lds_pad(base + r * P)] = u[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <bool INV, int T, int N, int P, int R, int... Rest>
+__device__ __forceinline__ void mr_fft_ct(c32 *lds, const float2 *tw, int t, const float2 *h, bool hconj) {
+  mr_pass_ct<N, R, P, INV, T>(lds, tw, t, h, hconj);
+  if constexpr (sizeof...(Rest) > 0)
+    mr_fft_ct<INV, T, N, P * R, Rest...>(lds, tw + (P > 1 ? (R - 1) * P : 0), t, nullptr, false);
+}
+
+// a compile-time plan: edge N, radices Rs in pass order
+template <int N_, int... Rs>
+struct MrCt {
+  static constexpr int N = N_;
+  static constexpr unsigned packed() {
+    unsigned p = 0;
+    int s = 0;
+    for (int r : {Rs...}) p |= unsigned(r) << (5 * s++);
+    return p;
+  }
+  template <bool INV, int T>
+  __device__ __forceinline__ static void fft(c32 *lds, const float2 *tw, int t, const float2 *h, bool hconj) {
+    mr_fft_ct<INV, T, N_, 1, Rs...>(lds, tw, t, h, hconj);
+  }
+};
+
 // Host side. Greedy radix plan of an n-point line: the largest supported radix that divides
 // what is left, at most maxpass passes; false if n does not factor that way.
 inline bool mr_plan_build(int n, int maxn, int maxpass, int *npass, int *radix) {

@@ -94,13 +94,16 @@ int mr_plan_orders(int n, int max, unsigned *plans, int *npass);
 unsigned mr_pack(int npass, const int *radix);
 int mr_twiddle_count(int npass, const int *radix);
 void mr_twiddle_build(int npass, const int *radix, float2 *out);  // host
-// rows then columns for forward planes, columns then rows for adjoint planes; persistent
-// grids of at most blocks_rows / blocks_cols blocks
-hipError_t launch_mr_batch(const MrBatch &all, int blocks_rows, int blocks_cols, hipStream_t s,
-                           const LaunchHook &hook);
-// blocks of the two persistent sweeps that one compute unit holds at once (their grids hold that
-// many per unit, so no block waits for a slot while others loop); a device query, made at
-// context creation
+// rows then columns for forward planes, columns then rows for adjoint planes; persistent grids
+// of cus x the resident blocks per compute unit of the instance that runs them (a compile-time
+// plan when every plane has the same edge and one of the broadband grids' plans, else the
+// runtime plan)
+hipError_t launch_mr_batch(const MrBatch &all, const int *rows_per_cu, const int *cols_per_cu, int cus,
+                           hipStream_t s, const LaunchHook &hook);
+// blocks of each instance of the two persistent sweeps that one compute unit holds at once
+// (index 0 the runtime plan, then the compile-time plans); a device query, made at context
+// creation
+constexpr int kMrPolicies = 8;
 void mr_resident(int *rows_per_cu, int *cols_per_cu);
 
 // ---- MFT: out = alpha * c * A in B^T (+ beta * out) (* mask), complex, FP32 MFMA ------

@@ -29,7 +29,8 @@ using TableKey = std::tuple<int, int, uint64_t, uint64_t, uint64_t, uint64_t>;
 struct Ctx {
   int device = 0;
   int cus = 256;  // compute units of the device
-  int mr_rows_per_cu = 2, mr_cols_per_cu = 1;  // resident blocks of the mixed-radix sweeps
+  // resident blocks per compute unit of the mixed-radix sweep instances (mr_resident)
+  int mr_rows_per_cu[kMrPolicies] = {2, 2, 2, 2, 2, 2, 2, 2}, mr_cols_per_cu[kMrPolicies] = {1, 1, 1, 1, 1, 1, 1, 1};
   std::map<TableKey, void *> tables;
   size_t max_tables = 4096;  // fr_set_cache_limit
   // start of an entry point that may fetch tables (before the first fetch): trims the cache

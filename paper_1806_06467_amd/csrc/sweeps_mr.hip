@@ -13,6 +13,9 @@
 // All global accesses use raw buffer instructions with a per-lane offset clamped inside the
 // array, so every access is range-checked by the hardware.
 #include <algorithm>
+#include <tuple>
+#include <type_traits>
+#include <utility>
 
 #include "fft_mr.hpp"
 #include "fr_internal.h"
@@ -101,9 +104,18 @@ __device__ __forceinline__ bool mr_has_pre(const PlaneArgs &pa) {
   return pa.amp || pa.opd || pa.pre_surf || pa.lens;
 }
 
-template <bool INV>
+// The plan policy of a sweep instance: MrRuntime takes each plane's packed plan (any edge),
+// MrCt<N, Rs...> one compile-time plan (every plane of the launch has edge N and that plan).
+struct MrRuntime {
+  static constexpr int N = 0;
+};
+
+template <class F, bool INV>
 __device__ __forceinline__ void plane_fft(c32 *lds, const MrPlane &mp, int t, const float2 *h, bool hconj) {
-  mr_fft<INV, kT, kMrMaxN>(lds, mp.n, mp.npass, mp.plan, mp.tw, t, h, hconj);
+  if constexpr (F::N == 0)
+    mr_fft<INV, kT, kMrMaxN>(lds, mp.n, mp.npass, mp.plan, mp.tw, t, h, hconj);
+  else
+    F::template fft<INV, kT>(lds, mp.tw, mr_opaque(t), h, hconj);
 }
 
 // The batch is the kernel's only argument, so it sits at offset 0 of the kernel-argument
@@ -150,6 +162,7 @@ __device__ __forceinline__ void apply_pre(c32 (&v)[kEM], const PlaneArgs &pa, in
   }
 }
 
+template <class F>
 __global__ void __launch_bounds__(kT) mr_row_sweep(MrBatch) {
   const MrBatch &args = kernarg_batch();
   __shared__ c32 lds[LdsLine<kMrMaxN>::size];
@@ -160,7 +173,7 @@ __global__ void __launch_bounds__(kT) mr_row_sweep(MrBatch) {
     if (item < args.total) {
       const MrPlane &mp = args.p[mr_find(args, item)];
       const PlaneArgs &pa = mp.pa;
-      const int n = mp.n, y = item - mp.first;
+      const int n = F::N ? F::N : mp.n, y = item - mp.first;
       const int t = mr_opaque(t0);
       const bool adj = pa.flags & FR_ADJOINT;
       const bool source = pa.flags & kSourceOptic;
@@ -179,8 +192,8 @@ __global__ void __launch_bounds__(kT) mr_row_sweep(MrBatch) {
       for (int m = 0; m < kEM; ++m)
         if (t + kT * m < n) lds[lds_pad(t + kT * m)] = v[m];
       __syncthreads();
-      plane_fft<false>(lds, mp, t, nullptr, false);
-      plane_fft<true>(lds, mp, t, pa.h, adj);
+      plane_fft<F, false>(lds, mp, t, nullptr, false);
+      plane_fft<F, true>(lds, mp, t, pa.h, adj);
 #pragma unroll
       for (int m = 0; m < kEM; ++m) v[m] = lds[lds_pad(min(t + kT * m, n - 1))];
       if (adj && pre) apply_pre<true>(v, pa, n, y, t, false);
@@ -193,6 +206,7 @@ __global__ void __launch_bounds__(kT) mr_row_sweep(MrBatch) {
 }
 
 // 4 adjacent columns per item (32-byte row segments), one line of kT threads per column
+template <class F>
 __global__ void __launch_bounds__(kT * 4) mr_col_sweep(MrBatch) {
   const MrBatch &args = kernarg_batch();
   __shared__ c32 lds[4 * (LdsLine<kMrMaxN>::size + 4)];
@@ -204,7 +218,7 @@ __global__ void __launch_bounds__(kT * 4) mr_col_sweep(MrBatch) {
     if (item < args.total) {
       const MrPlane &mp = args.p[mr_find(args, item)];
       const PlaneArgs &pa = mp.pa;
-      const int n = mp.n;
+      const int n = F::N ? F::N : mp.n;
       const int t = mr_opaque(t0);
       const int x = (item - mp.first) * 4 + c;
       const bool xin = x < n;
@@ -232,8 +246,8 @@ __global__ void __launch_bounds__(kT * 4) mr_col_sweep(MrBatch) {
       for (int m = 0; m < kEM; ++m)
         if (t + kT * m < n) my[lds_pad(t + kT * m)] = v[m];
       __syncthreads();
-      plane_fft<false>(my, mp, t, nullptr, false);
-      plane_fft<true>(my, mp, t, pa.h, adj);
+      plane_fft<F, false>(my, mp, t, nullptr, false);
+      plane_fft<F, true>(my, mp, t, pa.h, adj);
 #pragma unroll
       for (int m = 0; m < kEM; ++m) v[m] = my[lds_pad(min(t + kT * m, n - 1))];
       if (!adj && has_post) {
@@ -283,13 +297,55 @@ int resident_blocks(K kernel, int threads, int fallback) {
   return nb;
 }
 
-void mr_resident(int *rows_per_cu, int *cols_per_cu) {
-  *rows_per_cu = resident_blocks(mr_row_sweep, kT, 2);
-  *cols_per_cu = resident_blocks(mr_col_sweep, 4 * kT, 1);
+// compile-time plans: the greedy plans of the 7-smooth grid edges of a broadband model
+// (3584 ... 4032, Sec. 1.2); other edges and other pass orders take the runtime plan
+using MrCtPlans = std::tuple<MrCt<3584, 16, 16, 14>, MrCt<3600, 16, 15, 15>, MrCt<3840, 16, 16, 15>,
+                             MrCt<3888, 16, 9, 9, 3>, MrCt<3920, 16, 7, 7, 5>, MrCt<4000, 16, 10, 5, 5>,
+                             MrCt<4032, 16, 14, 9, 2>>;
+constexpr int kMrCt = std::tuple_size<MrCtPlans>::value;
+
+// calls f(policy) for the instance that runs planes of edge n with packed plan `plan` (the
+// runtime policy when no compile-time plan matches)
+template <class Fn, int I = 0>
+auto with_mr_policy(int n, unsigned plan, Fn &&f) {
+  if constexpr (I == kMrCt) {
+    return f(MrRuntime{});
+  } else {
+    using P = std::tuple_element_t<I, MrCtPlans>;
+    if (n == P::N && plan == P::packed()) return f(P{});
+    return with_mr_policy<Fn, I + 1>(n, plan, std::forward<Fn>(f));
+  }
 }
 
-hipError_t launch_mr_batch(const MrBatch &all, int blocks_rows, int blocks_cols, hipStream_t s,
-                           const LaunchHook &hook) {
+template <int I = 0>
+void resident_all(int *rows, int *cols) {
+  if constexpr (I <= kMrCt) {
+    using P = std::conditional_t<I == 0, MrRuntime, std::tuple_element_t<(I > 0 ? I - 1 : 0), MrCtPlans>>;
+    rows[I] = resident_blocks(mr_row_sweep<P>, kT, 2);
+    cols[I] = resident_blocks(mr_col_sweep<P>, 4 * kT, 1);
+    resident_all<I + 1>(rows, cols);
+  }
+}
+
+// 0 for the runtime plan, 1 + the index of the matching compile-time plan
+template <int I = 0>
+int mr_policy_index(int n, unsigned plan) {
+  if constexpr (I == kMrCt) {
+    return 0;
+  } else {
+    using P = std::tuple_element_t<I, MrCtPlans>;
+    if (n == P::N && plan == P::packed()) return I + 1;
+    return mr_policy_index<I + 1>(n, plan);
+  }
+}
+
+void mr_resident(int *rows_per_cu, int *cols_per_cu) {
+  static_assert(kMrCt + 1 <= kMrPolicies, "residency table size");
+  resident_all(rows_per_cu, cols_per_cu);
+}
+
+hipError_t launch_mr_batch(const MrBatch &all, const int *rows_per_cu, const int *cols_per_cu, int cus,
+                           hipStream_t s, const LaunchHook &hook) {
   // forward planes: rows then columns; adjoint planes: columns then rows (see the power-of-two
   // sweeps: the optic maps are always read along rows)
   MrBatch fwd, adj;
@@ -315,10 +371,20 @@ hipError_t launch_mr_batch(const MrBatch &all, int blocks_rows, int blocks_cols,
     }
     b.total = acc;
   };
+  // one compile-time instance when every plane of the batch has the same edge and its plan
+  int pol = all.count ? mr_policy_index(all.p[0].n, all.p[0].plan) : 0;
+  for (int i = 1; i < all.count && pol; ++i)
+    if (all.p[i].n != all.p[0].n || all.p[i].plan != all.p[0].plan) pol = 0;
+  const int n0 = pol ? all.p[0].n : 0;
+  const unsigned plan0 = pol ? all.p[0].plan : 0u;
+  const int blocks_rows = cus * rows_per_cu[pol], blocks_cols = cus * cols_per_cu[pol];
   auto rows = [&](MrBatch b, const char *name) {
     rows_list(b);
     hook(s, name, b.count, 0);
-    hipLaunchKernelGGL(mr_row_sweep, dim3(std::max(1, std::min(blocks_rows, b.total))), dim3(kT), 0, s, b);
+    with_mr_policy(n0, plan0, [&](auto p) {
+      hipLaunchKernelGGL((mr_row_sweep<decltype(p)>), dim3(std::max(1, std::min(blocks_rows, b.total))), dim3(kT),
+                         0, s, b);
+    });
     hipError_t e = hipGetLastError();
     hook(s, name, b.count, 1);
     return e;
@@ -326,7 +392,10 @@ hipError_t launch_mr_batch(const MrBatch &all, int blocks_rows, int blocks_cols,
   auto cols = [&](MrBatch b, const char *name) {
     cols_list(b);
     hook(s, name, b.count, 0);
-    hipLaunchKernelGGL(mr_col_sweep, dim3(std::max(1, std::min(blocks_cols, b.total))), dim3(4 * kT), 0, s, b);
+    with_mr_policy(n0, plan0, [&](auto p) {
+      hipLaunchKernelGGL((mr_col_sweep<decltype(p)>), dim3(std::max(1, std::min(blocks_cols, b.total))),
+                         dim3(4 * kT), 0, s, b);
+    });
     hipError_t e = hipGetLastError();
     hook(s, name, b.count, 1);
     return e;

@@ -206,9 +206,10 @@ def test_mixed_radix_step_matches_oracle(n, adjoint):
 
 
 # the padded per-wavelength grids of the broadband workload (radix plans 16.16.14, 16.15.15,
-# 16.9.9.3, 16.7.7.5, 16.10.5.5, 16.14.9.2), forward and adjoint spread over the set
-@pytest.mark.parametrize("n,adjoint", [(3584, False), (3600, True), (3888, False), (3920, True),
-                                       (4000, False), (4032, True)])
+# 16.16.15, 16.9.9.3, 16.7.7.5, 16.10.5.5, 16.14.9.2: the compile-time instances of the
+# mixed-radix sweeps), forward and adjoint spread over the set
+@pytest.mark.parametrize("n,adjoint", [(3584, False), (3600, True), (3840, False), (3888, False), (3920, True),
+                                       (4000, False), (4032, True), (3840, True)])
 def test_broadband_grid_step_matches_oracle(n, adjoint):
     banner(f"fresnel_step broadband grid n={n} adjoint={adjoint} (oracle takes a few seconds)")
     field, amp, opd, dx, lam, z, f = _case(n, n + adjoint)
@@ -433,3 +434,23 @@ def test_fresnel_step_8192_plane_waves_closed_form(adjoint):
     got = to_np(t)
     del t
     assert rel_l2(got, ref) <= TOL
+
+
+def test_broadband_grid_runtime_plan_matches_compile_time_plan(tmp_path):
+    """A broadband grid edge under another pass order (a tuning file's `plan` line) runs the
+    runtime-planned sweeps instead of the compile-time instance: both against the oracle."""
+    n = 3600
+    banner("mixed-radix n=3600: compile-time plan 16.15.15 vs runtime plan 15.16.15")
+    field, amp, opd, dx, lam, z, f = _case(n, 77)
+    ref = oracle.fresnel_step(f32(field), dx, lam, z, amp=f32(amp), opd=f32(opd), lens_focal=f)
+    got_ct = _run_gpu(field, amp, opd, dx, lam, z, f, False)
+    path = tmp_path / "tune.txt"
+    path.write_text("plan 3600 %d\n" % (15 | (16 << 5) | (15 << 10)))
+    fb.autotune_load(str(path))
+    try:
+        got_rt = _run_gpu(field, amp, opd, dx, lam, z, f, False)
+    finally:
+        path.write_text("plan 3600 %d\n" % (16 | (15 << 5) | (15 << 10)))
+        fb.autotune_load(str(path))
+    assert rel_l2(got_ct, ref) <= TOL
+    assert rel_l2(got_rt, ref) <= TOL
