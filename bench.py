@@ -55,16 +55,16 @@ METRIC = "Fresnel planes/sec at 4096^2 c64 (fwd+adjoint, batched vs plain), %HBM
 # 128 MiB plane in the same runs (FETCH x 2.0, WRITE x 1.0). Each entry carries the SHA-256 of the
 # sources it was measured on and reads as unknown (null) once they change.
 MEASURED_TRAFFIC = {
-    "row_sweep": (269226249, 134217728),
-    "col_sweep": (136670558, 162994189),
-    "col_sweep_adj": (136681753, 150908683),
-    "row_sweep_adj": (269251713, 134217728),
+    "row_sweep": (269226328, 134217728),
+    "col_sweep": (136708966, 163001667),
+    "col_sweep_adj": (136683773, 150807363),
+    "row_sweep_adj": (269242740, 134217728),
 }
 _SWEEP_SOURCES = {
     "paper_1806_06467_amd/csrc/sweeps.hip": "f440ccc9622d739c8ab4f89a7f0bf1947ef47dc43a759800ee6075639881e8bb",
     "paper_1806_06467_amd/csrc/fft_line.hpp": "66f504dc38f9cb71c51b0dd9e259e966acb90c9d9d1b256d8d7ca415edac6fae",
     "paper_1806_06467_amd/csrc/dft_small.hpp": "f079518edd36aa105b5a40ce60935e1cdb8f3c06c3c59d0fa46a65eea89b7209",
-    "paper_1806_06467_amd/csrc/fr_internal.h": "82b876eca30f282551467af7da66a055c94d466ca7982c57b9856e331faadb45",
+    "paper_1806_06467_amd/csrc/fr_internal.h": "ad79674c34a8ddf721ff1f60bdf40c721889be1f2928717a95019b9fe14101bb",
 }
 TRAFFIC_SOURCES = {k: _SWEEP_SOURCES for k in MEASURED_TRAFFIC}
 
