@@ -365,6 +365,7 @@ def main():
     if not args.no_extras:
         # ---- the whole coronagraph train (secondary): two DMs, PSF + gradient, 21 wavelengths --
         result_extra["train_step"] = train_step(args, fb, synth, np, torch, dev, timed, profiled, lams)
+        result_extra["train_8192"] = train_8192(fb, synth, np, torch, dev, timed)
         # ---- the direct and exact-transfer-function steps, one plane per call ------------------
         z_dir = 2.0 * N * DX * DX / min(lams)
 
@@ -583,6 +584,56 @@ def train_step(args, fb, synth, np, torch, dev, timed, profiled, lams):
                                            "(per wavelength the last-DM plane and the detector field)"},
             "kernels_ms_per_step": top, "gemm_rooflines": gemms,
             "checksum_psf_sum": float(psf.sum())}
+
+
+def train_8192(fb, synth, np, torch, dev, timed):
+    """The large batched forward + adjoint: a 2048 px pupil (pitch 12.5 um) padded 4x to 8192^2
+    (512 MiB per plane), two 64 x 64-actuator DMs 1 m apart, 8 wavelengths over 500-600 nm, the
+    occulter, Lyot stop and detector of the 4096^2 train; the PSF and the gradient of the mean
+    dark-hole contrast with respect to the 8192 actuators, batched + graph, plain, and in two
+    calls through the caller's checkpoint (forward save, then backward)."""
+    nd, n, nl, na = 2048, 8192, 8, 64
+    # tuned (untimed) for its own shapes: the 8192 sweeps and the MFT GEMMs of its planes
+    t0 = time.perf_counter()
+    fb.autotune_fresnel(n)
+    for n_, m_ in ((n, OCC_M), (nd, OCC_M), (nd, DET_M)):
+        fb.autotune_mft(n_, m_)
+    t_tune = time.perf_counter() - t0
+
+    def f(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    pupil = synth.pupil_amplitude(nd, 0.1, 0.01)
+    tr = fb.Train(nd, nd * 12.5e-6, Z, f(pupil), f(synth.lyot_stop(nd, 0.9)),
+                  f(synth.occulter_spot(OCC_M, OCC_DU, 3.0)), OCC_DU, DET_M, DET_DU, LAMBDA_C,
+                  f(synth.power_law_opd(nd, pupil, 10e-9, -3.0, 0)), n_act=na, n_dm=2)
+    lams8 = [float(x) for x in synth.wavelengths(nl)]
+    ns, w = [n] * nl, [1.0 / nl] * nl
+    hg = f(np.stack([synth.dm_heights(na, 1 + k) for k in range(2)]))
+    dh = synth.dark_hole(DET_M, DET_DU, 3.0, 10.0)
+    g_psf = f(dh / dh.sum())
+    psf = torch.empty((DET_M, DET_M), dtype=torch.float32, device=dev)
+    gh = torch.empty_like(hg)
+    ck = torch.empty(fb.train_ckpt_bytes(tr, ns), dtype=torch.uint8, device=dev)
+
+    def batched():
+        fb.propagate_train(tr, lams8, ns, w, hg, grad_psf=g_psf, batched=True, graph=True, out=psf, grad_out=gh)
+
+    def plain():
+        fb.propagate_train(tr, lams8, ns, w, hg, grad_psf=g_psf, out=psf, grad_out=gh)
+
+    def two_calls():
+        fb.propagate_train(tr, lams8, ns, w, hg, batched=True, out=psf, ckpt=ck, phase="save")
+        fb.propagate_train(tr, lams8, ns, w, hg, grad_psf=g_psf, batched=True, grad_out=gh, ckpt=ck,
+                           phase="backward")
+    ms_b = timed(batched, 2, 1) / 2
+    ms_p = timed(plain, 1, 1)
+    ms_two = timed(two_calls, 1, 1)
+    del ck
+    planes = 2 * nl
+    return {"workload": "lyot_train_8192_8lambda_2dm_64act_psf_and_gradient", "fresnel_planes_per_step": planes,
+            "batched_graph": {"ms_per_step": ms_b, "fresnel_planes_per_s": planes / (ms_b * 1e-3)},
+            "plain": {"ms_per_step": ms_p, "fresnel_planes_per_s": planes / (ms_p * 1e-3)},
+            "checkpointed_two_calls_ms": ms_two, "autotune_seconds": t_tune, "checksum_psf_sum": float(psf.sum())}
 
 
 if __name__ == "__main__":
