@@ -66,8 +66,11 @@ typedef struct {
   double re, im;
 } fr_c128;
 
-/* Create a context bound to HIP device `device`. *ctx receives the handle. */
-int fr_create(fr_ctx **ctx, int device);
+/* Create a context bound to HIP device `device`. *ctx receives the handle. autotune_path, when
+ * not NULL, names a tuning file (fr_autotune_save's format) whose choices the context takes at
+ * once, as fr_autotune_load would; a file it cannot read or parse fails the call (FR_EINVAL,
+ * *ctx left NULL). */
+int fr_create(fr_ctx **ctx, int device, const char *autotune_path);
 /* Free every cached table and the context (synchronises the device). NULL is accepted. */
 int fr_destroy(fr_ctx *ctx);
 /* Bound of the context's table cache (default 4096 tables; max_tables >= 1, else FR_EINVAL).

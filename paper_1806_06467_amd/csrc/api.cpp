@@ -544,7 +544,7 @@ using fr::Ctx;
 
 extern "C" {
 
-int fr_create(fr_ctx **ctx, int device) {
+int fr_create(fr_ctx **ctx, int device, const char *autotune_path) {
   if (!ctx) return FR_EINVAL;
   *ctx = nullptr;
   int ndev = 0;
@@ -562,6 +562,13 @@ int fr_create(fr_ctx **ctx, int device) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->cus = cus;
   fr::mr_resident(c->mr_rows_per_cu, c->mr_cols_per_cu);
+  if (autotune_path) {
+    const int st = fr_autotune_load(reinterpret_cast<fr_ctx *>(c), autotune_path);
+    if (st != FR_OK) {
+      delete c;
+      return st;
+    }
+  }
   *ctx = reinterpret_cast<fr_ctx *>(c);
   return FR_OK;
 }

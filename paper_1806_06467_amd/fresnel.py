@@ -85,7 +85,7 @@ def lib():
         L = _c.CDLL(LIB_PATH)
         i32, f64, f32, sz = _c.c_int32, _c.c_double, _c.c_float, _c.c_size_t
         sig = {
-            "fr_create": (_c.c_int, [_c.POINTER(_vp), _c.c_int]),
+            "fr_create": (_c.c_int, [_c.POINTER(_vp), _c.c_int, _c.c_char_p]),
             "fr_destroy": (_c.c_int, [_vp]),
             "fr_set_cache_limit": (_c.c_int, [_vp, i32]),
             "fr_status_string": (_c.c_char_p, [_c.c_int]),
@@ -152,10 +152,11 @@ def _check(status, where):
 class Context:
     """An fr_ctx bound to one HIP device (owns the cached float64-built tables)."""
 
-    def __init__(self, device=0):
+    def __init__(self, device=0, tune_file=None):
         self.device = int(device)
         h = _vp()
-        _check(lib().fr_create(_c.byref(h), self.device), "fr_create")
+        path = None if tune_file is None else os.fsencode(tune_file)
+        _check(lib().fr_create(_c.byref(h), self.device, path), "fr_create")
         self.handle = h
 
     def close(self):

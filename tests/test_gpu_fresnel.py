@@ -454,3 +454,19 @@ def test_broadband_grid_runtime_plan_matches_compile_time_plan(tmp_path):
         fb.autotune_load(str(path))
     assert rel_l2(got_ct, ref) <= TOL
     assert rel_l2(got_rt, ref) <= TOL
+
+
+def test_context_created_with_a_tuning_file(tmp_path):
+    """fr_create takes a tuning file: a valid one is applied at creation, a malformed one fails
+    the call (FR_EINVAL) and leaves no context."""
+    banner("fr_create with a tuning file")
+    good = tmp_path / "good.txt"
+    good.write_text("sweep 4096 1 0\nplan 3600 %d\n" % (16 | (15 << 5) | (15 << 10)))
+    ctx = fb.Context(0, tune_file=str(good))
+    assert ctx.handle
+    ctx.close()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("sweep 4096 99 0\n")
+    with pytest.raises(fb.FrError) as err:
+        fb.Context(0, tune_file=str(bad))
+    assert err.value.status == fb.FR_EINVAL

@@ -153,6 +153,10 @@ def test_batched_argument_errors(L):
         assert fn(null, bad, 1, null) == fb.FR_EUNSUPPORTED
 
 
+def test_create_argument_errors(L):
+    assert L.fr_create(None, 0, None) == fb.FR_EINVAL     # no handle to fill
+
+
 def test_exact_batched_argument_errors(L):
     null = ctypes.c_void_p()
     fn = L.fresnel_step_exact_batched
