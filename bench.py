@@ -158,9 +158,9 @@ def main():
                          "134217728 B written) so HBM byte counters can be scaled")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X (the wavelength "
-              "sharding over several GPUs is a design note, not a run); use --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library runs on a single MI355X (sharding the "
+              "wavelengths over several GPUs is described in the design notes, not implemented); "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
