@@ -27,8 +27,14 @@ struct LaunchHook {
 // window amp is 0 when given. pre_surf is an n x n surface map [m], row-major; post_surf is the
 // same kind of map stored in 4-column tiles (post_tiled_index) so that the column sweep, which
 // applies it, reads it contiguously.
+// A forward plane with a windowed amplitude (win < n) has zero rows outside the window after
+// the optic; the power-of-two sweeps neither store them (row sweep) nor load them (column sweep).
 constexpr int kSourceOptic = 2;  // forward only: the input field is 1 (it is not read)
 constexpr int kTowardSource = 4;  // direct step over z < 0: the transforms' kernel sign flips
+// adjoint planes: only the centred win rows of the output are needed (the others are left
+// unspecified): the power-of-two column sweep, which runs first, stores only those rows, and
+// the row sweep skips the blocks whose rows all lie outside them
+constexpr int kWindowRowsOnly = 8;
 struct PlaneArgs {
   float2 *field;             // n x n, in place
   const float *amp;          // win x win or null
@@ -40,7 +46,7 @@ struct PlaneArgs {
   float inv_lambda;          // 1 / lambda [1/m]
   int n;                     // plane edge
   int win;                   // window edge of amp / opd (n for full maps)
-  int flags;                 // FR_ADJOINT | kSourceOptic | kTowardSource
+  int flags;                 // FR_ADJOINT | kSourceOptic | kTowardSource | kWindowRowsOnly
 };
 
 // element (y, x) of an n x n map stored in 4-column tiles: tile x/4 holds rows 0..n-1 of its

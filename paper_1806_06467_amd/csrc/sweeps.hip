@@ -188,6 +188,11 @@ row_sweep(BatchArgs args, const float2 *tw) {
   const int t = threadIdx.x - line * T;
   const int y = blockIdx.x * LINES + line;
   const bool adj = pa.flags & FR_ADJOINT;
+  if (adj && (pa.flags & kWindowRowsOnly)) {
+    // rows of this block all outside the rows wanted from the step (block-uniform)
+    const int y0 = blockIdx.x * LINES, off = (N - pa.win) >> 1;
+    if (y0 + LINES <= off || y0 >= off + pa.win) return;
+  }
   const PlaneBuf buf(pa.field, unsigned(N) * N * 8u);
   const unsigned vo = unsigned(y * N + t) * 8u;
   c32 v[E];
@@ -195,12 +200,10 @@ row_sweep(BatchArgs args, const float2 *tw) {
     c32 ph[E];
     const bool nonzero = pre_optic_row<E, T>(pa, N, y, t, ph);
     if constexpr (LINES == 1) {
-      // a whole row outside the pupil stays zero through the row transform (block-uniform)
-      if (!nonzero) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * 8u, c32{0.0f, 0.0f});
-        return;
-      }
+      // a whole row outside the amplitude window stays zero through the row transform
+      // (block-uniform); the column sweep takes it as zero without reading it, so it is not
+      // stored
+      if (!nonzero) return;
     }
     if (!nonzero) {
 #pragma unroll
@@ -269,8 +272,19 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   const PlaneBuf buf(pa.field, unsigned(N) * N * 8u);
   const unsigned vo = unsigned(t * N + x) * 8u;
   c32 v[E];
+  if (!adj && pa.amp && pa.win < N) {
+    // forward plane with a windowed amplitude: the rows outside the window are zero after the
+    // row sweep, which did not store them (uniform over a wavefront when the window edges are
+    // multiples of the wavefront's rows)
+    const int off = (N - pa.win) >> 1;
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = buf.load(vo, unsigned(T * m) * unsigned(N) * 8u);
+    for (int m = 0; m < E; ++m)
+      v[m] = unsigned(t + T * m - off) < unsigned(pa.win) ? buf.load(vo, unsigned(T * m) * unsigned(N) * 8u)
+                                                         : c32{0.0f, 0.0f};
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = buf.load(vo, unsigned(T * m) * unsigned(N) * 8u);
+  }
   if (adj && pa.post_surf) {
     c32 ph[E];
     post_optic_col<E, T>(pa, N, t, x, ph);
@@ -345,8 +359,16 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = cmul(v[m], ph[m]);
   }
+  if (adj && (pa.flags & kWindowRowsOnly)) {
+    // the row sweep that follows transforms only the rows of the window
+    const int off = (N - pa.win) >> 1;
 #pragma unroll
-  for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
+    for (int m = 0; m < E; ++m)
+      if (unsigned(t + T * m - off) < unsigned(pa.win)) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
+  }
 }
 
 // Forward planes run the row sweep first (optic prologue on contiguous rows) and the column

@@ -213,10 +213,13 @@ struct GradChunk {
 // multiplies actuator tile w & 1 over chunk columns [32 (w >> 1), 32 (w >> 1) + 32) with
 // v_mfma_f32_32x32x2f32, accumulating in float32 across the group's chunks; the two column
 // halves are added at the end. The next chunk's loads are issued before this chunk's products.
+// Only rows [row0, row1) and columns [col0, col1) are visited (g_s is zero elsewhere: the
+// pupil optic's amplitude window); T rows outside are not written.
 template <bool SYNTH>
 __global__ void __launch_bounds__(256) dm_grad_T(const float2 *E, const float2 *B, const float *G, int n, int na,
                                                  float kappa, const float *amp, const float *opd, int nd,
-                                                 const float *pre, float inv_lambda, float *tpart) {
+                                                 const float *pre, float inv_lambda, int row0, int row1,
+                                                 int col0, int col1, float *tpart) {
   // g_s [column][row] and G [column][actuator] per chunk; after the last chunk the same memory
   // holds the column-half sums
   __shared__ union {
@@ -230,9 +233,9 @@ __global__ void __launch_bounds__(256) dm_grad_T(const float2 *E, const float2 *
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int tile = w & 1, half = w >> 1;
-  const int i0 = blockIdx.x * kRows;
+  const int i0 = row0 + blockIdx.x * kRows;
   const int g = blockIdx.y;
-  const int jbeg = g * kGroup, jend = min(n, jbeg + kGroup);
+  const int jbeg = col0 + g * kGroup, jend = min(col1, jbeg + kGroup);
   const int off = (n - nd) / 2;
   floatx16 acc = floatx16{0.f};
   Chunk cur;
@@ -245,7 +248,7 @@ __global__ void __launch_bounds__(256) dm_grad_T(const float2 *E, const float2 *
       const int r = (tid >> 6) + 4 * q;
       const int i = i0 + r, j = j0 + c;
       float2 e2 = cur.ev[q];
-      bool in = i < n && c < cj;
+      bool in = i < row1 && c < cj;
       if constexpr (SYNTH) {
         const bool win = unsigned(i - off) < unsigned(nd) && unsigned(j - off) < unsigned(nd);
         float sn, cs;
@@ -288,16 +291,18 @@ __global__ void __launch_bounds__(256) dm_grad_T(const float2 *E, const float2 *
     for (int r = 0; r < 16; ++r) {
       const int row = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
       const int i = i0 + row, a = tile * 32 + (lane & 31);
-      if (i < n && a < na) tpart[(size_t(g) * n + i) * na + a] = acc[r] + sm.red[tile][row][lane & 31];
+      if (i < row1 && a < na) tpart[(size_t(g) * n + i) * na + a] = acc[r] + sm.red[tile][row][lane & 31];
     }
   }
 }
 
-// T_sum[e] += sum over groups of tpart[group][e], in group order
-__global__ void __launch_bounds__(256) dm_grad_acc(const float *tpart, int groups, int total, float *tsum) {
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+// T_sum[e] += sum over groups of tpart[group][e] (groups `stride` floats apart), in group
+// order, for e < count
+__global__ void __launch_bounds__(256) dm_grad_acc(const float *tpart, int groups, int count, size_t stride,
+                                                   float *tsum) {
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < count; e += gridDim.x * 256) {
     float v = 0.f;
-    for (int q = 0; q < groups; ++q) v += tpart[size_t(q) * total + e];
+    for (int q = 0; q < groups; ++q) v += tpart[size_t(q) * stride + e];
     tsum[e] += v;
   }
 }
@@ -622,8 +627,9 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     pb->n = n;
     pb->post_surf = surf_of(j) + size_t(ndm - 1) * surf_stride(n);
     pb->inv_lambda = float(1.0 / lam[j]);
-    pb->win = n;
-    pb->flags = FR_ADJOINT;
+    // B1 is read only inside the pupil window (the pupil DM's gradient)
+    pb->win = nd;
+    pb->flags = FR_ADJOINT | kWindowRowsOnly;
     return ctx->transfer(n, dx, lam[j], d->z_m, s, &pb->h);
   };
 
@@ -683,7 +689,9 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     const int n = n_pad[j];
     const float *G = nullptr;
     FR_TRY(ctx->dm_influence(n, nd, na, s, &G));
-    const int strips = (n + kRows - 1) / kRows, groups = (n + kGroup - 1) / kGroup;
+    // the pupil optic (E == null) is zero outside its nd x nd window, and so is g_s there
+    const int lo = E ? 0 : (n - nd) / 2, hi = E ? n : lo + nd;
+    const int strips = (hi - lo + kRows - 1) / kRows, groups = (hi - lo + kGroup - 1) / kGroup;
     const int tn = n * na;
     float *T = TSUM + size_t(k) * nmax * na;
     if (sum_n[k] != n) {
@@ -696,13 +704,16 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     hook(s, tname, n, 0);
     if (E)
       hipLaunchKernelGGL(dm_grad_T<false>, dim3(strips, groups), dim3(256), 0, s, E, B, G, n, na, kappa,
-                         d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), TPART);
+                         d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), lo, hi, lo, hi, TPART);
     else
       hipLaunchKernelGGL(dm_grad_T<true>, dim3(strips, groups), dim3(256), 0, s, E, B, G, n, na, kappa,
-                         d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), TPART);
+                         d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), lo, hi, lo, hi, TPART);
     FR_TRY_HIP(hipGetLastError());
     hook(s, tname, n, 1);
-    FR_TRY_HIP(launch1d(dm_grad_acc, size_t(tn), s, hook, "dm_grad_acc", (const float *)TPART, groups, tn, T));
+    // T rows outside [lo, hi) keep what they hold (zero from the fill, for this DM's pupil sums)
+    FR_TRY_HIP(launch1d(dm_grad_acc, size_t(hi - lo) * na, s, hook, "dm_grad_acc",
+                        (const float *)(TPART + size_t(lo) * na), groups, (hi - lo) * na, size_t(tn),
+                        T + size_t(lo) * na));
     return FR_OK;
   };
 
