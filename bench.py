@@ -152,7 +152,9 @@ def main():
     ap.add_argument("--tune-file", default=None,
                     help="load tuned kernel choices from this file (written by --save-tune) instead "
                          "of running the autotuner, so that repeated runs launch the same kernels")
-    ap.add_argument("--save-tune", default=None, help="write the tuned kernel choices to this file")
+    ap.add_argument("--save-tune", default=None,
+                    help="write the tuned kernel choices to this file (at the end of the run, so that "
+                         "the 8192^2 train's own choices are in it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of one 4096^2 c64 plane (134217728 B read, "
                          "134217728 B written) so HBM byte counters can be scaled")
@@ -365,7 +367,7 @@ def main():
     if not args.no_extras:
         # ---- the whole coronagraph train (secondary): two DMs, PSF + gradient, 21 wavelengths --
         result_extra["train_step"] = train_step(args, fb, synth, np, torch, dev, timed, profiled, lams)
-        result_extra["train_8192"] = train_8192(fb, synth, np, torch, dev, timed)
+        result_extra["train_8192"] = train_8192(fb, synth, np, torch, dev, timed, not args.tune_file)
         # ---- the direct and exact-transfer-function steps, one plane per call ------------------
         z_dir = 2.0 * N * DX * DX / min(lams)
 
@@ -498,6 +500,8 @@ def main():
     }
     result.update(result_extra)
     result["autotuned"] = {"choices": tuned, "seconds": t_tune, "loaded_from_file": bool(args.tune_file)}
+    if args.save_tune:
+        fb.autotune_save(args.save_tune)
     result["wall_s"] = t_wall
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(np)
@@ -586,18 +590,20 @@ def train_step(args, fb, synth, np, torch, dev, timed, profiled, lams):
             "checksum_psf_sum": float(psf.sum())}
 
 
-def train_8192(fb, synth, np, torch, dev, timed):
+def train_8192(fb, synth, np, torch, dev, timed, tune=True):
     """The large batched forward + adjoint: a 2048 px pupil (pitch 12.5 um) padded 4x to 8192^2
     (512 MiB per plane), two 64 x 64-actuator DMs 1 m apart, 8 wavelengths over 500-600 nm, the
     occulter, Lyot stop and detector of the 4096^2 train; the PSF and the gradient of the mean
     dark-hole contrast with respect to the 8192 actuators, batched + graph, plain, and in two
     calls through the caller's checkpoint (forward save, then backward)."""
     nd, n, nl, na = 2048, 8192, 8, 64
-    # tuned (untimed) for its own shapes: the 8192 sweeps and the MFT GEMMs of its planes
+    # tuned (untimed) for its own shapes: the 8192 sweeps and the MFT GEMMs of its planes (unless
+    # the choices were loaded from a file)
     t0 = time.perf_counter()
-    fb.autotune_fresnel(n)
-    for n_, m_ in ((n, OCC_M), (nd, OCC_M), (nd, DET_M)):
-        fb.autotune_mft(n_, m_)
+    if tune:
+        fb.autotune_fresnel(n)
+        for n_, m_ in ((n, OCC_M), (nd, OCC_M), (nd, DET_M)):
+            fb.autotune_mft(n_, m_)
     t_tune = time.perf_counter() - t0
 
     def f(a):
