@@ -186,6 +186,38 @@ def test_checkpointed_backward_equals_one_call_gradient(n_dm, batched):
         assert torch.isfinite(junk).all()
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_rows_outside_the_pupil_window_are_never_read(batched):
+    """The forward sweeps leave the zero rows outside the pupil window unstored and unread, and
+    the step back to the pupil DM stores and transforms only the window's rows: with the workspace
+    and the checkpoint filled with NaN bytes beforehand, the PSF and the gradient are bit for bit
+    those of a run on a clean workspace (4096^2 planes, whose row sweeps skip the rows, and a
+    mixed-radix 3840^2 plane; two DMs, with and without the occulter, one call and the checkpoint
+    pair)."""
+    banner(f"pupil window rows, NaN-filled workspace, batched={batched}")
+    _, tr, _, hg = make(256, 64, 8 / 64, 64, 0.5, 0.5, 8, 2, spider=0.02)
+    lams = list(synth.wavelengths(2))
+    ns, w = [4096, 3840], [0.5, 0.5]
+    dhn = synth.dark_hole(64, 0.5, 3.0, 7.0)
+    g = to_gpu(dhn / dhn.sum(), torch.float32)
+    for occulter in (True, False):
+        fb.workspace(1, 0).zero_()
+        p_ref, g_ref = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g, batched=batched, occulter=occulter)
+        torch.cuda.synchronize()
+        fb.workspace(1, 0).fill_(0xFF)
+        p1, g1 = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g, batched=batched, occulter=occulter)
+        ck = torch.full((fb.train_ckpt_bytes(tr, ns),), 0xFF, dtype=torch.uint8, device="cuda:0")
+        fb.workspace(1, 0).fill_(0xFF)
+        p2 = fb.propagate_train(tr, lams, ns, w, hg, batched=batched, occulter=occulter, ckpt=ck, phase="save")
+        fb.workspace(1, 0).fill_(0xFF)
+        g2 = fb.propagate_train(tr, lams, ns, w, hg, grad_psf=g, batched=batched, occulter=occulter, ckpt=ck,
+                                phase="backward")
+        torch.cuda.synchronize()
+        assert torch.isfinite(p_ref).all() and torch.isfinite(g_ref).all()
+        assert torch.equal(p1, p_ref) and torch.equal(g1, g_ref), occulter
+        assert torch.equal(p2, p_ref) and torch.equal(g2, g_ref), occulter
+
+
 def test_batched_matches_plain_mixed_grids():
     # a batch of mixed edges runs each plane through the kernels the plain mode gives it (the
     # power-of-two sweeps for 128, the mixed-radix sweeps for the others): bit-identical, as for
