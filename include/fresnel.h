@@ -380,7 +380,9 @@ int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda,
  * fr_autotune times the candidate kernel configurations of one workload shape on `stream` and
  * keeps the fastest in the context; later calls of every entry point use it:
  *   FR_TUNE_FRESNEL, a = plane edge n (b unused): the tile variants of the power-of-two sweeps
- *     (rows per block, columns per tile) and the pass orders of the mixed-radix plan of n;
+ *     (rows per block, columns per tile) and the pass orders of the mixed-radix plan of n (the
+ *     orders of its greedy radices and, for the per-wavelength grids of a broadband model, the
+ *     plan of the register-resident sweeps, which is also their default);
  *   FR_TUNE_MFT, a = pupil-side edge n, b = focal edge m: the GEMM tile configuration and split-K
  *     factor of each of the two GEMMs of mft_forward (n -> m) and mft_adjoint (m -> n). Tiles
  *     0-3 form each complex k-step from four real products, tiles 4-5 from three (Gauss; the
@@ -394,7 +396,8 @@ int propagate_train(fr_ctx *ctx, const fr_train_desc *desc, int32_t n_lambda,
  * a hot loop or a graph capture. Errors: FR_EINVAL, FR_EUNSUPPORTED, FR_ENOMEM, FR_EHIP.
  * fr_autotune_save / fr_autotune_load write / read the tuned choices as a text file (one
  * "sweep n variant [planes]" (planes: the power-of-two sweeps' planes per launch in batched calls,
- * 1..64, or 0 = as many as fit the last-level cache together), "plan n packed_order",
+ * 1..64, or 0 = as many as fit the last-level cache together), "plan n packed_order" (radices
+ * 2-10, 12, 14, 15 or 16, 5 bits each from the first pass up, at most 6, product n),
  * "gemm M N K transA transB tile [split]" or
  * "gemm_default tile split" per line; the default applies to GEMM shapes without their own line,
  * tile -1 restoring the choice by shape); a malformed or inconsistent line makes load return

@@ -230,9 +230,14 @@ int Ctx::mr(int n, hipStream_t s, MrPlane *out, unsigned plan) {
   if (!mr_plan(n, &np, rad)) return FR_EUNSUPPORTED;
   if (plan == 0)
     if (auto it = tuned_plan.find(n); it != tuned_plan.end()) plan = it->second;
+  if (plan == 0) plan = mr_default_plan(n);
   if (plan != 0) {
-    // a reordering of the same radices (validated by the caller that chose it)
-    for (int i = 0; i < np; ++i) rad[i] = int((plan >> (5 * i)) & 31u);
+    // another factorisation into supported radices (validated by the caller that chose it)
+    np = 0;
+    while (np < kMrMaxPass && ((plan >> (5 * np)) & 31u)) {
+      rad[np] = int((plan >> (5 * np)) & 31u);
+      ++np;
+    }
   }
   TableKey key{kMrTw, n, uint64_t(mr_pack(np, rad)), 0, 0, 0};
   void *d = nullptr;

@@ -102,9 +102,12 @@ int tune_fresnel(Ctx *ctx, int n, hipStream_t s) {
     ctx->tuned_variant[n] = best;
   }
   // mixed-radix sweeps (used for this edge in batches of mixed edges): pass orders
-  unsigned plans[kMaxOrders];
+  unsigned plans[kMaxOrders + 1];
   int np = 0;
-  const int count = mr_plan_orders(n, kMaxOrders, plans, &np);
+  int count = mr_plan_orders(n, kMaxOrders, plans, &np);
+  // the edge's default order (a register-resident plan) is always among the candidates
+  if (const unsigned d = mr_default_plan(n); d != 0u && std::find(plans, plans + count, d) == plans + count)
+    plans[count++] = d;
   unsigned best_plan = 0;
   float best_ms = -1.f;
   for (int c = 0; c < count; ++c) {
@@ -176,16 +179,19 @@ int tune_mft(Ctx *ctx, int n, int m, hipStream_t s) {
   return record_hip(hipStreamSynchronize(s));
 }
 
-// a pass order read back from a file must be a reordering of the edge's own plan
+// a pass order read back from a file: radices the sweeps support (2-10, 12, 14, 15, 16), at
+// most kMrMaxPass of them, whose product is the edge
 bool valid_plan(int n, unsigned plan) {
-  int np = 0, rad[kMrMaxPass];
-  if (!mr_plan(n, &np, rad)) return false;
-  int got[kMrMaxPass];
-  for (int i = 0; i < np; ++i) got[i] = int((plan >> (5 * i)) & 31u);
-  if ((plan >> (5 * np)) != 0u) return false;
-  std::sort(rad, rad + np);
-  std::sort(got, got + np);
-  return std::equal(rad, rad + np, got);
+  int np = 0, greedy[kMrMaxPass];
+  if (!mr_plan(n, &np, greedy)) return false;
+  long long prod = 1;
+  int s = 0;
+  for (; s < kMrMaxPass && ((plan >> (5 * s)) & 31u); ++s) {
+    const int r = int((plan >> (5 * s)) & 31u);
+    if (r < 2 || r == 11 || r == 13 || r > 16) return false;
+    prod *= r;
+  }
+  return s > 0 && (s == kMrMaxPass ? (plan >> (5 * s)) == 0u : true) && prod == n;
 }
 
 }  // namespace

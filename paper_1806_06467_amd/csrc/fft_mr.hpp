@@ -168,6 +168,122 @@ struct MrCt {
   }
 };
 
+// Register-resident form of a compile-time plan: the line is held E elements per thread (slot m
+// of thread t is element t + T m, T = N / E threads), as in the power-of-two sweeps. The first
+// pass (span 1) takes its butterflies from the registers and the last pass leaves its outputs
+// in them (in the same slot order), which needs E divisible by the first and the last radix;
+// the passes between go through the LDS as above. So a transform costs the LDS traffic of the
+// power-of-two plans of the same pass count, and a forward transform, a product in frequency
+// and an inverse transform chain without touching the LDS in between. Same twiddle table layout
+// and the same arithmetic per butterfly as mr_fft for the same radix order.
+// A middle pass through the LDS that holds only its butterflies' inputs across the barrier
+// between reading and writing the line: the twiddles are read and the butterflies run after it,
+// one at a time (the same arithmetic as mr_pass_ct, fewer registers).
+template <int N, int R, int P, bool INV, int T>
+__device__ __forceinline__ void mrr_mid_pass(c32 *lds, const float2 *__restrict__ tw, int t) {
+  constexpr int NR = N / R;
+  constexpr int NB = (NR + T - 1) / T;
+  c32 u[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = t + i * T;
+    if (NR % T == 0 || b < NR) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[i][r] = lds[lds_pad(b + r * NR)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = t + i * T;
+    if (NR % T == 0 || b < NR) {
+      const int k = b % P;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 q = tw[(r - 1) * P + k];
+        u[i][r] = INV ? cmulc(u[i][r], c32{q.x, q.y}) : cmul(u[i][r], c32{q.x, q.y});
+      }
+      DftDir<R, INV>::run(u[i]);
+      const int base = (b / P) * (P * R) + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lds_pad(base + r * P)] = u[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int E, bool INV, int P, int R, int... Rest>
+__device__ __forceinline__ void mrr_passes(c32 (&v)[E], c32 *lds, int t, const float2 *__restrict__ tw) {
+  constexpr int T = N / E;
+  if constexpr (sizeof...(Rest) > 0) {
+    mrr_mid_pass<N, R, P, INV, T>(lds, tw, t);
+    mrr_passes<N, E, INV, P * R, Rest...>(v, lds, t, tw + (R - 1) * P);
+  } else {
+    // last pass: span P = N / R, butterfly b = t + j T < P reads elements b + r P (slot j + r NB)
+    // and leaves output r in the same slot
+    static_assert(P * R == N && E % R == 0, "the last radix must divide the elements per thread");
+    constexpr int NB = E / R;
+    c32 u[NB][R];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[j][r] = lds[lds_pad(t + T * (j + r * NB))];
+    __syncthreads();  // the line is read out: the LDS is free for the next transform
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int k = t + j * T;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 q = tw[(r - 1) * P + k];
+        u[j][r] = INV ? cmulc(u[j][r], c32{q.x, q.y}) : cmul(u[j][r], c32{q.x, q.y});
+      }
+      DftDir<R, INV>::run(u[j]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[j + r * NB] = u[j][r];
+    }
+  }
+}
+
+template <int N, int E, bool INV, int R1, int... Rest>
+__device__ __forceinline__ void mrr_fft(c32 (&v)[E], c32 *lds, int t, const float2 *__restrict__ tw) {
+  constexpr int T = N / E;
+  static_assert(N % E == 0 && E % R1 == 0, "the first radix must divide the elements per thread");
+  static_assert(sizeof...(Rest) >= 2, "first, middle and last passes");
+  // first pass (span 1): butterfly b = t + j T reads elements b + r N / R1 (slot j + r NB) and
+  // writes output r to b R1 + r
+  constexpr int NB = E / R1;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    c32 u[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) u[r] = v[j + r * NB];
+    DftDir<R1, INV>::run(u);
+    const int b = t + j * T;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) lds[lds_pad(b * R1 + r)] = u[r];
+  }
+  __syncthreads();
+  mrr_passes<N, E, INV, R1, Rest...>(v, lds, t, tw);
+}
+
+// a register-resident plan: edge N, E elements per thread, radices Rs in pass order
+template <int N_, int E_, int... Rs>
+struct MrReg {
+  static constexpr int N = N_;
+  static constexpr int E = E_;
+  static constexpr int T = N_ / E_;
+  static constexpr unsigned packed() {
+    unsigned p = 0;
+    int s = 0;
+    for (int r : {Rs...}) p |= unsigned(r) << (5 * s++);
+    return p;
+  }
+  template <bool INV>
+  __device__ __forceinline__ static void fft(c32 (&v)[E_], c32 *lds, int t, const float2 *tw) {
+    mrr_fft<N_, E_, INV, Rs...>(v, lds, t, tw);
+  }
+};
+
 // Host side. Greedy radix plan of an n-point line: the largest supported radix that divides
 // what is left, at most maxpass passes; false if n does not factor that way.
 inline bool mr_plan_build(int n, int maxn, int maxpass, int *npass, int *radix) {

@@ -19,6 +19,11 @@ namespace fr {
 // read what the previous one has just written from that cache instead of from HBM.
 constexpr size_t kCacheGroupBytes = size_t(160) << 20;
 
+// the default pass order of a mixed-radix edge n (sweeps_mr.hip): the order of its
+// register-resident sweeps when it has them (the per-wavelength grids of a broadband model),
+// else 0 (the greedy plan)
+unsigned mr_default_plan(int n);
+
 enum TableKind : int {
   kRoots = 1, kTransfer, kLens, kMft, kDm, kMrTw, kDirectPre, kDirectPost, kExactPrm, kMft64,
   kRoots64, kTransfer64, kLens64

@@ -8,7 +8,10 @@
 // the twiddles (per-pass float32 tables built in float64 on the host), runs DFT_R, and writes
 // the outputs after a barrier. The transfer function is applied while the first inverse pass
 // reads its inputs. Blocks loop over a flattened list of (plane, row) or (plane, 4-column tile)
-// work items, so one launch covers a whole batch of uneven planes.
+// work items, so one launch covers a whole batch of uneven planes. For some of a broadband
+// model's grid edges a register-resident form (MrReg: the line in registers between a
+// transform's first and last passes, as in the power-of-two sweeps) runs instead, one row or
+// 4-column tile per block, when every plane of the launch has that edge and its plan.
 //
 // All global accesses use raw buffer instructions with a per-lane offset clamped inside the
 // array, so every access is range-checked by the hardware.
@@ -269,6 +272,119 @@ __global__ void __launch_bounds__(kT * 4) mr_col_sweep(MrBatch) {
   }
 }
 
+// ---- register-resident sweeps of the broadband grids' plans ------------------------------
+// One row (row sweep) or one 4-column tile (column sweep, 32-byte row segments) per block, the
+// line held in registers E elements per thread between a transform's first and last passes and
+// from one transform to the next (MrReg); grid (lines, planes) with every plane of the launch of
+// the policy's edge and plan.
+
+// the pre optic on the slots x = t + T m of row y (conjugated when CONJ; the source optic itself
+// when `source`), loads issued kOptBatch slots at a time
+template <int E, int T, bool CONJ>
+__device__ __forceinline__ void apply_pre_reg(c32 (&v)[E], const PlaneArgs &pa, int n, int y, int t, bool source) {
+  const PreMaps pm(pa, n);
+  const c32 ly = pm.lens.load(unsigned(y) * 8u);
+#pragma unroll
+  for (int m0 = 0; m0 < E; m0 += kOptBatch) {
+    constexpr int B = kOptBatch;
+    PreVals pv[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      if (m0 + q < E) pv[q] = pre_fetch(pm, y, t + T * (m0 + q));
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      if (m0 + q < E) {
+        const c32 ph = pre_optic(pm, pv[q], y, t + T * (m0 + q), ly);
+        v[m0 + q] = source ? ph : (CONJ ? cmulc(v[m0 + q], ph) : cmul(v[m0 + q], ph));
+      }
+  }
+}
+
+// the frequency product with h (conj(h) for the adjoint); slot m holds frequency t + T m
+template <int E, int T>
+__device__ __forceinline__ void freq_reg(c32 (&v)[E], const float2 *h, int t, bool adj) {
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const float2 q = h[t + T * m];
+    v[m] = adj ? cmulc(v[m], c32{q.x, q.y}) : cmul(v[m], c32{q.x, q.y});
+  }
+}
+
+template <class F>
+__global__ void __launch_bounds__(F::T) mrr_row_sweep(MrBatch) {
+  constexpr int N = F::N, E = F::E, T = F::T;
+  const MrBatch &args = kernarg_batch();
+  __shared__ c32 lds[LdsLine<N>::size];
+  const MrPlane &mp = args.p[blockIdx.y];
+  const PlaneArgs &pa = mp.pa;
+  const int y = blockIdx.x, t = threadIdx.x;
+  const bool adj = pa.flags & FR_ADJOINT;
+  const bool source = pa.flags & kSourceOptic;
+  const bool pre = mr_has_pre(pa);
+  const Buf64 fb(pa.field, unsigned(N) * unsigned(N) * 8u);
+  c32 v[E];
+  if (source) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = {1.0f, 0.0f};
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = fb.load(unsigned(y * N + t + T * m) * 8u);
+  }
+  if (!adj && pre) apply_pre_reg<E, T, false>(v, pa, N, y, t, source);
+  F::template fft<false>(v, lds, t, mp.tw);
+  freq_reg<E, T>(v, pa.h, t, adj);
+  F::template fft<true>(v, lds, t, mp.tw);
+  if (adj && pre) apply_pre_reg<E, T, true>(v, pa, N, y, t, false);
+#pragma unroll
+  for (int m = 0; m < E; ++m) fb.store(unsigned(y * N + t + T * m) * 8u, v[m]);
+}
+
+// the post surface phasor exp(2 pi i 2 s / lambda) at rows t + T m of column x (conjugated when
+// CONJ), from the 4-column tiled map
+template <int E, int T, bool CONJ>
+__device__ __forceinline__ void apply_post_reg(c32 (&v)[E], const PlaneArgs &pa, int n, int t, int x) {
+  const Buf32 post(pa.post_surf, unsigned(post_tiled_size(n)) * 4u);
+  float sv[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) sv[m] = post.load(unsigned(post_tiled_index(n, t + T * m, x)) * 4u);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    float sn, cs;
+    sincos_turns(2.0f * sv[m] * pa.inv_lambda, &sn, &cs);
+    v[m] = CONJ ? cmulc(v[m], c32{cs, sn}) : cmul(v[m], c32{cs, sn});
+  }
+}
+
+template <class F>
+__global__ void __launch_bounds__(4 * F::T) mrr_col_sweep(MrBatch) {
+  constexpr int N = F::N, E = F::E, T = F::T;
+  static_assert(N % 4 == 0, "4-column tiles");
+  constexpr int G = N / 4;  // column tiles per plane
+  constexpr int LINE = LdsLine<N>::size + 8;
+  const MrBatch &args = kernarg_batch();
+  __shared__ c32 lds[4 * LINE];
+  const MrPlane &mp = args.p[blockIdx.y];
+  const PlaneArgs &pa = mp.pa;
+  const int c = threadIdx.x & 3, t = threadIdx.x >> 2;
+  // blocks are dealt round-robin to the 8 XCDs: XCD i takes a contiguous run of the tiles
+  const int i = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const int g = i * (G / 8) + min(i, G % 8) + k;
+  const int x = g * 4 + c;
+  const bool adj = pa.flags & FR_ADJOINT;
+  const Buf64 fb(pa.field, unsigned(N) * unsigned(N) * 8u);
+  c32 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = fb.load(unsigned((t + T * m) * N + x) * 8u);
+  if (adj && pa.post_surf) apply_post_reg<E, T, true>(v, pa, N, t, x);
+  c32 *my = lds + c * LINE;
+  F::template fft<false>(v, my, t, mp.tw);
+  freq_reg<E, T>(v, pa.h, t, adj);
+  F::template fft<true>(v, my, t, mp.tw);
+  if (!adj && pa.post_surf) apply_post_reg<E, T, false>(v, pa, N, t, x);
+#pragma unroll
+  for (int m = 0; m < E; ++m) fb.store(unsigned((t + T * m) * N + x) * 8u, v[m]);
+}
+
 }  // namespace
 
 bool mr_plan(int n, int *npass, int *radix) { return mr_plan_build(n, kMrMaxN, kMrMaxPass, npass, radix); }
@@ -304,6 +420,45 @@ using MrCtPlans = std::tuple<MrCt<3584, 16, 16, 14>, MrCt<3600, 16, 15, 15>, MrC
                              MrCt<4032, 16, 14, 9, 2>>;
 constexpr int kMrCt = std::tuple_size<MrCtPlans>::value;
 
+// register-resident plans of the same edges: factorisations whose first and last radices divide
+// the elements per thread (E), T = N / E threads per line, 4 T per column tile. With E = 14 or 15
+// and every middle radix 16 a middle pass's butterflies fit the threads (one each), so 3584, 3600
+// and 3840 run as the power-of-two sweeps do (measured per plane, rows / columns: 3584 81 / 109 us
+// against 113 / 124 us for the greedy compile-time plan, 3600 96 / 104 against 117 / 129, 3840
+// 99 / 119 against 118 / 134); for 4032 the middle passes take two rounds and the column sweep
+// spills at its 128 registers (152 / 179 against 181 / 166 us: still ahead over both sweeps).
+// 3888, 3920 and 4000 have no such factorisation under the 256-thread lines of a 4-column tile
+// and keep the greedy compile-time plans. These orders are the edges' default plans
+// (mr_default_plan); a tuning file may choose another.
+using MrRegPlans = std::tuple<MrReg<3584, 14, 7, 16, 16, 2>, MrReg<3600, 15, 15, 16, 15>,
+                              MrReg<3840, 15, 3, 16, 16, 5>, MrReg<4032, 18, 9, 16, 14, 2>>;
+constexpr int kMrReg = std::tuple_size<MrRegPlans>::value;
+
+// calls f(policy) and returns true when a register-resident plan runs edge n with plan `plan`
+template <class Fn, int I = 0>
+bool with_mr_reg(int n, unsigned plan, Fn &&f) {
+  if constexpr (I == kMrReg) {
+    return false;
+  } else {
+    using P = std::tuple_element_t<I, MrRegPlans>;
+    if (n == P::N && plan == P::packed()) {
+      f(P{});
+      return true;
+    }
+    return with_mr_reg<Fn, I + 1>(n, plan, std::forward<Fn>(f));
+  }
+}
+
+template <int I = 0>
+unsigned mr_reg_plan(int n) {
+  if constexpr (I == kMrReg) {
+    return 0u;
+  } else {
+    using P = std::tuple_element_t<I, MrRegPlans>;
+    return n == P::N ? P::packed() : mr_reg_plan<I + 1>(n);
+  }
+}
+
 // calls f(policy) for the instance that runs planes of edge n with packed plan `plan` (the
 // runtime policy when no compile-time plan matches)
 template <class Fn, int I = 0>
@@ -338,6 +493,8 @@ int mr_policy_index(int n, unsigned plan) {
     return mr_policy_index<I + 1>(n, plan);
   }
 }
+
+unsigned mr_default_plan(int n) { return mr_reg_plan(n); }
 
 void mr_resident(int *rows_per_cu, int *cols_per_cu) {
   static_assert(kMrCt + 1 <= kMrPolicies, "residency table size");
@@ -375,16 +532,27 @@ hipError_t launch_mr_batch(const MrBatch &all, const int *rows_per_cu, const int
   int pol = all.count ? mr_policy_index(all.p[0].n, all.p[0].plan) : 0;
   for (int i = 1; i < all.count && pol; ++i)
     if (all.p[i].n != all.p[0].n || all.p[i].plan != all.p[0].plan) pol = 0;
+  // one register-resident instance when every plane has the same edge and its plan
+  bool same = all.count > 0;
+  for (int i = 1; i < all.count && same; ++i)
+    if (all.p[i].n != all.p[0].n || all.p[i].plan != all.p[0].plan) same = false;
+  const int nr = same ? all.p[0].n : 0;
+  const unsigned planr = same ? all.p[0].plan : 0u;
   const int n0 = pol ? all.p[0].n : 0;
   const unsigned plan0 = pol ? all.p[0].plan : 0u;
   const int blocks_rows = cus * rows_per_cu[pol], blocks_cols = cus * cols_per_cu[pol];
   auto rows = [&](MrBatch b, const char *name) {
     rows_list(b);
     hook(s, name, b.count, 0);
-    with_mr_policy(n0, plan0, [&](auto p) {
-      hipLaunchKernelGGL((mr_row_sweep<decltype(p)>), dim3(std::max(1, std::min(blocks_rows, b.total))), dim3(kT),
-                         0, s, b);
+    const bool reg = with_mr_reg(nr, planr, [&](auto p) {
+      using P = decltype(p);
+      hipLaunchKernelGGL((mrr_row_sweep<P>), dim3(P::N, b.count), dim3(P::T), 0, s, b);
     });
+    if (!reg)
+      with_mr_policy(n0, plan0, [&](auto p) {
+        hipLaunchKernelGGL((mr_row_sweep<decltype(p)>), dim3(std::max(1, std::min(blocks_rows, b.total))),
+                           dim3(kT), 0, s, b);
+      });
     hipError_t e = hipGetLastError();
     hook(s, name, b.count, 1);
     return e;
@@ -392,10 +560,15 @@ hipError_t launch_mr_batch(const MrBatch &all, const int *rows_per_cu, const int
   auto cols = [&](MrBatch b, const char *name) {
     cols_list(b);
     hook(s, name, b.count, 0);
-    with_mr_policy(n0, plan0, [&](auto p) {
-      hipLaunchKernelGGL((mr_col_sweep<decltype(p)>), dim3(std::max(1, std::min(blocks_cols, b.total))),
-                         dim3(4 * kT), 0, s, b);
+    const bool reg = with_mr_reg(nr, planr, [&](auto p) {
+      using P = decltype(p);
+      hipLaunchKernelGGL((mrr_col_sweep<P>), dim3(P::N / 4, b.count), dim3(4 * P::T), 0, s, b);
     });
+    if (!reg)
+      with_mr_policy(n0, plan0, [&](auto p) {
+        hipLaunchKernelGGL((mr_col_sweep<decltype(p)>), dim3(std::max(1, std::min(blocks_cols, b.total))),
+                           dim3(4 * kT), 0, s, b);
+      });
     hipError_t e = hipGetLastError();
     hook(s, name, b.count, 1);
     return e;

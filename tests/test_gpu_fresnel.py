@@ -436,24 +436,34 @@ def test_fresnel_step_8192_plane_waves_closed_form(adjoint):
     assert rel_l2(got, ref) <= TOL
 
 
-def test_broadband_grid_runtime_plan_matches_compile_time_plan(tmp_path):
-    """A broadband grid edge under another pass order (a tuning file's `plan` line) runs the
-    runtime-planned sweeps instead of the compile-time instance: both against the oracle."""
-    n = 3600
-    banner("mixed-radix n=3600: compile-time plan 16.15.15 vs runtime plan 15.16.15")
+def _pack(*radices):
+    return sum(r << (5 * i) for i, r in enumerate(radices))
+
+
+@pytest.mark.parametrize("n,default,greedy,other", [
+    (3600, (15, 16, 15), (16, 15, 15), (15, 15, 16)),
+    (3584, (7, 16, 16, 2), (16, 16, 14), (14, 16, 16)),
+    (3840, (3, 16, 16, 5), (16, 16, 15), (15, 16, 16)),
+    (4032, (9, 16, 14, 2), (16, 14, 9, 2), (2, 9, 14, 16)),
+])
+def test_broadband_grid_plans_match_oracle(n, default, greedy, other, tmp_path):
+    """A broadband grid edge under three pass orders (a tuning file's `plan` line): its default
+    (the register-resident sweeps), the greedy order (the compile-time instance) and another order
+    (the runtime-planned sweeps), forward and adjoint, each against the oracle."""
+    banner(f"mixed-radix n={n}: register-resident {default}, compile-time {greedy}, runtime {other}")
     field, amp, opd, dx, lam, z, f = _case(n, 77)
     ref = oracle.fresnel_step(f32(field), dx, lam, z, amp=f32(amp), opd=f32(opd), lens_focal=f)
-    got_ct = _run_gpu(field, amp, opd, dx, lam, z, f, False)
+    ref_adj = oracle.fresnel_step(f32(field), dx, lam, z, amp=f32(amp), opd=f32(opd), lens_focal=f, adjoint=True)
     path = tmp_path / "tune.txt"
-    path.write_text("plan 3600 %d\n" % (15 | (16 << 5) | (15 << 10)))
-    fb.autotune_load(str(path))
     try:
-        got_rt = _run_gpu(field, amp, opd, dx, lam, z, f, False)
+        for order in (default, greedy, other):
+            path.write_text("plan %d %d\n" % (n, _pack(*order)))
+            fb.autotune_load(str(path))
+            assert rel_l2(_run_gpu(field, amp, opd, dx, lam, z, f, False), ref) <= TOL, order
+            assert rel_l2(_run_gpu(field, amp, opd, dx, lam, z, f, True), ref_adj) <= TOL, order
     finally:
-        path.write_text("plan 3600 %d\n" % (16 | (15 << 5) | (15 << 10)))
+        path.write_text("plan %d %d\n" % (n, _pack(*default)))
         fb.autotune_load(str(path))
-    assert rel_l2(got_ct, ref) <= TOL
-    assert rel_l2(got_rt, ref) <= TOL
 
 
 def test_context_created_with_a_tuning_file(tmp_path):
