@@ -346,8 +346,9 @@ def main():
                         "hbm_frac_bytes_weighted": frac_of(ms_u, ubytes)},
             "plain": {"value": n_pl / (ms_up * 1e-3), "unit": "Fresnel planes/s", "ms_per_step": ms_up,
                       "hbm_frac_bytes_weighted": frac_of(ms_up, ubytes)},
-            "note": "the 4096^2 planes take the power-of-two sweeps, the others the persistent "
-                    "mixed-radix sweeps (in the batched form one launch per sweep for each group)"}
+            "note": "the 4096^2 planes take the power-of-two sweeps, 3584, 3600, 3840 and 4032 the "
+                    "register-resident mixed-radix sweeps, 3888, 3920 and 4000 the persistent ones "
+                    "(in the batched form one launch per sweep for each group)"}
         del ufields, ua, uo, maps
 
     # ---- device-copy ceiling: 1 GiB copied (2 GiB moved), beyond the last-level cache ----------
