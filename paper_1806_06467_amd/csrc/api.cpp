@@ -362,13 +362,9 @@ int Ctx::mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, c
 }
 
 // G[i][a] = exp(-(c(i) - xi_a)^2 / (2 p^2)), xi_a = (a - (n_act-1)/2) p, p = n_d / n_act
-int Ctx::dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **out) {
-  TableKey key{kDm, n, uint64_t(n_d), uint64_t(n_act), 0, 0};
-  if (auto it = tables.find(key); it != tables.end()) {
-    *out = static_cast<const float *>(it->second);
-    return FR_OK;
-  }
-  std::vector<float> h(size_t(n) * n_act);
+// G[i][a] = exp(-(c(i) - xi_a)^2 / (2 p^2)) in float64, rounded once: actuators centred on the
+// pupil at pitch p = n_d / n_act, sigma one pitch
+static void dm_influence_fill(int n, int n_d, int n_act, float *h) {
   const double p = double(n_d) / double(n_act);
   for (int i = 0; i < n; ++i) {
     const double c = double(i - n / 2);
@@ -378,10 +374,40 @@ int Ctx::dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **ou
       h[size_t(i) * n_act + a] = float(std::exp(-d * d / (2.0 * p * p)));
     }
   }
+}
+
+int Ctx::dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **out) {
+  TableKey key{kDm, n, uint64_t(n_d), uint64_t(n_act), 0, 0};
+  if (auto it = tables.find(key); it != tables.end()) {
+    *out = static_cast<const float *>(it->second);
+    return FR_OK;
+  }
+  std::vector<float> h(size_t(n) * n_act);
+  dm_influence_fill(n, n_d, n_act, h.data());
   void *d;
   int st = upload(key, h.data(), h.size() * sizeof(float), s, &d);
   *out = static_cast<const float *>(d);
   return st;
+}
+
+void Ctx::dm_band(int n, int n_d, int n_act, int *lo, int *hi) {
+  const auto key = std::make_tuple(n, n_d, n_act);
+  auto it = dm_bands.find(key);
+  if (it == dm_bands.end()) {
+    std::vector<float> h(size_t(n) * n_act);
+    dm_influence_fill(n, n_d, n_act, h.data());
+    int l = n, u = 0;
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < n_act; ++a)
+        if (h[size_t(i) * n_act + a] != 0.0f) {
+          l = std::min(l, i);
+          u = std::max(u, i + 1);
+        }
+    if (u <= l) l = u = 0;
+    it = dm_bands.emplace(key, std::make_pair(l, u)).first;
+  }
+  *lo = it->second.first;
+  *hi = it->second.second;
 }
 
 

@@ -86,7 +86,8 @@ struct Ctx {
   // choices made by the autotuner (fr_autotune), consulted by every later call
   std::map<int, int> tuned_variant;                 // power-of-two sweep tile variant per edge
   std::map<int, int> tuned_group;                   // planes per launch group per edge (0: cache-sized)
-  std::map<int, unsigned> tuned_plan;               // mixed-radix pass order per edge
+  std::map<int, unsigned> tuned_plan;
+  std::map<std::tuple<int, int, int>, std::pair<int, int>> dm_bands;  // dm_band results               // mixed-radix pass order per edge
   struct GemmChoice {
     int tile;   // tile configuration
     int split;  // K slices (0: the default for the tile)
@@ -101,6 +102,9 @@ struct Ctx {
   int mft_matrix(int m_out, int n_in, double n_d, double du, hipStream_t s, const float2 **out,
                  bool transposed = false);
   int dm_influence(int n, int n_d, int n_act, hipStream_t s, const float **out);
+  // the rows [lo, hi) of that table with a nonzero entry (the Gaussians underflow float32 to
+  // exactly 0 beyond about 14.4 actuator pitches from the outermost actuators); host arithmetic
+  void dm_band(int n, int n_d, int n_act, int *lo, int *hi);
 };
 
 int record_hip(hipError_t e);

@@ -214,7 +214,8 @@ struct GradChunk {
 // v_mfma_f32_32x32x2f32, accumulating in float32 across the group's chunks; the two column
 // halves are added at the end. The next chunk's loads are issued before this chunk's products.
 // Only rows [row0, row1) and columns [col0, col1) are visited (g_s is zero elsewhere: the
-// pupil optic's amplitude window); T rows outside are not written.
+// pupil optic's amplitude window; or G is: the band of the Gaussian influence functions); T rows
+// outside are not written.
 template <bool SYNTH>
 __global__ void __launch_bounds__(256) dm_grad_T(const float2 *E, const float2 *B, const float *G, int n, int na,
                                                  float kappa, const float *amp, const float *opd, int nd,
@@ -689,9 +690,19 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     const int n = n_pad[j];
     const float *G = nullptr;
     FR_TRY(ctx->dm_influence(n, nd, na, s, &G));
-    // the pupil optic (E == null) is zero outside its nd x nd window, and so is g_s there
-    const int lo = E ? 0 : (n - nd) / 2, hi = E ? n : lo + nd;
-    const int strips = (hi - lo + kRows - 1) / kRows, groups = (hi - lo + kGroup - 1) / kGroup;
+    // The pupil optic (E == null) is zero outside its nd x nd window, and so is g_s there. For a
+    // stored plane the rows and columns outside the band where G has a nonzero float32 entry
+    // add exact zeros to T and to G^T T: they are skipped, the columns in whole kGroup groups
+    // (the groups that remain are the same groups, added in the same order: the same sums).
+    int r0 = (n - nd) / 2, r1 = r0 + nd, c0 = r0, c1 = r1;
+    if (E) {
+      int blo = 0, bhi = n;
+      ctx->dm_band(n, nd, na, &blo, &bhi);
+      if (bhi <= blo) blo = 0, bhi = n;
+      r0 = blo, r1 = bhi;
+      c0 = blo / kGroup * kGroup, c1 = std::min(n, (bhi + kGroup - 1) / kGroup * kGroup);
+    }
+    const int strips = (r1 - r0 + kRows - 1) / kRows, groups = (c1 - c0 + kGroup - 1) / kGroup;
     const int tn = n * na;
     float *T = TSUM + size_t(k) * nmax * na;
     if (sum_n[k] != n) {
@@ -704,16 +715,17 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     hook(s, tname, n, 0);
     if (E)
       hipLaunchKernelGGL(dm_grad_T<false>, dim3(strips, groups), dim3(256), 0, s, E, B, G, n, na, kappa,
-                         d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), lo, hi, lo, hi, TPART);
+                         d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), r0, r1, c0, c1, TPART);
     else
       hipLaunchKernelGGL(dm_grad_T<true>, dim3(strips, groups), dim3(256), 0, s, E, B, G, n, na, kappa,
-                         d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), lo, hi, lo, hi, TPART);
+                         d->pupil_amp, d->pupil_opd_m, nd, pre, float(1.0 / lam[j]), r0, r1, c0, c1, TPART);
     FR_TRY_HIP(hipGetLastError());
     hook(s, tname, n, 1);
-    // T rows outside [lo, hi) keep what they hold (zero from the fill, for this DM's pupil sums)
-    FR_TRY_HIP(launch1d(dm_grad_acc, size_t(hi - lo) * na, s, hook, "dm_grad_acc",
-                        (const float *)(TPART + size_t(lo) * na), groups, (hi - lo) * na, size_t(tn),
-                        T + size_t(lo) * na));
+    // T rows outside [r0, r1) keep what they hold (zero from the fill: those rows of T are zero,
+    // or meet only zero rows of G in the projection)
+    FR_TRY_HIP(launch1d(dm_grad_acc, size_t(r1 - r0) * na, s, hook, "dm_grad_acc",
+                        (const float *)(TPART + size_t(r0) * na), groups, (r1 - r0) * na, size_t(tn),
+                        T + size_t(r0) * na));
     return FR_OK;
   };
 
