@@ -22,7 +22,8 @@ uint64_t dbits(double v) {
 
 // one checked plane's arguments with its tables fetched (z / lambda and (lambda / (n dx))^2 in
 // float64, the lens chirp, the twiddles); returns the plane's warning bits or an error
-int exact_plane(fr::Ctx *ctx, const fr_plane &p, hipStream_t s, fr::PlaneArgs *a, const float2 **root) {
+int exact_plane(fr::Ctx *ctx, const fr_plane &p, hipStream_t s, fr::PlaneArgs *a, const float2 **root,
+                bool *split_out) {
   const int n = p.n;
   std::memset(a, 0, sizeof *a);
   a->field = reinterpret_cast<float2 *>(p.field);
@@ -32,14 +33,36 @@ int exact_plane(fr::Ctx *ctx, const fr_plane &p, hipStream_t s, fr::PlaneArgs *a
   a->win = n;
   a->inv_lambda = float(1.0 / p.wavelength_m);
   a->flags = p.flags;
+  // float64 words: z / lambda, (lambda / (n dx))^2, the split flag, padding; with the split flag
+  // set, then n float2: the paraxial factor along one axis, exp(-i pi lambda z k~^2 / (n dx)^2) / n
+  // over the signed index k~ (so that H = h[kx] h[ky] exp(2 pi i c), with the non-separable rest
+  // c = -(z / lambda) u^2 / (2 (1 + sqrt(1 - u))^2) turns, u = (lambda f)^2, small enough to form
+  // in float32: no evanescent frequency on the grid and |c| <= 1/4 turn)
+  const double q = p.wavelength_m / (double(n) * p.dx_m);
+  const double zl = p.z_m / p.wavelength_m, a2 = q * q;
+  const double umax = a2 * 2.0 * double(n / 2) * double(n / 2);
+  const double rmax = 1.0 + std::sqrt(std::max(0.0, 1.0 - umax));
+  const bool split = umax < 1.0 && std::fabs(zl) * umax * umax / (2.0 * rmax * rmax) <= 0.25;
+  *split_out = split;
   const fr::TableKey key{fr::kExactPrm, n, dbits(p.dx_m), dbits(p.wavelength_m), dbits(p.z_m), 0};
   void *d = nullptr;
   if (auto it = ctx->tables.find(key); it != ctx->tables.end()) {
     d = it->second;
   } else {
-    const double q = p.wavelength_m / (double(n) * p.dx_m);
-    const double prm[2] = {p.z_m / p.wavelength_m, q * q};
-    const int st = ctx->upload(key, prm, sizeof prm, s, &d);
+    std::vector<double> prm(4 + (split ? n : 0), 0.0);
+    prm[0] = zl;
+    prm[1] = a2;
+    prm[2] = split ? 1.0 : 0.0;
+    if (split) {
+      float2 *h = reinterpret_cast<float2 *>(prm.data() + 4);
+      for (int k = 0; k < n; ++k) {
+        const double kk = double(k < n / 2 ? k : k - n);
+        double t = -0.5 * zl * a2 * kk * kk;
+        t -= std::rint(t);
+        h[k] = make_float2(float(std::cos(2.0 * M_PI * t) / n), float(std::sin(2.0 * M_PI * t) / n));
+      }
+    }
+    const int st = ctx->upload(key, prm.data(), prm.size() * sizeof(double), s, &d);
     if (st != FR_OK) return st;
   }
   a->h = static_cast<const float2 *>(d);
@@ -94,12 +117,16 @@ extern "C" int fresnel_step_exact_batched(fr_ctx *ctx_, const fr_plane *planes, 
   for (int i0 = 0; i0 < count; i0 += group) {
     const int g = std::min(group, count - i0);
     const float2 *root = nullptr;
+    // the planes whose H takes the split form (as in a call of their own)
+    uint64_t split_mask = 0;
     for (int j = 0; j < g; ++j) {
-      const int st = exact_plane(ctx, planes[i0 + j], s, &args[j], &root);
+      bool split = false;
+      const int st = exact_plane(ctx, planes[i0 + j], s, &args[j], &root, &split);
       if (st < 0) return st;
       warn |= st;
+      if (split) split_mask |= uint64_t(1) << j;
     }
-    e = fr::launch_exact_batch(args.data(), g, n, root, s, ctx->hook());
+    e = fr::launch_exact_batch(args.data(), g, n, root, s, ctx->hook(), split_mask);
     if (e != hipSuccess) return fr::record_hip(e);
   }
   return warn;

@@ -8,9 +8,12 @@
 namespace fr {
 
 // count planes of power-of-two edge n (count <= kMaxBatch), forward or (FR_ADJOINT) adjoint,
-// in place; `planes[i].h` points at two float64 parameters, z / lambda and (lambda / (n dx))^2,
-// `lens` at the thin lens or null
+// in place; `planes[i].h` points at float64 words z / lambda, (lambda / (n dx))^2, a split flag
+// and padding, then (split flag 1) the n float2 of the paraxial factor along one axis (H is
+// then formed as h[kx] h[ky] times a small float32 rest); `lens` at the thin lens or null
+// split: bit i set when plane i's table carries the split form (its column sweep then forms H in
+// registers)
 hipError_t launch_exact_batch(const PlaneArgs *planes, int count, int n, const float2 *tw, hipStream_t s,
-                              const LaunchHook &hook);
+                              const LaunchHook &hook, uint64_t split);
 
 }  // namespace fr

@@ -251,8 +251,9 @@ row_sweep(BatchArgs args, const float2 *tw) {
 // HALF: the FFT exchanges go through half-size LDS lines in two rounds, so that two blocks fit
 // on a compute unit. DIRECT: the column half of the direct Fresnel step: the forward transform,
 // then the output quadratic phase of both axes (h holds it per index, with the constant's root).
-// EXACT (with DIRECT): the column sweep of the exact-transfer-function step (fr_exact.h).
-template <class PL, int LINES, bool HALF = false, bool DIRECT = false, bool EXACT = false>
+// EXACT (with DIRECT): the column sweep of the exact-transfer-function step (fr_exact.h), 1 with
+// H's phase formed per element in float64, 2 in its split form.
+template <class PL, int LINES, bool HALF = false, bool DIRECT = false, int EXACT = 0>
 __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const float2 *tw) {
   static_assert(!EXACT || (DIRECT && !HALF), "the exact mode runs on full LDS lines");
   constexpr int N = PL::N, E = PL::E, T = PL::T;
@@ -301,35 +302,60 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
       // forward one ends on a barrier after its last read).
       const double *prm = reinterpret_cast<const double *>(pa.h);
       const double zl = prm[0], a2 = prm[1];
-      PL::template forward<HALF>(v, my, t, tw);
-#pragma unroll
-      for (int m = 0; m < E; ++m) my[t + T * m] = v[m];
       const int kx = x < N / 2 ? x : x - N;
-      constexpr float inv_n2 = 1.0f / (float(N) * float(N));
-#pragma unroll 1
-      for (int m = 0; m < E; ++m) {
-        const int k = t + T * m;
-        const int ky = k < N / 2 ? k : k - N;
-        const double u = a2 * double(kx * kx + ky * ky);  // (lambda f)^2
-        float amp = inv_n2, turns;
-        if (u < 1.0) {
-          const double tr = -zl * u / (sqrt(1.0 - u) + 1.0);
-          turns = float(tr - rint(tr));
-        } else {
-          amp *= float(exp(-2.0 * kPi * fabs(zl) * sqrt(u - 1.0)));
-          turns = float(-(zl - rint(zl)));
+      if constexpr (EXACT == 2) {
+        // H = h[kx] h[ky] exp(2 pi i c): the paraxial part from its float64-built table (it
+        // carries the 1/n of each inverse transform), the rest c = -(z/lambda) u^2 /
+        // (2 (1 + sqrt(1 - u))^2) turns, at most a quarter turn on this grid, in float32
+        const float2 *hp = reinterpret_cast<const float2 *>(prm + 4);
+        const float zlf = float(zl), a2f = float(a2);
+        const c32 hx = ld2(hp + x);
+        PL::template forward<HALF>(v, my, t, tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int k = t + T * m;
+          const int ky = k < N / 2 ? k : k - N;
+          const float u = a2f * float(kx * kx + ky * ky);
+          const float r = 1.0f + sqrtf(1.0f - u);
+          float sn, cs;
+          sincos_turns(-zlf * u * u / (2.0f * r * r), &sn, &cs);
+          const c32 hh = cmul(cmul(hx, ld2(hp + k)), c32{cs, sn});
+          v[m] = adj ? cmulc(v[m], hh) : cmul(v[m], hh);
         }
-        float sn, cs;
-        sincos_turns(adj ? -turns : turns, &sn, &cs);
-        my[k] = cmul(my[k], c32{amp * cs, amp * sn});
+        PL::template inverse<HALF>(v, my, t, tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
+        return;
+      } else {
+        PL::template forward<HALF>(v, my, t, tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m) my[t + T * m] = v[m];
+        constexpr float inv_n2 = 1.0f / (float(N) * float(N));
+#pragma unroll 1
+        for (int m = 0; m < E; ++m) {
+          const int k = t + T * m;
+          const int ky = k < N / 2 ? k : k - N;
+          const double u = a2 * double(kx * kx + ky * ky);  // (lambda f)^2
+          float amp = inv_n2, turns;
+          if (u < 1.0) {
+            const double tr = -zl * u / (sqrt(1.0 - u) + 1.0);
+            turns = float(tr - rint(tr));
+          } else {
+            amp *= float(exp(-2.0 * kPi * fabs(zl) * sqrt(u - 1.0)));
+            turns = float(-(zl - rint(zl)));
+          }
+          float sn, cs;
+          sincos_turns(adj ? -turns : turns, &sn, &cs);
+          my[k] = cmul(my[k], c32{amp * cs, amp * sn});
+        }
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = my[t + T * m];
+        __syncthreads();  // every slot read back before the inverse transform's first exchange
+        PL::template inverse<HALF>(v, my, t, tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
+        return;
       }
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = my[t + T * m];
-      __syncthreads();  // every slot read back before the inverse transform's first exchange
-      PL::template inverse<HALF>(v, my, t, tw);
-#pragma unroll
-      for (int m = 0; m < E; ++m) buf.store(vo, unsigned(T * m) * unsigned(N) * 8u, v[m]);
-      return;
     }
     // slot m holds frequency row ky = t + T m of column kx = x (after the forward transform;
     // the adjoint, which runs this sweep first, multiplies the conjugate phases before its
@@ -508,11 +534,15 @@ hipError_t launch_fresnel_batch(const PlaneArgs *planes, int count, int n, const
 // the exact-transfer-function step: row FFT (optic prologue, or plain for the adjoint), column
 // FFT * H * IFFT, row IFFT (plain, or the conjugate optic epilogue for the adjoint), each sweep
 // the direct step's kernel with its own plane arguments
+// (planes whose bit is set in `split` have H in its split form: their column sweep is the split
+// instance's launch, the others' the float64 one's, so each plane takes the kernels it takes in
+// a call of its own)
 template <class PL, int RL, int CL>
 hipError_t launch_exact_sweeps(const PlaneArgs *planes, int count, const float2 *tw, hipStream_t s,
-                               const LaunchHook &hook) {
+                               const LaunchHook &hook, uint64_t split) {
   constexpr int N = PL::N;
-  BatchArgs a, b, c;
+  BatchArgs a, b, c, bs;
+  int nb = 0, ns = 0;
   for (int i = 0; i < count; ++i) {
     const PlaneArgs &p = planes[i];
     const bool adj = p.flags & FR_ADJOINT;
@@ -521,8 +551,9 @@ hipError_t launch_exact_sweeps(const PlaneArgs *planes, int count, const float2 
     plain.lens = nullptr;
     a.p[i] = adj ? plain : p;
     a.p[i].flags = 0;                        // forward row transform (optic first when forward)
-    b.p[i] = p;
-    b.p[i].flags = p.flags & FR_ADJOINT;
+    PlaneArgs &col = (split >> i) & 1u ? bs.p[ns++] : b.p[nb++];
+    col = p;
+    col.flags = p.flags & FR_ADJOINT;
     c.p[i] = adj ? p : plain;
     c.p[i].flags = FR_ADJOINT;               // inverse row transform (conjugate optic after when adjoint)
   }
@@ -535,25 +566,34 @@ hipError_t launch_exact_sweeps(const PlaneArgs *planes, int count, const float2 
   };
   hipError_t e = rows(a, "exact_rows_fwd");
   if (e != hipSuccess) return e;
-  hook(s, "exact_cols", count, 0);
-  hipLaunchKernelGGL((col_sweep<PL, CL, false, true, true>), dim3(N / CL, count), dim3(PL::T * CL), 0, s, b, tw);
-  e = hipGetLastError();
-  hook(s, "exact_cols", count, 1);
+  if (ns) {
+    hook(s, "exact_cols", ns, 0);
+    hipLaunchKernelGGL((col_sweep<PL, CL, false, true, 2>), dim3(N / CL, ns), dim3(PL::T * CL), 0, s, bs, tw);
+    e = hipGetLastError();
+    hook(s, "exact_cols", ns, 1);
+    if (e != hipSuccess) return e;
+  }
+  if (nb) {
+    hook(s, "exact_cols_f64", nb, 0);
+    hipLaunchKernelGGL((col_sweep<PL, CL, false, true, 1>), dim3(N / CL, nb), dim3(PL::T * CL), 0, s, b, tw);
+    e = hipGetLastError();
+    hook(s, "exact_cols_f64", nb, 1);
+  }
   if (e != hipSuccess) return e;
   return rows(c, "exact_rows_inv");
 }
 
 hipError_t launch_exact_batch(const PlaneArgs *planes, int count, int n, const float2 *root, hipStream_t s,
-                              const LaunchHook &hook) {
+                              const LaunchHook &hook, uint64_t split) {
   switch (n) {
-    case 64: return launch_exact_sweeps<Plan<64, 8, 8, 8>, 8, 16>(planes, count, root, s, hook);
-    case 128: return launch_exact_sweeps<Plan<128, 16, 16, 8>, 16, 32>(planes, count, root, s, hook);
-    case 256: return launch_exact_sweeps<Plan<256, 16, 16, 16>, 16, 32>(planes, count, root, s, hook);
-    case 512: return launch_exact_sweeps<Plan<512, 8, 8, 8, 8>, 4, 16>(planes, count, root, s, hook);
-    case 1024: return launch_exact_sweeps<Plan<1024, 16, 16, 8, 8>, 4, 8>(planes, count, root, s, hook);
-    case 2048: return launch_exact_sweeps<Plan<2048, 16, 16, 16, 8>, 2, 8>(planes, count, root, s, hook);
-    case 4096: return launch_exact_sweeps<Plan<4096, 16, 16, 16, 16>, 1, 4>(planes, count, root, s, hook);
-    case 8192: return launch_exact_sweeps<Plan<8192, 16, 16, 16, 16, 2>, 1, 2>(planes, count, root, s, hook);
+    case 64: return launch_exact_sweeps<Plan<64, 8, 8, 8>, 8, 16>(planes, count, root, s, hook, split);
+    case 128: return launch_exact_sweeps<Plan<128, 16, 16, 8>, 16, 32>(planes, count, root, s, hook, split);
+    case 256: return launch_exact_sweeps<Plan<256, 16, 16, 16>, 16, 32>(planes, count, root, s, hook, split);
+    case 512: return launch_exact_sweeps<Plan<512, 8, 8, 8, 8>, 4, 16>(planes, count, root, s, hook, split);
+    case 1024: return launch_exact_sweeps<Plan<1024, 16, 16, 8, 8>, 4, 8>(planes, count, root, s, hook, split);
+    case 2048: return launch_exact_sweeps<Plan<2048, 16, 16, 16, 8>, 2, 8>(planes, count, root, s, hook, split);
+    case 4096: return launch_exact_sweeps<Plan<4096, 16, 16, 16, 16>, 1, 4>(planes, count, root, s, hook, split);
+    case 8192: return launch_exact_sweeps<Plan<8192, 16, 16, 16, 16, 2>, 1, 2>(planes, count, root, s, hook, split);
     default: return hipErrorInvalidValue;
   }
 }
