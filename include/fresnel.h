@@ -116,7 +116,11 @@ int fresnel_step_f64(fr_ctx *ctx, fr_c128 *field, int32_t n, double dx_m, double
  * the piston exp(2 pi i z / lambda) left out as in the paraxial form (which is this phase to
  * second order in lambda f); evanescent components (f > 1/lambda) decay as
  * exp(-2 pi |z| sqrt(f^2 - 1/lambda^2)) in either direction. H is not separable, so a plane takes
- * three sweeps (row FFT, column FFT * H * inverse FFT, inverse row FFT). Implemented edges:
+ * three sweeps (row FFT, column FFT * H * inverse FFT, inverse row FFT). H's phase is formed per
+ * element in float64 and reduced before the float32 sine and cosine; on a grid with no evanescent
+ * frequency whose phase differs from the paraxial one by at most a quarter turn, H is formed
+ * instead as its paraxial factors along x and y (built in float64) times exp(2 pi i c) with that
+ * difference c in float32, to the same accuracy. Implemented edges:
  * powers of two from 64 to 8192. Errors: FR_EINVAL (null field, n <= 0, dx / lambda <= 0, a
  * non-finite value, unknown flag), FR_EUNSUPPORTED (edge). Warning: FR_W_AS_UNDERSAMPLED. Uses no
  * workspace. */
