@@ -191,7 +191,9 @@ bool valid_plan(int n, unsigned plan) {
     if (r < 2 || r == 11 || r == 13 || r > 16) return false;
     prod *= r;
   }
-  return s > 0 && (s == kMrMaxPass ? (plan >> (5 * s)) == 0u : true) && prod == n;
+  // nothing after the last radix (shifts of 32 or more bits are avoided)
+  const bool tail_clear = 5 * s >= 32 || (plan >> (5 * s)) == 0u;
+  return s > 0 && tail_clear && prod == n;
 }
 
 }  // namespace

@@ -316,9 +316,18 @@ def test_autotuner_choices_keep_parity(tmp_path):
     assert "sweep 4096" in text and "plan 3840" in text and "gemm 4096 256 4096" in text
     fb.autotune_load(str(path))
     bad = tmp_path / "bad.txt"
-    bad.write_text("plan 3840 17\n")  # not an order of 3840's radices
-    with pytest.raises(fb.FrError):
-        fb.autotune_load(str(bad))
+    # not a factorisation of 3840 into supported radices: 17; radix 11; product 3600; a sixth
+    # radix's bits after a zero radix
+    for line in ("plan 3840 17", "plan 3840 %d" % (11 | (16 << 5) | (15 << 10)),
+                 "plan 3840 %d" % (15 | (16 << 5) | (15 << 10)),
+                 "plan 3840 %d" % (3 | (16 << 5) | (16 << 10) | (5 << 15) | (2 << 25))):
+        bad.write_text(line + "\n")
+        with pytest.raises(fb.FrError):
+            fb.autotune_load(str(bad))
+    # another factorisation of 3840 (not an order of its greedy radices) is accepted
+    good = tmp_path / "good.txt"
+    good.write_text("plan 3840 %d\n" % (3 | (16 << 5) | (16 << 10) | (5 << 15)))
+    fb.autotune_load(str(good))
 
 
 def test_sweep_variants_4096_agree_bitwise(tmp_path):
