@@ -47,6 +47,7 @@ struct PlaneArgs {
   int n;                     // plane edge
   int win;                   // window edge of amp / opd (n for full maps)
   int flags;                 // FR_ADJOINT | kSourceOptic | kTowardSource | kWindowRowsOnly
+  int post_lo, post_hi;      // when post_hi > post_lo: post_surf is 0 outside columns [post_lo, post_hi)
 };
 
 // element (y, x) of an n x n map stored in 4-column tiles: tile x/4 holds rows 0..n-1 of its

@@ -272,6 +272,9 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   const bool adj = pa.flags & FR_ADJOINT;
   const PlaneBuf buf(pa.field, unsigned(N) * N * 8u);
   const unsigned vo = unsigned(t * N + x) * 8u;
+  // the post surface's phasor, unless this tile lies where the surface is 0 (the phasor is 1)
+  const int x0 = g * LINES;
+  const bool post = pa.post_surf && !(pa.post_hi > pa.post_lo && (x0 + LINES <= pa.post_lo || x0 >= pa.post_hi));
   c32 v[E];
   if (!adj && pa.amp && pa.win < N) {
     // forward plane with a windowed amplitude: the rows outside the window are zero after the
@@ -286,7 +289,7 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = buf.load(vo, unsigned(T * m) * unsigned(N) * 8u);
   }
-  if (adj && pa.post_surf) {
+  if (adj && post) {
     c32 ph[E];
     post_optic_col<E, T>(pa, N, t, x, ph);
 #pragma unroll
@@ -379,7 +382,7 @@ __global__ void __launch_bounds__(PL::T *LINES) col_sweep(BatchArgs args, const 
   PL::template forward<HALF>(v, my, t, tw);
   freq_product<E, T>(v, pa.h, t, adj);
   PL::template inverse<HALF>(v, my, t, tw);
-  if (!adj && pa.post_surf) {
+  if (!adj && post) {
     c32 ph[E];
     post_optic_col<E, T>(pa, N, t, x, ph);
 #pragma unroll

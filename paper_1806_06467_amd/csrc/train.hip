@@ -616,6 +616,8 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     pa->win = nd;
     pa->pre_surf = ndm == 2 ? surf : nullptr;
     pa->post_surf = ndm >= 1 ? surf + size_t(ndm - 1) * surf_stride(n) : nullptr;
+    // the surface G A G^T is exactly 0 outside the band where G has nonzero entries
+    if (ndm >= 1) ctx->dm_band(n, nd, na, &pa->post_lo, &pa->post_hi);
     pa->inv_lambda = float(1.0 / lam[j]);
     pa->flags = kSourceOptic;
     return ctx->transfer(n, dx, lam[j], d->z_m, s, &pa->h);
@@ -627,6 +629,7 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     pb->field = c64at(L.b[j]);
     pb->n = n;
     pb->post_surf = surf_of(j) + size_t(ndm - 1) * surf_stride(n);
+    ctx->dm_band(n, nd, na, &pb->post_lo, &pb->post_hi);
     pb->inv_lambda = float(1.0 / lam[j]);
     // B1 is read only inside the pupil window (the pupil DM's gradient)
     pb->win = nd;
