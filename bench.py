@@ -55,16 +55,16 @@ METRIC = "Fresnel planes/sec at 4096^2 c64 (fwd+adjoint, batched vs plain), %HBM
 # 128 MiB plane in the same runs (FETCH x 2.0, WRITE x 1.0). Each entry carries the SHA-256 of the
 # sources it was measured on and reads as unknown (null) once they change.
 MEASURED_TRAFFIC = {
-    "row_sweep": (269226486, 134217728),
-    "col_sweep": (137015755, 170336970),
-    "col_sweep_adj": (136703430, 154198848),
-    "row_sweep_adj": (269275437, 134217728),
+    "row_sweep": (269218249, 134217728),
+    "col_sweep": (136636795, 165001379),
+    "col_sweep_adj": (136488486, 167391150),
+    "row_sweep_adj": (269255542, 134217728),
 }
 _SWEEP_SOURCES = {
-    "paper_1806_06467_amd/csrc/sweeps.hip": "e323ecbd6109ccf0e8b98c2b98f2538637909c83f51156fb20c65e6e312ce83e",
+    "paper_1806_06467_amd/csrc/sweeps.hip": "98e23daf76c939ad81ff8b609719321fd595eab8fd48228ec815f5a9aed09750",
     "paper_1806_06467_amd/csrc/fft_line.hpp": "66f504dc38f9cb71c51b0dd9e259e966acb90c9d9d1b256d8d7ca415edac6fae",
     "paper_1806_06467_amd/csrc/dft_small.hpp": "f079518edd36aa105b5a40ce60935e1cdb8f3c06c3c59d0fa46a65eea89b7209",
-    "paper_1806_06467_amd/csrc/fr_internal.h": "4550d78171dc2f343483d3115581126d5142893658ccc2849c7b709bc9b7ba35",
+    "paper_1806_06467_amd/csrc/fr_internal.h": "02c3e065cf6306f08322cfd1ba1a1b4c9e8d4cd9567bdc661d2d3afd895ca19a",
 }
 TRAFFIC_SOURCES = {k: _SWEEP_SOURCES for k in MEASURED_TRAFFIC}
 
