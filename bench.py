@@ -10,8 +10,9 @@ OPD maps of the whole plane, read by the row sweep), on 42 fields resident in HB
       recorded once as a graph and replayed);
   plain form: 42 fresnel_step calls per step, stream-ordered, no graph.
 Beside it: per-iteration spread (median / IQR over 50 steps) and the paper's own timing style
-(mean +- sigma over 7 runs); the same 42 planes on the uneven per-wavelength grids 3584..4096
-(bytes-weighted); the whole Lyot coronagraph train with two DMs, PSF and gradient (the rest of
+(mean +- sigma over 7 runs); the same 42 planes on 512^2 grids, batched against plain (where
+the launches, not the sweeps, set the plain form's time); the same 42 planes on the uneven
+per-wavelength grids 3584..4096 (bytes-weighted); the whole Lyot coronagraph train with two DMs, PSF and gradient (the rest of
 the hot path: MFTs, PSF accumulation, DM synthesis and adjoint) as a secondary figure; the
 direct and exact-transfer-function steps (the exact one also batched); the App. B relay analogue
 at 4096^2; the float64 Fresnel plane and MFT; a device-copy ceiling.
@@ -312,6 +313,39 @@ def main():
               "runs7_mean_ms": statistics.mean(runs), "runs7_sigma_ms": statistics.stdev(runs),
               "runs7_steps_each": steps}
     result_extra = {}
+
+    # ---- the same 42 planes on small grids (512^2, the first configuration's padded grid), ----
+    # ---- where a plane's sweeps take microseconds and the launches dominate the plain form ----
+    if not args.no_extras:
+        ns_ = 512
+        r = np.random.default_rng(512)
+        amp_s = torch.from_numpy(r.uniform(0.99, 1.0, (ns_, ns_)).astype(np.float32)).to(dev)
+        opd_s = torch.from_numpy(r.normal(0.0, 10e-9, (ns_, ns_)).astype(np.float32)).to(dev)
+        sfields = []
+        for i in range(n_pl):
+            g = torch.Generator(device=dev)
+            g.manual_seed(3000 + i)
+            sfields.append(torch.randn((ns_, ns_), dtype=torch.complex64, device=dev, generator=g))
+        dx_s, z_s = 1e-4, 1.0
+
+        def small_batched():
+            fb.fresnel_step_batched(sfields, dx_s, lam_pl, z_s, amps=amp_s, opds=opd_s, adjoints=adjs, graph=True)
+
+        def small_plain():
+            for i in range(n_pl):
+                fb.fresnel_step(sfields[i], dx_s, lam_pl[i], z_s, amp=amp_s, opd=opd_s, adjoint=adjs[i])
+        s_steps = max(10, steps)
+        ms_sb = timed(small_batched, s_steps, 3) / s_steps
+        ms_sp = timed(small_plain, s_steps, 2) / s_steps
+        result_extra["small_grid_batching"] = {
+            "n": ns_, "planes_per_step": n_pl,
+            "batched": {"value": n_pl / (ms_sb * 1e-3), "unit": "Fresnel planes/s", "ms_per_step": ms_sb,
+                        "form": "one fresnel_step_batched_graph call (all 42 planes in one cache-sized group: "
+                                "four launches)"},
+            "plain": {"value": n_pl / (ms_sp * 1e-3), "unit": "Fresnel planes/s", "ms_per_step": ms_sp,
+                      "form": "42 fresnel_step calls (84 launches)"},
+            "batched_over_plain": ms_sp / ms_sb}
+        del sfields, amp_s, opd_s
 
     # ---- uneven per-wavelength grids (3584..4096), forward + adjoint, bytes-weighted ---------
     if not args.no_extras:
