@@ -40,7 +40,8 @@ struct RGemm {
   float *C;
   int ldc;
   float alpha, beta;
-  int tiled;  // 1: C is an M x M map stored in 4-column tiles (post_tiled_index), ldc unused
+  int tiled;  // 1: C is an n x n map stored in 4-column tiles (post_tiled_index), ldc unused
+  int tn, t0; // tiled: the map's edge n and the offset of C's element (0, 0) on both axes
 };
 
 __global__ void __launch_bounds__(256) rgemm_kernel(RGemm g) {
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(256) rgemm_kernel(RGemm g) {
     __syncthreads();
   }
   if (i < g.M && j < g.N) {
-    float *cp = g.tiled ? g.C + post_tiled_index(g.M, i, j) : g.C + size_t(i) * g.ldc + j;
+    float *cp = g.tiled ? g.C + post_tiled_index(g.tn, i + g.t0, j + g.t0) : g.C + size_t(i) * g.ldc + j;
     *cp = g.alpha * acc + (g.beta != 0.f ? g.beta * *cp : 0.f);
   }
 }
@@ -583,16 +584,25 @@ int train_run(Ctx *ctx, const fr_train_desc *d, int32_t n_lambda, const double *
     if (_s != FR_OK) return _s; \
   } while (0)
 
-  // DM surfaces s = G A G^T on an n grid (a8): TDM (na x n) = A G^T ; SURF_k (n x n) = G TDM
+  // DM surfaces s = G A G^T on an n grid (a8): TDM (na x n) = A G^T ; SURF_k (n x n) = G TDM.
+  // Rows and columns of G outside its band [lo, hi) are exactly 0, and so is the surface there:
+  // the map is cleared, and the product formed on the band only (the same sums where it is).
   auto surfaces = [&](int n, float *surf) -> int {
     const float *G = nullptr;
     FR_TRY(ctx->dm_influence(n, nd, na, s, &G));
+    int lo = 0, hi = n;
+    ctx->dm_band(n, nd, na, &lo, &hi);
+    if (hi <= lo) lo = 0, hi = n;
+    const int nb = hi - lo;
     for (int k = 0; k < ndm; ++k) {
-      RGemm g1{na, n, na, d->dm_heights_m + size_t(k) * na * na, na, 0, G, na, 1, TDM, n, 1.f, 0.f, 0};
+      RGemm g1{na, n, na, d->dm_heights_m + size_t(k) * na * na, na, 0, G, na, 1, TDM, n, 1.f, 0.f, 0, 0, 0};
       FR_TRY_HIP(rgemm(g1, s, hook));
+      float *sk = surf + size_t(k) * surf_stride(n);
       // the DM after the step is applied by the column sweep: 4-column tiles
       const int tiled = k == ndm - 1 ? 1 : 0;
-      RGemm g2{n, n, na, G, na, 0, TDM, n, 0, surf + size_t(k) * surf_stride(n), n, 1.f, 0.f, tiled};
+      if (nb < n) FR_TRY_HIP(launch1d(fill_f32, surf_stride(n), s, hook, "fill", sk, surf_stride(n), 0.f));
+      RGemm g2{nb, nb, na, G + size_t(lo) * na, na, 0, TDM + lo, n, 0, tiled ? sk : sk + size_t(lo) * n + lo, n,
+               1.f, 0.f, tiled, n, lo};
       FR_TRY_HIP(rgemm(g2, s, hook));
     }
     return FR_OK;
