@@ -162,6 +162,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) z
     }
 }
 
+// most partials zsum_kernel adds
+constexpr int kMaxZsum = 32;
+
 // split-K factors of the forward transform's two products (m x n x n, then m x m x n): 4 and 32
 // where their 64 x 64 tiles alone would give a launch fewer than 4 blocks per compute unit and
 // the pupil is large
@@ -171,20 +174,26 @@ int f64_split(int n, int m) {
 }
 int f64_split2(int n, int m) {
   const long tiles = long((m + 63) / 64) * long((m + 63) / 64);
-  return tiles < 1024 && n >= 1024 ? 32 : 1;
+  return tiles < 1024 && n >= 1024 ? kMaxZsum : 1;
 }
 
-// out[i] = s sum_p part[p stride + i], the partials added in order
+// out[i] = s sum_p part[p stride + i], the partials added in order (np <= kMaxZsum; every
+// partial's load is issued before the first addition)
 __global__ void __launch_bounds__(256) zsum_kernel(const z64 *__restrict__ part, size_t stride, int np,
                                                    z64 *__restrict__ out, size_t count, double s) {
   const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= count) return;
-  z64 acc = part[i];
-  for (int p = 1; p < np; ++p) {
-    const z64 v = part[p * stride + i];
-    acc.x += v.x;
-    acc.y += v.y;
-  }
+  z64 v[kMaxZsum];
+#pragma unroll
+  for (int p = 0; p < kMaxZsum; ++p)
+    if (p < np) v[p] = part[p * stride + i];
+  z64 acc = v[0];
+#pragma unroll
+  for (int p = 1; p < kMaxZsum; ++p)
+    if (p < np) {
+      acc.x += v[p].x;
+      acc.y += v[p].y;
+    }
   out[i] = {s * acc.x, s * acc.y};
 }
 
